@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs for TT multiplication.
+
+This module generates the tensor trains that both the CPU oracle and the GPU
+library multiply.  It holds no step of the multiplication itself: it builds
+cores (random, closed-form, or compressed from a synthetic field) and nothing
+else.
+
+Core layout everywhere: a tensor train is a list of NumPy float64 arrays,
+core ``i`` of shape ``[r_{i-1}, d_i, r_i]`` with ``r_0 = r_N = 1``
+(the carriage of Eq. (TT): one ``r_{i-1} x r_i`` matrix per physical value).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "structural_bonds",
+    "random_tt",
+    "ones_tt",
+    "exp_qtt",
+    "sin_qtt",
+    "cos_qtt",
+    "poly1_qtt",
+    "square_qtt",
+    "const_qtt",
+    "turbulence_component",
+    "qtt_encode_3d",
+    "tt_svd",
+    "turbulence_qtt",
+    "app_a_toy_tt",
+]
+
+
+def structural_bonds(phys, chi):
+    """Bond caps r_i = min(prod_{k<=i} d_k, prod_{k>i} d_k, chi), r_0 = r_N = 1.
+
+    This is Eq. (bond) generalised from d = 2 to per-site physical
+    dimensions d_k.  ``chi <= 0`` means no cap.
+    """
+    n = len(phys)
+    cap = 1 << 62
+    bonds = [1] * (n + 1)
+    for i in range(1, n):
+        left = 1
+        for k in range(i):
+            left = min(left * int(phys[k]), cap)
+        right = 1
+        for k in range(i, n):
+            right = min(right * int(phys[k]), cap)
+        b = min(left, right)
+        if chi and chi > 0:
+            b = min(b, int(chi))
+        bonds[i] = b
+    return bonds
+
+
+def random_tt(n_sites, d, chi, seed, scale=None):
+    """Random TT with structural bonds capped at ``chi``.
+
+    Entries are i.i.d. N(0,1) times ``scale`` (default 1/sqrt(2*chi)), drawn
+    from NumPy's PCG64 stream ``seed`` core by core, left to right, in C order.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    phys = [d] * n_sites if np.isscalar(d) else list(d)
+    bonds = structural_bonds(phys, chi)
+    if scale is None:
+        scale = 1.0 / np.sqrt(2.0 * chi)
+    cores = []
+    for i in range(n_sites):
+        shape = (bonds[i], phys[i], bonds[i + 1])
+        cores.append(rng.standard_normal(shape) * scale)
+    return cores
+
+
+def ones_tt(n_sites, d):
+    """The all-ones tensor as a TT: every bond 1, every entry 1."""
+    phys = [d] * n_sites if np.isscalar(d) else list(d)
+    return [np.ones((1, p, 1)) for p in phys]
+
+
+def _grid_weights(n_sites, dx):
+    # x = a + dx * sum_i sigma_i 2^{i-1}: site 1 carries the finest bit
+    # (the one-dimensional quantics encoding of the benchmark section).
+    return [dx * float(2 ** i) for i in range(n_sites)]
+
+
+def const_qtt(n_sites, value):
+    cores = [np.ones((1, 2, 1)) for _ in range(n_sites)]
+    cores[0] = cores[0] * value
+    return cores
+
+
+def exp_qtt(n_sites, c, a=0.0, dx=None):
+    """QTT of exp(c x) on the 2^N grid x = a + dx * sum sigma_i 2^{i-1}; rank 1."""
+    if dx is None:
+        dx = 1.0 / (2 ** n_sites - 1)
+    w = _grid_weights(n_sites, dx)
+    cores = []
+    for i in range(n_sites):
+        core = np.empty((1, 2, 1))
+        core[0, 0, 0] = 1.0
+        core[0, 1, 0] = np.exp(c * w[i])
+        cores.append(core)
+    cores[0] = cores[0] * np.exp(c * a)
+    return cores
+
+
+def _trig_qtt(n_sites, c, a, dx, want_sin):
+    if dx is None:
+        dx = 1.0 / (2 ** n_sites - 1)
+    w = _grid_weights(n_sites, dx)
+    # state after site i: (cos phi_i, sin phi_i), phi_i = c*(a + partial sum)
+    cores = []
+    for i in range(n_sites):
+        if i == 0:
+            core = np.empty((1, 2, 2))
+            for s in range(2):
+                ph = c * (a + w[0] * s)
+                core[0, s, :] = (np.cos(ph), np.sin(ph))
+        else:
+            core = np.empty((2, 2, 2))
+            for s in range(2):
+                th = c * w[i] * s
+                ct, st = np.cos(th), np.sin(th)
+                core[:, s, :] = [[ct, st], [-st, ct]]
+        cores.append(core)
+    last = cores[-1]
+    col = 1 if want_sin else 0
+    cores[-1] = last[:, :, col:col + 1].copy()
+    return cores
+
+
+def sin_qtt(n_sites, c, a=0.0, dx=None):
+    """QTT of sin(c x); rank 2."""
+    return _trig_qtt(n_sites, c, a, dx, True)
+
+
+def cos_qtt(n_sites, c, a=0.0, dx=None):
+    """QTT of cos(c x); rank 2."""
+    return _trig_qtt(n_sites, c, a, dx, False)
+
+
+def poly1_qtt(n_sites, a=0.0, dx=None):
+    """QTT of x itself; rank 2 (state: 1, partial sum)."""
+    if dx is None:
+        dx = 1.0 / (2 ** n_sites - 1)
+    w = _grid_weights(n_sites, dx)
+    cores = []
+    for i in range(n_sites):
+        core = np.zeros((2, 2, 2))
+        for s in range(2):
+            t = w[i] * s
+            core[:, s, :] = [[1.0, t], [0.0, 1.0]]
+        cores.append(core)
+    cores[0] = cores[0][0:1] + 0.0
+    cores[0][0, :, 1] += a
+    cores[-1] = cores[-1][:, :, 1:2].copy()
+    return cores
+
+
+def square_qtt(n_sites, a=0.0, dx=None):
+    """QTT of x^2; rank 3 (state: 1, s, s^2)."""
+    if dx is None:
+        dx = 1.0 / (2 ** n_sites - 1)
+    w = _grid_weights(n_sites, dx)
+    cores = []
+    for i in range(n_sites):
+        core = np.zeros((3, 2, 3))
+        for s in range(2):
+            t = w[i] * s
+            core[:, s, :] = [[1.0, t, t * t], [0.0, 1.0, 2.0 * t], [0.0, 0.0, 1.0]]
+        cores.append(core)
+    first = np.zeros((1, 2, 3))
+    for s in range(2):
+        t = a + w[0] * s
+        first[0, s, :] = (1.0, t, t * t)
+    cores[0] = first
+    cores[-1] = cores[-1][:, :, 2:3].copy()
+    return cores
+
+
+def turbulence_component(n, seed, kprime=None):
+    """One component of a 3D random-phase synthetic turbulence field on n^3.
+
+    Follows the artificial turbulence recipe of App. B lifted to three
+    dimensions: amplitude |u(k)| = c k^{-11/6} sigma(k) (the 3D analogue of the
+    2D k^{-2} law, giving E(k) ~ k^{-5/3}), sigmoid cut-off
+    sigma(k) = 1/(1+exp(beta (k - k'))) with beta = 2/k', random phases with
+    theta(-k) = -theta(k) (taken from the FFT of real white noise, which has
+    that symmetry), division by sqrt(2), a real inverse DFT, and modes with
+    k = 0 or |k| > n/2 set to zero.  The grid is periodic with integer wave
+    numbers; c is fixed by normalising the field to unit RMS.
+    """
+    if kprime is None:
+        kprime = n / 8.0
+    beta = 2.0 / kprime
+    rng = np.random.Generator(np.random.PCG64(seed))
+    noise = rng.standard_normal((n, n, n))
+    phase = np.angle(np.fft.rfftn(noise))
+    del noise
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    kr = np.fft.rfftfreq(n, 1.0 / n)
+    k = np.sqrt(k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    with np.errstate(divide="ignore", over="ignore"):
+        amp = np.where(k > 1e-16, k ** (-11.0 / 6.0), 0.0) / (1.0 + np.exp(beta * (k - kprime)))
+    amp[k > n / 2.0] = 0.0
+    uk = amp * np.exp(1j * phase) / np.sqrt(2.0)
+    del amp, phase, k
+    u = np.fft.irfftn(uk, s=(n, n, n), axes=(0, 1, 2))
+    u /= np.sqrt(np.mean(u * u))
+    return u
+
+
+def qtt_encode_3d(field):
+    """Reshape an n^3 field (n = 2^L) to the interleaved-bit order.
+
+    Site s = 1..L carries bit s (most significant first) of x, y and z, with
+    physical index eta_s = 4 x_s + 2 y_s + z_s.  Returns a dense array of
+    shape (8,)*L in that site order.
+    """
+    n = field.shape[0]
+    L = int(round(np.log2(n)))
+    assert 2 ** L == n and field.shape == (n, n, n)
+    t = field.reshape((2,) * (3 * L))
+    order = []
+    for s in range(L):
+        order += [s, L + s, 2 * L + s]
+    return t.transpose(order).reshape((8,) * L)
+
+
+def tt_svd(dense, chi):
+    """Left-to-right TT-SVD of a dense tensor, keeping at most ``chi`` values
+    per bond (``chi <= 0``: no cap) and dropping exact zeros only."""
+    shape = dense.shape
+    n = len(shape)
+    cores = []
+    rest = dense.reshape(1, -1)
+    r_left = 1
+    for i in range(n - 1):
+        mat = rest.reshape(r_left * shape[i], -1)
+        u, s, vt = np.linalg.svd(mat, full_matrices=False)
+        r = int(np.count_nonzero(s > 0))
+        r = max(r, 1)
+        if chi and chi > 0:
+            r = min(r, chi)
+        cores.append(u[:, :r].reshape(r_left, shape[i], r))
+        rest = s[:r, None] * vt[:r]
+        r_left = r
+    cores.append(rest.reshape(r_left, shape[-1], 1))
+    return cores
+
+
+def turbulence_qtt(n, seed, chi, kprime=None):
+    """QTT (N = log2 n sites, d = 8) of one synthetic turbulence component."""
+    u = turbulence_component(n, seed, kprime)
+    t = qtt_encode_3d(u)
+    del u
+    return tt_svd(t, chi)
+
+
+def app_a_toy_tt(n_sites, d_rest=2, chi=4, seed=0):
+    """The toy TT of App. A: the first two carriages are
+
+        M^{s2=0} = (M^{s1=0})^T = 2^{-1/4} (1, 0),
+        (M^{s2=1})^T = M^{s1=1} = 2^{-1/4} (0, 1),
+
+    so bits 1 and 2 are maximally correlated with each other and with nothing
+    else (the bond between carriages 2 and 3 is 1); carriages 3..N are random.
+    """
+    assert n_sites > 2
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = 2.0 ** -0.25
+    m1 = np.zeros((1, 2, 2))
+    m1[0, 0, :] = (c, 0.0)
+    m1[0, 1, :] = (0.0, c)
+    m2 = np.zeros((2, 2, 1))
+    m2[:, 0, 0] = (c, 0.0)
+    m2[:, 1, 0] = (0.0, c)
+    phys = [2, 2] + [d_rest] * (n_sites - 2)
+    rest_bonds = structural_bonds(phys[2:], chi)
+    cores = [m1, m2]
+    for i in range(n_sites - 2):
+        cores.append(rng.standard_normal((rest_bonds[i], phys[2 + i], rest_bonds[i + 1])))
+    return cores
