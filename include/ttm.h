@@ -1,0 +1,164 @@
+/*
+ * ttm.h - C ABI of libttm: elementwise (Hadamard) product of two tensor
+ * trains on one AMD Instinct MI355X (gfx950), FP64.
+ *
+ * Method: Michailidis, Fenton, Kiffner, "Tensor Train Multiplication"
+ * (arXiv 2410.19747).  The product Omega = psi * phi of two TTs (problem
+ * statement of Sec. II) is formed by the TTM algorithm of Sec. II.B:
+ *   - the two trains are concatenated with the second one reversed
+ *     (Eq. tensor);
+ *   - carriages with the same site index are contracted through the local
+ *     COPY tensor (Eq. contract);
+ *   - the second train's carriages are moved next to their partners by
+ *     Swap operations, each a contraction, an exchange of physical legs and
+ *     a truncated SVD under the rule of Eq. (eps), in mixed-canonical gauge;
+ *   - the gauge centre is moved with QR decompositions after every
+ *     contraction.
+ * conventional_multiply is the baseline of Sec. II.A: a single-site
+ * variational fit of Omega to the MPO form of phi (Eq. PhiMPO) applied to
+ * psi, never forming the Kronecker carriages of Eq. (carriageXi).
+ *
+ * Layout of a tensor train ("TT"): N cores; core i (0-based) is a row-major
+ * array [r_i][d_i][r_{i+1}] of doubles (the carriage of Eq. (TT): one
+ * r_i x r_{i+1} matrix per physical value), with r_0 = r_N = 1.  Core i
+ * starts at element offsets[i] of the device buffer data.
+ *
+ * Ownership: the caller owns every pointer.  Input cores, the output buffer
+ * and the workspace are device memory that the caller allocates; the
+ * library allocates no device memory.  Host arrays (phys, bonds, offsets,
+ * traces) are read or written only during the call.
+ *
+ * Blocking: every compute entry point enqueues its kernels on the given
+ * stream (a hipStream_t; NULL is the default stream) and returns only when
+ * they have finished, because the ranks chosen by each truncation are read
+ * back to size the next step.  Output bonds and offsets are valid on return.
+ *
+ * Errors: 0 on success, a negative TTM_E* code otherwise; no exception
+ * crosses this boundary.  Argument errors are detected on the host before
+ * any GPU work is enqueued.  Calls on distinct streams with distinct
+ * workspaces and outputs may run concurrently; calls sharing a workspace
+ * must not overlap.
+ */
+#ifndef TTM_H
+#define TTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TTM_OK = 0,
+  TTM_EINVAL = -1,       /* null pointer, bad size, bad option value          */
+  TTM_ESHAPE = -2,       /* A and B differ in N or d, or a bond is not 1 at an end */
+  TTM_EWORKSPACE = -3,   /* workspace missing or smaller than ttm_query says  */
+  TTM_ECAPACITY = -4,    /* output buffer smaller than ttm_query says         */
+  TTM_ENOCONV = -5,      /* an SVD did not converge within its sweep limit    */
+  TTM_ENONFINITE = -6,   /* NaN or Inf met in the data                        */
+  TTM_EHIP = -7,         /* a HIP runtime call failed                         */
+  TTM_EFORCED = -8,      /* forced rank list too short or out of range        */
+  TTM_EUNSUPPORTED = -9  /* dtype other than TTM_F64                          */
+};
+
+typedef enum { TTM_F64 = 0 } ttm_dtype;
+
+/* Borrowed view of an input TT. */
+typedef struct ttm_tt {
+  int32_t n_sites;         /* N >= 1                                          */
+  const int32_t *phys;     /* host [N]: d_i >= 1                              */
+  const int32_t *bonds;    /* host [N+1]: r_0 = r_N = 1, r_i >= 1             */
+  const int64_t *offsets;  /* host [N]: element offset of core i in data      */
+  const void *data;        /* device: doubles                                 */
+  int32_t dtype;           /* TTM_F64                                         */
+} ttm_tt;
+
+/* Output TT: the caller provides the buffers, the library fills them. */
+typedef struct ttm_tt_out {
+  int32_t *bonds;          /* host [N+1], written                              */
+  int64_t *offsets;        /* host [N], written (cores packed in site order)   */
+  void *data;              /* device, at least `capacity` doubles              */
+  int64_t capacity;        /* in doubles; must be >= ttm_query's out_capacity  */
+} ttm_tt_out;
+
+/* Options.  Fill with ttm_default_options, then change fields. */
+typedef struct ttm_options {
+  int32_t chi_mid;         /* rank cap of every swap; 0 = uncapped; -1 (default) = chi_out */
+  int32_t final_round;     /* 1 (default): left-to-right truncated-SVD sweep with cap chi_out */
+  int32_t max_sweeps;      /* conventional_multiply: sweep limit (default 10) */
+  int32_t svd_max_sweeps;  /* Jacobi sweep limit per SVD (default 40)         */
+  uint64_t seed;           /* conventional_multiply: initial-guess seed (default 12345) */
+  const int32_t *forced_ranks; /* host [n_forced]: ranks replacing the rule of Eq. (eps),
+                                  consumed in order (swaps, then the final sweep); NULL = none */
+  int32_t n_forced;
+  int32_t trace_cap;       /* capacity of the two trace arrays              */
+  int32_t *rank_trace;     /* host [trace_cap]: rank of each truncating SVD, or NULL */
+  double *discard_trace;   /* host [trace_cap]: discarded weight sum_{i>r} lambda_i^2, or NULL */
+} ttm_options;
+
+/* Statistics of one call. */
+typedef struct ttm_stats {
+  int32_t max_bond;        /* largest bond present in the chain during the call */
+  int32_t n_contract;      /* contractions (Eq. contract): N                   */
+  int32_t n_swap;          /* swaps: N(N-1)/2                                  */
+  int32_t n_qr;            /* QR gauge moves, including input canonicalisation */
+  int32_t n_svd;           /* truncating SVDs (swaps + final sweep)            */
+  int32_t n_trace;         /* entries written to the traces                    */
+  int32_t sweeps;          /* conventional: sweeps run; TTM: total Jacobi sweeps */
+  int32_t jacobi_max_sweeps; /* most Jacobi sweeps any one SVD needed          */
+  double discarded_sq_sum; /* sum over SVDs of the discarded weight            */
+  double error_bound;      /* sum over SVDs of sqrt(discarded weight): bounds ||C - A*B|| */
+  double model_flops;      /* algorithmic flops of the recorded schedule       */
+  double svd_model_flops;  /* the part of model_flops spent in SVDs            */
+  size_t peak_ws_bytes;    /* workspace bytes the call used                    */
+} ttm_stats;
+
+/* Defaults: chi_mid = -1 (same as chi_out), final_round = 1, max_sweeps = 10,
+ * svd_max_sweeps = 40, seed = 12345, no forced ranks, no traces. */
+void ttm_default_options(ttm_options *opt);
+
+/* Sizes for ttm_multiply (host only, no GPU work).  Writes the workspace
+ * bytes and the output capacity (doubles) needed for these inputs and
+ * options: out_capacity = sum_i c_i d_i c_{i+1} with
+ * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, cap), cap = chi_out when
+ * final_round is set, else the swap cap.  Either output pointer may be NULL. */
+int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
+              size_t *ws_bytes, int64_t *out_capacity);
+
+/* C = A * B elementwise by TTM (Sec. II.B).  tol is the eps of Eq. (eps),
+ * applied relative to each SVD's total weight; chi_out caps the output bonds.
+ * ws: device workspace of ws_bytes >= ttm_query's size.  stream: hipStream_t. */
+int ttm_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, ttm_tt_out *C,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* As ttm_multiply, with options (NULL = defaults) and statistics (may be NULL). */
+int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
+                    ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
+                    const ttm_options *opt, ttm_stats *stats);
+
+/* Sizes for conventional_multiply (host only). */
+int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
+                       size_t *ws_bytes, int64_t *out_capacity);
+
+/* C ~ A * B by the single-site variational fit of Sec. II.A with bonds
+ * capped at chi_out.  tol: stop when the norm of the centre changes by at
+ * most tol (relative) between two full sweeps. */
+int conventional_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
+                          ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream);
+
+int conventional_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
+                             ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
+                             const ttm_options *opt, ttm_stats *stats);
+
+/* Static message for an error code. */
+const char *ttm_strerror(int code);
+
+/* Library version string. */
+const char *ttm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTM_H */

@@ -1,0 +1,51 @@
+/*
+ * ttm_testing.h - kernel-level entry points of libttm for parity tests.
+ *
+ * Each call runs one building block of the TTM sweep on device buffers the
+ * caller owns and returns after the stream has finished (0 or a negative
+ * TTM_E* code from ttm.h).  They exist so that tests can check every kernel
+ * against a plain reference on random operands; the product itself only
+ * needs ttm.h.
+ */
+#ifndef TTM_TESTING_H
+#define TTM_TESTING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Batched FP64 product with the split-stride output mapping used by the
+ * Contract (Eq. contract) and swap-merge steps:
+ *   C[b](i,j) = sum_k A[b](i,k) B[b](k,j), A(i,k) at A + b*a_bs + i*a_rs + k*a_cs,
+ *   B(k,j) at B + b*b_bs + k*b_rs + j*b_cs, C(i,j) at
+ *   C + b*c_bs + (i/c_rdiv)*c_rs1 + (i%c_rdiv)*c_rs0 + (j/c_cdiv)*c_cs1 + (j%c_cdiv)*c_cs0. */
+int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs, int64_t a_cs,
+                  int64_t a_bs, const double *B, int64_t b_rs, int64_t b_cs, int64_t b_bs,
+                  double *C, int64_t c_bs, int c_rdiv, int c_cdiv, int64_t c_rs1, int64_t c_rs0,
+                  int64_t c_cs1, int64_t c_cs0, void *stream);
+
+/* Householder QR of the m x n row-major matrix M (device): Q (m x k,
+ * row-major, k = min(m,n)) and R (k x n, row-major).  scratch: device,
+ * ttm_test_qr_scratch(m, n) doubles. */
+size_t ttm_test_qr_scratch(int m, int n);
+int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scratch, void *stream);
+
+/* Truncated SVD of the m x n row-major matrix M (device) by the one-sided
+ * block Jacobi kernels and the rule of Eq. (eps) (cap > 0 caps the rank,
+ * forced > 0 replaces the rule).  Writes left = U_r diag(s)^left_pow (m x r)
+ * and right = diag(s)^right_pow V_r^T (r x n), both row-major, the sorted
+ * singular values (min(m,n) doubles, device) and, on the host, the rank and
+ * the number of sweeps.  ws: device, ttm_test_svd_ws_bytes(m, n) bytes. */
+size_t ttm_test_svd_ws_bytes(int m, int n);
+int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
+                 int right_pow, double *left, double *right, double *sigma, int *rank,
+                 int *sweeps, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTM_TESTING_H */

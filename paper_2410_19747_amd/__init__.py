@@ -1,0 +1,228 @@
+"""Python binding of libttm: tensor-train multiplication on an MI355X (gfx950).
+
+Argument marshalling only.  Every step of the product runs in the HIP
+kernels of ``libttm.so``; PyTorch provides device memory and the stream.
+The functions mirror the C entry points of ``include/ttm.h``:
+
+    multiply(A, B, chi_out, tol, **options)       -> ttm_multiply_ex
+    conventional(A, B, chi_out, tol, **options)   -> conventional_multiply_ex
+    query(A, B, chi_out, **options)               -> ttm_query
+
+A tensor train is a list of float64 CUDA tensors, core i of shape
+[r_i, d_i, r_{i+1}] (r_0 = r_N = 1), or a ``PackedTT``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from ._abi import (  # noqa: F401
+    TTM_OK, TTM_EINVAL, TTM_ESHAPE, TTM_EWORKSPACE, TTM_ECAPACITY, TTM_ENOCONV, TTM_ENONFINITE,
+    TTM_EHIP, TTM_EFORCED, TTM_EUNSUPPORTED, TtmTT, TtmTTOut, TtmOptions, TtmStats, load_library,
+    library_path,
+)
+
+__all__ = [
+    "TTMError", "PackedTT", "pack", "multiply", "conventional", "query", "conventional_query",
+    "Workspace", "lib",
+]
+
+
+class TTMError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().ttm_strerror(code).decode()
+        super().__init__("%s failed: %s (code %d)" % (where, msg, code))
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libttm.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class PackedTT:
+    """A TT packed into one contiguous float64 device buffer plus host arrays."""
+
+    def __init__(self, data, phys, bonds, offsets):
+        import torch
+
+        assert data.dtype == torch.float64 and data.is_contiguous()
+        self.data = data
+        self.phys = list(int(p) for p in phys)
+        self.bonds = list(int(b) for b in bonds)
+        self.offsets = list(int(o) for o in offsets)
+        n = len(self.phys)
+        self._phys = (ctypes.c_int32 * n)(*self.phys)
+        self._bonds = (ctypes.c_int32 * (n + 1))(*self.bonds)
+        self._offsets = (ctypes.c_int64 * n)(*self.offsets)
+        self.view = TtmTT(n, ctypes.cast(self._phys, ctypes.POINTER(ctypes.c_int32)),
+                          ctypes.cast(self._bonds, ctypes.POINTER(ctypes.c_int32)),
+                          ctypes.cast(self._offsets, ctypes.POINTER(ctypes.c_int64)),
+                          ctypes.c_void_p(data.data_ptr()), 0)
+
+    @property
+    def n_sites(self):
+        return len(self.phys)
+
+    def cores(self):
+        out = []
+        for i, p in enumerate(self.phys):
+            rl, rr = self.bonds[i], self.bonds[i + 1]
+            o = self.offsets[i]
+            out.append(self.data[o:o + rl * p * rr].view(rl, p, rr))
+        return out
+
+
+def pack(cores, device=None):
+    """Pack a list of cores (NumPy arrays or tensors) into a PackedTT on the GPU."""
+    import numpy as np
+    import torch
+
+    if isinstance(cores, PackedTT):
+        return cores
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    flat = []
+    phys, bonds, offsets = [], [int(cores[0].shape[0])], []
+    pos = 0
+    for c in cores:
+        t = torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+        t = t.to(dtype=torch.float64)
+        assert t.dim() == 3
+        phys.append(int(t.shape[1]))
+        bonds.append(int(t.shape[2]))
+        offsets.append(pos)
+        pos += t.numel()
+        flat.append(t.reshape(-1).cpu())
+    data = torch.cat(flat).to(device).contiguous()
+    return PackedTT(data, phys, bonds, offsets)
+
+
+class Workspace:
+    """A reusable device workspace (grows on demand)."""
+
+    def __init__(self, device=None):
+        self.buf = None
+        self.device = device
+
+    def get(self, nbytes):
+        import torch
+
+        if self.buf is None or self.buf.numel() < nbytes:
+            dev = self.device or torch.device("cuda", torch.cuda.current_device())
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+        return self.buf
+
+
+_DEFAULT_WS = {}
+
+
+def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, seed=12345,
+             forced_ranks=None, trace_cap=0):
+    o = TtmOptions()
+    lib().ttm_default_options(ctypes.byref(o))
+    o.chi_mid = -1 if chi_mid is None else int(chi_mid)
+    o.final_round = 1 if final_round else 0
+    o.max_sweeps = int(max_sweeps)
+    o.svd_max_sweeps = int(svd_max_sweeps)
+    o.seed = int(seed)
+    keep = []
+    if forced_ranks is not None:
+        arr = (ctypes.c_int32 * max(1, len(forced_ranks)))(*[int(r) for r in forced_ranks])
+        keep.append(arr)
+        o.forced_ranks = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+        o.n_forced = len(forced_ranks)
+    if trace_cap:
+        ra = (ctypes.c_int32 * trace_cap)()
+        da = (ctypes.c_double * trace_cap)()
+        keep += [ra, da]
+        o.trace_cap = trace_cap
+        o.rank_trace = ctypes.cast(ra, ctypes.POINTER(ctypes.c_int32))
+        o.discard_trace = ctypes.cast(da, ctypes.POINTER(ctypes.c_double))
+    return o, keep
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _query(fn, A, B, chi_out, o):
+    ws = ctypes.c_size_t(0)
+    cap = ctypes.c_int64(0)
+    rc = fn(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), ctypes.byref(o),
+            ctypes.byref(ws), ctypes.byref(cap))
+    if rc != TTM_OK:
+        raise TTMError(rc, fn.__name__)
+    return ws.value, cap.value
+
+
+def query(A, B, chi_out, **opts):
+    A, B = pack(A), pack(B)
+    o, _keep = _options(**opts)
+    return _query(lib().ttm_query, A, B, chi_out, o)
+
+
+def conventional_query(A, B, chi_out, **opts):
+    A, B = pack(A), pack(B)
+    o, _keep = _options(**opts)
+    return _query(lib().conventional_query, A, B, chi_out, o)
+
+
+def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts):
+    import torch
+
+    A, B = pack(A), pack(B)
+    trace_cap = opts.pop("trace_cap", None)
+    if trace_cap is None:
+        trace_cap = 4 * A.n_sites * A.n_sites + 16
+    o, keep = _options(trace_cap=trace_cap, **opts)
+    L = lib()
+    qfn = L.ttm_query if kind == "ttm" else L.conventional_query
+    mfn = L.ttm_multiply_ex if kind == "ttm" else L.conventional_multiply_ex
+    ws_bytes, cap = _query(qfn, A, B, chi_out, o)
+    if workspace is None:
+        dev = A.data.device
+        workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
+    wbuf = workspace.get(ws_bytes)
+    if out is None or out.numel() < cap:
+        out = torch.empty(max(cap, 1), dtype=torch.float64, device=A.data.device)
+    n = A.n_sites
+    bonds = (ctypes.c_int32 * (n + 1))()
+    offs = (ctypes.c_int64 * n)()
+    cout = TtmTTOut(ctypes.cast(bonds, ctypes.POINTER(ctypes.c_int32)),
+                    ctypes.cast(offs, ctypes.POINTER(ctypes.c_int64)),
+                    ctypes.c_void_p(out.data_ptr()), out.numel())
+    st = TtmStats()
+    rc = mfn(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), float(tol), ctypes.byref(cout),
+             ctypes.c_void_p(wbuf.data_ptr()), ctypes.c_size_t(wbuf.numel()), _stream_handle(stream),
+             ctypes.byref(o), ctypes.byref(st))
+    if rc != TTM_OK:
+        raise TTMError(rc, mfn.__name__)
+    res = PackedTT(out, [A.phys[i] for i in range(n)], list(bonds), list(offs))
+    stats = {f: getattr(st, f) for f, _ in TtmStats._fields_}
+    nt = min(st.n_trace, o.trace_cap)
+    if o.trace_cap:
+        stats["ranks"] = [o.rank_trace[i] for i in range(nt)]
+        stats["discards"] = [o.discard_trace[i] for i in range(nt)]
+    del keep
+    return res, stats
+
+
+def multiply(A, B, chi_out, tol, **opts):
+    """C = A * B elementwise by TTM.  Returns (PackedTT, stats dict)."""
+    return _run("ttm", A, B, chi_out, tol, **opts)
+
+
+def conventional(A, B, chi_out, tol, **opts):
+    """C ~ A * B by the variational baseline.  Returns (PackedTT, stats dict)."""
+    return _run("conv", A, B, chi_out, tol, **opts)

@@ -1,0 +1,136 @@
+"""ctypes mirror of include/ttm.h (structures, codes, prototypes)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+TTM_OK = 0
+TTM_EINVAL = -1
+TTM_ESHAPE = -2
+TTM_EWORKSPACE = -3
+TTM_ECAPACITY = -4
+TTM_ENOCONV = -5
+TTM_ENONFINITE = -6
+TTM_EHIP = -7
+TTM_EFORCED = -8
+TTM_EUNSUPPORTED = -9
+
+I32P = ctypes.POINTER(ctypes.c_int32)
+I64P = ctypes.POINTER(ctypes.c_int64)
+F64P = ctypes.POINTER(ctypes.c_double)
+
+
+class TtmTT(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32),
+        ("phys", I32P),
+        ("bonds", I32P),
+        ("offsets", I64P),
+        ("data", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+    ]
+
+
+class TtmTTOut(ctypes.Structure):
+    _fields_ = [
+        ("bonds", I32P),
+        ("offsets", I64P),
+        ("data", ctypes.c_void_p),
+        ("capacity", ctypes.c_int64),
+    ]
+
+
+class TtmOptions(ctypes.Structure):
+    _fields_ = [
+        ("chi_mid", ctypes.c_int32),
+        ("final_round", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32),
+        ("svd_max_sweeps", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("forced_ranks", I32P),
+        ("n_forced", ctypes.c_int32),
+        ("trace_cap", ctypes.c_int32),
+        ("rank_trace", I32P),
+        ("discard_trace", F64P),
+    ]
+
+
+class TtmStats(ctypes.Structure):
+    _fields_ = [
+        ("max_bond", ctypes.c_int32),
+        ("n_contract", ctypes.c_int32),
+        ("n_swap", ctypes.c_int32),
+        ("n_qr", ctypes.c_int32),
+        ("n_svd", ctypes.c_int32),
+        ("n_trace", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("jacobi_max_sweeps", ctypes.c_int32),
+        ("discarded_sq_sum", ctypes.c_double),
+        ("error_bound", ctypes.c_double),
+        ("model_flops", ctypes.c_double),
+        ("svd_model_flops", ctypes.c_double),
+        ("peak_ws_bytes", ctypes.c_size_t),
+    ]
+
+
+# Every symbol include/ttm.h declares, with its prototype.
+PROTOTYPES = {
+    "ttm_default_options": (None, [ctypes.POINTER(TtmOptions)]),
+    "ttm_query": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                 ctypes.POINTER(TtmOptions), ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "ttm_multiply": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                    ctypes.c_double, ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]),
+    "ttm_multiply_ex": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                       ctypes.c_double, ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(TtmOptions),
+                                       ctypes.POINTER(TtmStats)]),
+    "conventional_query": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                          ctypes.POINTER(TtmOptions), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "conventional_multiply": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT),
+                                             ctypes.c_int32, ctypes.c_double, ctypes.POINTER(TtmTTOut),
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "conventional_multiply_ex": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT),
+                                                ctypes.c_int32, ctypes.c_double,
+                                                ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
+                                                ctypes.c_size_t, ctypes.c_void_p,
+                                                ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats)]),
+    "ttm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ttm_version": (ctypes.c_char_p, []),
+}
+
+
+# Kernel-level test hooks declared in include/ttm_testing.h.
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+TESTING_PROTOTYPES = {
+    "ttm_test_gemm": (ctypes.c_int, [ctypes.c_int] * 4 + [_VP, _I64, _I64, _I64, _VP, _I64, _I64, _I64,
+                                                          _VP, _I64, ctypes.c_int, ctypes.c_int,
+                                                          _I64, _I64, _I64, _I64, _VP]),
+    "ttm_test_qr_scratch": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "ttm_test_qr": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP]),
+    "ttm_test_svd_ws_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "ttm_test_svd": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _VP,
+                                    ctypes.c_size_t, _VP]),
+}
+
+
+def library_path():
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttm.so")
+
+
+def load_library():
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError("libttm.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_2410_19747_amd.build" % path)
+    L = ctypes.CDLL(path)
+    for name, (res, args) in list(PROTOTYPES.items()) + list(TESTING_PROTOTYPES.items()):
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L

@@ -1,0 +1,230 @@
+// Small data-movement kernels and the Householder QR used for gauge moves.
+#include "ttm_internal.h"
+
+namespace ttm {
+
+__global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void fill_kernel(double *__restrict__ dst, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+__global__ void zero_int_kernel(int *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// out[b][w][a] = in[a][w][b]: reversing the order of a train transposes
+// every carriage (the second factor enters Eq. (tensor) reversed).
+__global__ void reverse_core_kernel(double *__restrict__ out, const double *__restrict__ in, int rl,
+                                    int d, int rr) {
+  const int64_t n = (int64_t)rl * d * rr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % rl);
+    const int64_t t = e / rl;
+    const int w = (int)(t % d);
+    const int b = (int)(t / d);
+    out[e] = in[((int64_t)a * d + w) * rr + b];
+  }
+}
+
+__global__ void transpose_kernel(double *__restrict__ out, const double *__restrict__ in, int m, int n) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int i = by + k, j = bx + tx;
+    if (i < m && j < n) tile[k][tx] = in[(int64_t)i * n + j];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int j = bx + k, i = by + tx;
+    if (i < m && j < n) out[(int64_t)j * m + i] = tile[tx][k];
+  }
+}
+
+__global__ void nonfinite_kernel(const double *__restrict__ x, int64_t n, int *flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) flag[0] = 1;  // benign race: every writer stores the same value
+}
+
+static int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_core(double *out, const double *in, int rl, int d, int rr, hipStream_t s) {
+  const int64_t n = (int64_t)rl * d * rr;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reverse_core_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, out, in, rl, d, rr);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(double *out, const double *in, int m, int n, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((n + 31) / 32, (m + 31) / 32);
+  if (grid.y > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, out, in, m, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_check(const double *x, int64_t n, int *flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- QR
+// One workgroup factors the whole matrix with Householder reflections
+// H_j = I - tau_j v_j v_j^T (v_j[j] = 1), then accumulates Q = H_0 ... H_{k-1}
+// applied to the first k columns of the identity.  The matrix lives in a
+// column-major scratch copy so column operations are contiguous.
+namespace {
+constexpr int QR_NT = 1024;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) t += red[w];  // fixed order: every thread gets the same sum
+  return t;
+}
+}  // namespace
+
+__global__ __launch_bounds__(QR_NT) void qr_kernel(const double *__restrict__ M, int m, int n,
+                                                   int64_t rs, int64_t cs, double *__restrict__ q,
+                                                   double *__restrict__ r, double *__restrict__ S) {
+  __shared__ double red[QR_NT / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = QR_NT / 64;
+  const int k = m < n ? m : n;
+  double *tau = S + (int64_t)m * n;
+  double *Qs = tau + n;  // m x k column-major
+
+  for (int64_t e = tid; e < (int64_t)m * n; e += QR_NT) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    S[e] = M[(int64_t)i * rs + (int64_t)j * cs];
+  }
+  __syncthreads();
+
+  for (int j = 0; j < k; ++j) {
+    double *col = S + (int64_t)j * m;
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += QR_NT) part += col[i] * col[i];
+    const double xnorm2 = block_sum(part, red);
+    const double alpha = col[j];
+    double t = 0.0, scale = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (xnorm2 > 0.0) {
+      for (int i = j + 1 + tid; i < m; i += QR_NT) col[i] *= scale;
+    }
+    if (tid == 0) {
+      col[j] = beta;
+      tau[j] = t;
+    }
+    __syncthreads();
+    if (t != 0.0) {
+      // trailing columns, one wave per column
+      for (int c = j + 1 + wave; c < n; c += nwave) {
+        double *x = S + (int64_t)c * m;
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w += col[i] * x[i];
+        w = wave_sum(w) + x[j];
+        const double tw = t * w;
+        if (lane == 0) x[j] -= tw;
+        for (int i = j + 1 + lane; i < m; i += 64) x[i] -= tw * col[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  // R (k x n, row-major)
+  for (int64_t e = tid; e < (int64_t)k * n; e += QR_NT) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    r[e] = (c >= i) ? S[(int64_t)c * m + i] : 0.0;
+  }
+  // Q: identity columns, then H_{k-1} ... H_0 applied from the left.
+  for (int64_t e = tid; e < (int64_t)m * k; e += QR_NT) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    Qs[e] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double t = tau[j];
+    const double *v = S + (int64_t)j * m;
+    if (t != 0.0) {
+      for (int c = j + wave; c < k; c += nwave) {
+        double *x = Qs + (int64_t)c * m;
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w += v[i] * x[i];
+        w = wave_sum(w) + x[j];
+        const double tw = t * w;
+        if (lane == 0) x[j] -= tw;
+        for (int i = j + 1 + lane; i < m; i += 64) x[i] -= tw * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)m * k; e += QR_NT) {
+    const int i = (int)(e / k), c = (int)(e % k);
+    q[e] = Qs[(int64_t)c * m + i];
+  }
+}
+
+size_t qr_scratch_doubles(int m, int n) {
+  const int k = m < n ? m : n;
+  return (size_t)m * n + (size_t)n + (size_t)m * k + 2;
+}
+
+hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
+                     double *scratch, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(QR_NT), 0, s, M, m, n, rs, cs, q, r, scratch);
+  return hipGetLastError();
+}
+
+}  // namespace ttm

@@ -1,0 +1,756 @@
+// Host runtime of libttm: argument validation, workspace planning, the TTM
+// schedule of Sec. II.B, and the C ABI declared in include/ttm.h.
+//
+// Schedule (N sites, 0-based):
+//   1. copy the inputs into workspace slots; bring A and B to left-orthonormal
+//      form by QR sweeps in their own orientation;
+//   2. reverse B (Eq. tensor): B~_i[b, w, a] = B_i[a, w, b]; the chain
+//      [A_0 .. A_{N-1}, B~_{N-1} .. B~_0] is then in mixed-canonical gauge;
+//   3. contract site N-1 (Eq. contract);
+//   4. for j = N-2 .. 0: move the gauge centre from Pi_{j+1} to Pi_{N-1} by
+//      QR; move X = B~_j leftwards through Pi_{N-1} .. Pi_{j+1} by Swaps
+//      (merge, leg exchange, truncated SVD under Eq. (eps), singular values
+//      kept in X so the centre stays inside the next pair); contract A_j
+//      with X into Pi_j;
+//   5. optionally a left-to-right truncated-SVD sweep with cap chi_out;
+//   6. pack the cores into the caller's output buffer.
+// Every rank is read back to the host to size the next launches, so the call
+// synchronises with its stream once per SVD.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ttm.h"
+#include "ttm_internal.h"
+
+namespace ttm {
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+constexpr int64_t kSat = (int64_t)1 << 40;  // saturation of structural products
+
+struct Shape {
+  int rl = 1, d = 1, rr = 1;
+  int64_t size() const { return (int64_t)rl * d * rr; }
+};
+
+struct Options {
+  int chi_mid = -1;   // resolved: 0 = uncapped
+  int final_round = 1;
+  int max_sweeps = 10;
+  int svd_max_sweeps = 40;
+  uint64_t seed = 12345;
+  const int32_t *forced = nullptr;
+  int n_forced = 0;
+  int trace_cap = 0;
+  int32_t *rank_trace = nullptr;
+  double *discard_trace = nullptr;
+};
+
+int64_t sat_mul(int64_t a, int64_t b) {
+  if (a >= kSat || b >= kSat) return kSat;
+  int64_t p = a * b;
+  return p > kSat ? kSat : p;
+}
+
+// ------------------------------------------------------------------ validation
+int validate_tt(const ttm_tt *t) {
+  if (!t) return TTM_EINVAL;
+  if (t->n_sites < 1 || t->n_sites > 4096) return TTM_EINVAL;
+  if (!t->phys || !t->bonds || !t->offsets || !t->data) return TTM_EINVAL;
+  if (t->dtype != TTM_F64) return TTM_EUNSUPPORTED;
+  if (t->bonds[0] != 1 || t->bonds[t->n_sites] != 1) return TTM_ESHAPE;
+  for (int i = 0; i < t->n_sites; ++i) {
+    if (t->phys[i] < 1 || t->phys[i] > 65536) return TTM_EINVAL;
+    if (t->bonds[i] < 1 || t->bonds[i] > (1 << 20)) return TTM_EINVAL;
+    if (t->offsets[i] < 0) return TTM_EINVAL;
+  }
+  return TTM_OK;
+}
+
+int validate_pair(const ttm_tt *A, const ttm_tt *B) {
+  int e = validate_tt(A);
+  if (e) return e;
+  e = validate_tt(B);
+  if (e) return e;
+  if (A->n_sites != B->n_sites) return TTM_ESHAPE;
+  for (int i = 0; i < A->n_sites; ++i)
+    if (A->phys[i] != B->phys[i]) return TTM_ESHAPE;
+  return TTM_OK;
+}
+
+int resolve_options(const ttm_options *o, int chi_out, Options &r) {
+  ttm_options d;
+  ttm_default_options(&d);
+  if (!o) o = &d;
+  if (o->chi_mid < -1) return TTM_EINVAL;
+  r.chi_mid = (o->chi_mid == -1) ? chi_out : o->chi_mid;
+  if (o->final_round != 0 && o->final_round != 1) return TTM_EINVAL;
+  r.final_round = o->final_round;
+  if (o->max_sweeps < 1 || o->max_sweeps > 10000) return TTM_EINVAL;
+  r.max_sweeps = o->max_sweeps;
+  if (o->svd_max_sweeps < 1 || o->svd_max_sweeps > 10000) return TTM_EINVAL;
+  r.svd_max_sweeps = o->svd_max_sweeps;
+  r.seed = o->seed;
+  if (o->n_forced < 0) return TTM_EINVAL;
+  if (o->n_forced > 0 && !o->forced_ranks) return TTM_EINVAL;
+  for (int i = 0; i < o->n_forced; ++i)
+    if (o->forced_ranks[i] < 1) return TTM_EFORCED;
+  r.forced = o->forced_ranks;
+  r.n_forced = o->n_forced;
+  if (o->trace_cap < 0) return TTM_EINVAL;
+  if (o->trace_cap > 0 && (!o->rank_trace || !o->discard_trace)) return TTM_EINVAL;
+  r.trace_cap = o->trace_cap;
+  r.rank_trace = o->rank_trace;
+  r.discard_trace = o->discard_trace;
+  return TTM_OK;
+}
+
+// ------------------------------------------------------------------ planning
+// A symbolic run of the schedule with upper bounds in place of ranks.  The
+// same caps are applied to the real ranks, so every buffer sized here holds
+// whatever the run produces.
+struct Plan {
+  int n = 0;
+  std::vector<int> phys;
+  int64_t max_core = 1;  // doubles of the largest core
+  int max_bond = 1;
+  int64_t max_w = 1;     // doubles of the largest Jacobi workspace
+  int64_t max_qr = 1;    // doubles of the largest QR scratch
+  int64_t max_r = 1;     // doubles of the largest R / S V^T factor
+  int64_t out_capacity = 0;
+  std::vector<Shape> out_shapes;
+  size_t ws_bytes = 0;
+  int nslots = 0;
+};
+
+// Structural bound of a bond of the product: min(prod_{k<i} d_k, prod_{k>=i} d_k).
+int64_t product_bound(const std::vector<int> &phys, int i) {
+  int64_t l = 1, r = 1;
+  for (int k = 0; k < i; ++k) l = sat_mul(l, phys[k]);
+  for (int k = i; k < (int)phys.size(); ++k) r = sat_mul(r, phys[k]);
+  return std::min(l, r);
+}
+
+// Bound of the bond created by the swap of X (the carriage of site j) with
+// Pi_p: its left holds sites 0..j of A, X and Pi_{j+1}..Pi_{p-1}; its right
+// holds Pi_p..Pi_{N-1} and B~_{j-1}..B~_0.
+int64_t swap_cut_bound(const std::vector<int> &phys, int j, int p) {
+  int64_t l = 1, r = 1;
+  for (int k = 0; k <= j; ++k) l = sat_mul(l, phys[k]);
+  l = sat_mul(l, phys[j]);
+  for (int k = j + 1; k < p; ++k) l = sat_mul(l, phys[k]);
+  for (int k = p; k < (int)phys.size(); ++k) r = sat_mul(r, phys[k]);
+  for (int k = 0; k < j; ++k) r = sat_mul(r, phys[k]);
+  return std::min(l, r);
+}
+
+int swap_cap(const Options &o, const std::vector<int> &phys, int j, int p, const Shape &P,
+             const Shape &X) {
+  int64_t c = std::min<int64_t>((int64_t)P.rl * X.d, (int64_t)P.d * X.rr);
+  c = std::min(c, swap_cut_bound(phys, j, p));
+  if (o.chi_mid > 0) c = std::min<int64_t>(c, o.chi_mid);
+  return (int)c;
+}
+
+int round_cap(int chi_out, const std::vector<int> &phys, int i, const Shape &M) {
+  int64_t c = std::min<int64_t>((int64_t)M.rl * M.d, M.rr);
+  c = std::min(c, product_bound(phys, i + 1));
+  c = std::min<int64_t>(c, chi_out);
+  return (int)c;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void note_core(Plan &pl, const Shape &s) {
+  pl.max_core = std::max(pl.max_core, s.size());
+  pl.max_bond = std::max(pl.max_bond, std::max(s.rl, s.rr));
+}
+void note_svd(Plan &pl, int m, int n) {
+  const int L = std::max(m, n), nc = std::min(m, n);
+  JacobiPlan jp = jacobi_plan(L, nc);
+  pl.max_w = std::max<int64_t>(pl.max_w, (int64_t)jacobi_ws_doubles(jp));
+}
+void note_qr(Plan &pl, int m, int n) {
+  pl.max_qr = std::max<int64_t>(pl.max_qr, (int64_t)qr_scratch_doubles(m, n));
+  const int k = std::min(m, n);
+  pl.max_r = std::max<int64_t>(pl.max_r, (int64_t)k * n);
+}
+
+int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, Plan &pl) {
+  const int n = A->n_sites;
+  pl.n = n;
+  pl.phys.assign(A->phys, A->phys + n);
+  std::vector<Shape> a(n), b(n), pi(n);
+  for (int i = 0; i < n; ++i) {
+    a[i] = {A->bonds[i], A->phys[i], A->bonds[i + 1]};
+    b[i] = {B->bonds[i], B->phys[i], B->bonds[i + 1]};
+    note_core(pl, a[i]);
+    note_core(pl, b[i]);
+  }
+  auto qr_sweep = [&](std::vector<Shape> &t) {
+    for (int i = 0; i + 1 < n; ++i) {
+      const int m = t[i].rl * t[i].d, nn = t[i].rr;
+      note_qr(pl, m, nn);
+      const int k = std::min(m, nn);
+      t[i].rr = k;
+      t[i + 1].rl = k;
+      note_core(pl, t[i]);
+      note_core(pl, t[i + 1]);
+    }
+  };
+  qr_sweep(a);
+  qr_sweep(b);
+  std::vector<Shape> bt(n);
+  for (int i = 0; i < n; ++i) bt[i] = {b[i].rr, b[i].d, b[i].rl};
+  pi[n - 1] = {a[n - 1].rl, a[n - 1].d, bt[n - 1].rr};
+  note_core(pl, pi[n - 1]);
+  for (int j = n - 2; j >= 0; --j) {
+    for (int p = j + 1; p <= n - 2; ++p) {
+      const int m = pi[p].rl * pi[p].d, nn = pi[p].rr;
+      note_qr(pl, m, nn);
+      const int k = std::min(m, nn);
+      pi[p].rr = k;
+      pi[p + 1].rl = k;
+      note_core(pl, pi[p]);
+      note_core(pl, pi[p + 1]);
+    }
+    Shape x = bt[j];
+    for (int p = n - 1; p > j; --p) {
+      const int m = pi[p].rl * x.d, nn = pi[p].d * x.rr;
+      note_svd(pl, m, nn);
+      const int r = swap_cap(o, pl.phys, j, p, pi[p], x);
+      Shape xn = {pi[p].rl, x.d, r};
+      Shape pn = {r, pi[p].d, x.rr};
+      note_core(pl, xn);
+      note_core(pl, pn);
+      x = xn;
+      pi[p] = pn;
+    }
+    pi[j] = {a[j].rl, a[j].d, x.rr};
+    note_core(pl, pi[j]);
+  }
+  if (o.final_round) {
+    for (int i = 0; i + 1 < n; ++i) {
+      const int m = pi[i].rl * pi[i].d, nn = pi[i].rr;
+      note_svd(pl, m, nn);
+      const int r = round_cap(chi_out, pl.phys, i, pi[i]);
+      pl.max_r = std::max<int64_t>(pl.max_r, (int64_t)r * nn);
+      pi[i].rr = r;
+      pi[i + 1].rl = r;
+      note_core(pl, pi[i]);
+      note_core(pl, pi[i + 1]);
+    }
+  }
+  pl.out_shapes = pi;
+  pl.out_capacity = 0;
+  for (int i = 0; i < n; ++i) pl.out_capacity += pi[i].size();
+  // Slots: A (N) + B (N) + B~/Pi (N) + X + 3 spares.
+  pl.nslots = 3 * n + 4;
+  size_t bytes = 0;
+  bytes += (size_t)pl.nslots * align_up((size_t)pl.max_core * 8);
+  bytes += align_up((size_t)pl.max_w * 8);
+  bytes += align_up((size_t)pl.max_qr * 8);
+  bytes += align_up((size_t)pl.max_r * 8);
+  bytes += 256;  // flags
+  pl.ws_bytes = bytes;
+  if (pl.max_bond > (1 << 20) || pl.max_core > ((int64_t)1 << 33)) return TTM_EINVAL;
+  return TTM_OK;
+}
+
+// ------------------------------------------------------------------ device state
+struct Core {
+  double *p = nullptr;
+  Shape s;
+};
+
+struct Runner {
+  hipStream_t st;
+  const Options &o;
+  std::vector<double *> free_slots;
+  double *wbuf = nullptr, *qrbuf = nullptr, *rbuf = nullptr;
+  int *flags = nullptr;
+  int64_t max_core = 0;
+  bool trace = false;
+  // stats
+  int n_contract = 0, n_swap = 0, n_qr = 0, n_svd = 0, n_trace = 0, max_bond = 1;
+  int jac_sweeps = 0, jac_max = 0;
+  double disc_sum = 0.0, err_bound = 0.0, flops = 0.0, svd_flops = 0.0;
+  int forced_pos = 0;
+  int err = TTM_OK;
+
+  Runner(hipStream_t s, const Options &opt) : st(s), o(opt) {
+    trace = getenv("TTM_TRACE") != nullptr;
+  }
+
+  double *take() {
+    if (free_slots.empty()) {
+      err = TTM_EINVAL;  // planning error: never expected
+      return nullptr;
+    }
+    double *p = free_slots.back();
+    free_slots.pop_back();
+    return p;
+  }
+  void give(double *p) {
+    if (p) free_slots.push_back(p);
+  }
+  bool hip(hipError_t e) {
+    if (e != hipSuccess) {
+      if (err == TTM_OK) err = TTM_EHIP;
+      if (trace) fprintf(stderr, "[ttm] HIP error %s\n", hipGetErrorString(e));
+      return false;
+    }
+    return true;
+  }
+  void note(const Shape &s) { max_bond = std::max(max_bond, std::max(s.rl, s.rr)); }
+
+  // ---- Eq. (contract): out[a, e, b] = sum_c K[a, e, c] M[c, e, b]
+  Core contract(const Core &k, const Core &m) {
+    Core out;
+    out.p = take();
+    out.s = {k.s.rl, k.s.d, m.s.rr};
+    if (!out.p) return out;
+    GemmArgs g;
+    g.M = k.s.rl; g.N = m.s.rr; g.K = k.s.rr; g.batch = k.s.d;
+    g.A = k.p; g.a_rs = (int64_t)k.s.d * k.s.rr; g.a_cs = 1; g.a_bs = k.s.rr;
+    g.B = m.p; g.b_rs = (int64_t)m.s.d * m.s.rr; g.b_cs = 1; g.b_bs = m.s.rr;
+    g.C = out.p; g.c_rs1 = (int64_t)k.s.d * m.s.rr; g.c_cs1 = 1; g.c_bs = m.s.rr;
+    hip(launch_gemm(g, st));
+    flops += 2.0 * k.s.d * k.s.rl * k.s.rr * m.s.rr;
+    ++n_contract;
+    note(out.s);
+    if (trace) fprintf(stderr, "[ttm] contract %dx%dx%d * %dx%dx%d\n", k.s.rl, k.s.d, k.s.rr, m.s.rl, m.s.d, m.s.rr);
+    return out;
+  }
+
+  // ---- gauge move: QR of cores[p], R into cores[p+1]
+  void qr_move(std::vector<Core> &c, int p) {
+    Core &cur = c[p];
+    Core &nxt = c[p + 1];
+    const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
+    const int k = std::min(m, n);
+    double *q = take();
+    if (!q) return;
+    hip(launch_qr(cur.p, m, n, n, 1, q, rbuf, qrbuf, st));
+    double *nn = take();
+    if (!nn) return;
+    const int ncol = nxt.s.d * nxt.s.rr;
+    hip(launch_gemm(gemm_rowmajor(k, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st));
+    give(cur.p);
+    give(nxt.p);
+    cur.p = q;
+    cur.s.rr = k;
+    nxt.p = nn;
+    nxt.s.rl = k;
+    ++n_qr;
+    flops += (m >= n) ? 4.0 * m * n * (double)n - (4.0 / 3.0) * n * (double)n * n
+                      : 2.0 * n * m * (double)m + (2.0 / 3.0) * m * (double)m * m;
+    flops += 2.0 * k * n * (double)ncol;
+    note(cur.s);
+    note(nxt.s);
+  }
+
+  // ---- one SVD of the matrix already in wbuf's W region.
+  // Returns the rank (or -1 on error) and fills disc.
+  struct SvdOut {
+    int r = -1;
+    double disc = 0.0, total = 0.0;
+  };
+  SvdOut jacobi(const JacobiPlan &jp, const JacobiBufs &jb, double eps, int cap) {
+    SvdOut out;
+    int forced = 0;
+    if (o.forced) {
+      if (forced_pos >= o.n_forced) {
+        err = TTM_EFORCED;
+        return out;
+      }
+      forced = o.forced[forced_pos++];
+      // a forced rank may not exceed what the buffers were sized for
+      if (forced > std::min(jp.nc, cap)) {
+        err = TTM_EFORCED;
+        return out;
+      }
+    }
+    if (!hip(launch_jacobi_init(jp, jb, st))) return out;
+    const double tol = sqrt((double)std::max(jp.L, 1)) * kEps;
+    double prev = INFINITY;
+    int sweeps = 0;
+    bool ok = false;
+    double host_res[8];
+    for (int sw = 0; sw < o.svd_max_sweeps; ++sw) {
+      if (!hip(launch_jacobi_sweep(jp, jb, tol, st))) return out;
+      ++sweeps;
+      if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
+      if (!hip(hipStreamSynchronize(st))) return out;
+      const double off = host_res[3];
+      if (trace) fprintf(stderr, "[ttm]   jacobi %dx%d sweep %d off=%.3e tol=%.3e\n", jp.L, jp.nc, sw, off, tol);
+      if (!(off == off)) break;  // NaN
+      if (off <= tol) { ok = true; break; }
+      // stagnation at the rounding floor
+      if (off < 1e3 * tol && off > 0.5 * prev) { ok = true; break; }
+      prev = off;
+    }
+    jac_sweeps += sweeps;
+    jac_max = std::max(jac_max, sweeps);
+    if (!ok) {
+      if (err == TTM_OK) err = TTM_ENOCONV;
+      if (trace) fprintf(stderr, "[ttm] jacobi %dx%d did not converge\n", jp.L, jp.nc);
+      return out;
+    }
+    if (!hip(launch_jacobi_finish(jp, jb, eps, cap, forced, st))) return out;
+    if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
+    if (!hip(hipStreamSynchronize(st))) return out;
+    if (host_res[4] != 0.0) {
+      err = TTM_ENONFINITE;
+      return out;
+    }
+    out.r = (int)host_res[0];
+    out.disc = host_res[1];
+    out.total = host_res[2];
+    if (trace)
+      fprintf(stderr, "[ttm] svd %dx%d sweeps=%d rank=%d disc=%.3e total=%.3e\n", jp.L, jp.nc, sweeps,
+              out.r, out.disc, out.total);
+    ++n_svd;
+    disc_sum += out.disc;
+    err_bound += sqrt(std::max(out.disc, 0.0));
+    if (n_trace < o.trace_cap) {
+      o.rank_trace[n_trace] = out.r;
+      o.discard_trace[n_trace] = out.disc;
+    }
+    ++n_trace;
+    const int m = std::max(jp.L, jp.nc), n = std::min(jp.L, jp.nc);
+    const double f = 4.0 * m * (double)n * n - (4.0 / 3.0) * n * (double)n * n + 4.0 * (m + n) * (double)n * out.r;
+    flops += f;
+    svd_flops += f;
+    return out;
+  }
+
+  JacobiBufs carve(const JacobiPlan &jp) {
+    JacobiBufs b;
+    double *p = wbuf;
+    auto adv = [&](size_t nd) {
+      double *q = p;
+      p += (nd + 31) & ~(size_t)31;
+      return q;
+    };
+    b.W = adv((size_t)jp.L * jp.ncp);
+    b.V = adv((size_t)jp.ncp * jp.ncp);
+    b.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
+    b.conv = adv((size_t)jp.rounds * jp.pairs);
+    b.sigma = adv((size_t)jp.ncp);
+    b.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
+    b.result = adv(8);
+    return b;
+  }
+
+  // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
+  void swap(Core &P, Core &X, int cap) {
+    const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
+    const int m = Dl * dx, n = dp * Dr;
+    const bool tall = m >= n;
+    const int L = tall ? m : n, nc = tall ? n : m;
+    JacobiPlan jp = jacobi_plan(L, nc);
+    JacobiBufs jb = carve(jp);
+    // merge: theta[(a,e),(w,b)] = sum_c P[a,e,c] X[c,w,b], stored as the
+    // leg-exchanged unfolding Theta[(a,w),(e,b)] (tall) or its transpose.
+    GemmArgs g;
+    g.M = Dl * dp; g.N = dx * Dr; g.K = Dm;
+    g.A = P.p; g.a_rs = Dm; g.a_cs = 1;
+    g.B = X.p; g.b_rs = (int64_t)dx * Dr; g.b_cs = 1;
+    g.C = jb.W;
+    g.c_rdiv = dp; g.c_cdiv = Dr;
+    if (tall) {
+      g.c_rs1 = dx; g.c_rs0 = (int64_t)m * Dr; g.c_cs1 = 1; g.c_cs0 = m;
+    } else {
+      g.c_rs1 = (int64_t)n * dx; g.c_rs0 = Dr; g.c_cs1 = n; g.c_cs0 = 1;
+    }
+    if (!hip(launch_gemm(g, st))) return;
+    flops += 2.0 * Dl * dp * (double)Dm * dx * Dr;
+    SvdOut so = jacobi(jp, jb, eps_, cap);
+    if (so.r < 1) return;
+    const int r = so.r;
+    double *xn = take();
+    double *pn = take();
+    if (!xn || !pn) return;
+    // X' = U_r S_r  -> [Dl, dx, r];  P' = V_r^T -> [r, dp, Dr]
+    if (!hip(launch_svd_write(jp, jb, r, tall, 1, 0, xn, pn, st))) return;
+    give(P.p);
+    give(X.p);
+    X.p = xn;
+    X.s = {Dl, dx, r};
+    P.p = pn;
+    P.s = {r, dp, Dr};
+    ++n_swap;
+    note(X.s);
+    note(P.s);
+  }
+
+  // ---- final rounding step at site i: Pi_i <- U_r, Pi_{i+1} <- S_r V_r^T Pi_{i+1}
+  void round_step(std::vector<Core> &c, int i, int cap) {
+    Core &cur = c[i];
+    Core &nxt = c[i + 1];
+    const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
+    const bool tall = m >= n;
+    const int L = tall ? m : n, nc = tall ? n : m;
+    JacobiPlan jp = jacobi_plan(L, nc);
+    JacobiBufs jb = carve(jp);
+    if (tall) {
+      if (!hip(launch_transpose(jb.W, cur.p, m, n, st))) return;  // column-major copy
+    } else {
+      if (!hip(launch_copy(jb.W, cur.p, (int64_t)m * n, st))) return;  // already Theta^T col-major
+    }
+    SvdOut so = jacobi(jp, jb, eps_, cap);
+    if (so.r < 1) return;
+    const int r = so.r;
+    double *un = take();
+    double *nn = take();
+    if (!un || !nn) return;
+    if (!hip(launch_svd_write(jp, jb, r, tall, 0, 1, un, rbuf, st))) return;
+    const int ncol = nxt.s.d * nxt.s.rr;
+    if (!hip(launch_gemm(gemm_rowmajor(r, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st))) return;
+    flops += 2.0 * r * (double)n * ncol;
+    give(cur.p);
+    give(nxt.p);
+    cur.p = un;
+    cur.s.rr = r;
+    nxt.p = nn;
+    nxt.s.rl = r;
+    note(cur.s);
+    note(nxt.s);
+  }
+
+  double eps_ = 0.0;
+};
+
+int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C, void *ws,
+                 size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats, bool &enqueued) {
+  Plan pl;
+  int e = make_plan(A, B, chi_out, o, pl);
+  if (e) return e;
+  if (!ws || ws_bytes < pl.ws_bytes) return TTM_EWORKSPACE;
+  if (!C || !C->bonds || !C->offsets || !C->data) return TTM_EINVAL;
+  if (C->capacity < pl.out_capacity) return TTM_ECAPACITY;
+  const int n = pl.n;
+
+  Runner R(st, o);
+  R.eps_ = tol;
+  enqueued = true;
+  char *base = static_cast<char *>(ws);
+  size_t off = 0;
+  const size_t slot_bytes = align_up((size_t)pl.max_core * 8);
+  for (int i = 0; i < pl.nslots; ++i) {
+    R.free_slots.push_back(reinterpret_cast<double *>(base + off));
+    off += slot_bytes;
+  }
+  std::reverse(R.free_slots.begin(), R.free_slots.end());
+  R.wbuf = reinterpret_cast<double *>(base + off);
+  off += align_up((size_t)pl.max_w * 8);
+  R.qrbuf = reinterpret_cast<double *>(base + off);
+  off += align_up((size_t)pl.max_qr * 8);
+  R.rbuf = reinterpret_cast<double *>(base + off);
+  off += align_up((size_t)pl.max_r * 8);
+  R.flags = reinterpret_cast<int *>(base + off);
+  off += 256;
+
+  const double *Ad = static_cast<const double *>(A->data);
+  const double *Bd = static_cast<const double *>(B->data);
+  std::vector<Core> a(n), b(n), pi(n);
+  R.hip(launch_zero_int(R.flags, 4, st));
+  for (int i = 0; i < n; ++i) {
+    a[i].s = {A->bonds[i], A->phys[i], A->bonds[i + 1]};
+    b[i].s = {B->bonds[i], B->phys[i], B->bonds[i + 1]};
+    a[i].p = R.take();
+    b[i].p = R.take();
+    if (R.err) return R.err;
+    R.hip(launch_copy(a[i].p, Ad + A->offsets[i], a[i].s.size(), st));
+    R.hip(launch_copy(b[i].p, Bd + B->offsets[i], b[i].s.size(), st));
+    R.hip(launch_nonfinite_check(a[i].p, a[i].s.size(), R.flags, st));
+    R.hip(launch_nonfinite_check(b[i].p, b[i].s.size(), R.flags, st));
+    R.note(a[i].s);
+    R.note(b[i].s);
+  }
+  {
+    int hflag[4] = {0, 0, 0, 0};
+    R.hip(hipMemcpyAsync(hflag, R.flags, sizeof(hflag), hipMemcpyDeviceToHost, st));
+    R.hip(hipStreamSynchronize(st));
+    if (R.err) return R.err;
+    if (hflag[0]) return TTM_ENONFINITE;
+  }
+  // 1. canonical form of both inputs
+  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(a, i);
+  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(b, i);
+  // 2. reversal of B
+  std::vector<Core> bt(n);
+  for (int i = 0; i < n && !R.err; ++i) {
+    bt[i].p = R.take();
+    bt[i].s = {b[i].s.rr, b[i].s.d, b[i].s.rl};
+    if (!bt[i].p) break;
+    R.hip(launch_reverse_core(bt[i].p, b[i].p, b[i].s.rl, b[i].s.d, b[i].s.rr, st));
+    R.give(b[i].p);
+    b[i].p = nullptr;
+  }
+  if (R.err) return R.err;
+  // 3. contract site N-1
+  pi[n - 1] = R.contract(a[n - 1], bt[n - 1]);
+  R.give(a[n - 1].p);
+  R.give(bt[n - 1].p);
+  // 4. swaps and contractions
+  for (int j = n - 2; j >= 0 && !R.err; --j) {
+    for (int p = j + 1; p <= n - 2 && !R.err; ++p) R.qr_move(pi, p);
+    Core x = bt[j];
+    for (int p = n - 1; p > j && !R.err; --p) {
+      const int cap = swap_cap(o, pl.phys, j, p, pi[p].s, x.s);
+      R.swap(pi[p], x, cap);
+    }
+    if (R.err) break;
+    pi[j] = R.contract(a[j], x);
+    R.give(a[j].p);
+    R.give(x.p);
+  }
+  // 5. final rounding sweep
+  if (o.final_round) {
+    for (int i = 0; i + 1 < n && !R.err; ++i) {
+      const int cap = round_cap(chi_out, pl.phys, i, pi[i].s);
+      R.round_step(pi, i, cap);
+    }
+  }
+  if (R.err) return R.err;
+  if (o.forced && R.forced_pos != o.n_forced) {
+    // extra forced ranks are an inconsistency of the caller's schedule
+    return TTM_EFORCED;
+  }
+  // 6. pack
+  int64_t pos = 0;
+  for (int i = 0; i < n; ++i) pos += pi[i].s.size();
+  if (pos > C->capacity) return TTM_ECAPACITY;
+  pos = 0;
+  double *Cd = static_cast<double *>(C->data);
+  for (int i = 0; i < n; ++i) {
+    C->offsets[i] = pos;
+    C->bonds[i] = pi[i].s.rl;
+    R.hip(launch_copy(Cd + pos, pi[i].p, pi[i].s.size(), st));
+    pos += pi[i].s.size();
+  }
+  C->bonds[n] = pi[n - 1].s.rr;
+  R.hip(hipStreamSynchronize(st));
+  if (R.err) return R.err;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->max_bond = R.max_bond;
+    stats->n_contract = R.n_contract;
+    stats->n_swap = R.n_swap;
+    stats->n_qr = R.n_qr;
+    stats->n_svd = R.n_svd;
+    stats->n_trace = std::min(R.n_trace, o.trace_cap);
+    stats->sweeps = R.jac_sweeps;
+    stats->jacobi_max_sweeps = R.jac_max;
+    stats->discarded_sq_sum = R.disc_sum;
+    stats->error_bound = R.err_bound;
+    stats->model_flops = R.flops;
+    stats->svd_model_flops = R.svd_flops;
+    stats->peak_ws_bytes = pl.ws_bytes;
+  }
+  return TTM_OK;
+}
+
+int run_ttm(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C, void *ws,
+            size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats) {
+  bool enqueued = false;
+  const int e = run_ttm_impl(A, B, chi_out, tol, C, ws, ws_bytes, st, o, stats, enqueued);
+  // On an error after work was enqueued, drain the stream so the caller may
+  // release the workspace as soon as the call returns.
+  if (e != TTM_OK && enqueued) (void)hipStreamSynchronize(st);
+  return e;
+}
+
+}  // namespace
+}  // namespace ttm
+
+// ====================================================================== C ABI
+extern "C" {
+
+void ttm_default_options(ttm_options *opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->chi_mid = -1;
+  opt->final_round = 1;
+  opt->max_sweeps = 10;
+  opt->svd_max_sweeps = 40;
+  opt->seed = 12345;
+}
+
+const char *ttm_strerror(int code) {
+  switch (code) {
+    case TTM_OK: return "ok";
+    case TTM_EINVAL: return "invalid argument";
+    case TTM_ESHAPE: return "shape mismatch between the two trains or bad end bonds";
+    case TTM_EWORKSPACE: return "workspace missing or too small";
+    case TTM_ECAPACITY: return "output buffer too small";
+    case TTM_ENOCONV: return "SVD did not converge";
+    case TTM_ENONFINITE: return "NaN or Inf in the data";
+    case TTM_EHIP: return "HIP runtime error";
+    case TTM_EFORCED: return "forced rank list inconsistent with the schedule";
+    case TTM_EUNSUPPORTED: return "unsupported dtype";
+    default: return "unknown error";
+  }
+}
+
+const char *ttm_version(void) { return "libttm 0.1 (gfx950, fp64)"; }
+
+int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
+              size_t *ws_bytes, int64_t *out_capacity) {
+  int e = ttm::validate_pair(A, B);
+  if (e) return e;
+  if (chi_out < 1) return TTM_EINVAL;
+  ttm::Options o;
+  e = ttm::resolve_options(opt, chi_out, o);
+  if (e) return e;
+  ttm::Plan pl;
+  e = ttm::make_plan(A, B, chi_out, o, pl);
+  if (e) return e;
+  if (ws_bytes) *ws_bytes = pl.ws_bytes;
+  if (out_capacity) *out_capacity = pl.out_capacity;
+  return TTM_OK;
+}
+
+int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, ttm_tt_out *C,
+                    void *ws, size_t ws_bytes, void *stream, const ttm_options *opt,
+                    ttm_stats *stats) {
+  int e = ttm::validate_pair(A, B);
+  if (e) return e;
+  if (chi_out < 1) return TTM_EINVAL;
+  if (!(tol >= 0.0) || !isfinite(tol)) return TTM_EINVAL;
+  ttm::Options o;
+  e = ttm::resolve_options(opt, chi_out, o);
+  if (e) return e;
+  return ttm::run_ttm(A, B, chi_out, tol, C, ws, ws_bytes, static_cast<hipStream_t>(stream), o, stats);
+}
+
+int ttm_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, ttm_tt_out *C,
+                 void *ws, size_t ws_bytes, void *stream) {
+  return ttm_multiply_ex(A, B, chi_out, tol, C, ws, ws_bytes, stream, nullptr, nullptr);
+}
+
+int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
+                       size_t *ws_bytes, int64_t *out_capacity) {
+  return ttm::conventional_query_impl(A, B, chi_out, opt, ws_bytes, out_capacity);
+}
+
+int conventional_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
+                             ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
+                             const ttm_options *opt, ttm_stats *stats) {
+  return ttm::conventional_multiply_impl(A, B, chi_out, tol, C, ws, ws_bytes, stream, opt, stats);
+}
+
+int conventional_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
+                          ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream) {
+  return conventional_multiply_ex(A, B, chi_out, tol, C, ws, ws_bytes, stream, nullptr, nullptr);
+}
+
+}  // extern "C"

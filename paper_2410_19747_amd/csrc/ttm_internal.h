@@ -1,0 +1,127 @@
+// Internal declarations shared by the kernel and runtime translation units
+// of libttm.  Host-side launchers enqueue gfx950 kernels on a stream; they do
+// no allocation and no synchronisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ttm.h"
+
+namespace ttm {
+
+// ------------------------------------------------------------------ GEMM
+// C = alpha * A B + beta * C for a batch of independent products.
+//   A[i][k] at A + b*a_bs + i*a_rs + k*a_cs     (i < M, k < K)
+//   B[k][j] at B + b*b_bs + k*b_rs + j*b_cs     (k < K, j < N)
+//   C[i][j] at C + b*c_bs + (i / c_rdiv)*c_rs1 + (i % c_rdiv)*c_rs0
+//                         + (j / c_cdiv)*c_cs1 + (j % c_cdiv)*c_cs0
+// The split output mapping lets a product write a permuted layout (the
+// leg exchange of a swap) directly.  beta == 0 never reads C.
+struct GemmArgs {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const double *A = nullptr;
+  int64_t a_rs = 0, a_cs = 0, a_bs = 0;
+  const double *B = nullptr;
+  int64_t b_rs = 0, b_cs = 0, b_bs = 0;
+  double *C = nullptr;
+  int64_t c_bs = 0;
+  int c_rdiv = 1, c_cdiv = 1;
+  int64_t c_rs1 = 0, c_rs0 = 0, c_cs1 = 0, c_cs0 = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+
+// Plain row-major helper: C[M x N] (ldc) = A[M x K] (lda) * B[K x N] (ldb).
+GemmArgs gemm_rowmajor(int M, int N, int K, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, double *C, int64_t ldc);
+
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+
+// ------------------------------------------------------------------ element-wise
+// dst[i] = src[i], i < n.
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
+// dst[i] = v, i < n.
+hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t s);
+// Reversal of a carriage: out[b][w][a] = in[a][w][b], in is [rl][d][rr].
+hipError_t launch_reverse_core(double *out, const double *in, int rl, int d, int rr, hipStream_t s);
+// flag[0] = 1 if any of x[0..n) is NaN or Inf (flag must be zeroed first).
+hipError_t launch_nonfinite_check(const double *x, int64_t n, int *flag, hipStream_t s);
+hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+
+// ------------------------------------------------------------------ QR
+// Householder QR of an m x n matrix M (element (i,j) at M + i*rs + j*cs).
+// Writes Q (m x k, k = min(m,n)) row-major with leading dimension k into q,
+// and R (k x n) row-major into r.  scratch: at least m*n + m*k + 2*n doubles.
+// q, r and scratch must not overlap M.
+hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
+                     double *scratch, hipStream_t s);
+size_t qr_scratch_doubles(int m, int n);
+
+// ------------------------------------------------------------------ SVD
+// One-sided block Jacobi SVD of an L x nc column-major matrix W (ld = L,
+// nc <= L not required) with accumulated right rotations V (ncp x ncp,
+// column-major).  Columns are padded to ncp = nblk * bw (nblk even).
+struct JacobiPlan {
+  int L = 0, nc = 0;     // rows, real columns
+  int bw = 0;            // block width
+  int nblk = 0;          // number of blocks (even)
+  int ncp = 0;           // padded columns = nblk * bw
+  int rows_per_wg = 0;   // row chunk per workgroup for Gram and update
+  int sw = 0;            // row chunks of W
+  int sv = 0;            // row chunks of V
+  int rounds = 0;        // nblk - 1
+  int pairs = 0;         // nblk / 2
+};
+JacobiPlan jacobi_plan(int L, int nc);
+// Workspace doubles for the W/V/partials/conv arrays of a plan.
+size_t jacobi_ws_doubles(const JacobiPlan &p);
+
+// Device buffers of one Jacobi run (carved from the workspace).
+struct JacobiBufs {
+  double *W = nullptr;      // L x ncp (column-major)
+  double *V = nullptr;      // ncp x ncp
+  double *part = nullptr;   // pairs * sw * (2bw)^2 partial Grams
+  double *conv = nullptr;   // rounds * pairs: scaled off-diagonal maxima
+  double *sigma = nullptr;  // ncp
+  int *perm = nullptr;      // ncp: perm[k] = column index of the k-th largest value
+  double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,[5]=squared Frobenius norm of W
+};
+
+// Prepare: pad W's extra columns with zeros and set V = I.
+hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStream_t s);
+// One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
+// off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.
+hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s);
+// Column norms, descending order, and the rank rule of Eq. (eps):
+// r = min{k>=1 : tail_k < eps*total or tail_k == 0}, then min(r, cap) when
+// cap > 0; forced > 0 replaces the rule.  Writes result[0..2].
+hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double eps, int cap,
+                                int forced, hipStream_t s);
+
+// Write-out of a truncated factorisation Theta ~= U_r S_r V_r^T (r = rank):
+//   left  (rows_l x r, row-major): U_r * diag(s)^left_pow
+//   right (r x cols_r, row-major): diag(s)^right_pow * V_r^T
+// `w_holds_u` says whether W's columns are U*S (W was Theta, rows_l = L) or
+// V*S (W was Theta^T, cols_r = L); the other factor comes from the rotations
+// V.  left_pow/right_pow in {0,1} choose where the singular values go.
+hipError_t launch_svd_write(const JacobiPlan &p, const JacobiBufs &b, int r, bool w_holds_u,
+                            int left_pow, int right_pow, double *left, double *right,
+                            hipStream_t s);
+
+// ------------------------------------------------------------------ conventional
+// Dense transposed copy used by the variational driver:
+// out[j][i] = in[i][j] for an m x n row-major input.
+hipError_t launch_transpose(double *out, const double *in, int m, int n, hipStream_t s);
+
+}  // namespace ttm
+
+// ------------------------------------------------------------------ conventional product
+namespace ttm {
+// The single-site variational baseline (conventional.hip).
+int conventional_query_impl(const ::ttm_tt *A, const ::ttm_tt *B, int32_t chi_out,
+                            const ::ttm_options *opt, size_t *ws_bytes, int64_t *out_capacity);
+int conventional_multiply_impl(const ::ttm_tt *A, const ::ttm_tt *B, int32_t chi_out, double tol,
+                               ::ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
+                               const ::ttm_options *opt, ::ttm_stats *stats);
+}  // namespace ttm

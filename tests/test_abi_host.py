@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library loads, exports every function include/ttm.h declares, sizes
+workspaces from shapes alone, and rejects bad arguments with the documented
+codes before touching the GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_19747_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _abi.load_library()
+
+
+def _declared_functions(header="ttm.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported(L):
+    names = _declared_functions()
+    assert "ttm_multiply" in names and "conventional_multiply" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_abi.PROTOTYPES)
+    tnames = _declared_functions("ttm_testing.h")
+    for n in tnames:
+        assert hasattr(L, n), n
+    assert set(tnames) == set(_abi.TESTING_PROTOTYPES)
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["ttm.h", "ttm_testing.h"]
+
+
+def test_version_and_strerror(L):
+    assert b"gfx950" in L.ttm_version()
+    for code in range(0, -10, -1):
+        assert L.ttm_strerror(code) not in (None, b"unknown error")
+    assert L.ttm_strerror(-99) == b"unknown error"
+
+
+class _TT:
+    def __init__(self, phys, bonds, data_ptr=0x1000):
+        n = len(phys)
+        self.p = (ctypes.c_int32 * n)(*phys)
+        self.b = (ctypes.c_int32 * (n + 1))(*bonds)
+        offs, pos = [], 0
+        for i in range(n):
+            offs.append(pos)
+            pos += bonds[i] * phys[i] * bonds[i + 1]
+        self.o = (ctypes.c_int64 * n)(*offs)
+        self.view = _abi.TtmTT(n, ctypes.cast(self.p, _abi.I32P), ctypes.cast(self.b, _abi.I32P),
+                               ctypes.cast(self.o, _abi.I64P), ctypes.c_void_p(data_ptr), 0)
+
+
+def _query(L, A, B, chi, opt=None):
+    ws = ctypes.c_size_t(0)
+    cap = ctypes.c_int64(0)
+    rc = L.ttm_query(ctypes.byref(A.view), ctypes.byref(B.view), chi,
+                     ctypes.byref(opt) if opt is not None else None, ctypes.byref(ws), ctypes.byref(cap))
+    return rc, ws.value, cap.value
+
+
+def test_query_sizes_config_shapes(L):
+    b10 = [1, 2, 4, 8, 8, 8, 8, 8, 4, 2, 1]
+    A = _TT([2] * 10, b10)
+    rc, ws, cap = _query(L, A, A, 8)
+    assert rc == 0 and ws > 0
+    assert cap == sum(b10[i] * 2 * b10[i + 1] for i in range(10))
+    b8 = [1, 8, 64, 128, 128, 128, 64, 8, 1]
+    A = _TT([8] * 8, b8)
+    rc, ws, cap = _query(L, A, A, 128)
+    assert rc == 0
+    assert cap == sum(b8[i] * 8 * b8[i + 1] for i in range(8))
+    assert ws < 512 * 1024 * 1024   # O(d^2 chi^2) workspace, far below the chi^3 environments
+
+
+def test_query_capacity_follows_chi_out(L):
+    b = [1, 2, 4, 8, 8, 8, 8, 8, 4, 2, 1]
+    A = _TT([2] * 10, b)
+    import ttm_inputs as I
+    for chi in (1, 3, 8, 64):
+        rc, ws, cap = _query(L, A, A, chi)
+        sb = I.structural_bonds([2] * 10, chi)
+        assert rc == 0 and cap == sum(sb[i] * 2 * sb[i + 1] for i in range(10))
+
+
+def test_validation_codes(L):
+    good = _TT([2] * 4, [1, 2, 4, 2, 1])
+    rc, _, _ = _query(L, good, good, 0)
+    assert rc == _abi.TTM_EINVAL                       # chi_out < 1
+    other = _TT([2] * 5, [1, 2, 4, 4, 2, 1])
+    assert _query(L, good, other, 4)[0] == _abi.TTM_ESHAPE   # N differs
+    d3 = _TT([2, 3, 2, 2], [1, 2, 4, 2, 1])
+    assert _query(L, good, d3, 4)[0] == _abi.TTM_ESHAPE      # d differs
+    bad_end = _TT([2] * 4, [2, 2, 4, 2, 1])
+    assert _query(L, bad_end, bad_end, 4)[0] == _abi.TTM_ESHAPE
+    neg = _TT([2] * 4, [1, 2, 0, 2, 1])
+    assert _query(L, neg, neg, 4)[0] == _abi.TTM_EINVAL
+    null = _TT([2] * 4, [1, 2, 4, 2, 1], data_ptr=0)
+    assert _query(L, null, null, 4)[0] == _abi.TTM_EINVAL
+    f32 = _TT([2] * 4, [1, 2, 4, 2, 1])
+    f32.view.dtype = 1
+    assert _query(L, f32, f32, 4)[0] == _abi.TTM_EUNSUPPORTED
+    o = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(o))
+    o.chi_mid = -5
+    assert _query(L, good, good, 4, o)[0] == _abi.TTM_EINVAL
+    L.ttm_default_options(ctypes.byref(o))
+    arr = (ctypes.c_int32 * 2)(3, 0)
+    o.forced_ranks = ctypes.cast(arr, _abi.I32P)
+    o.n_forced = 2
+    assert _query(L, good, good, 4, o)[0] == _abi.TTM_EFORCED
+    L.ttm_default_options(ctypes.byref(o))
+    o.trace_cap = 4      # arrays missing
+    assert _query(L, good, good, 4, o)[0] == _abi.TTM_EINVAL
+
+
+def test_multiply_rejects_before_gpu_work(L):
+    """Argument errors come back before any HIP call (this host has no GPU)."""
+    A = _TT([2] * 4, [1, 2, 4, 2, 1])
+    bonds = (ctypes.c_int32 * 5)()
+    offs = (ctypes.c_int64 * 4)()
+    out = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P),
+                        ctypes.c_void_p(0x2000), 1 << 20)
+    args = (ctypes.byref(A.view), ctypes.byref(A.view), 4)
+    # negative / NaN tolerance
+    assert L.ttm_multiply(*args, -1.0, ctypes.byref(out), ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_EINVAL
+    assert L.ttm_multiply(*args, float("nan"), ctypes.byref(out), ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_EINVAL
+    # workspace too small / missing
+    assert L.ttm_multiply(*args, 1e-12, ctypes.byref(out), ctypes.c_void_p(0x3000), 16, None) == _abi.TTM_EWORKSPACE
+    assert L.ttm_multiply(*args, 1e-12, ctypes.byref(out), None, 1 << 30, None) == _abi.TTM_EWORKSPACE
+    # output capacity too small
+    small = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P),
+                          ctypes.c_void_p(0x2000), 3)
+    assert L.ttm_multiply(*args, 1e-12, ctypes.byref(small), ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_ECAPACITY
+    # null output
+    assert L.ttm_multiply(*args, 1e-12, None, ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_EINVAL

@@ -1,0 +1,164 @@
+"""GPU parity: libttm's TTM product against the CPU oracle, through the C ABI.
+
+Results are compared gauge-free (relative Frobenius error of the product),
+at <= 1e-12 for FP64.  Where the rule of Eq. (eps) could flip a rank on
+rounding noise, the GPU run takes the oracle's rank schedule through the
+forced-rank hook and a second, unforced run must agree on the ranks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import ttm_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _host_cores(packed):
+    return [c.detach().cpu().numpy() for c in packed.cores()]
+
+
+def _run(A, B, chi_out, eps, **kw):
+    import paper_2410_19747_amd as T
+    _torch()
+    C, st = T.multiply(A, B, chi_out, eps, **kw)
+    return _host_cores(C), st
+
+
+def test_gpu_single_site_contract():
+    _say("case: N=1 d=5 contract")
+    A, B = I.random_tt(1, 5, 4, 1), I.random_tt(1, 5, 4, 2)
+    C, st = _run(A, B, 4, 1e-28)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= 1e-15
+    assert st["n_contract"] == 1 and st["n_swap"] == 0
+
+
+def test_gpu_two_sites():
+    _say("case: N=2 d=3")
+    A, B = I.random_tt(2, 3, 3, 3), I.random_tt(2, 3, 3, 4)
+    C, st = _run(A, B, 9, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
+    assert st["n_swap"] == 1 and st["n_contract"] == 2
+
+
+def test_gpu_config1_exact_brute_force():
+    _say("case: R10 exact")
+    A, B = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2)
+    ref = O.brute_force(A, B)
+    C, st = _run(A, B, 64, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, ref) <= TOL
+    assert st["n_contract"] == 10 and st["n_swap"] == 45
+    o = O.ttm(A, B, 64, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, o.cores) <= TOL
+
+
+def test_gpu_config1_truncated_vs_oracle():
+    _say("case: R10 chi_out=8")
+    A, B = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2)
+    o = O.ttm(A, B, 8, 1e-14)
+    C, st = _run(A, B, 8, 1e-14)
+    assert st["ranks"] == o.ranks
+    assert O.rel_frob(C, o.cores) <= TOL
+    Cf, stf = _run(A, B, 8, 1e-14, forced_ranks=o.ranks)
+    assert O.rel_frob(Cf, o.cores) <= TOL
+    assert np.isclose(st["model_flops"], o.flops, rtol=1e-12)
+    assert np.isclose(st["error_bound"], o.error_bound, rtol=1e-6)
+
+
+def test_gpu_mixed_dims_exact():
+    _say("case: mixed physical dims")
+    phys = [3, 2, 4, 2, 3]
+    A, B = I.random_tt(5, phys, 100, 21), I.random_tt(5, phys, 100, 22)
+    C, _ = _run(A, B, 10 ** 6, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
+
+
+def test_gpu_turbulence_t16_exact():
+    _say("case: T16 turbulence exact")
+    A, B = I.turbulence_qtt(16, 201, 0), I.turbulence_qtt(16, 202, 0)
+    C, _ = _run(A, B, 64, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
+
+
+def test_gpu_identity_all_ones():
+    _say("case: identity d=8 N=8 chi=128")
+    A = I.random_tt(8, 8, 128, 5)
+    one = I.ones_tt(8, 8)
+    C, st = _run(A, one, 128, 1e-28)
+    assert O.rel_frob(C, A) <= TOL
+    assert st["max_bond"] <= 128
+
+
+def test_gpu_commutativity():
+    _say("case: commutativity R10")
+    A, B = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2)
+    C1, _ = _run(A, B, 64, 1e-28, chi_mid=0)
+    C2, _ = _run(B, A, 64, 1e-28, chi_mid=0)
+    assert O.rel_frob(C1, C2) <= TOL
+
+
+def test_gpu_closed_form_long_chain():
+    _say("case: x*x = x^2, N=40")
+    n = 40
+    A = I.poly1_qtt(n, a=-0.3)
+    C, st = _run(A, A, 16, 1e-28)
+    assert O.rel_frob(C, I.square_qtt(n, a=-0.3)) <= TOL
+    assert max(O.bonds_of(C)) == 3
+
+
+def test_gpu_output_gauge():
+    _say("case: output gauge")
+    A, B = I.random_tt(8, 2, 8, 3), I.random_tt(8, 2, 8, 4)
+    C, st = _run(A, B, 12, 1e-12)
+    for c in C[:-1]:
+        assert O.is_left_orthonormal(c, 1e-12)
+    assert st["n_contract"] == 8 and st["n_swap"] == 28
+
+
+@pytest.mark.parametrize("chi", [64, 128])
+def test_gpu_config2_turbulence_vs_oracle(chi):
+    _say("case: 256^3 turbulence chi=%d" % chi)
+    A = I.turbulence_qtt(256, 101, chi)
+    B = I.turbulence_qtt(256, 102, chi)
+    o = O.ttm(A, B, chi, 1e-14)
+    C, st = _run(A, B, chi, 1e-14, forced_ranks=o.ranks)
+    assert O.rel_frob(C, o.cores) <= TOL
+    C2, st2 = _run(A, B, chi, 1e-14)
+    assert st2["ranks"] == o.ranks
+    assert O.rel_frob(C2, o.cores) <= TOL
+    assert st2["max_bond"] == o.max_bond
+
+
+def test_gpu_error_codes():
+    import paper_2410_19747_amd as T
+    _say("case: error codes")
+    A, B = I.random_tt(6, 2, 4, 1), I.random_tt(6, 2, 4, 2)
+    with pytest.raises(T.TTMError) as ei:
+        T.multiply(A, B, 4, 1e-12, forced_ranks=[1, 2])    # list too short
+    assert ei.value.code == T.TTM_EFORCED
+    bad = [c.copy() for c in A]
+    bad[2][0, 0, 0] = np.nan
+    with pytest.raises(T.TTMError) as ei:
+        T.multiply(bad, B, 4, 1e-12)
+    assert ei.value.code == T.TTM_ENONFINITE
+    with pytest.raises(T.TTMError) as ei:
+        T.multiply(I.random_tt(8, 8, 64, 1), I.random_tt(8, 8, 64, 2), 64, 1e-12, svd_max_sweeps=1)
+    assert ei.value.code == T.TTM_ENOCONV
+    # the library stays usable after errors
+    C, _ = _run(A, B, 16, 1e-28, chi_mid=0)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
