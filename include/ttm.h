@@ -95,7 +95,20 @@ typedef struct ttm_options {
   int32_t trace_cap;       /* capacity of the two trace arrays              */
   int32_t *rank_trace;     /* host [trace_cap]: rank of each truncating SVD, or NULL */
   double *discard_trace;   /* host [trace_cap]: discarded weight sum_{i>r} lambda_i^2, or NULL */
+  int32_t profile;         /* 1: time every kernel launch with HIP events on the stream and
+                              report per-class totals in ttm_stats (default 0) */
 } ttm_options;
+
+/* Kernel classes of ttm_stats.kernel_ms / kernel_launches. */
+enum {
+  TTM_KC_GEMM = 0,         /* contractions, merges, R and S V^T products          */
+  TTM_KC_QR = 1,           /* Householder QR of gauge moves                        */
+  TTM_KC_JAC_GRAM = 2,     /* Jacobi SVD: partial Gram matrices of block pairs     */
+  TTM_KC_JAC_ROTATE = 3,   /* Jacobi SVD: block-pair diagonalisation and rotation  */
+  TTM_KC_JAC_OTHER = 4,    /* Jacobi SVD: set-up, convergence, norms, sort, write  */
+  TTM_KC_OTHER = 5,        /* copies, reversal, transposes, checks                 */
+  TTM_KC_COUNT = 6
+};
 
 /* Statistics of one call. */
 typedef struct ttm_stats {
@@ -112,6 +125,8 @@ typedef struct ttm_stats {
   double model_flops;      /* algorithmic flops of the recorded schedule       */
   double svd_model_flops;  /* the part of model_flops spent in SVDs            */
   size_t peak_ws_bytes;    /* workspace bytes the call used                    */
+  double kernel_ms[TTM_KC_COUNT];        /* with opt.profile: summed event time per class */
+  int64_t kernel_launches[TTM_KC_COUNT]; /* with opt.profile: launches per class          */
 } ttm_stats;
 
 /* Defaults: chi_mid = -1 (same as chi_out), final_round = 1, max_sweeps = 10,

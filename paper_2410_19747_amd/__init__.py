@@ -124,7 +124,7 @@ _DEFAULT_WS = {}
 
 
 def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, seed=12345,
-             forced_ranks=None, trace_cap=0):
+             forced_ranks=None, trace_cap=0, profile=False):
     o = TtmOptions()
     lib().ttm_default_options(ctypes.byref(o))
     o.chi_mid = -1 if chi_mid is None else int(chi_mid)
@@ -132,6 +132,7 @@ def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, s
     o.max_sweeps = int(max_sweeps)
     o.svd_max_sweeps = int(svd_max_sweeps)
     o.seed = int(seed)
+    o.profile = 1 if profile else 0
     keep = []
     if forced_ranks is not None:
         arr = (ctypes.c_int32 * max(1, len(forced_ranks)))(*[int(r) for r in forced_ranks])
@@ -209,7 +210,10 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
     if rc != TTM_OK:
         raise TTMError(rc, mfn.__name__)
     res = PackedTT(out, [A.phys[i] for i in range(n)], list(bonds), list(offs))
-    stats = {f: getattr(st, f) for f, _ in TtmStats._fields_}
+    from ._abi import KERNEL_CLASSES
+    stats = {f: getattr(st, f) for f, _ in TtmStats._fields_ if f not in ("kernel_ms", "kernel_launches")}
+    stats["kernel_ms"] = dict(zip(KERNEL_CLASSES, list(st.kernel_ms)))
+    stats["kernel_launches"] = dict(zip(KERNEL_CLASSES, list(st.kernel_launches)))
     nt = min(st.n_trace, o.trace_cap)
     if o.trace_cap:
         stats["ranks"] = [o.rank_trace[i] for i in range(nt)]

@@ -52,6 +52,7 @@ class TtmOptions(ctypes.Structure):
         ("trace_cap", ctypes.c_int32),
         ("rank_trace", I32P),
         ("discard_trace", F64P),
+        ("profile", ctypes.c_int32),
     ]
 
 
@@ -70,7 +71,12 @@ class TtmStats(ctypes.Structure):
         ("model_flops", ctypes.c_double),
         ("svd_model_flops", ctypes.c_double),
         ("peak_ws_bytes", ctypes.c_size_t),
+        ("kernel_ms", ctypes.c_double * 6),
+        ("kernel_launches", ctypes.c_int64 * 6),
     ]
+
+
+KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_rotate", "jacobi_other", "other"]
 
 
 # Every symbol include/ttm.h declares, with its prototype.

@@ -3,6 +3,51 @@
 
 namespace ttm {
 
+// ---------------------------------------------------------------- kernel timer
+namespace {
+struct EventPool {
+  hipEvent_t ev[2 * 4096];
+  int n = 0;  // events created
+};
+EventPool &pool() {
+  static thread_local EventPool p;
+  return p;
+}
+}  // namespace
+
+void KernelTimer::begin(int cls, hipStream_t s) {
+  EventPool &p = pool();
+  if (npending >= 4096) return;  // callers collect well before this
+  pending_cls[npending] = 1 << 30;  // not open until the start event is recorded
+  const int i = 2 * npending;
+  while (p.n < i + 2) {
+    if (hipEventCreate(&p.ev[p.n]) != hipSuccess) return;
+    ++p.n;
+  }
+  if (hipEventRecord(p.ev[i], s) != hipSuccess) return;
+  pending_cls[npending] = -1 - cls;  // open
+}
+
+void KernelTimer::end(int cls, hipStream_t s) {
+  EventPool &p = pool();
+  if (npending >= 4096 || pending_cls[npending] != -1 - cls) return;
+  if (hipEventRecord(p.ev[2 * npending + 1], s) != hipSuccess) return;
+  pending_cls[npending] = cls;
+  ++npending;
+}
+
+void KernelTimer::collect() {
+  EventPool &p = pool();
+  for (int k = 0; k < npending; ++k) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p.ev[2 * k], p.ev[2 * k + 1]) == hipSuccess) {
+      ms[pending_cls[k]] += t;
+      launches[pending_cls[k]] += 1;
+    }
+  }
+  npending = 0;
+}
+
 __global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__ src, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

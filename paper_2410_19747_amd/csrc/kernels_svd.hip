@@ -351,18 +351,28 @@ __global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restr
   }
 }
 
-hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s) {
+hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
+                               KernelTimer *timer) {
   if (2 * p.bw > MAXB2) return hipErrorInvalidValue;
   const double ns = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;
   const double noise2 = ns * ns;
   for (int round = 0; round < p.rounds; ++round) {
-    hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.bw,
-                       p.nblk, round, b.part, p.sw);
-    hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(p.pairs, p.sw + p.sv), dim3(JNT), 0, s, b.W, b.V,
-                       p.L, p.ncp, p.bw, p.nblk, round, b.part, p.sw, b.conv, tol, b.result, noise2);
+    {
+      Timed tm(timer, KC_JAC_GRAM, s);
+      hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.bw,
+                         p.nblk, round, b.part, p.sw);
+    }
+    {
+      Timed tm(timer, KC_JAC_ROTATE, s);
+      hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(p.pairs, p.sw + p.sv), dim3(JNT), 0, s, b.W, b.V,
+                         p.L, p.ncp, p.bw, p.nblk, round, b.part, p.sw, b.conv, tol, b.result, noise2);
+    }
   }
-  hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs,
-                     b.result);
+  {
+    Timed tm(timer, KC_JAC_OTHER, s);
+    hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs,
+                       b.result);
+  }
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ struct Options {
   int trace_cap = 0;
   int32_t *rank_trace = nullptr;
   double *discard_trace = nullptr;
+  int profile = 0;
 };
 
 int64_t sat_mul(int64_t a, int64_t b) {
@@ -108,6 +109,8 @@ int resolve_options(const ttm_options *o, int chi_out, Options &r) {
   r.trace_cap = o->trace_cap;
   r.rank_trace = o->rank_trace;
   r.discard_trace = o->discard_trace;
+  if (o->profile != 0 && o->profile != 1) return TTM_EINVAL;
+  r.profile = o->profile;
   return TTM_OK;
 }
 
@@ -283,9 +286,17 @@ struct Runner {
   double disc_sum = 0.0, err_bound = 0.0, flops = 0.0, svd_flops = 0.0;
   int forced_pos = 0;
   int err = TTM_OK;
+  KernelTimer timer;
 
   Runner(hipStream_t s, const Options &opt) : st(s), o(opt) {
     trace = getenv("TTM_TRACE") != nullptr;
+    timer.on = opt.profile != 0;
+  }
+  // synchronise the stream and read the event timers
+  bool sync() {
+    if (!hip(hipStreamSynchronize(st))) return false;
+    if (timer.on) timer.collect();
+    return true;
   }
 
   double *take() {
@@ -321,7 +332,10 @@ struct Runner {
     g.A = k.p; g.a_rs = (int64_t)k.s.d * k.s.rr; g.a_cs = 1; g.a_bs = k.s.rr;
     g.B = m.p; g.b_rs = (int64_t)m.s.d * m.s.rr; g.b_cs = 1; g.b_bs = m.s.rr;
     g.C = out.p; g.c_rs1 = (int64_t)k.s.d * m.s.rr; g.c_cs1 = 1; g.c_bs = m.s.rr;
-    hip(launch_gemm(g, st));
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      hip(launch_gemm(g, st));
+    }
     flops += 2.0 * k.s.d * k.s.rl * k.s.rr * m.s.rr;
     ++n_contract;
     note(out.s);
@@ -337,11 +351,17 @@ struct Runner {
     const int k = std::min(m, n);
     double *q = take();
     if (!q) return;
-    hip(launch_qr(cur.p, m, n, n, 1, q, rbuf, qrbuf, st));
+    {
+      Timed tm(&timer, KC_QR, st);
+      hip(launch_qr(cur.p, m, n, n, 1, q, rbuf, qrbuf, st));
+    }
     double *nn = take();
     if (!nn) return;
     const int ncol = nxt.s.d * nxt.s.rr;
-    hip(launch_gemm(gemm_rowmajor(k, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st));
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      hip(launch_gemm(gemm_rowmajor(k, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st));
+    }
     give(cur.p);
     give(nxt.p);
     cur.p = q;
@@ -377,17 +397,20 @@ struct Runner {
         return out;
       }
     }
-    if (!hip(launch_jacobi_init(jp, jb, st))) return out;
+    {
+      Timed tm(&timer, KC_JAC_OTHER, st);
+      if (!hip(launch_jacobi_init(jp, jb, st))) return out;
+    }
     const double tol = sqrt((double)std::max(jp.L, 1)) * kEps;
     double prev = INFINITY;
     int sweeps = 0;
     bool ok = false;
     double host_res[8];
     for (int sw = 0; sw < o.svd_max_sweeps; ++sw) {
-      if (!hip(launch_jacobi_sweep(jp, jb, tol, st))) return out;
+      if (!hip(launch_jacobi_sweep(jp, jb, tol, st, &timer))) return out;
       ++sweeps;
       if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
-      if (!hip(hipStreamSynchronize(st))) return out;
+      if (!sync()) return out;
       const double off = host_res[3];
       if (trace) fprintf(stderr, "[ttm]   jacobi %dx%d sweep %d off=%.3e tol=%.3e\n", jp.L, jp.nc, sw, off, tol);
       if (!(off == off)) break;  // NaN
@@ -403,9 +426,12 @@ struct Runner {
       if (trace) fprintf(stderr, "[ttm] jacobi %dx%d did not converge\n", jp.L, jp.nc);
       return out;
     }
-    if (!hip(launch_jacobi_finish(jp, jb, eps, cap, forced, st))) return out;
+    {
+      Timed tm(&timer, KC_JAC_OTHER, st);
+      if (!hip(launch_jacobi_finish(jp, jb, eps, cap, forced, st))) return out;
+    }
     if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
-    if (!hip(hipStreamSynchronize(st))) return out;
+    if (!sync()) return out;
     if (host_res[4] != 0.0) {
       err = TTM_ENONFINITE;
       return out;
@@ -470,7 +496,10 @@ struct Runner {
     } else {
       g.c_rs1 = (int64_t)n * dx; g.c_rs0 = Dr; g.c_cs1 = n; g.c_cs0 = 1;
     }
-    if (!hip(launch_gemm(g, st))) return;
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(g, st))) return;
+    }
     flops += 2.0 * Dl * dp * (double)Dm * dx * Dr;
     SvdOut so = jacobi(jp, jb, eps_, cap);
     if (so.r < 1) return;
@@ -479,7 +508,10 @@ struct Runner {
     double *pn = take();
     if (!xn || !pn) return;
     // X' = U_r S_r  -> [Dl, dx, r];  P' = V_r^T -> [r, dp, Dr]
-    if (!hip(launch_svd_write(jp, jb, r, tall, 1, 0, xn, pn, st))) return;
+    {
+      Timed tm(&timer, KC_JAC_OTHER, st);
+      if (!hip(launch_svd_write(jp, jb, r, tall, 1, 0, xn, pn, st))) return;
+    }
     give(P.p);
     give(X.p);
     X.p = xn;
@@ -500,10 +532,13 @@ struct Runner {
     const int L = tall ? m : n, nc = tall ? n : m;
     JacobiPlan jp = jacobi_plan(L, nc);
     JacobiBufs jb = carve(jp);
-    if (tall) {
-      if (!hip(launch_transpose(jb.W, cur.p, m, n, st))) return;  // column-major copy
-    } else {
-      if (!hip(launch_copy(jb.W, cur.p, (int64_t)m * n, st))) return;  // already Theta^T col-major
+    {
+      Timed tm(&timer, KC_OTHER, st);
+      if (tall) {
+        if (!hip(launch_transpose(jb.W, cur.p, m, n, st))) return;  // column-major copy
+      } else {
+        if (!hip(launch_copy(jb.W, cur.p, (int64_t)m * n, st))) return;  // already Theta^T col-major
+      }
     }
     SvdOut so = jacobi(jp, jb, eps_, cap);
     if (so.r < 1) return;
@@ -511,9 +546,15 @@ struct Runner {
     double *un = take();
     double *nn = take();
     if (!un || !nn) return;
-    if (!hip(launch_svd_write(jp, jb, r, tall, 0, 1, un, rbuf, st))) return;
+    {
+      Timed tm(&timer, KC_JAC_OTHER, st);
+      if (!hip(launch_svd_write(jp, jb, r, tall, 0, 1, un, rbuf, st))) return;
+    }
     const int ncol = nxt.s.d * nxt.s.rr;
-    if (!hip(launch_gemm(gemm_rowmajor(r, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st))) return;
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(gemm_rowmajor(r, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st))) return;
+    }
     flops += 2.0 * r * (double)n * ncol;
     give(cur.p);
     give(nxt.p);
@@ -568,6 +609,7 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     a[i].p = R.take();
     b[i].p = R.take();
     if (R.err) return R.err;
+    Timed tm(&R.timer, KC_OTHER, st);
     R.hip(launch_copy(a[i].p, Ad + A->offsets[i], a[i].s.size(), st));
     R.hip(launch_copy(b[i].p, Bd + B->offsets[i], b[i].s.size(), st));
     R.hip(launch_nonfinite_check(a[i].p, a[i].s.size(), R.flags, st));
@@ -578,7 +620,7 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
   {
     int hflag[4] = {0, 0, 0, 0};
     R.hip(hipMemcpyAsync(hflag, R.flags, sizeof(hflag), hipMemcpyDeviceToHost, st));
-    R.hip(hipStreamSynchronize(st));
+    R.sync();
     if (R.err) return R.err;
     if (hflag[0]) return TTM_ENONFINITE;
   }
@@ -591,6 +633,7 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     bt[i].p = R.take();
     bt[i].s = {b[i].s.rr, b[i].s.d, b[i].s.rl};
     if (!bt[i].p) break;
+    Timed tm(&R.timer, KC_OTHER, st);
     R.hip(launch_reverse_core(bt[i].p, b[i].p, b[i].s.rl, b[i].s.d, b[i].s.rr, st));
     R.give(b[i].p);
     b[i].p = nullptr;
@@ -634,11 +677,12 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
   for (int i = 0; i < n; ++i) {
     C->offsets[i] = pos;
     C->bonds[i] = pi[i].s.rl;
+    Timed tm(&R.timer, KC_OTHER, st);
     R.hip(launch_copy(Cd + pos, pi[i].p, pi[i].s.size(), st));
     pos += pi[i].s.size();
   }
   C->bonds[n] = pi[n - 1].s.rr;
-  R.hip(hipStreamSynchronize(st));
+  R.sync();
   if (R.err) return R.err;
   if (stats) {
     memset(stats, 0, sizeof(*stats));
@@ -655,6 +699,10 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     stats->model_flops = R.flops;
     stats->svd_model_flops = R.svd_flops;
     stats->peak_ws_bytes = pl.ws_bytes;
+    for (int c = 0; c < KC_COUNT; ++c) {
+      stats->kernel_ms[c] = R.timer.ms[c];
+      stats->kernel_launches[c] = R.timer.launches[c];
+    }
   }
   return TTM_OK;
 }

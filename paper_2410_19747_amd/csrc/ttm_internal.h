@@ -11,6 +11,45 @@
 
 namespace ttm {
 
+// ------------------------------------------------------------------ kernel timing
+// Optional per-launch timing with HIP events on the launching stream.  Kernel
+// classes follow ttm_stats.kernel_ms.  Events come from a process-wide pool
+// (no device memory); elapsed times are collected after the next
+// synchronisation of the stream.
+enum KernelClass {
+  KC_GEMM = 0,
+  KC_QR = 1,
+  KC_JAC_GRAM = 2,
+  KC_JAC_ROTATE = 3,
+  KC_JAC_OTHER = 4,
+  KC_OTHER = 5,
+  KC_COUNT = 6
+};
+struct KernelTimer {
+  bool on = false;
+  double ms[KC_COUNT] = {};
+  int64_t launches[KC_COUNT] = {};
+  // indices into the pool of (start, end) pairs recorded but not yet read
+  int pending_cls[4096];
+  int npending = 0;
+  void begin(int cls, hipStream_t s);
+  void end(int cls, hipStream_t s);
+  // Reads every pending pair; the stream must have been synchronised.
+  void collect();
+};
+// RAII helper: times one launch when the timer is on.
+struct Timed {
+  KernelTimer *t;
+  int cls;
+  hipStream_t s;
+  Timed(KernelTimer *t_, int c, hipStream_t s_) : t(t_), cls(c), s(s_) {
+    if (t && t->on) t->begin(cls, s);
+  }
+  ~Timed() {
+    if (t && t->on) t->end(cls, s);
+  }
+};
+
 // ------------------------------------------------------------------ GEMM
 // C = alpha * A B + beta * C for a batch of independent products.
 //   A[i][k] at A + b*a_bs + i*a_rs + k*a_cs     (i < M, k < K)
@@ -92,7 +131,8 @@ struct JacobiBufs {
 hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStream_t s);
 // One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
 // off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.
-hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s);
+hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
+                               KernelTimer *timer = nullptr);
 // Column norms, descending order, and the rank rule of Eq. (eps):
 // r = min{k>=1 : tail_k < eps*total or tail_k == 0}, then min(r, cap) when
 // cap > 0; forced > 0 replaces the rule.  Writes result[0..2].
