@@ -103,6 +103,35 @@ __global__ void nonfinite_kernel(const double *__restrict__ x, int64_t n, int *f
   if (bad) flag[0] = 1;  // benign race: every writer stores the same value
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014) in counter form: output k of stream
+// `seed` is mix(seed + (k+1) * gamma), mapped to [-1, 1).
+__global__ void splitmix_fill_kernel(double *__restrict__ dst, int64_t n, uint64_t seed, int64_t start) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(start + i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    dst[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+// out[0] = sum of squares of x[0..n), one workgroup, fixed order.
+__global__ __launch_bounds__(1024) void sumsq_kernel(const double *__restrict__ x, int64_t n,
+                                                     double *__restrict__ out) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) acc = fma(x[i], x[i], acc);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[0] = t;
+  }
+}
+
 static int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   if (g > 4096) g = 4096;
@@ -119,6 +148,17 @@ hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s)
 hipError_t launch_fill(double *dst, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitmix_fill(double *dst, int64_t n, uint64_t seed, int64_t start, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(splitmix_fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, n, seed, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double *x, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
   return hipGetLastError();
 }
 

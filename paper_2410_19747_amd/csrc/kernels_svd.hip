@@ -37,7 +37,8 @@ namespace ttm {
 
 namespace {
 constexpr int JNT = 256;
-constexpr int MAXB2 = 32;     // largest 2*bw
+constexpr int BW = 16;        // block width
+constexpr int MAXB2 = 2 * BW; // columns of a block pair
 constexpr int ROWS_PER_WG = 128;
 
 __device__ __forceinline__ void rr_pair(int n, int round, int k, int &a, int &b) {
@@ -65,13 +66,9 @@ JacobiPlan jacobi_plan(int L, int nc) {
   JacobiPlan p;
   p.L = L;
   p.nc = nc;
-  int bw = 16;
-  if (const char *e = getenv("TTM_JACOBI_BW")) {
-    int v = atoi(e);
-    if (v >= 1 && v <= MAXB2 / 2) bw = v;
-  }
-  if (nc <= 2 * bw) bw = (nc + 1) / 2;
-  if (bw < 1) bw = 1;
+  // Fixed block width: the kernels are specialised for 2 * BW = 32 columns;
+  // narrower problems are padded with zero columns, which never rotate.
+  const int bw = BW;
   int nblk = (nc + bw - 1) / bw;
   if (nblk < 2) nblk = 2;
   if (nblk & 1) ++nblk;
@@ -128,35 +125,63 @@ hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStrea
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ MFMA helpers
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One wave computes a 16 x 16 tile D = sum_k A(i,k) B(k,j) over k < K (K a
+// multiple of 4) with v_mfma_f64_16x16x4f64.  Lane l supplies A(l%16, k+l/16)
+// and B(k+l/16, l%16); accumulator register t of lane l holds
+// D(4t + l/16, l%16).  a(i,k) / b(k,j) are LDS accessors.
+template <typename FA, typename FB>
+__device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int r = lane & 15, kq = lane >> 4;
+  for (int k = 0; k < K; k += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(r, k + kq), b(k + kq, r), acc, 0, 0, 0);
+  return acc;
+}
+
 // ------------------------------------------------------------------ Gram partials
-// grid (pairs, sw).  Partial G over rows [s*R, s*R+R) of the pair's columns.
+// grid (pairs, sw).  Partial G = P^T P over rows [s*R, s*R+R) of the pair's
+// 2*bw columns (zero-padded to 32), one 16 x 16 tile per wave on MFMA.
 __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int bw,
                                                           int nblk, int round,
                                                           double *__restrict__ part, int sw) {
   __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
   const int pair = blockIdx.x, s = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
   const int b2 = 2 * bw;
   const int r0 = s * ROWS_PER_WG;
   const int nr = min(ROWS_PER_WG, L - r0);
-  for (int e = threadIdx.x; e < ROWS_PER_WG * b2; e += JNT) {
+  for (int e = tid; e < ROWS_PER_WG * MAXB2; e += JNT) {
     const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
-    P[i][c] = (i < nr) ? W[(int64_t)col * L + r0 + i] : 0.0;
+    double v = 0.0;
+    if (c < b2 && i < nr) {
+      const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
+      v = W[(int64_t)col * L + r0 + i];
+    }
+    P[i][c] = v;
   }
   __syncthreads();
+  const int ti = wave >> 1, tj = wave & 1;
+  dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
+                       [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
   double *out = part + ((int64_t)pair * sw + s) * b2 * b2;
-  for (int e = threadIdx.x; e < b2 * b2; e += JNT) {
-    const int p = e / b2, q = e % b2;
-    double acc = 0.0;
-    for (int i = 0; i < nr; ++i) acc = fma(P[i][p], P[i][q], acc);
-    out[e] = acc;
+  for (int t = 0; t < 4; ++t) {
+    const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
+    if (i < b2 && j < b2) out[i * b2 + j] = acc[t];
   }
 }
 
 // ------------------------------------------------------------------ rotate
-// grid (pairs, sw + sv).  Reduce partial Grams, diagonalise in LDS, apply.
+// grid (pairs, sw + sv).  Every workgroup of a pair reduces the partial Grams
+// in the same fixed order, runs one cyclic sweep of two-sided Jacobi on the
+// 2bw x 2bw Gram in LDS (bit-identical in all of them), re-orthogonalises the
+// accumulated rotation, and applies it to its row chunk of W (chunk < sw) or
+// of V.  A step of the inner sweep rotates bw disjoint index pairs at once;
+// G <- J^T G J then splits into independent 2 x 2 blocks, one per thread.
 __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__ W, double *__restrict__ V,
                                                             int L, int ncp, int bw, int nblk, int round,
                                                             const double *__restrict__ part, int sw,
@@ -165,33 +190,37 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
                                                             double noise2) {
   __shared__ double G[MAXB2][MAXB2 + 1];
   __shared__ double Q[MAXB2][MAXB2 + 1];
+  __shared__ double S[MAXB2][MAXB2 + 1];
   __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
-  __shared__ double rc[MAXB2 / 2], rs[MAXB2 / 2];
-  __shared__ int rp[MAXB2 / 2], rq[MAXB2 / 2];
-  __shared__ int any_rot, sweep_rot;
+  __shared__ double rc[BW], rs[BW];
+  __shared__ unsigned char tp[MAXB2 - 1][BW], tq[MAXB2 - 1][BW];
+  __shared__ int any_rot;
   __shared__ double redmax[JNT / 64];
+  static_assert(JNT == BW * BW, "one 2x2 block per thread");
 
   const int pair = blockIdx.x, chunk = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
   const int b2 = 2 * bw;
-  const int npair_in = bw;  // b2 / 2 rotations per inner step
   const double thr = noise2 * result[5];
   const double floor_n = sqrt(result[5] / (double)L);  // F / sqrt(L)
 
-  // Reduce partial Grams in a fixed order.
-  for (int e = tid; e < b2 * b2; e += JNT) {
-    const double *src = part + (int64_t)pair * sw * b2 * b2 + e;
+  // Reduce partial Grams in a fixed order; pad to 32 x 32 with the identity.
+  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
+    const int i = e / MAXB2, j = e % MAXB2;
     double acc = 0.0;
-    for (int s = 0; s < sw; ++s) acc += src[(int64_t)s * b2 * b2];
-    G[e / b2][e % b2] = acc;
-    Q[e / b2][e % b2] = (e / b2 == e % b2) ? 1.0 : 0.0;
+    if (i < b2 && j < b2) {
+      const double *src = part + (int64_t)pair * sw * b2 * b2 + i * b2 + j;
+      for (int s = 0; s < sw; ++s) acc += src[(int64_t)s * b2 * b2];
+    }
+    G[i][j] = acc;
+    Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) any_rot = 0;
   __syncthreads();
 
-  // Convergence measure of this visit: largest scaled off-diagonal.
+  // Convergence measure of this visit (scaled off-diagonal, see the header).
   if (chunk == 0) {
     double m = 0.0;
     for (int e = tid; e < b2 * b2; e += JNT) {
@@ -206,7 +235,7 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
       }
     }
     m = wave_max(m);
-    if ((tid & 63) == 0) redmax[tid >> 6] = m;
+    if (lane == 0) redmax[wave] = m;
     __syncthreads();
     if (tid == 0) {
       double t = 0.0;
@@ -215,87 +244,107 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
     }
   }
 
-  // One cyclic sweep of two-sided Jacobi on G (round-robin over the b2
-  // indices); the outer sweeps repeat the visit, so one inner sweep suffices.
-  for (int isw = 0; isw < 1; ++isw) {
-    if (tid == 0) sweep_rot = 0;
-    __syncthreads();
-    for (int step = 0; step < b2 - 1; ++step) {
-      if (tid < npair_in) {
-        int p, q;
-        rr_pair(b2, step, tid, p, q);
-        if (p > q) { int t = p; p = q; q = t; }
-        const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
-        double c = 1.0, sn = 0.0;
-        const double a = sqrt(gpp), b = sqrt(gqq);
-        const double lo = fmin(a, b);
-        if ((gpp > thr || gqq > thr) && fabs(gpq) > tol * (fmax(a, b) * (lo * lo > thr ? lo : floor_n))) {
-          const double zeta = (gqq - gpp) / (2.0 * gpq);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = c * t;
-          sweep_rot = 1;
+  // One cyclic sweep of two-sided Jacobi over the 32 indices: 31 steps of
+  // 16 disjoint rotations (round-robin pairs from a table built here).
+  for (int e = tid; e < (MAXB2 - 1) * BW; e += JNT) {
+    const int st = e / BW, k = e % BW;
+    int p, q;
+    rr_pair(MAXB2, st, k, p, q);
+    tp[st][k] = (unsigned char)min(p, q);
+    tq[st][k] = (unsigned char)max(p, q);
+  }
+  const double tol2 = tol * tol, floor2 = floor_n * floor_n;
+  __syncthreads();
+  for (int step = 0; step < MAXB2 - 1; ++step) {
+    if (tid < BW) {
+      const int p = tp[step][tid], q = tq[step][tid];
+      const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
+      const double hi2 = fmax(gpp, gqq), lo2 = fmin(gpp, gqq);
+      double c = 1.0, sn = 0.0;
+      // |g_pq| > tol * hi * (lo^2 > thr ? lo : F/sqrt(L)), squared
+      if (hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2)) {
+        // tan of the rotation angle from zeta = (g_qq - g_pp) / (2 g_pq); the
+        // hardware reciprocal / rsqrt approximations are enough for t, and
+        // one Newton step on c makes c^2 + s^2 = 1 to rounding.
+        const double zeta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
+        const double az = fabs(zeta);
+        double t;
+        if (az > 1e100) {
+          t = 0.5 * __builtin_amdgcn_rcp(zeta);
+        } else {
+          const double w = 1.0 + zeta * zeta;
+          const double root = w * __builtin_amdgcn_rsq(w);
+          t = copysign(__builtin_amdgcn_rcp(az + root), zeta);
         }
-        rc[tid] = c; rs[tid] = sn; rp[tid] = p; rq[tid] = q;
+        const double x = 1.0 + t * t;
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * (1.5 - 0.5 * x * y * y);
+        y = y * (1.5 - 0.5 * x * y * y);
+        c = y;
+        sn = y * t;
+        any_rot = 1;
       }
-      __syncthreads();
-      // rows: G <- J^T G
-      for (int e = tid; e < npair_in * b2; e += JNT) {
-        const int t = e / b2, k = e % b2;
-        const double c = rc[t], sn = rs[t];
-        if (sn != 0.0) {
-          const int p = rp[t], q = rq[t];
-          const double gp = G[p][k], gq = G[q][k];
-          G[p][k] = c * gp - sn * gq;
-          G[q][k] = sn * gp + c * gq;
-        }
-      }
-      __syncthreads();
-      // columns: G <- G J ; Q <- Q J
-      for (int e = tid; e < npair_in * b2; e += JNT) {
-        const int t = e / b2, k = e % b2;
-        const double c = rc[t], sn = rs[t];
-        if (sn != 0.0) {
-          const int p = rp[t], q = rq[t];
-          const double gp = G[k][p], gq = G[k][q];
-          G[k][p] = c * gp - sn * gq;
-          G[k][q] = sn * gp + c * gq;
-          const double qp = Q[k][p], qq = Q[k][q];
-          Q[k][p] = c * qp - sn * qq;
-          Q[k][q] = sn * qp + c * qq;
-        }
-      }
-      __syncthreads();
+      rc[tid] = c;
+      rs[tid] = sn;
     }
-    const int did = sweep_rot;
-    if (did && tid == 0) any_rot = 1;
     __syncthreads();
-    if (!did) break;
+    {
+      // G <- J^T G J on 2 x 2 blocks: thread (u, v) owns rows {p_u, q_u} x
+      // cols {p_v, q_v}; 16 x 16 blocks = 256 threads.
+      const int u = tid >> 4, v = tid & 15;
+      const double su = rs[u], sv = rs[v];
+      if (su != 0.0 || sv != 0.0) {
+        const double cu = rc[u], cv = rc[v];
+        const int pu = tp[step][u], qu = tq[step][u], pv = tp[step][v], qv = tq[step][v];
+        const double g00 = G[pu][pv], g01 = G[pu][qv], g10 = G[qu][pv], g11 = G[qu][qv];
+        const double h00 = cu * g00 - su * g10, h01 = cu * g01 - su * g11;
+        const double h10 = su * g00 + cu * g10, h11 = su * g01 + cu * g11;
+        G[pu][pv] = cv * h00 - sv * h01;
+        G[pu][qv] = sv * h00 + cv * h01;
+        G[qu][pv] = cv * h10 - sv * h11;
+        G[qu][qv] = sv * h10 + cv * h11;
+      }
+      // Q <- Q J: row k = tid / 8, pairs 2 (tid % 8) and 2 (tid % 8) + 1
+      const int k = tid >> 3;
+      for (int h = 0; h < 2; ++h) {
+        const int w = 2 * (tid & 7) + h;
+        const double sw_ = rs[w];
+        if (sw_ != 0.0) {
+          const double cw = rc[w];
+          const int pw = tp[step][w], qw = tq[step][w];
+          const double q0 = Q[k][pw], q1 = Q[k][qw];
+          Q[k][pw] = cw * q0 - sw_ * q1;
+          Q[k][qw] = sw_ * q0 + cw * q1;
+        }
+      }
+    }
+    __syncthreads();
   }
   if (!any_rot) return;  // Q = I: nothing to apply
 
   // One Newton-Schulz step, Q <- Q (3I - Q^T Q) / 2, restores orthogonality
-  // to rounding level.  Without it the O(u) drift of every visit accumulates
-  // over the thousands of visits a column receives.
-  for (int e = tid; e < b2 * b2; e += JNT) {  // G <- Q^T Q
-    const int i = e / b2, j = e % b2;
-    double acc = 0.0;
-    for (int k = 0; k < b2; ++k) acc = fma(Q[k][i], Q[k][j], acc);
-    G[i][j] = acc;
+  // to rounding level; without it the O(u) drift of every visit accumulates
+  // over the thousands of visits a column receives.  32 x 32 products on
+  // MFMA, one 16 x 16 tile per wave.
+  const int ti = wave >> 1, tj = wave & 1;
+  {
+    dbl4 acc = mfma_tile([&](int i, int k) { return Q[k][ti * 16 + i]; },
+                         [&](int k, int j) { return Q[k][tj * 16 + j]; }, MAXB2, lane);
+    for (int t = 0; t < 4; ++t) S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = acc[t];
   }
   __syncthreads();
-  double qn[(MAXB2 * MAXB2 + JNT - 1) / JNT];
-  for (int e = tid, t = 0; e < b2 * b2; e += JNT, ++t) {
-    const int i = e / b2, j = e % b2;
-    double acc = 0.0;
-    for (int k = 0; k < b2; ++k) acc = fma(Q[i][k], G[k][j], acc);
-    qn[t] = 1.5 * Q[i][j] - 0.5 * acc;
+  {
+    dbl4 acc = mfma_tile([&](int i, int k) { return Q[ti * 16 + i][k]; },
+                         [&](int k, int j) { return S[k][tj * 16 + j]; }, MAXB2, lane);
+    __syncthreads();  // every wave has read Q before it is overwritten
+    for (int t = 0; t < 4; ++t) {
+      const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
+      G[i][j] = 1.5 * Q[i][j] - 0.5 * acc[t];
+    }
   }
-  __syncthreads();
-  for (int e = tid, t = 0; e < b2 * b2; e += JNT, ++t) Q[e / b2][e % b2] = qn[t];
-  __syncthreads();
+  __syncthreads();  // the re-orthogonalised rotation is now in G
 
-  // Apply Q to one row chunk of W (chunk < sw) or of V.
+  // Apply to one row chunk of W (chunk < sw) or of V: P (rows x 32) <- P G.
   double *X;
   int ld, r0, nr;
   if (chunk < sw) {
@@ -304,19 +353,34 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
     X = V; ld = ncp; r0 = (chunk - sw) * ROWS_PER_WG; nr = min(ROWS_PER_WG, ncp - r0);
   }
   if (nr <= 0) return;
-  for (int e = tid; e < ROWS_PER_WG * b2; e += JNT) {
+  for (int e = tid; e < ROWS_PER_WG * MAXB2; e += JNT) {
     const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
-    if (i < nr) P[i][c] = X[(int64_t)col * ld + r0 + i];
+    double v = 0.0;
+    if (c < b2 && i < nr) {
+      const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
+      v = X[(int64_t)col * ld + r0 + i];
+    }
+    P[i][c] = v;
   }
   __syncthreads();
-  for (int e = tid; e < ROWS_PER_WG * b2; e += JNT) {
-    const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    if (i < nr) {
-      double acc = 0.0;
-      for (int k = 0; k < b2; ++k) acc = fma(P[i][k], Q[k][c], acc);
-      const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
-      X[(int64_t)col * ld + r0 + i] = acc;
+  // 8 x 2 output tiles of 16 x 16; wave w owns row tiles 2w, 2w+1.
+  dbl4 acc[2][2];
+  for (int x = 0; x < 2; ++x) {
+    const int rt = 2 * wave + x;
+    for (int y = 0; y < 2; ++y)
+      acc[x][y] = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
+                            [&](int k, int j) { return G[k][y * 16 + j]; }, MAXB2, lane);
+  }
+  for (int x = 0; x < 2; ++x) {
+    const int rt = 2 * wave + x;
+    for (int y = 0; y < 2; ++y) {
+      for (int t = 0; t < 4; ++t) {
+        const int i = rt * 16 + 4 * t + (lane >> 4), c = y * 16 + (lane & 15);
+        if (i < nr && c < b2) {
+          const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
+          X[(int64_t)col * ld + r0 + i] = acc[x][y][t];
+        }
+      }
     }
   }
 }

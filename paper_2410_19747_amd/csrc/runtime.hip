@@ -717,6 +717,317 @@ int run_ttm(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_ou
   return e;
 }
 
+
+// ====================================================================== conventional
+// Single-site variational fit (Sec. II.A): C ~ A * B with bonds capped at
+// chi_out, never forming the chi_A chi_B Kronecker carriages of
+// Eq. (carriageXi).  Per site the optimal core is the projection
+//   C_i[c, s, c'] = sum L[c, a, b] A_i[a, s, a'] B_i[b, s, b'] R[c', a', b'],
+// contracted as (L B) then A over the shared physical index s, then R:
+// chi^4 work, chi^3 environments.  Reading of the unstated details: seeded
+// initial guess (counter-based SplitMix64), left-to-right then right-to-left
+// sweeps, stop when the centre's norm changes by at most tol (relative)
+// between two full sweeps, or after max_sweeps.
+
+struct ConvPlan {
+  int n = 0;
+  std::vector<int> phys;
+  std::vector<Shape> a, b, c;   // c: initial bonds (structural, capped at chi_out)
+  std::vector<int64_t> lsz, rsz; // environment sizes (doubles)
+  int64_t tmax = 1, core_max = 1, qr_max = 1, rmax = 1;
+  int64_t out_capacity = 0;
+  size_t ws_bytes = 0;
+};
+
+int make_conv_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, ConvPlan &pl) {
+  const int n = A->n_sites;
+  pl.n = n;
+  pl.phys.assign(A->phys, A->phys + n);
+  pl.a.resize(n); pl.b.resize(n); pl.c.resize(n);
+  std::vector<int> cb(n + 1, 1);
+  for (int i = 1; i < n; ++i) cb[i] = (int)std::min<int64_t>(product_bound(pl.phys, i), chi_out);
+  for (int i = 0; i < n; ++i) {
+    pl.a[i] = {A->bonds[i], A->phys[i], A->bonds[i + 1]};
+    pl.b[i] = {B->bonds[i], B->phys[i], B->bonds[i + 1]};
+    pl.c[i] = {cb[i], pl.phys[i], cb[i + 1]};
+    pl.core_max = std::max(pl.core_max, pl.c[i].size());
+    pl.out_capacity += pl.c[i].size();
+  }
+  pl.lsz.assign(n + 1, 1);
+  pl.rsz.assign(n + 1, 1);
+  for (int i = 0; i <= n; ++i) {
+    const int64_t e = (int64_t)cb[i] * A->bonds[i] * B->bonds[i];
+    pl.lsz[i] = e;
+    pl.rsz[i] = e;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int64_t cl = cb[i], cr = cb[i + 1], al = pl.a[i].rl, ar = pl.a[i].rr, bl = pl.b[i].rl,
+                  br = pl.b[i].rr, d = pl.phys[i];
+    pl.tmax = std::max(pl.tmax, std::max(cl * al * d * br, cl * d * ar * br));
+    pl.qr_max = std::max<int64_t>(pl.qr_max, (int64_t)qr_scratch_doubles((int)(cl * d), (int)cr));
+    pl.qr_max = std::max<int64_t>(pl.qr_max, (int64_t)qr_scratch_doubles((int)(d * cr), (int)cl));
+    pl.rmax = std::max(pl.rmax, std::max(cl * d, cr) * std::max(cl, cr));
+  }
+  size_t bytes = 0;
+  for (int i = 0; i <= n; ++i) bytes += align_up((size_t)pl.lsz[i] * 8) + align_up((size_t)pl.rsz[i] * 8);
+  bytes += 2 * align_up((size_t)pl.tmax * 8);
+  bytes += (size_t)(n + 3) * align_up((size_t)pl.core_max * 8);
+  bytes += align_up((size_t)pl.qr_max * 8) + align_up((size_t)pl.rmax * 8) + 256;
+  pl.ws_bytes = bytes;
+  if (pl.tmax > ((int64_t)1 << 36)) return TTM_EINVAL;
+  return TTM_OK;
+}
+
+struct ConvRunner {
+  hipStream_t st;
+  KernelTimer timer;
+  int err = TTM_OK;
+  double flops = 0.0;
+  int n_qr = 0;
+  bool hip(hipError_t e) {
+    if (e != hipSuccess && err == TTM_OK) err = TTM_EHIP;
+    return e == hipSuccess;
+  }
+  void gemm(const GemmArgs &g) {
+    Timed tm(&timer, KC_GEMM, st);
+    hip(launch_gemm(g, st));
+    flops += 2.0 * g.M * (double)g.N * g.K * g.batch;
+  }
+};
+
+int run_conventional_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C,
+                          void *ws, size_t ws_bytes, hipStream_t st, const Options &o,
+                          ttm_stats *stats, bool &enqueued) {
+  ConvPlan pl;
+  int e = make_conv_plan(A, B, chi_out, pl);
+  if (e) return e;
+  if (!ws || ws_bytes < pl.ws_bytes) return TTM_EWORKSPACE;
+  if (!C || !C->bonds || !C->offsets || !C->data) return TTM_EINVAL;
+  if (C->capacity < pl.out_capacity) return TTM_ECAPACITY;
+  const int n = pl.n;
+  ConvRunner R;
+  R.st = st;
+  R.timer.on = o.profile != 0;
+  enqueued = true;
+
+  char *base = static_cast<char *>(ws);
+  size_t off = 0;
+  auto carve = [&](int64_t nd) {
+    double *p = reinterpret_cast<double *>(base + off);
+    off += align_up((size_t)nd * 8);
+    return p;
+  };
+  std::vector<double *> L(n + 1), Rv(n + 1);
+  for (int i = 0; i <= n; ++i) L[i] = carve(pl.lsz[i]);
+  for (int i = 0; i <= n; ++i) Rv[i] = carve(pl.rsz[i]);
+  double *T1 = carve(pl.tmax), *T2 = carve(pl.tmax);
+  std::vector<double *> slots;
+  for (int i = 0; i < n + 3; ++i) slots.push_back(carve(pl.core_max));
+  double *qrs = carve(pl.qr_max), *rbuf = carve(pl.rmax);
+  double *scal = carve(32);
+  std::vector<double *> freeq(slots.begin() + n, slots.end());
+  auto take = [&]() { double *p = freeq.back(); freeq.pop_back(); return p; };
+  auto give = [&](double *p) { freeq.push_back(p); };
+
+  const double *Ad = static_cast<const double *>(A->data);
+  const double *Bd = static_cast<const double *>(B->data);
+  std::vector<const double *> Ap(n), Bp(n);
+  for (int i = 0; i < n; ++i) {
+    Ap[i] = Ad + A->offsets[i];
+    Bp[i] = Bd + B->offsets[i];
+  }
+  // initial guess
+  std::vector<double *> Cp(slots.begin(), slots.begin() + n);
+  std::vector<Shape> cs = pl.c;
+  {
+    Timed tm(&R.timer, KC_OTHER, st);
+    int64_t start = 0;
+    for (int i = 0; i < n; ++i) {
+      R.hip(launch_splitmix_fill(Cp[i], cs[i].size(), o.seed, start, st));
+      start += cs[i].size();
+    }
+    R.hip(launch_fill(L[0], 1.0, 1, st));
+    R.hip(launch_fill(Rv[n], 1.0, 1, st));
+  }
+
+  // LQ of core i (rows: left bond), the R factor pushed into core i-1.
+  auto lq_left = [&](int i, bool push) {
+    const Shape s = cs[i];
+    const int m = s.d * s.rr, nn = s.rl, k = std::min(m, nn);
+    double *q = take();
+    {
+      Timed tm(&R.timer, KC_QR, st);
+      R.hip(launch_qr(Cp[i], m, nn, 1, m, q, rbuf, qrs, st));
+    }
+    double *qt = take();
+    {
+      Timed tm(&R.timer, KC_OTHER, st);
+      R.hip(launch_transpose(qt, q, m, k, st));
+    }
+    give(q);
+    ++R.n_qr;
+    R.flops += 4.0 * m * (double)nn * nn;
+    if (push) {
+      const Shape p = cs[i - 1];
+      double *np_ = take();
+      GemmArgs g;
+      g.M = p.rl * p.d; g.N = k; g.K = nn;
+      g.A = Cp[i - 1]; g.a_rs = p.rr; g.a_cs = 1;
+      g.B = rbuf; g.b_rs = 1; g.b_cs = nn;  // R^T
+      g.C = np_; g.c_rs1 = k; g.c_cs1 = 1;
+      R.gemm(g);
+      give(Cp[i - 1]);
+      Cp[i - 1] = np_;
+      cs[i - 1].rr = k;
+    }
+    give(Cp[i]);
+    Cp[i] = qt;
+    cs[i].rl = k;
+  };
+
+  // right environment R_i from core i and R_{i+1}
+  auto right_env = [&](int i) {
+    const int64_t cl = cs[i].rl, d = cs[i].d, cr = cs[i].rr;
+    const int64_t al = pl.a[i].rl, ar = pl.a[i].rr, bl = pl.b[i].rl, br = pl.b[i].rr;
+    R.gemm(gemm_rowmajor((int)(cl * d), (int)(ar * br), (int)cr, Cp[i], cr, Rv[i + 1], ar * br, T1, ar * br));
+    for (int s = 0; s < d; ++s) {
+      GemmArgs g;
+      g.M = (int)al; g.N = (int)br; g.K = (int)ar; g.batch = (int)cl;
+      g.A = Ap[i] + s * ar; g.a_rs = d * ar; g.a_cs = 1; g.a_bs = 0;
+      g.B = T1 + s * ar * br; g.b_rs = br; g.b_cs = 1; g.b_bs = d * ar * br;
+      g.C = T2 + s * br; g.c_rs1 = d * br; g.c_cs1 = 1; g.c_bs = al * d * br;
+      R.gemm(g);
+    }
+    GemmArgs g;
+    g.M = (int)al; g.N = (int)bl; g.K = (int)(d * br); g.batch = (int)cl;
+    g.A = T2; g.a_rs = d * br; g.a_cs = 1; g.a_bs = al * d * br;
+    g.B = Bp[i]; g.b_rs = 1; g.b_cs = d * br; g.b_bs = 0;
+    g.C = Rv[i]; g.c_rs1 = bl; g.c_cs1 = 1; g.c_bs = al * bl;
+    R.gemm(g);
+  };
+
+  // local optimum at site i from L_i and R_{i+1}; leaves T2 = (L B) A
+  auto local = [&](int i, double *out) {
+    const int64_t cl = cs[i].rl, d = pl.phys[i], cr = cs[i].rr;
+    const int64_t al = pl.a[i].rl, ar = pl.a[i].rr, bl = pl.b[i].rl, br = pl.b[i].rr;
+    R.gemm(gemm_rowmajor((int)(cl * al), (int)(d * br), (int)bl, L[i], bl, Bp[i], d * br, T1, d * br));
+    for (int s = 0; s < d; ++s) {
+      GemmArgs g;
+      g.M = (int)ar; g.N = (int)br; g.K = (int)al; g.batch = (int)cl;
+      g.A = Ap[i] + s * ar; g.a_rs = 1; g.a_cs = d * ar; g.a_bs = 0;
+      g.B = T1 + s * br; g.b_rs = d * br; g.b_cs = 1; g.b_bs = al * d * br;
+      g.C = T2 + s * ar * br; g.c_rs1 = br; g.c_cs1 = 1; g.c_bs = d * ar * br;
+      R.gemm(g);
+    }
+    GemmArgs g;
+    g.M = (int)(cl * d); g.N = (int)cr; g.K = (int)(ar * br);
+    g.A = T2; g.a_rs = ar * br; g.a_cs = 1;
+    g.B = Rv[i + 1]; g.b_rs = 1; g.b_cs = ar * br;
+    g.C = out; g.c_rs1 = cr; g.c_cs1 = 1;
+    R.gemm(g);
+  };
+
+  // right-orthogonalise the initial guess and build the right environments
+  for (int i = n - 1; i >= 1 && !R.err; --i) lq_left(i, true);
+  for (int i = n - 1; i >= 1 && !R.err; --i) right_env(i);
+
+  int sweeps = 0;
+  double prev = -1.0, nrm = 0.0;
+  for (int sw = 0; sw < o.max_sweeps && !R.err; ++sw) {
+    ++sweeps;
+    for (int i = 0; i < n && !R.err; ++i) {
+      double *cn = take();
+      local(i, cn);
+      give(Cp[i]);
+      Cp[i] = cn;
+      if (i < n - 1) {
+        const Shape s = cs[i];
+        const int m = s.rl * s.d, nn = s.rr, k = std::min(m, nn);
+        double *q = take();
+        {
+          Timed tm(&R.timer, KC_QR, st);
+          R.hip(launch_qr(Cp[i], m, nn, nn, 1, q, rbuf, qrs, st));
+        }
+        ++R.n_qr;
+        R.flops += 4.0 * m * (double)nn * nn;
+        give(Cp[i]);
+        Cp[i] = q;
+        cs[i].rr = k;
+        cs[i + 1].rl = k;
+        // L_{i+1}[c', a', b'] = sum_{c,s} Q[c,s,c'] T2[c,s,a',b']
+        const int64_t ar = pl.a[i].rr, br = pl.b[i].rr;
+        GemmArgs g;
+        g.M = k; g.N = (int)(ar * br); g.K = m;
+        g.A = Cp[i]; g.a_rs = 1; g.a_cs = k;
+        g.B = T2; g.b_rs = ar * br; g.b_cs = 1;
+        g.C = L[i + 1]; g.c_rs1 = ar * br; g.c_cs1 = 1;
+        R.gemm(g);
+      }
+    }
+    for (int i = n - 1; i >= 0 && !R.err; --i) {
+      double *cn = take();
+      local(i, cn);
+      give(Cp[i]);
+      Cp[i] = cn;
+      if (i > 0) {
+        lq_left(i, false);
+        cs[i - 1].rr = cs[i].rl;
+        right_env(i);
+      }
+    }
+    {
+      Timed tm(&R.timer, KC_OTHER, st);
+      R.hip(launch_sumsq(Cp[0], cs[0].size(), scal, st));
+    }
+    double h = 0.0;
+    R.hip(hipMemcpyAsync(&h, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    R.hip(hipStreamSynchronize(st));
+    if (R.timer.on) R.timer.collect();
+    if (R.err) break;
+    if (!std::isfinite(h)) return TTM_ENONFINITE;
+    nrm = sqrt(h);
+    if (prev >= 0.0 && fabs(nrm - prev) <= tol * nrm) break;
+    prev = nrm;
+  }
+  if (R.err) return R.err;
+  int64_t pos = 0;
+  double *Cd = static_cast<double *>(C->data);
+  for (int i = 0; i < n; ++i) {
+    C->offsets[i] = pos;
+    C->bonds[i] = cs[i].rl;
+    Timed tm(&R.timer, KC_OTHER, st);
+    R.hip(launch_copy(Cd + pos, Cp[i], cs[i].size(), st));
+    pos += cs[i].size();
+  }
+  C->bonds[n] = cs[n - 1].rr;
+  R.hip(hipStreamSynchronize(st));
+  if (R.timer.on) R.timer.collect();
+  if (R.err) return R.err;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    int mb = 1;
+    for (int i = 0; i < n; ++i) mb = std::max(mb, cs[i].rr);
+    stats->max_bond = mb;
+    stats->n_qr = R.n_qr;
+    stats->sweeps = sweeps;
+    stats->model_flops = R.flops;
+    stats->peak_ws_bytes = pl.ws_bytes;
+    for (int c = 0; c < KC_COUNT; ++c) {
+      stats->kernel_ms[c] = R.timer.ms[c];
+      stats->kernel_launches[c] = R.timer.launches[c];
+    }
+  }
+  return TTM_OK;
+}
+
+int run_conventional(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C, void *ws,
+                     size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats) {
+  bool enqueued = false;
+  const int e = run_conventional_impl(A, B, chi_out, tol, C, ws, ws_bytes, st, o, stats, enqueued);
+  if (e != TTM_OK && enqueued) (void)hipStreamSynchronize(st);
+  return e;
+}
+
 }  // namespace
 }  // namespace ttm
 
@@ -787,13 +1098,32 @@ int ttm_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, 
 
 int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
                        size_t *ws_bytes, int64_t *out_capacity) {
-  return ttm::conventional_query_impl(A, B, chi_out, opt, ws_bytes, out_capacity);
+  int e = ttm::validate_pair(A, B);
+  if (e) return e;
+  if (chi_out < 1) return TTM_EINVAL;
+  ttm::Options o;
+  e = ttm::resolve_options(opt, chi_out, o);
+  if (e) return e;
+  ttm::ConvPlan pl;
+  e = ttm::make_conv_plan(A, B, chi_out, pl);
+  if (e) return e;
+  if (ws_bytes) *ws_bytes = pl.ws_bytes;
+  if (out_capacity) *out_capacity = pl.out_capacity;
+  return TTM_OK;
 }
 
 int conventional_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
                              ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
                              const ttm_options *opt, ttm_stats *stats) {
-  return ttm::conventional_multiply_impl(A, B, chi_out, tol, C, ws, ws_bytes, stream, opt, stats);
+  int e = ttm::validate_pair(A, B);
+  if (e) return e;
+  if (chi_out < 1) return TTM_EINVAL;
+  if (!(tol >= 0.0) || !isfinite(tol)) return TTM_EINVAL;
+  ttm::Options o;
+  e = ttm::resolve_options(opt, chi_out, o);
+  if (e) return e;
+  return ttm::run_conventional(A, B, chi_out, tol, C, ws, ws_bytes, static_cast<hipStream_t>(stream), o,
+                               stats);
 }
 
 int conventional_multiply(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,

@@ -87,6 +87,10 @@ hipError_t launch_reverse_core(double *out, const double *in, int rl, int d, int
 // flag[0] = 1 if any of x[0..n) is NaN or Inf (flag must be zeroed first).
 hipError_t launch_nonfinite_check(const double *x, int64_t n, int *flag, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+// dst[i] = counter-based SplitMix64 uniform in [-1, 1) for counters start + i.
+hipError_t launch_splitmix_fill(double *dst, int64_t n, uint64_t seed, int64_t start, hipStream_t s);
+// out[0] = sum_i x[i]^2.
+hipError_t launch_sumsq(const double *x, int64_t n, double *out, hipStream_t s);
 
 // ------------------------------------------------------------------ QR
 // Householder QR of an m x n matrix M (element (i,j) at M + i*rs + j*cs).
@@ -156,12 +160,3 @@ hipError_t launch_transpose(double *out, const double *in, int m, int n, hipStre
 
 }  // namespace ttm
 
-// ------------------------------------------------------------------ conventional product
-namespace ttm {
-// The single-site variational baseline (conventional.hip).
-int conventional_query_impl(const ::ttm_tt *A, const ::ttm_tt *B, int32_t chi_out,
-                            const ::ttm_options *opt, size_t *ws_bytes, int64_t *out_capacity);
-int conventional_multiply_impl(const ::ttm_tt *A, const ::ttm_tt *B, int32_t chi_out, double tol,
-                               ::ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
-                               const ::ttm_options *opt, ::ttm_stats *stats);
-}  // namespace ttm

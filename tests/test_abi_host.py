@@ -144,3 +144,21 @@ def test_multiply_rejects_before_gpu_work(L):
     assert L.ttm_multiply(*args, 1e-12, ctypes.byref(small), ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_ECAPACITY
     # null output
     assert L.ttm_multiply(*args, 1e-12, None, ctypes.c_void_p(0x3000), 1 << 30, None) == _abi.TTM_EINVAL
+
+
+def test_conventional_query_sizes(L):
+    import ttm_inputs as I
+    b8 = [1, 8, 64, 64, 64, 64, 64, 8, 1]
+    A = _TT([8] * 8, b8)
+    ws = ctypes.c_size_t(0)
+    cap = ctypes.c_int64(0)
+    rc = L.conventional_query(ctypes.byref(A.view), ctypes.byref(A.view), 64, None, ctypes.byref(ws),
+                              ctypes.byref(cap))
+    assert rc == 0
+    sb = I.structural_bonds([8] * 8, 64)
+    assert cap.value == sum(sb[i] * 8 * sb[i + 1] for i in range(8))
+    # chi^3 environments: at least 2 (N+1) of them at chi_C chi_A chi_B doubles
+    assert ws.value >= 64 ** 3 * 8
+    bad = _TT([8] * 8, b8, data_ptr=0)
+    assert L.conventional_query(ctypes.byref(bad.view), ctypes.byref(A.view), 64, None, ctypes.byref(ws),
+                                ctypes.byref(cap)) == _abi.TTM_EINVAL
