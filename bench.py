@@ -9,7 +9,7 @@ with truncated SVD, gauge moves and the final rounding) on inputs already
 resident in device memory.
 
 Prints one JSON line with the throughput, the roofline of the dominant
-kernel (the Jacobi rotation kernel of the swap SVDs, timed with HIP events on
+kernel (the Jacobi block-pair solve kernel of the swap SVDs, timed with HIP events on
 the library's stream during the timed steps), and the CPU oracle's rate on a
 bounded sample of the same workload.
 """
@@ -121,17 +121,18 @@ def main():
             pstats.append(s_)
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp
-        rot_ms = sum(s["kernel_ms"]["jacobi_rotate"] for s in pstats)
-        rot_n = sum(s["kernel_launches"]["jacobi_rotate"] for s in pstats)
+        rot_ms = sum(s["kernel_ms"]["jacobi_solve"] for s in pstats)
+        rot_n = sum(s["kernel_launches"]["jacobi_solve"] for s in pstats)
         tot_ms = sum(sum(s["kernel_ms"].values()) for s in pstats)
-        # Algorithmic SVD flops of the product, attributed to its rotation
-        # launches (one launch = one round of one Jacobi sweep of one SVD).
+        # Algorithmic SVD flops of the product, attributed to the launches of
+        # its dominant kernel (one launch = one round of one Jacobi sweep of
+        # one SVD: every block pair's Gram diagonalised, V rotated).
         flops_per_launch = sum(s["svd_model_flops"] for s in pstats) / rot_n
         avg_launch_s = rot_ms / rot_n / 1e3
         achieved = flops_per_launch / avg_launch_s / 1e12
         roofline = {
             "bound": "mfma",
-            "kernel": "jacobi_rotate_kernel",
+            "kernel": "jacobi_solve_kernel",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -104,10 +104,11 @@ enum {
   TTM_KC_GEMM = 0,         /* contractions, merges, R and S V^T products          */
   TTM_KC_QR = 1,           /* Householder QR of gauge moves                        */
   TTM_KC_JAC_GRAM = 2,     /* Jacobi SVD: partial Gram matrices of block pairs     */
-  TTM_KC_JAC_ROTATE = 3,   /* Jacobi SVD: block-pair diagonalisation and rotation  */
+  TTM_KC_JAC_SOLVE = 3,    /* Jacobi SVD: diagonalisation of each block-pair Gram  */
   TTM_KC_JAC_OTHER = 4,    /* Jacobi SVD: set-up, convergence, norms, sort, write  */
   TTM_KC_OTHER = 5,        /* copies, reversal, transposes, checks                 */
-  TTM_KC_COUNT = 6
+  TTM_KC_JAC_APPLY = 6,    /* Jacobi SVD: rotation of the column blocks and of V   */
+  TTM_KC_COUNT = 7
 };
 
 /* Statistics of one call. */

@@ -71,12 +71,12 @@ class TtmStats(ctypes.Structure):
         ("model_flops", ctypes.c_double),
         ("svd_model_flops", ctypes.c_double),
         ("peak_ws_bytes", ctypes.c_size_t),
-        ("kernel_ms", ctypes.c_double * 6),
-        ("kernel_launches", ctypes.c_int64 * 6),
+        ("kernel_ms", ctypes.c_double * 7),
+        ("kernel_launches", ctypes.c_int64 * 7),
     ]
 
 
-KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_rotate", "jacobi_other", "other"]
+KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_solve", "jacobi_other", "other", "jacobi_apply"]
 
 
 # Every symbol include/ttm.h declares, with its prototype.

@@ -86,14 +86,16 @@ JacobiPlan jacobi_plan(int L, int nc) {
 size_t jacobi_ws_doubles(const JacobiPlan &p) {
   const size_t b2 = 2 * (size_t)p.bw;
   size_t n = 0;
-  n += (size_t)p.L * p.ncp;               // W
-  n += (size_t)p.ncp * p.ncp;             // V
+  n += 2 * (size_t)p.L * p.ncp;           // W and its reordering buffer
+  n += 2 * (size_t)p.ncp * p.ncp;         // V and its reordering buffer
   n += (size_t)p.pairs * p.sw * b2 * b2;  // partial Grams
   n += (size_t)p.rounds * p.pairs;        // conv
+  n += 2 * (size_t)p.pairs * MAXB2 * MAXB2;  // rotations of two rounds
+  n += 2 * (size_t)p.pairs;                  // rotation flags (ints)
   n += (size_t)p.ncp;                     // sigma
   n += (size_t)p.ncp;                     // perm (ints, padded as doubles)
   n += 8;                                 // result
-  return n + 8 * 32;                      // each of the 7 regions is rounded up to 32 doubles
+  return n + 12 * 32;                     // each of the 11 regions is rounded up to 32 doubles
 }
 
 __global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restrict__ W, int64_t n,
@@ -168,159 +170,178 @@ __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restri
   const int ti = wave >> 1, tj = wave & 1;
   dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
                        [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
-  double *out = part + ((int64_t)pair * sw + s) * b2 * b2;
+  double *out = part + ((int64_t)pair * sw + s) * MAXB2 * MAXB2;
   for (int t = 0; t < 4; ++t) {
     const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-    if (i < b2 && j < b2) out[i * b2 + j] = acc[t];
+    out[i * MAXB2 + j] = acc[t];
   }
 }
 
 // ------------------------------------------------------------------ rotate
-// grid (pairs, sw + sv).  Every workgroup of a pair reduces the partial Grams
-// in the same fixed order, runs one cyclic sweep of two-sided Jacobi on the
-// 2bw x 2bw Gram in LDS (bit-identical in all of them), re-orthogonalises the
-// accumulated rotation, and applies it to its row chunk of W (chunk < sw) or
-// of V.  A step of the inner sweep rotates bw disjoint index pairs at once;
-// G <- J^T G J then splits into independent 2 x 2 blocks, one per thread.
-__global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__ W, double *__restrict__ V,
-                                                            int L, int ncp, int bw, int nblk, int round,
-                                                            const double *__restrict__ part, int sw,
-                                                            double *__restrict__ conv, double tol,
-                                                            const double *__restrict__ result,
-                                                            double noise2) {
-  __shared__ double G[MAXB2][MAXB2 + 1];
+// Rotation (c, s) annihilating g_pq of a symmetric 2 x 2 block, or (1, 0)
+// when the pair is already orthogonal to tolerance (see the header).  The
+// hardware reciprocal / rsqrt approximations are enough for the angle; one
+// Newton step on c makes c^2 + s^2 = 1 to rounding.  Every thread that needs
+// a rotation computes it from the same inputs, so all copies agree bitwise.
+__device__ __forceinline__ void rot_params(double gpp, double gqq, double gpq, double thr, double tol2,
+                                           double floor2, double &c, double &sn) {
+  const double hi2 = fmax(gpp, gqq), lo2 = fmin(gpp, gqq);
+  c = 1.0;
+  sn = 0.0;
+  if (hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2)) {
+    // The angle only has to be approximately right (the outer sweeps repeat
+    // every pair): zeta = (g_qq - g_pp) / (2 g_pq) and t = tan(angle) in FP32.
+    // c = 1 / sqrt(1 + t^2) is then refined in FP64 so that c^2 + s^2 = 1
+    // to rounding for the t actually used.
+    const double zeta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
+    double t;
+    if (fabs(zeta) > 1e15) {
+      t = 0.5 * __builtin_amdgcn_rcp(zeta);
+    } else {
+      const float zf = (float)zeta;
+      const float az = fabsf(zf);
+      const float w = 1.0f + zf * zf;
+      const float tf = __builtin_amdgcn_rcpf(az + w * __builtin_amdgcn_rsqf(w));
+      t = copysign((double)tf, zeta);
+    }
+    const double x = 1.0 + t * t;
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    c = y;
+    sn = y * t;
+  }
+}
+
+// Pair k of step st of the round-robin over 32 indices, ordered p < q.
+__device__ __forceinline__ void pair32(int st, int k, int &p, int &q) {
+  int a, b;
+  if (k == 0) {
+    a = st;
+    b = MAXB2 - 1;
+  } else {
+    a = (st + k) % (MAXB2 - 1);
+    b = (st - k + (MAXB2 - 1)) % (MAXB2 - 1);
+  }
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// grid (pairs).  One workgroup per block pair: reduce the partial Grams in a
+// fixed order, measure convergence, run one cyclic sweep of two-sided Jacobi
+// on the 32 x 32 Gram in LDS, re-orthogonalise the accumulated rotation and
+// store it (qbuf[pair], 32 x 32 row-major; flag[pair] = 1 when it is not the
+// identity).  A step rotates 16 disjoint index pairs at once; G <- J^T G J
+// splits into independent 2 x 2 blocks, one per thread, read from one copy of
+// G and written to the other, so a step needs a single barrier.
+__device__ void apply_chunk(double *__restrict__ X, int ld, int nrows, int chunk, int bi, int bj,
+                            const double *__restrict__ qsrc, double (*Qn)[MAXB2 + 1],
+                            double (*P)[MAXB2 + 1]);
+
+__global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int round,
+                                                           const double *__restrict__ part, int sw,
+                                                           double *__restrict__ conv, double tol,
+                                                           const double *__restrict__ result,
+                                                           double noise2, double *__restrict__ qbuf,
+                                                           int *__restrict__ flag, double *__restrict__ V,
+                                                           int ncp, int vround,
+                                                           const double *__restrict__ qprev,
+                                                           const int *__restrict__ fprev) {
+  // Workgroups past the first `pairs` rotate V by the previous round's
+  // rotations (independent of this round's solve, so it overlaps it).
+  if ((int)blockIdx.x >= nblk / 2) {
+    __shared__ double Qv[MAXB2][MAXB2 + 1];
+    __shared__ double Pv[ROWS_PER_WG][MAXB2 + 1];
+    const int e = blockIdx.x - nblk / 2;
+    const int vp = e % (nblk / 2), chunk = e / (nblk / 2);
+    if (fprev[vp] == 0) return;
+    int vi, vj;
+    rr_pair(nblk, vround, vp, vi, vj);
+    apply_chunk(V, ncp, ncp, chunk, vi, vj, qprev + (int64_t)vp * MAXB2 * MAXB2, Qv, Pv);
+    return;
+  }
+  __shared__ double Gb[2][MAXB2][MAXB2 + 1];
   __shared__ double Q[MAXB2][MAXB2 + 1];
   __shared__ double S[MAXB2][MAXB2 + 1];
-  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
-  __shared__ double rc[BW], rs[BW];
-  __shared__ unsigned char tp[MAXB2 - 1][BW], tq[MAXB2 - 1][BW];
-  __shared__ int any_rot;
   __shared__ double redmax[JNT / 64];
   static_assert(JNT == BW * BW, "one 2x2 block per thread");
 
-  const int pair = blockIdx.x, chunk = blockIdx.y;
+  const int pair = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int bi, bj;
-  rr_pair(nblk, round, pair, bi, bj);
-  const int b2 = 2 * bw;
   const double thr = noise2 * result[5];
-  const double floor_n = sqrt(result[5] / (double)L);  // F / sqrt(L)
-
-  // Reduce partial Grams in a fixed order; pad to 32 x 32 with the identity.
+  const double floor2 = result[5] / (double)L;  // (F / sqrt(L))^2
+  const double tol2 = tol * tol;
+  // Reduce partial Grams in a fixed order.
+  const int64_t pstride = (int64_t)MAXB2 * MAXB2;
   for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
     const int i = e / MAXB2, j = e % MAXB2;
+    const double *src = part + (int64_t)pair * sw * pstride + e;
     double acc = 0.0;
-    if (i < b2 && j < b2) {
-      const double *src = part + (int64_t)pair * sw * b2 * b2 + i * b2 + j;
-      for (int s = 0; s < sw; ++s) acc += src[(int64_t)s * b2 * b2];
-    }
-    G[i][j] = acc;
+    for (int s = 0; s < sw; ++s) acc += src[s * pstride];
+    Gb[0][i][j] = acc;
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  if (tid == 0) any_rot = 0;
   __syncthreads();
 
   // Convergence measure of this visit (scaled off-diagonal, see the header).
-  if (chunk == 0) {
+  {
     double m = 0.0;
-    for (int e = tid; e < b2 * b2; e += JNT) {
-      const int p = e / b2, q = e % b2;
+    for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
+      const int p = e / MAXB2, q = e % MAXB2;
       if (p < q) {
-        const double gp = G[p][p], gq = G[q][q];
+        const double gp = Gb[0][p][p], gq = Gb[0][q][q];
         if (gp > thr || gq > thr) {
           const double a = sqrt(gp), b = sqrt(gq);
           const double lo = fmin(a, b);
-          m = fmax(m, fabs(G[p][q]) / (fmax(a, b) * (lo * lo > thr ? lo : floor_n)));
+          m = fmax(m, fabs(Gb[0][p][q]) / (fmax(a, b) * (lo * lo > thr ? lo : sqrt(floor2))));
         }
       }
     }
     m = wave_max(m);
     if (lane == 0) redmax[wave] = m;
     __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < JNT / 64; ++w) t = fmax(t, redmax[w]);
-      conv[(int64_t)round * (nblk / 2) + pair] = t;
+    m = 0.0;
+    for (int w = 0; w < JNT / 64; ++w) m = fmax(m, redmax[w]);
+    if (tid == 0) conv[(int64_t)round * (nblk / 2) + pair] = m;
+    // No pair above tolerance: the inner sweep would rotate nothing.
+    if (!(m > tol)) {
+      if (tid == 0) flag[pair] = 0;
+      return;
     }
   }
 
-  // One cyclic sweep of two-sided Jacobi over the 32 indices: 31 steps of
-  // 16 disjoint rotations (round-robin pairs from a table built here).
-  for (int e = tid; e < (MAXB2 - 1) * BW; e += JNT) {
-    const int st = e / BW, k = e % BW;
-    int p, q;
-    rr_pair(MAXB2, st, k, p, q);
-    tp[st][k] = (unsigned char)min(p, q);
-    tq[st][k] = (unsigned char)max(p, q);
-  }
-  const double tol2 = tol * tol, floor2 = floor_n * floor_n;
-  __syncthreads();
+  // One cyclic sweep of two-sided Jacobi over the 32 indices (31 steps).
+  const int u = tid >> 4, v = tid & 15;
+  int cur = 0;
   for (int step = 0; step < MAXB2 - 1; ++step) {
-    if (tid < BW) {
-      const int p = tp[step][tid], q = tq[step][tid];
-      const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
-      const double hi2 = fmax(gpp, gqq), lo2 = fmin(gpp, gqq);
-      double c = 1.0, sn = 0.0;
-      // |g_pq| > tol * hi * (lo^2 > thr ? lo : F/sqrt(L)), squared
-      if (hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2)) {
-        // tan of the rotation angle from zeta = (g_qq - g_pp) / (2 g_pq); the
-        // hardware reciprocal / rsqrt approximations are enough for t, and
-        // one Newton step on c makes c^2 + s^2 = 1 to rounding.
-        const double zeta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
-        const double az = fabs(zeta);
-        double t;
-        if (az > 1e100) {
-          t = 0.5 * __builtin_amdgcn_rcp(zeta);
-        } else {
-          const double w = 1.0 + zeta * zeta;
-          const double root = w * __builtin_amdgcn_rsq(w);
-          t = copysign(__builtin_amdgcn_rcp(az + root), zeta);
-        }
-        const double x = 1.0 + t * t;
-        double y = __builtin_amdgcn_rsq(x);
-        y = y * (1.5 - 0.5 * x * y * y);
-        y = y * (1.5 - 0.5 * x * y * y);
-        c = y;
-        sn = y * t;
-        any_rot = 1;
-      }
-      rc[tid] = c;
-      rs[tid] = sn;
-    }
-    __syncthreads();
-    {
-      // G <- J^T G J on 2 x 2 blocks: thread (u, v) owns rows {p_u, q_u} x
-      // cols {p_v, q_v}; 16 x 16 blocks = 256 threads.
-      const int u = tid >> 4, v = tid & 15;
-      const double su = rs[u], sv = rs[v];
-      if (su != 0.0 || sv != 0.0) {
-        const double cu = rc[u], cv = rc[v];
-        const int pu = tp[step][u], qu = tq[step][u], pv = tp[step][v], qv = tq[step][v];
-        const double g00 = G[pu][pv], g01 = G[pu][qv], g10 = G[qu][pv], g11 = G[qu][qv];
-        const double h00 = cu * g00 - su * g10, h01 = cu * g01 - su * g11;
-        const double h10 = su * g00 + cu * g10, h11 = su * g01 + cu * g11;
-        G[pu][pv] = cv * h00 - sv * h01;
-        G[pu][qv] = sv * h00 + cv * h01;
-        G[qu][pv] = cv * h10 - sv * h11;
-        G[qu][qv] = sv * h10 + cv * h11;
-      }
-      // Q <- Q J: row k = tid / 8, pairs 2 (tid % 8) and 2 (tid % 8) + 1
-      const int k = tid >> 3;
+    int pu, qu, pv, qv;
+    pair32(step, u, pu, qu);
+    pair32(step, v, pv, qv);
+    double (*Gc)[MAXB2 + 1] = Gb[cur];
+    double (*Gn)[MAXB2 + 1] = Gb[cur ^ 1];
+    double cu, su, cv, sv;
+    rot_params(Gc[pu][pu], Gc[qu][qu], Gc[pu][qu], thr, tol2, floor2, cu, su);
+    rot_params(Gc[pv][pv], Gc[qv][qv], Gc[pv][qv], thr, tol2, floor2, cv, sv);
+    const double g00 = Gc[pu][pv], g01 = Gc[pu][qv], g10 = Gc[qu][pv], g11 = Gc[qu][qv];
+    // rows (J_u^T), then columns (J_v)
+    const double h00 = cu * g00 - su * g10, h01 = cu * g01 - su * g11;
+    const double h10 = su * g00 + cu * g10, h11 = su * g01 + cu * g11;
+    Gn[pu][pv] = cv * h00 - sv * h01;
+    Gn[pu][qv] = sv * h00 + cv * h01;
+    Gn[qu][pv] = cv * h10 - sv * h11;
+    Gn[qu][qv] = sv * h10 + cv * h11;
+    // Q <- Q J_v on rows 2u, 2u + 1
+    if (sv != 0.0) {
       for (int h = 0; h < 2; ++h) {
-        const int w = 2 * (tid & 7) + h;
-        const double sw_ = rs[w];
-        if (sw_ != 0.0) {
-          const double cw = rc[w];
-          const int pw = tp[step][w], qw = tq[step][w];
-          const double q0 = Q[k][pw], q1 = Q[k][qw];
-          Q[k][pw] = cw * q0 - sw_ * q1;
-          Q[k][qw] = sw_ * q0 + cw * q1;
-        }
+        const int k = 2 * u + h;
+        const double q0 = Q[k][pv], q1 = Q[k][qv];
+        Q[k][pv] = cv * q0 - sv * q1;
+        Q[k][qv] = sv * q0 + cv * q1;
       }
     }
+    cur ^= 1;
     __syncthreads();
   }
-  if (!any_rot) return;  // Q = I: nothing to apply
 
   // One Newton-Schulz step, Q <- Q (3I - Q^T Q) / 2, restores orthogonality
   // to rounding level; without it the O(u) drift of every visit accumulates
@@ -336,31 +357,31 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
   {
     dbl4 acc = mfma_tile([&](int i, int k) { return Q[ti * 16 + i][k]; },
                          [&](int k, int j) { return S[k][tj * 16 + j]; }, MAXB2, lane);
-    __syncthreads();  // every wave has read Q before it is overwritten
     for (int t = 0; t < 4; ++t) {
       const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-      G[i][j] = 1.5 * Q[i][j] - 0.5 * acc[t];
+      qbuf[(int64_t)pair * MAXB2 * MAXB2 + i * MAXB2 + j] = 1.5 * Q[i][j] - 0.5 * acc[t];
     }
   }
-  __syncthreads();  // the re-orthogonalised rotation is now in G
+  if (tid == 0) flag[pair] = 1;
+}
 
-  // Apply to one row chunk of W (chunk < sw) or of V: P (rows x 32) <- P G.
-  double *X;
-  int ld, r0, nr;
-  if (chunk < sw) {
-    X = W; ld = L; r0 = chunk * ROWS_PER_WG; nr = min(ROWS_PER_WG, L - r0);
-  } else {
-    X = V; ld = ncp; r0 = (chunk - sw) * ROWS_PER_WG; nr = min(ROWS_PER_WG, ncp - r0);
-  }
-  if (nr <= 0) return;
+
+// Rotate one 128-row chunk of the pair's 32 columns of X (column-major, leading
+// dimension ld, nrows rows): P (rows x 32) <- P Q, Q from qsrc (32 x 32).
+__device__ void apply_chunk(double *__restrict__ X, int ld, int nrows, int chunk, int bi, int bj,
+                            const double *__restrict__ qsrc, double (*Qn)[MAXB2 + 1],
+                            double (*P)[MAXB2 + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, nrows - r0);
+  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) Qn[e / MAXB2][e % MAXB2] = qsrc[e];
   for (int e = tid; e < ROWS_PER_WG * MAXB2; e += JNT) {
     const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    double v = 0.0;
-    if (c < b2 && i < nr) {
-      const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
-      v = X[(int64_t)col * ld + r0 + i];
+    double val = 0.0;
+    if (i < nr) {
+      const int col = (c < BW) ? bi * BW + c : bj * BW + (c - BW);
+      val = X[(int64_t)col * ld + r0 + i];
     }
-    P[i][c] = v;
+    P[i][c] = val;
   }
   __syncthreads();
   // 8 x 2 output tiles of 16 x 16; wave w owns row tiles 2w, 2w+1.
@@ -369,20 +390,47 @@ __global__ __launch_bounds__(JNT) void jacobi_rotate_kernel(double *__restrict__
     const int rt = 2 * wave + x;
     for (int y = 0; y < 2; ++y)
       acc[x][y] = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
-                            [&](int k, int j) { return G[k][y * 16 + j]; }, MAXB2, lane);
+                            [&](int k, int j) { return Qn[k][y * 16 + j]; }, MAXB2, lane);
   }
   for (int x = 0; x < 2; ++x) {
     const int rt = 2 * wave + x;
     for (int y = 0; y < 2; ++y) {
       for (int t = 0; t < 4; ++t) {
         const int i = rt * 16 + 4 * t + (lane >> 4), c = y * 16 + (lane & 15);
-        if (i < nr && c < b2) {
-          const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
+        if (i < nr) {
+          const int col = (c < BW) ? bi * BW + c : bj * BW + (c - BW);
           X[(int64_t)col * ld + r0 + i] = acc[x][y][t];
         }
       }
     }
   }
+}
+
+// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
+// of W; V follows one round later inside the next solve launch.
+__global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
+                                                           const double *__restrict__ qbuf,
+                                                           const int *__restrict__ flag) {
+  __shared__ double Qn[MAXB2][MAXB2 + 1];
+  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
+  const int pair = blockIdx.x, chunk = blockIdx.y;
+  if (flag[pair] == 0) return;
+  int bi, bj;
+  rr_pair(nblk, round, pair, bi, bj);
+  apply_chunk(W, L, L, chunk, bi, bj, qbuf + (int64_t)pair * MAXB2 * MAXB2, Qn, P);
+}
+
+// grid (pairs, sv).  V by the rotations of the last round of a sweep.
+__global__ __launch_bounds__(JNT) void jacobi_vtail_kernel(double *__restrict__ V, int ncp, int nblk,
+                                                           int round, const double *__restrict__ qbuf,
+                                                           const int *__restrict__ flag) {
+  __shared__ double Qn[MAXB2][MAXB2 + 1];
+  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
+  const int pair = blockIdx.x, chunk = blockIdx.y;
+  if (flag[pair] == 0) return;
+  int bi, bj;
+  rr_pair(nblk, round, pair, bi, bj);
+  apply_chunk(V, ncp, ncp, chunk, bi, bj, qbuf + (int64_t)pair * MAXB2 * MAXB2, Qn, P);
 }
 
 __global__ void jacobi_convmax_kernel(const double *__restrict__ conv, int n, double *result) {
@@ -417,20 +465,39 @@ __global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restr
 
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer) {
-  if (2 * p.bw > MAXB2) return hipErrorInvalidValue;
   const double ns = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;
   const double noise2 = ns * ns;
+  // Two rotation buffers alternate between rounds: round r writes buffer
+  // r % 2 while its solve launch applies round r - 1 (the other buffer) to V.
+  const size_t qstride = (size_t)p.pairs * MAXB2 * MAXB2;
   for (int round = 0; round < p.rounds; ++round) {
+    double *qcur = b.qbuf + (round & 1) * qstride;
+    int *fcur = b.flag + (round & 1) * p.pairs;
+    const double *qprev = b.qbuf + ((round + 1) & 1) * qstride;
+    const int *fprev = b.flag + ((round + 1) & 1) * p.pairs;
     {
       Timed tm(timer, KC_JAC_GRAM, s);
       hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.bw,
                          p.nblk, round, b.part, p.sw);
     }
     {
-      Timed tm(timer, KC_JAC_ROTATE, s);
-      hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(p.pairs, p.sw + p.sv), dim3(JNT), 0, s, b.W, b.V,
-                         p.L, p.ncp, p.bw, p.nblk, round, b.part, p.sw, b.conv, tol, b.result, noise2);
+      Timed tm(timer, KC_JAC_SOLVE, s);
+      const int extra = round > 0 ? p.pairs * p.sv : 0;
+      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(p.pairs + extra), dim3(JNT), 0, s, p.L, p.nblk, round,
+                         b.part, p.sw, b.conv, tol, b.result, noise2, qcur, fcur, b.V, p.ncp, round - 1,
+                         qprev, fprev);
     }
+    {
+      Timed tm(timer, KC_JAC_APPLY, s);
+      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk,
+                         round, qcur, fcur);
+    }
+  }
+  {
+    Timed tm(timer, KC_JAC_APPLY, s);
+    const int last = p.rounds - 1;
+    hipLaunchKernelGGL(jacobi_vtail_kernel, dim3(p.pairs, p.sv), dim3(JNT), 0, s, b.V, p.ncp, p.nblk,
+                       last, b.qbuf + (last & 1) * qstride, b.flag + (last & 1) * p.pairs);
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
@@ -536,6 +603,44 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
                      b.perm);
   hipLaunchKernelGGL(jacobi_rank_kernel, dim3(1), dim3(1024), 0, s, b.sigma, b.perm, nc, eps, cap,
                      forced, b.result);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ column order
+// Wt[:, k] = W[:, perm[k]], Vt[:, k] = V[:, perm[k]] for k < ncp.
+__global__ void jacobi_gather_kernel(const double *__restrict__ W, const double *__restrict__ V,
+                                     const int *__restrict__ perm, int L, int ncp,
+                                     double *__restrict__ Wt, double *__restrict__ Vt) {
+  const int64_t nw = (int64_t)L * ncp, nv = (int64_t)ncp * ncp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw + nv;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nw) {
+      const int k = (int)(e / L), i = (int)(e % L);
+      Wt[e] = W[(int64_t)perm[k] * L + i];
+    } else {
+      const int64_t f = e - nw;
+      const int k = (int)(f / ncp), i = (int)(f % ncp);
+      Vt[f] = V[(int64_t)perm[k] * ncp + i];
+    }
+  }
+}
+
+hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStream_t s) {
+  // De Rijk-style ordering: before each sweep the columns are sorted by
+  // decreasing norm, so large columns meet each other first.  Zero padding
+  // columns sort last.
+  const int n = p.ncp;
+  hipLaunchKernelGGL(jacobi_sigma_kernel, dim3((n + 3) / 4), dim3(JNT), 0, s, b.W, p.L, n, b.sigma);
+  const size_t shm = (size_t)n * sizeof(double);
+  if (shm > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + JNT - 1) / JNT), dim3(JNT), shm, s, b.sigma, n, b.perm);
+  const int64_t tot = (int64_t)p.L * n + (int64_t)n * n;
+  int64_t g = (tot + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(jacobi_gather_kernel, dim3((int)g), dim3(256), 0, s, b.W, b.V, b.perm, p.L, n, b.Wt,
+                     b.Vt);
+  double *t = b.W; b.W = b.Wt; b.Wt = t;
+  t = b.V; b.V = b.Vt; b.Vt = t;
   return hipGetLastError();
 }
 

@@ -382,7 +382,7 @@ struct Runner {
     int r = -1;
     double disc = 0.0, total = 0.0;
   };
-  SvdOut jacobi(const JacobiPlan &jp, const JacobiBufs &jb, double eps, int cap) {
+  SvdOut jacobi(const JacobiPlan &jp, JacobiBufs &jb, double eps, int cap) {
     SvdOut out;
     int forced = 0;
     if (o.forced) {
@@ -407,6 +407,10 @@ struct Runner {
     bool ok = false;
     double host_res[8];
     for (int sw = 0; sw < o.svd_max_sweeps; ++sw) {
+      {
+        Timed tm(&timer, KC_JAC_OTHER, st);
+        if (!hip(launch_jacobi_sort_columns(jp, jb, st))) return out;
+      }
       if (!hip(launch_jacobi_sweep(jp, jb, tol, st, &timer))) return out;
       ++sweeps;
       if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
@@ -466,9 +470,13 @@ struct Runner {
       return q;
     };
     b.W = adv((size_t)jp.L * jp.ncp);
+    b.Wt = adv((size_t)jp.L * jp.ncp);
     b.V = adv((size_t)jp.ncp * jp.ncp);
+    b.Vt = adv((size_t)jp.ncp * jp.ncp);
     b.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
     b.conv = adv((size_t)jp.rounds * jp.pairs);
+    b.qbuf = adv(2 * (size_t)jp.pairs * 32 * 32);
+    b.flag = reinterpret_cast<int *>(adv(2 * (size_t)jp.pairs));
     b.sigma = adv((size_t)jp.ncp);
     b.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
     b.result = adv(8);

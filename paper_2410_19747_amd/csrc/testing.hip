@@ -22,9 +22,13 @@ JacobiBufs carve_test(double *base, const JacobiPlan &jp) {
     return q;
   };
   b.W = adv((size_t)jp.L * jp.ncp);
+  b.Wt = adv((size_t)jp.L * jp.ncp);
   b.V = adv((size_t)jp.ncp * jp.ncp);
+  b.Vt = adv((size_t)jp.ncp * jp.ncp);
   b.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
   b.conv = adv((size_t)jp.rounds * jp.pairs);
+  b.qbuf = adv(2 * (size_t)jp.pairs * 32 * 32);
+  b.flag = reinterpret_cast<int *>(adv(2 * (size_t)jp.pairs));
   b.sigma = adv((size_t)jp.ncp);
   b.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
   b.result = adv(8);
@@ -89,6 +93,7 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
   bool ok = false;
   double prev = INFINITY;
   for (; sw < 60;) {
+    if (ttm::launch_jacobi_sort_columns(jp, jb, s) != hipSuccess) return TTM_EHIP;
     if (ttm::launch_jacobi_sweep(jp, jb, tol, s) != hipSuccess) return TTM_EHIP;
     ++sw;
     if (hipMemcpyAsync(res, jb.result, sizeof(res), hipMemcpyDeviceToHost, s) != hipSuccess) return TTM_EHIP;

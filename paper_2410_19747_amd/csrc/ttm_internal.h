@@ -20,10 +20,11 @@ enum KernelClass {
   KC_GEMM = 0,
   KC_QR = 1,
   KC_JAC_GRAM = 2,
-  KC_JAC_ROTATE = 3,
+  KC_JAC_SOLVE = 3,
   KC_JAC_OTHER = 4,
   KC_OTHER = 5,
-  KC_COUNT = 6
+  KC_JAC_APPLY = 6,
+  KC_COUNT = 7
 };
 struct KernelTimer {
   bool on = false;
@@ -124,10 +125,14 @@ size_t jacobi_ws_doubles(const JacobiPlan &p);
 struct JacobiBufs {
   double *W = nullptr;      // L x ncp (column-major)
   double *V = nullptr;      // ncp x ncp
+  double *Wt = nullptr;     // reordering buffers (swapped with W, V)
+  double *Vt = nullptr;
   double *part = nullptr;   // pairs * sw * (2bw)^2 partial Grams
   double *conv = nullptr;   // rounds * pairs: scaled off-diagonal maxima
   double *sigma = nullptr;  // ncp
   int *perm = nullptr;      // ncp: perm[k] = column index of the k-th largest value
+  double *qbuf = nullptr;   // 2 * pairs * 32 * 32: rotations of two consecutive rounds
+  int *flag = nullptr;      // 2 * pairs: rotation is not the identity
   double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,[5]=squared Frobenius norm of W
 };
 
@@ -137,6 +142,8 @@ hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStrea
 // off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer = nullptr);
+// Reorder the columns of W and V by decreasing norm (swaps W/Wt, V/Vt).
+hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStream_t s);
 // Column norms, descending order, and the rank rule of Eq. (eps):
 // r = min{k>=1 : tail_k < eps*total or tail_k == 0}, then min(r, cap) when
 // cap > 0; forced > 0 replaces the rule.  Writes result[0..2].
