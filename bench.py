@@ -33,6 +33,21 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile,
+    or None when the kernel source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "jacobi_solve_traffic_turbulence256_chi128.json")
+    try:
+        prof = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2410_19747_amd", "csrc", "kernels_svd.hip"), "rb").read()
+    except OSError:
+        return None
+    if prof.get("kernel") != kernel or prof.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(prof["traffic_bytes_per_dispatch"])
+
+
 def _cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -54,6 +69,8 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -71,6 +88,14 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+
+    if args.calibrate_copy:
+        # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     _log("generating inputs: %d^3 turbulence, chi=%d" % (args.grid, args.chi))
     t0 = time.time()
@@ -137,12 +162,14 @@ def main():
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": _measured_traffic("jacobi_solve_kernel"),
             "launches_per_step": rot_n / args.steps,
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_flops_per_launch": flops_per_launch,
             "profiled_ms_per_step": 1e3 * tp / args.steps,
         }
+        if roofline["traffic"] is not None:
+            roofline["traffic_gbs"] = roofline["traffic"] / avg_launch_s / 1e9
         kernel_share = {k: sum(s["kernel_ms"][k] for s in pstats) / tot_ms for k in st["kernel_ms"]}
 
     rel_err = None
