@@ -33,12 +33,15 @@ int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs,
 size_t ttm_test_qr_scratch(int m, int n);
 int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scratch, void *stream);
 
-/* Truncated SVD of the m x n row-major matrix M (device) by the one-sided
- * block Jacobi kernels and the rule of Eq. (eps) (cap > 0 caps the rank,
- * forced > 0 replaces the rule).  Writes left = U_r diag(s)^left_pow (m x r)
- * and right = diag(s)^right_pow V_r^T (r x n), both row-major, the sorted
- * singular values (min(m,n) doubles, device) and, on the host, the rank and
- * the number of sweeps.  ws: device, ttm_test_svd_ws_bytes(m, n) bytes. */
+/* Truncated SVD of the m x n row-major matrix M (device) by the swap's SVD
+ * path (column ordering, Householder QR, one-sided block Jacobi on R^T) and
+ * the rule of Eq. (eps) (cap > 0 caps the rank, forced > 0 replaces the
+ * rule).  Writes left = U_r diag(s)^left_pow (m x r) and
+ * right = diag(s)^right_pow V_r^T (r x n), both row-major, with exactly one
+ * of left_pow, right_pow equal to 1 (the other factor is the orthonormal
+ * one), the sorted singular values (min(m,n) doubles, device) and, on the
+ * host, the rank and the number of sweeps.  ws: device,
+ * ttm_test_svd_ws_bytes(m, n) bytes.  Returns TTM_EINVAL for other powers. */
 size_t ttm_test_svd_ws_bytes(int m, int n);
 int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
                  int right_pow, double *left, double *right, double *sigma, int *rank,

@@ -1,0 +1,417 @@
+// Blocked Householder QR (the geqrf / orgqr structure of LAPACK).
+//
+// Panels of QB = 16 columns are factored by one 1024-thread workgroup; the
+// panel's reflectors H_0 ... H_15 are combined into the compact-WY block
+// reflector I - V T V^T (T upper triangular, built column by column while the
+// panel is factored), and the block reflector is applied to the trailing
+// columns (and, when Q is wanted, to the identity) by one fused kernel whose
+// two 16-wide products run on FP64 MFMA.
+//
+// Panel layout: thread (wave w, lane l) owns column l & 15 of the panel at
+// the rows 64 s + 4 w + (l >> 4), s = 0 .. SL-1, in registers.  Every
+// reduction over rows is then a per-lane sum, two shuffles across the four
+// row groups of a wave and one LDS exchange across the 16 waves, and it
+// yields the sums of all 16 columns at once: one pass gives v^T x for every
+// trailing column of the panel and V^T v for the T recurrence.
+#include "ttm_internal.h"
+
+namespace ttm {
+namespace {
+constexpr int QB = 16;              // panel width
+constexpr int PNT = 1024;           // threads of a panel workgroup
+constexpr int UNT = 256;            // threads of an update workgroup
+constexpr int MAX_REG_SLOTS = 16;   // register panels cover up to 64 * 16 rows
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) t += red[w];  // fixed order: every thread gets the same sum
+  return t;
+}
+}  // namespace
+
+// S[i + j*m] = M[i*rs + j*cs]
+__global__ void strided_to_colmajor_kernel(double *__restrict__ S, const double *__restrict__ M, int m, int n,
+                                           int64_t rs, int64_t cs) {
+  const int64_t tot = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    S[e] = M[(int64_t)i * rs + (int64_t)j * cs];
+  }
+}
+
+// Factor columns j0 .. j0+jb-1 of S (column-major, ld m) in place, rows
+// j0 .. m-1 (mv = m - j0 <= 64 * SL).  Each reflector is H = I - tau v v^T
+// with v(pivot) = 1 (LAPACK dlarfg convention); R goes on and above the
+// diagonal, v below it.  Also writes the explicit V (mv x 16, column-major,
+// unit diagonal, zero above and in columns >= jb) and T (16 x 16, row-major,
+// zero outside the leading jb x jb upper triangle) with
+// H_0 H_1 ... H_{jb-1} = I - V T V^T.
+template <int SL>
+__global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ S, int m, int j0, int jb,
+                                                           double *__restrict__ Vb, double *__restrict__ T) {
+  __shared__ double red[2][16][QB];
+  __shared__ double Ts[QB][QB + 1];
+  __shared__ double sh_alpha;
+  constexpr bool kCache = SL <= 8;  // keep v in registers while they fit beside x
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int mv = m - j0;
+  double x[SL];
+  double vt[kCache ? SL : 1];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int i = 64 * s + 4 * w + g;
+    x[s] = (i < mv && c < jb) ? S[(int64_t)(j0 + c) * m + j0 + i] : 0.0;
+  }
+  for (int cc = 0; cc < jb; ++cc) {
+    const int src = (g << 4) | cc;  // lane holding column cc of this lane's rows
+    // Squared norm of every column below row cc, and the pivot x(cc, cc).
+    double p = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = 64 * s + 4 * w + g;
+      p = (i > cc) ? fma(x[s], x[s], p) : p;
+    }
+    p += __shfl_xor(p, 16, 64);
+    p += __shfl_xor(p, 32, 64);
+    if (g == 0) red[0][w][c] = p;
+    if (c == cc && 4 * w + g == cc) sh_alpha = x[0];
+    __syncthreads();
+    double xnorm2 = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 16; ++ww) xnorm2 += red[0][ww][cc];
+    const double alpha = sh_alpha;
+    double tau = 0.0, scale = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // Reflector v (1 at row cc, x / (alpha - beta) below) into column cc, and
+    // the partial sums of v^T x for every column of the panel.
+    double q = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = 64 * s + 4 * w + g;
+      const double xv = __shfl(x[s], src, 64);
+      const double v = (i > cc) ? xv * scale : (i == cc ? 1.0 : 0.0);
+      if (kCache) vt[s] = v;
+      q = fma(v, x[s], q);
+      if (c == cc) x[s] = (i > cc) ? v : (i == cc ? beta : x[s]);
+    }
+    q += __shfl_xor(q, 16, 64);
+    q += __shfl_xor(q, 32, 64);
+    if (g == 0) red[1][w][c] = q;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 16; ++ww) tot += red[1][ww][c];
+    // Columns right of cc: x <- x - tau (v^T x) v.  Columns left of cc hold
+    // earlier reflectors; their sums are V(:, 0:cc)^T v for T.
+    const double f = (c > cc) ? tau * tot : 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      double v;
+      if (kCache) {
+        v = vt[s];
+      } else {
+        const int i = 64 * s + 4 * w + g;
+        const double xv = __shfl(x[s], src, 64);
+        v = (i > cc) ? xv : (i == cc ? 1.0 : 0.0);
+      }
+      x[s] = fma(-f, v, x[s]);
+    }
+    // T(0:cc, cc) = -tau T(0:cc, 0:cc) (V(:, 0:cc)^T v), T(cc, cc) = tau.
+    // Lane a of wave 0 owns row a of T.
+    if (w == 0) {
+      double acc = 0.0;
+      for (int b = 0; b < cc; ++b) {
+        const double zb = __shfl(tot, b, 64);
+        if (g == 0 && b >= c) acc = fma(Ts[c][b], zb, acc);
+      }
+      if (g == 0 && c < cc) Ts[c][cc] = -tau * acc;
+      if (g == 0 && c == cc) Ts[cc][cc] = tau;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int i = 64 * s + 4 * w + g;
+    if (i < mv) {
+      if (c < jb) S[(int64_t)(j0 + c) * m + j0 + i] = x[s];
+      Vb[(int64_t)c * mv + i] = (c < jb && i >= c) ? (i == c ? 1.0 : x[s]) : 0.0;
+    }
+  }
+  if (w == 0 && g == 0) {
+    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb && b >= c) ? Ts[c][b] : 0.0;
+  }
+}
+
+// The same factorisation for panels taller than the register panels: the
+// columns stay in memory and one wave updates one trailing column.
+__global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int j0, int jb,
+                                                           double *__restrict__ Vb, double *__restrict__ T) {
+  __shared__ double red[PNT / 64];
+  __shared__ double Y[QB][QB + 1];
+  __shared__ double Tl[QB][QB + 1];
+  __shared__ double tl[QB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mv = m - j0;
+  for (int j = j0; j < j0 + jb; ++j) {
+    double *col = S + (int64_t)j * m;
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += PNT) part += col[i] * col[i];
+    const double xnorm2 = block_sum(part, red);
+    const double alpha = col[j];
+    double t = 0.0, scale = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (xnorm2 > 0.0)
+      for (int i = j + 1 + tid; i < m; i += PNT) col[i] *= scale;
+    if (tid == 0) {
+      col[j] = beta;
+      tl[j - j0] = t;
+    }
+    __syncthreads();
+    if (t != 0.0) {
+      for (int c = j + 1 + wave; c < j0 + jb; c += PNT / 64) {
+        double *x = S + (int64_t)c * m;
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w += col[i] * x[i];
+        w = wave_sum(w) + x[j];
+        const double tw = t * w;
+        if (lane == 0) x[j] -= tw;
+        for (int i = j + 1 + lane; i < m; i += 64) x[i] -= tw * col[i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)mv * QB; e += PNT) {
+    const int i = (int)(e % mv), c = (int)(e / mv);
+    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : S[(int64_t)(j0 + c) * m + j0 + i]) : 0.0;
+  }
+  __syncthreads();
+  {  // Y = V^T V: 4 threads per entry, rows split four ways
+    const int ent = tid >> 2, quarter = tid & 3;
+    const int a = ent / QB, b = ent % QB;
+    double acc = 0.0;
+    if (a < jb && b < jb) {
+      const double *va = Vb + (int64_t)a * mv, *vb = Vb + (int64_t)b * mv;
+      for (int i = quarter; i < mv; i += 4) acc += va[i] * vb[i];
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (quarter == 0 && a < jb && b < jb) Y[a][b] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < QB; ++i)
+      for (int r = 0; r < QB; ++r) Tl[r][i] = 0.0;
+    for (int i = 0; i < jb; ++i) {
+      const double ti = tl[i];
+      Tl[i][i] = ti;
+      for (int r = 0; r < i; ++r) {
+        double acc = 0.0;
+        for (int c = r; c < i; ++c) acc += Tl[r][c] * Y[c][i];
+        Tl[r][i] = -ti * acc;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < QB * QB; e += PNT) T[e] = Tl[e / QB][e % QB];
+}
+
+// A <- (I - V op(T) V^T) A for the rows j0 .. m-1 of columns c0 .. c0+nc-1
+// of the column-major S (ld m), with op(T) = T^T when `trans` (applying
+// Q^T: the trailing update of the factorisation) and T otherwise (forming
+// Q).  V: mv x 16 column-major, T: 16 x 16 row-major, both zero-padded.
+// One workgroup per 16 columns:
+//   W1 = V^T A (MFMA, the four waves split the rows), W2 = op(T) W1,
+//   A^T -= W2^T V^T (MFMA; the lanes of a row group write 16 consecutive
+//   rows of one column).
+__global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, int m, int j0, int c0, int nc,
+                                                        const double *__restrict__ Vb,
+                                                        const double *__restrict__ T, int trans) {
+  __shared__ double Wp[4][QB][QB + 1];
+  __shared__ double W2[QB][QB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mv = m - j0;
+  const int cb = c0 + QB * blockIdx.x;
+  const int ncol = min(QB, c0 + nc - cb);
+  double *A = S + (int64_t)cb * m + j0;  // A(i, j) = A[j * m + i]
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 4 * w; k0 < mv; k0 += 16) {
+    const int kk = k0 + q4;
+    const double va = (kk < mv) ? Vb[(int64_t)r16 * mv + kk] : 0.0;
+    const double ab = (kk < mv && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ab, acc, 0, 0, 0);
+  }
+  for (int t = 0; t < 4; ++t) Wp[w][4 * t + q4][r16] = acc[t];
+  __syncthreads();
+  const int ti = tid >> 4, tj = tid & 15;
+  Wp[0][ti][tj] = (Wp[0][ti][tj] + Wp[1][ti][tj]) + (Wp[2][ti][tj] + Wp[3][ti][tj]);
+  __syncthreads();
+  {
+    double s = 0.0;
+    for (int b = 0; b < QB; ++b) s = fma(trans ? T[b * QB + ti] : T[ti * QB + b], Wp[0][b][tj], s);
+    W2[ti][tj] = s;
+  }
+  __syncthreads();
+  const double wa0 = W2[q4][r16], wa1 = W2[4 + q4][r16], wa2 = W2[8 + q4][r16], wa3 = W2[12 + q4][r16];
+  for (int i0 = 16 * w; i0 < mv; i0 += 64) {
+    const int r = i0 + r16;
+    const bool ok = r < mv;
+    dbl4 d = {0.0, 0.0, 0.0, 0.0};
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, ok ? Vb[(int64_t)q4 * mv + r] : 0.0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa1, ok ? Vb[(int64_t)(4 + q4) * mv + r] : 0.0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa2, ok ? Vb[(int64_t)(8 + q4) * mv + r] : 0.0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa3, ok ? Vb[(int64_t)(12 + q4) * mv + r] : 0.0, d, 0, 0, 0);
+    if (ok) {
+      for (int t = 0; t < 4; ++t) {
+        const int col = 4 * t + q4;
+        if (col < ncol) A[(int64_t)col * m + r] -= d[t];
+      }
+    }
+  }
+}
+
+// R (k x n, row-major) = upper triangle of S[0:k, :]; Qs = first k columns of I.
+__global__ void qr_r_and_identity_kernel(const double *__restrict__ S, int m, int n, int k,
+                                         double *__restrict__ r, double *__restrict__ Qs) {
+  const int64_t nr = (int64_t)k * n, nq = (int64_t)m * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nr + nq;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nr) {
+      const int i = (int)(e / n), c = (int)(e % n);
+      r[e] = (c >= i) ? S[(int64_t)c * m + i] : 0.0;
+    } else {
+      const int64_t f = e - nr;
+      const int i = (int)(f % m), c = (int)(f / m);
+      Qs[f] = (i == c) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// Explicit V of the panel starting at column j0 (rows j0..m-1, 16 columns,
+// zero-padded) rebuilt from the factored S.
+__global__ void qr_extract_v_kernel(const double *__restrict__ S, int m, int j0, int jb,
+                                    double *__restrict__ Vb) {
+  const int mv = m - j0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)mv * QB;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mv), c = (int)(e / mv);
+    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : S[(int64_t)(j0 + c) * m + j0 + i]) : 0.0;
+  }
+}
+
+namespace {
+hipError_t launch_panel(double *S, int m, int j0, int jb, double *Vb, double *T, hipStream_t s) {
+  const int sl = (m - j0 + 63) / 64;
+  const dim3 g(1), b(PNT);
+  if (sl <= 1) hipLaunchKernelGGL(qr_panel_reg_kernel<1>, g, b, 0, s, S, m, j0, jb, Vb, T);
+  else if (sl <= 2) hipLaunchKernelGGL(qr_panel_reg_kernel<2>, g, b, 0, s, S, m, j0, jb, Vb, T);
+  else if (sl <= 4) hipLaunchKernelGGL(qr_panel_reg_kernel<4>, g, b, 0, s, S, m, j0, jb, Vb, T);
+  else if (sl <= 8) hipLaunchKernelGGL(qr_panel_reg_kernel<8>, g, b, 0, s, S, m, j0, jb, Vb, T);
+  else if (sl <= MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_reg_kernel<16>, g, b, 0, s, S, m, j0, jb, Vb, T);
+  else hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, S, m, j0, jb, Vb, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(double *S, int m, int j0, int c0, int nc, const double *Vb, const double *T,
+                         int trans, hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qr_update_kernel, dim3((nc + QB - 1) / QB), dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T,
+                     trans);
+  return hipGetLastError();
+}
+}  // namespace
+
+size_t qr_inplace_scratch_doubles(int m) { return (size_t)m * QB + QB * QB + 64; }
+
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipErrorInvalidValue;
+  const int k = m < n ? m : n;
+  double *Vb = scratch;
+  double *T = scratch + (((size_t)m * QB + 31) & ~(size_t)31);
+  for (int j0 = 0; j0 < k; j0 += QB) {
+    const int jb = (k - j0) < QB ? (k - j0) : QB;
+    hipError_t e = launch_panel(S, m, j0, jb, Vb, T, s);
+    if (e != hipSuccess) return e;
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t qr_scratch_doubles(int m, int n) {
+  const int k = m < n ? m : n;
+  const int np = (k + QB - 1) / QB;
+  size_t t = 0;
+  t += (size_t)m * n;          // S
+  t += (size_t)m * QB;         // Vb
+  t += (size_t)np * QB * QB;   // T per panel
+  t += (size_t)m * k;          // Qs
+  return t + 4 * 32;
+}
+
+hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
+                     double *scratch, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipErrorInvalidValue;
+  const int k = m < n ? m : n;
+  const int np = (k + QB - 1) / QB;
+  double *p = scratch;
+  auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
+  double *S = adv((size_t)m * n);
+  double *Vb = adv((size_t)m * QB);
+  double *Tall = adv((size_t)np * QB * QB);
+  double *Qs = adv((size_t)m * k);
+  const int64_t tot = (int64_t)m * n;
+  hipLaunchKernelGGL(strided_to_colmajor_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, S, M, m, n, rs, cs);
+  for (int pi = 0; pi < np; ++pi) {
+    const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
+    double *T = Tall + (size_t)pi * QB * QB;
+    hipError_t e = launch_panel(S, m, j0, jb, Vb, T, s);
+    if (e != hipSuccess) return e;
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(qr_r_and_identity_kernel, dim3(grid_for((int64_t)k * n + (int64_t)m * k, 256)), dim3(256),
+                     0, s, S, m, n, k, r, Qs);
+  // Q = H_0 ... H_{np-1} applied to [I_k; 0], panels in reverse order.
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
+    hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
+                       j0, jb, Vb);
+    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  // q (m x k, row-major) from Qs (column-major)
+  return launch_transpose(q, Qs, k, m, s);
+}
+
+}  // namespace ttm

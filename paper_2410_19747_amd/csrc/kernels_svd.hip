@@ -2,21 +2,25 @@
 //
 // The Swap of Sec. II.B needs the full singular spectrum of each unfolded
 // pair (the rule of Eq. (eps) sums the discarded weight from the smallest
-// value up) and the leading singular vectors.  One-sided Jacobi
-// orthogonalises the columns of W = Theta (or Theta^T) by plane rotations
-// accumulated in V; at convergence W = U S and the column norms are the
-// singular values, with high relative accuracy.
+// value up) and the leading singular vectors on the side that must come out
+// orthonormal.  One-sided Jacobi orthogonalises the columns of an L x nc
+// matrix W by plane rotations; at convergence W = U S, so the normalised
+// columns are orthonormal singular vectors over W's row index and the column
+// norms are the singular values, with high relative accuracy.  The rotations
+// themselves are not accumulated: the driver (svd.hip) arranges W so that
+// its rows index the orthonormal side and recovers the other factor with one
+// product.
 //
 // Blocked form: the columns are split into blocks of width bw; a sweep is a
 // round-robin tournament over blocks, every round pairing all blocks at once.
 // For a pair (I, J) the 2bw x 2bw Gram matrix G = [W_I W_J]^T [W_I W_J] is
-// formed from row chunks (kernel 1, partial sums in the workspace), then
-// every workgroup of the pair reduces the partials in a fixed order,
-// diagonalises G by cyclic two-sided Jacobi in LDS (identically, so the
-// result is deterministic) and applies the accumulated rotation Q to its row
-// chunk of W or V (kernel 2).  A rotation is applied only where
-// |g_pq| > tol sqrt(g_pp g_qq); a sweep in which no pair exceeds tol means
-// the columns are orthogonal to working accuracy.
+// formed from row chunks (partial sums in the workspace); one workgroup per
+// pair reduces the partials in a fixed order and diagonalises G by one
+// cyclic sweep of two-sided Jacobi in LDS, and the accumulated 2bw x 2bw
+// rotation is applied to the pair's columns of W by a third kernel.  A
+// rotation is applied only where |g_pq| > tol sqrt(g_pp g_qq); a sweep in
+// which no pair exceeds tol means the columns are orthogonal to working
+// accuracy.
 //
 // Accuracy target: that of a backward-stable FP64 SVD (errors of order
 // u ||Theta||).  With column norms a_p, a_q (hi = max, lo = min),
@@ -77,7 +81,6 @@ JacobiPlan jacobi_plan(int L, int nc) {
   p.ncp = nblk * bw;
   p.rows_per_wg = ROWS_PER_WG;
   p.sw = (L + ROWS_PER_WG - 1) / ROWS_PER_WG;
-  p.sv = (p.ncp + ROWS_PER_WG - 1) / ROWS_PER_WG;
   p.rounds = nblk - 1;
   p.pairs = nblk / 2;
   return p;
@@ -87,44 +90,14 @@ size_t jacobi_ws_doubles(const JacobiPlan &p) {
   const size_t b2 = 2 * (size_t)p.bw;
   size_t n = 0;
   n += 2 * (size_t)p.L * p.ncp;           // W and its reordering buffer
-  n += 2 * (size_t)p.ncp * p.ncp;         // V and its reordering buffer
   n += (size_t)p.pairs * p.sw * b2 * b2;  // partial Grams
   n += (size_t)p.rounds * p.pairs;        // conv
-  n += 2 * (size_t)p.pairs * MAXB2 * MAXB2;  // rotations of two rounds
-  n += 2 * (size_t)p.pairs;                  // rotation flags (ints)
+  n += (size_t)p.pairs * MAXB2 * MAXB2;   // rotations of the current round
+  n += (size_t)p.pairs;                   // rotation flags (ints)
   n += (size_t)p.ncp;                     // sigma
   n += (size_t)p.ncp;                     // perm (ints, padded as doubles)
   n += 8;                                 // result
-  return n + 12 * 32;                     // each of the 11 regions is rounded up to 32 doubles
-}
-
-__global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restrict__ W, int64_t n,
-                                                           double *__restrict__ result);
-
-// ------------------------------------------------------------------ init
-__global__ void jacobi_init_kernel(double *W, double *V, int L, int nc, int ncp) {
-  const int64_t nw = (int64_t)L * (ncp - nc);
-  const int64_t nv = (int64_t)ncp * ncp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw + nv;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    if (e < nw) {
-      W[(int64_t)L * nc + e] = 0.0;
-    } else {
-      const int64_t v = e - nw;
-      const int64_t i = v % ncp, j = v / ncp;
-      V[v] = (i == j) ? 1.0 : 0.0;
-    }
-  }
-}
-
-hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStream_t s) {
-  const int64_t n = (int64_t)p.L * (p.ncp - p.nc) + (int64_t)p.ncp * p.ncp;
-  int64_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(jacobi_init_kernel, dim3((int)g), dim3(256), 0, s, b.W, b.V, p.L, p.nc, p.ncp);
-  hipLaunchKernelGGL(jacobi_frob_kernel, dim3(1), dim3(1024), 0, s, b.W, (int64_t)p.L * p.nc, b.result);
-  return hipGetLastError();
+  return n + 9 * 32;                      // each of the 9 regions is rounded up to 32 doubles
 }
 
 // ------------------------------------------------------------------ MFMA helpers
@@ -234,32 +207,12 @@ __device__ __forceinline__ void pair32(int st, int k, int &p, int &q) {
 // identity).  A step rotates 16 disjoint index pairs at once; G <- J^T G J
 // splits into independent 2 x 2 blocks, one per thread, read from one copy of
 // G and written to the other, so a step needs a single barrier.
-__device__ void apply_chunk(double *__restrict__ X, int ld, int nrows, int chunk, int bi, int bj,
-                            const double *__restrict__ qsrc, double (*Qn)[MAXB2 + 1],
-                            double (*P)[MAXB2 + 1]);
-
 __global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int round,
                                                            const double *__restrict__ part, int sw,
                                                            double *__restrict__ conv, double tol,
                                                            const double *__restrict__ result,
                                                            double noise2, double *__restrict__ qbuf,
-                                                           int *__restrict__ flag, double *__restrict__ V,
-                                                           int ncp, int vround,
-                                                           const double *__restrict__ qprev,
-                                                           const int *__restrict__ fprev) {
-  // Workgroups past the first `pairs` rotate V by the previous round's
-  // rotations (independent of this round's solve, so it overlaps it).
-  if ((int)blockIdx.x >= nblk / 2) {
-    __shared__ double Qv[MAXB2][MAXB2 + 1];
-    __shared__ double Pv[ROWS_PER_WG][MAXB2 + 1];
-    const int e = blockIdx.x - nblk / 2;
-    const int vp = e % (nblk / 2), chunk = e / (nblk / 2);
-    if (fprev[vp] == 0) return;
-    int vi, vj;
-    rr_pair(nblk, vround, vp, vi, vj);
-    apply_chunk(V, ncp, ncp, chunk, vi, vj, qprev + (int64_t)vp * MAXB2 * MAXB2, Qv, Pv);
-    return;
-  }
+                                                           int *__restrict__ flag) {
   __shared__ double Gb[2][MAXB2][MAXB2 + 1];
   __shared__ double Q[MAXB2][MAXB2 + 1];
   __shared__ double S[MAXB2][MAXB2 + 1];
@@ -407,7 +360,7 @@ __device__ void apply_chunk(double *__restrict__ X, int ld, int nrows, int chunk
 }
 
 // grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
-// of W; V follows one round later inside the next solve launch.
+// of W.
 __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
                                                            const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
@@ -418,19 +371,6 @@ __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ 
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
   apply_chunk(W, L, L, chunk, bi, bj, qbuf + (int64_t)pair * MAXB2 * MAXB2, Qn, P);
-}
-
-// grid (pairs, sv).  V by the rotations of the last round of a sweep.
-__global__ __launch_bounds__(JNT) void jacobi_vtail_kernel(double *__restrict__ V, int ncp, int nblk,
-                                                           int round, const double *__restrict__ qbuf,
-                                                           const int *__restrict__ flag) {
-  __shared__ double Qn[MAXB2][MAXB2 + 1];
-  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
-  const int pair = blockIdx.x, chunk = blockIdx.y;
-  if (flag[pair] == 0) return;
-  int bi, bj;
-  rr_pair(nblk, round, pair, bi, bj);
-  apply_chunk(V, ncp, ncp, chunk, bi, bj, qbuf + (int64_t)pair * MAXB2 * MAXB2, Qn, P);
 }
 
 __global__ void jacobi_convmax_kernel(const double *__restrict__ conv, int n, double *result) {
@@ -467,14 +407,7 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
                                KernelTimer *timer) {
   const double ns = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;
   const double noise2 = ns * ns;
-  // Two rotation buffers alternate between rounds: round r writes buffer
-  // r % 2 while its solve launch applies round r - 1 (the other buffer) to V.
-  const size_t qstride = (size_t)p.pairs * MAXB2 * MAXB2;
   for (int round = 0; round < p.rounds; ++round) {
-    double *qcur = b.qbuf + (round & 1) * qstride;
-    int *fcur = b.flag + (round & 1) * p.pairs;
-    const double *qprev = b.qbuf + ((round + 1) & 1) * qstride;
-    const int *fprev = b.flag + ((round + 1) & 1) * p.pairs;
     {
       Timed tm(timer, KC_JAC_GRAM, s);
       hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.bw,
@@ -482,22 +415,14 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
     }
     {
       Timed tm(timer, KC_JAC_SOLVE, s);
-      const int extra = round > 0 ? p.pairs * p.sv : 0;
-      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(p.pairs + extra), dim3(JNT), 0, s, p.L, p.nblk, round,
-                         b.part, p.sw, b.conv, tol, b.result, noise2, qcur, fcur, b.V, p.ncp, round - 1,
-                         qprev, fprev);
+      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(p.pairs), dim3(JNT), 0, s, p.L, p.nblk, round, b.part,
+                         p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
     }
     {
       Timed tm(timer, KC_JAC_APPLY, s);
       hipLaunchKernelGGL(jacobi_apply_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk,
-                         round, qcur, fcur);
+                         round, b.qbuf, b.flag);
     }
-  }
-  {
-    Timed tm(timer, KC_JAC_APPLY, s);
-    const int last = p.rounds - 1;
-    hipLaunchKernelGGL(jacobi_vtail_kernel, dim3(p.pairs, p.sv), dim3(JNT), 0, s, b.V, p.ncp, p.nblk,
-                       last, b.qbuf + (last & 1) * qstride, b.flag + (last & 1) * p.pairs);
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
@@ -607,22 +532,37 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
 }
 
 // ------------------------------------------------------------------ column order
-// Wt[:, k] = W[:, perm[k]], Vt[:, k] = V[:, perm[k]] for k < ncp.
-__global__ void jacobi_gather_kernel(const double *__restrict__ W, const double *__restrict__ V,
-                                     const int *__restrict__ perm, int L, int ncp,
-                                     double *__restrict__ Wt, double *__restrict__ Vt) {
-  const int64_t nw = (int64_t)L * ncp, nv = (int64_t)ncp * ncp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw + nv;
+// dst[:, k] = src[:, perm[k]] for k < ncols; columns of L doubles.
+__global__ void gather_columns_kernel(const double *__restrict__ src, const int *__restrict__ perm, int L,
+                                      int ncols, double *__restrict__ dst) {
+  const int64_t n = (int64_t)L * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    if (e < nw) {
-      const int k = (int)(e / L), i = (int)(e % L);
-      Wt[e] = W[(int64_t)perm[k] * L + i];
-    } else {
-      const int64_t f = e - nw;
-      const int k = (int)(f / ncp), i = (int)(f % ncp);
-      Vt[f] = V[(int64_t)perm[k] * ncp + i];
-    }
+    const int k = (int)(e / L), i = (int)(e % L);
+    dst[e] = src[(int64_t)perm[k] * L + i];
   }
+}
+
+hipError_t launch_gather_columns(const double *src, const int *perm, int L, int ncols, double *dst,
+                                 hipStream_t s) {
+  const int64_t tot = (int64_t)L * ncols;
+  int64_t g = (tot + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(gather_columns_kernel, dim3((int)g), dim3(256), 0, s, src, perm, L, ncols, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_norms(const double *W, int L, int nc, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_sigma_kernel, dim3((nc + 3) / 4), dim3(JNT), 0, s, W, L, nc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_desc(const double *v, int n, int *perm, hipStream_t s) {
+  const size_t shm = (size_t)n * sizeof(double);
+  if (shm > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + JNT - 1) / JNT), dim3(JNT), shm, s, v, n, perm);
+  return hipGetLastError();
 }
 
 hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStream_t s) {
@@ -630,72 +570,75 @@ hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStr
   // decreasing norm, so large columns meet each other first.  Zero padding
   // columns sort last.
   const int n = p.ncp;
-  hipLaunchKernelGGL(jacobi_sigma_kernel, dim3((n + 3) / 4), dim3(JNT), 0, s, b.W, p.L, n, b.sigma);
-  const size_t shm = (size_t)n * sizeof(double);
-  if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + JNT - 1) / JNT), dim3(JNT), shm, s, b.sigma, n, b.perm);
-  const int64_t tot = (int64_t)p.L * n + (int64_t)n * n;
-  int64_t g = (tot + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(jacobi_gather_kernel, dim3((int)g), dim3(256), 0, s, b.W, b.V, b.perm, p.L, n, b.Wt,
-                     b.Vt);
+  hipError_t e = launch_column_norms(b.W, p.L, n, b.sigma, s);
+  if (e == hipSuccess) e = launch_sort_desc(b.sigma, n, b.perm, s);
+  if (e == hipSuccess) e = launch_gather_columns(b.W, b.perm, p.L, n, b.Wt, s);
   double *t = b.W; b.W = b.Wt; b.Wt = t;
-  t = b.V; b.V = b.Vt; b.Vt = t;
-  return hipGetLastError();
+  return e;
 }
 
 // ------------------------------------------------------------------ write-out
-__global__ void svd_write_kernel(const double *__restrict__ W, const double *__restrict__ V,
-                                 const double *__restrict__ sigma, const int *__restrict__ perm, int L,
-                                 int nc, int ncp, int r, int w_holds_u, int left_pow, int right_pow,
-                                 double *__restrict__ left, double *__restrict__ right) {
-  // left: rows_l x r; right: r x cols_r
-  const int rows_l = w_holds_u ? L : nc;
-  const int cols_r = w_holds_u ? nc : L;
-  const int64_t nl = (int64_t)rows_l * r, nrgt = (int64_t)r * cols_r;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nl + nrgt;
+// u[rowperm[j] * u_os + t * u_ts] = W[:, perm[t]](j) / sigma[perm[t]] for
+// j < L, t < r: the leading r columns of W normalised, their rows put back
+// in the caller's order (rowperm[j] = original index of row j).  Zero
+// singular values give zero vectors.
+__global__ void jacobi_write_u_kernel(const double *__restrict__ W, const double *__restrict__ sigma,
+                                      const int *__restrict__ perm, const int *__restrict__ rowperm, int L,
+                                      int r, double *__restrict__ u, int64_t u_os, int64_t u_ts) {
+  const int64_t n = (int64_t)L * r;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    if (e < nl) {
-      const int i = (int)(e / r), k = (int)(e % r);
-      const int c = perm[k];
-      const double sg = sigma[c];
-      double v;
-      if (w_holds_u) {
-        v = W[(int64_t)c * L + i];                 // u_k * sigma_k
-        if (!left_pow) v = (sg > 0.0) ? v / sg : 0.0;
-      } else {
-        v = V[(int64_t)c * ncp + i];               // u_k
-        if (left_pow) v *= sg;
-      }
-      left[e] = v;
-    } else {
-      const int64_t f = e - nl;
-      const int k = (int)(f / cols_r), j = (int)(f % cols_r);
-      const int c = perm[k];
-      const double sg = sigma[c];
-      double v;
-      if (w_holds_u) {
-        v = V[(int64_t)c * ncp + j];               // v_k
-        if (right_pow) v *= sg;
-      } else {
-        v = W[(int64_t)c * L + j];                 // v_k * sigma_k
-        if (!right_pow) v = (sg > 0.0) ? v / sg : 0.0;
-      }
-      right[f] = v;
-    }
+    const int t = (int)(e / L), j = (int)(e % L);
+    const int c = perm[t];
+    const double sg = sigma[c];
+    const double v = W[(int64_t)c * L + j];
+    u[(int64_t)rowperm[j] * u_os + (int64_t)t * u_ts] = (sg > 0.0) ? v / sg : 0.0;
   }
 }
 
-hipError_t launch_svd_write(const JacobiPlan &p, const JacobiBufs &b, int r, bool w_holds_u,
-                            int left_pow, int right_pow, double *left, double *right, hipStream_t s) {
-  const int rows_l = w_holds_u ? p.L : p.nc;
-  const int cols_r = w_holds_u ? p.nc : p.L;
-  const int64_t n = (int64_t)rows_l * r + (int64_t)r * cols_r;
+hipError_t launch_jacobi_write_u(const JacobiPlan &p, const JacobiBufs &b, const int *rowperm, int r,
+                                 double *u, int64_t u_os, int64_t u_ts, hipStream_t s) {
+  const int64_t n = (int64_t)p.L * r;
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(svd_write_kernel, dim3((int)g), dim3(256), 0, s, b.W, b.V, b.sigma, b.perm, p.L,
-                     p.nc, p.ncp, r, w_holds_u ? 1 : 0, left_pow, right_pow, left, right);
+  hipLaunchKernelGGL(jacobi_write_u_kernel, dim3((int)g), dim3(256), 0, s, b.W, b.sigma, b.perm, rowperm, p.L,
+                     r, u, u_os, u_ts);
+  return hipGetLastError();
+}
+
+// W (L x ncp, column-major) = R^T for R = the upper trapezoid of S[0:k, :]
+// (S column-major, ld m, L = n columns): W[c*L + j] = S[j*m + c] for
+// c < k, j >= c; zero below the diagonal of R and in padding columns.
+// 32 x 32 tiles through LDS.
+__global__ void rt_from_qr_kernel(const double *__restrict__ S, int m, int n, int k, int ncp,
+                                  double *__restrict__ W) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.y * 32, j0 = blockIdx.x * 32;  // tile of R: rows c0.., cols j0..
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int q = ty; q < 32; q += 8) {
+    const int j = j0 + q, c = c0 + tx;  // read S[j*m + c]: consecutive c along a column of S
+    double v = 0.0;
+    if (j < n && c < k && j >= c) v = S[(int64_t)j * m + c];
+    tile[q][tx] = v;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int c = c0 + q, j = j0 + tx;  // write W[c*L + j]: consecutive j
+    if (c < ncp && j < n) W[(int64_t)c * n + j] = tile[tx][q];
+  }
+}
+
+hipError_t launch_rt_from_qr(const double *S, int m, int n, int k, int ncp, double *W, hipStream_t s) {
+  dim3 grid((n + 31) / 32, (ncp + 31) / 32);
+  if (grid.y > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rt_from_qr_kernel, grid, dim3(256), 0, s, S, m, n, k, ncp, W);
+  return hipGetLastError();
+}
+
+// result[5] = sum_i x[i]^2 (the squared Frobenius norm from column norms).
+hipError_t launch_frob_from_norms(const double *x, int n, double *result, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_frob_kernel, dim3(1), dim3(1024), 0, s, x, (int64_t)n, result);
   return hipGetLastError();
 }
 

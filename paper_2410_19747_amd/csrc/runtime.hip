@@ -31,7 +31,6 @@
 namespace ttm {
 namespace {
 
-constexpr double kEps = 2.220446049250313e-16;
 constexpr int64_t kSat = (int64_t)1 << 40;  // saturation of structural products
 
 struct Shape {
@@ -123,7 +122,7 @@ struct Plan {
   std::vector<int> phys;
   int64_t max_core = 1;  // doubles of the largest core
   int max_bond = 1;
-  int64_t max_w = 1;     // doubles of the largest Jacobi workspace
+  int64_t max_w = 1;     // doubles of the largest SVD workspace
   int64_t max_qr = 1;    // doubles of the largest QR scratch
   int64_t max_r = 1;     // doubles of the largest R / S V^T factor
   int64_t out_capacity = 0;
@@ -174,10 +173,13 @@ void note_core(Plan &pl, const Shape &s) {
   pl.max_core = std::max(pl.max_core, s.size());
   pl.max_bond = std::max(pl.max_bond, std::max(s.rl, s.rr));
 }
-void note_svd(Plan &pl, int m, int n) {
-  const int L = std::max(m, n), nc = std::min(m, n);
-  JacobiPlan jp = jacobi_plan(L, nc);
-  pl.max_w = std::max<int64_t>(pl.max_w, (int64_t)jacobi_ws_doubles(jp));
+// Workspace of one truncated SVD of an np x no matrix; `own_y` adds room for
+// the matrix itself (the swap builds it there).
+void note_svd(Plan &pl, int np, int no, bool own_y) {
+  SvdPlan sp = svd_plan(np, no);
+  int64_t need = (int64_t)svd_ws_doubles(sp);
+  if (own_y) need += (((int64_t)np * no + 31) & ~(int64_t)31);
+  pl.max_w = std::max<int64_t>(pl.max_w, need);
 }
 void note_qr(Plan &pl, int m, int n) {
   pl.max_qr = std::max<int64_t>(pl.max_qr, (int64_t)qr_scratch_doubles(m, n));
@@ -226,7 +228,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     Shape x = bt[j];
     for (int p = n - 1; p > j; --p) {
       const int m = pi[p].rl * x.d, nn = pi[p].d * x.rr;
-      note_svd(pl, m, nn);
+      note_svd(pl, m, nn, true);
       const int r = swap_cap(o, pl.phys, j, p, pi[p], x);
       Shape xn = {pi[p].rl, x.d, r};
       Shape pn = {r, pi[p].d, x.rr};
@@ -241,7 +243,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
   if (o.final_round) {
     for (int i = 0; i + 1 < n; ++i) {
       const int m = pi[i].rl * pi[i].d, nn = pi[i].rr;
-      note_svd(pl, m, nn);
+      note_svd(pl, nn, m, false);
       const int r = round_cap(chi_out, pl.phys, i, pi[i]);
       pl.max_r = std::max<int64_t>(pl.max_r, (int64_t)r * nn);
       pi[i].rr = r;
@@ -376,149 +378,82 @@ struct Runner {
     note(nxt.s);
   }
 
-  // ---- one SVD of the matrix already in wbuf's W region.
-  // Returns the rank (or -1 on error) and fills disc.
-  struct SvdOut {
-    int r = -1;
-    double disc = 0.0, total = 0.0;
-  };
-  SvdOut jacobi(const JacobiPlan &jp, JacobiBufs &jb, double eps, int cap) {
-    SvdOut out;
+  // ---- one truncated SVD (svd_oside) with the bookkeeping of the rule of
+  // Eq. (eps): forced ranks, traces, discarded weight and the flop model.
+  // Returns the rank, or -1 after setting err.
+  int svd(const SvdPlan &sp, const double *Y, double *ws, int cap, double *u, int u_layout) {
     int forced = 0;
     if (o.forced) {
       if (forced_pos >= o.n_forced) {
         err = TTM_EFORCED;
-        return out;
+        return -1;
       }
       forced = o.forced[forced_pos++];
       // a forced rank may not exceed what the buffers were sized for
-      if (forced > std::min(jp.nc, cap)) {
+      if (forced > std::min(sp.k, cap)) {
         err = TTM_EFORCED;
-        return out;
+        return -1;
       }
     }
-    {
-      Timed tm(&timer, KC_JAC_OTHER, st);
-      if (!hip(launch_jacobi_init(jp, jb, st))) return out;
+    SvdResult so = svd_oside(sp, Y, eps_, cap, forced, o.svd_max_sweeps, u, u_layout, nullptr, ws, st, &timer,
+                             trace);
+    jac_sweeps += so.sweeps;
+    jac_max = std::max(jac_max, so.sweeps);
+    if (so.err != TTM_OK) {
+      if (err == TTM_OK) err = so.err;
+      return -1;
     }
-    const double tol = sqrt((double)std::max(jp.L, 1)) * kEps;
-    double prev = INFINITY;
-    int sweeps = 0;
-    bool ok = false;
-    double host_res[8];
-    for (int sw = 0; sw < o.svd_max_sweeps; ++sw) {
-      {
-        Timed tm(&timer, KC_JAC_OTHER, st);
-        if (!hip(launch_jacobi_sort_columns(jp, jb, st))) return out;
-      }
-      if (!hip(launch_jacobi_sweep(jp, jb, tol, st, &timer))) return out;
-      ++sweeps;
-      if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
-      if (!sync()) return out;
-      const double off = host_res[3];
-      if (trace) fprintf(stderr, "[ttm]   jacobi %dx%d sweep %d off=%.3e tol=%.3e\n", jp.L, jp.nc, sw, off, tol);
-      if (!(off == off)) break;  // NaN
-      if (off <= tol) { ok = true; break; }
-      // stagnation at the rounding floor
-      if (off < 1e3 * tol && off > 0.5 * prev) { ok = true; break; }
-      prev = off;
-    }
-    jac_sweeps += sweeps;
-    jac_max = std::max(jac_max, sweeps);
-    if (!ok) {
-      if (err == TTM_OK) err = TTM_ENOCONV;
-      if (trace) fprintf(stderr, "[ttm] jacobi %dx%d did not converge\n", jp.L, jp.nc);
-      return out;
-    }
-    {
-      Timed tm(&timer, KC_JAC_OTHER, st);
-      if (!hip(launch_jacobi_finish(jp, jb, eps, cap, forced, st))) return out;
-    }
-    if (!hip(hipMemcpyAsync(host_res, jb.result, 8 * sizeof(double), hipMemcpyDeviceToHost, st))) return out;
-    if (!sync()) return out;
-    if (host_res[4] != 0.0) {
-      err = TTM_ENONFINITE;
-      return out;
-    }
-    out.r = (int)host_res[0];
-    out.disc = host_res[1];
-    out.total = host_res[2];
-    if (trace)
-      fprintf(stderr, "[ttm] svd %dx%d sweeps=%d rank=%d disc=%.3e total=%.3e\n", jp.L, jp.nc, sweeps,
-              out.r, out.disc, out.total);
     ++n_svd;
-    disc_sum += out.disc;
-    err_bound += sqrt(std::max(out.disc, 0.0));
+    disc_sum += so.disc;
+    err_bound += sqrt(std::max(so.disc, 0.0));
     if (n_trace < o.trace_cap) {
-      o.rank_trace[n_trace] = out.r;
-      o.discard_trace[n_trace] = out.disc;
+      o.rank_trace[n_trace] = so.rank;
+      o.discard_trace[n_trace] = so.disc;
     }
     ++n_trace;
-    const int m = std::max(jp.L, jp.nc), n = std::min(jp.L, jp.nc);
-    const double f = 4.0 * m * (double)n * n - (4.0 / 3.0) * n * (double)n * n + 4.0 * (m + n) * (double)n * out.r;
+    const int m = std::max(sp.np, sp.no), n = std::min(sp.np, sp.no);
+    const double f = 4.0 * m * (double)n * n - (4.0 / 3.0) * n * (double)n * n + 4.0 * (m + n) * (double)n * so.rank;
     flops += f;
     svd_flops += f;
-    return out;
-  }
-
-  JacobiBufs carve(const JacobiPlan &jp) {
-    JacobiBufs b;
-    double *p = wbuf;
-    auto adv = [&](size_t nd) {
-      double *q = p;
-      p += (nd + 31) & ~(size_t)31;
-      return q;
-    };
-    b.W = adv((size_t)jp.L * jp.ncp);
-    b.Wt = adv((size_t)jp.L * jp.ncp);
-    b.V = adv((size_t)jp.ncp * jp.ncp);
-    b.Vt = adv((size_t)jp.ncp * jp.ncp);
-    b.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
-    b.conv = adv((size_t)jp.rounds * jp.pairs);
-    b.qbuf = adv(2 * (size_t)jp.pairs * 32 * 32);
-    b.flag = reinterpret_cast<int *>(adv(2 * (size_t)jp.pairs));
-    b.sigma = adv((size_t)jp.ncp);
-    b.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
-    b.result = adv(8);
-    return b;
+    return so.rank;
   }
 
   // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
   void swap(Core &P, Core &X, int cap) {
     const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
     const int m = Dl * dx, n = dp * Dr;
-    const bool tall = m >= n;
-    const int L = tall ? m : n, nc = tall ? n : m;
-    JacobiPlan jp = jacobi_plan(L, nc);
-    JacobiBufs jb = carve(jp);
+    const SvdPlan sp = svd_plan(m, n);
+    double *Y = wbuf;
+    double *sws = wbuf + ((((int64_t)m * n) + 31) & ~(int64_t)31);
     // merge: theta[(a,e),(w,b)] = sum_c P[a,e,c] X[c,w,b], stored as the
-    // leg-exchanged unfolding Theta[(a,w),(e,b)] (tall) or its transpose.
+    // leg-exchanged unfolding Theta[(a,w),(e,b)], column-major (ld m).
     GemmArgs g;
     g.M = Dl * dp; g.N = dx * Dr; g.K = Dm;
     g.A = P.p; g.a_rs = Dm; g.a_cs = 1;
     g.B = X.p; g.b_rs = (int64_t)dx * Dr; g.b_cs = 1;
-    g.C = jb.W;
+    g.C = Y;
     g.c_rdiv = dp; g.c_cdiv = Dr;
-    if (tall) {
-      g.c_rs1 = dx; g.c_rs0 = (int64_t)m * Dr; g.c_cs1 = 1; g.c_cs0 = m;
-    } else {
-      g.c_rs1 = (int64_t)n * dx; g.c_rs0 = Dr; g.c_cs1 = n; g.c_cs0 = 1;
-    }
+    g.c_rs1 = dx; g.c_rs0 = (int64_t)m * Dr; g.c_cs1 = 1; g.c_cs0 = m;
     {
       Timed tm(&timer, KC_GEMM, st);
       if (!hip(launch_gemm(g, st))) return;
     }
     flops += 2.0 * Dl * dp * (double)Dm * dx * Dr;
-    SvdOut so = jacobi(jp, jb, eps_, cap);
-    if (so.r < 1) return;
-    const int r = so.r;
     double *xn = take();
     double *pn = take();
     if (!xn || !pn) return;
-    // X' = U_r S_r  -> [Dl, dx, r];  P' = V_r^T -> [r, dp, Dr]
+    // P' = V_r^T -> [r, dp, Dr] (the orthonormal factor, over Theta's columns)
+    const int r = svd(sp, Y, sws, cap, pn, SVD_U_T);
+    if (r < 1) return;
+    // X' = Theta V_r = U_r S_r -> [Dl, dx, r]
+    GemmArgs z;
+    z.M = m; z.N = r; z.K = n;
+    z.A = Y; z.a_rs = 1; z.a_cs = m;
+    z.B = pn; z.b_rs = 1; z.b_cs = n;
+    z.C = xn; z.c_rs1 = r; z.c_cs1 = 1;
     {
-      Timed tm(&timer, KC_JAC_OTHER, st);
-      if (!hip(launch_svd_write(jp, jb, r, tall, 1, 0, xn, pn, st))) return;
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(z, st))) return;
     }
     give(P.p);
     give(X.p);
@@ -536,31 +471,24 @@ struct Runner {
     Core &cur = c[i];
     Core &nxt = c[i + 1];
     const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
-    const bool tall = m >= n;
-    const int L = tall ? m : n, nc = tall ? n : m;
-    JacobiPlan jp = jacobi_plan(L, nc);
-    JacobiBufs jb = carve(jp);
-    {
-      Timed tm(&timer, KC_OTHER, st);
-      if (tall) {
-        if (!hip(launch_transpose(jb.W, cur.p, m, n, st))) return;  // column-major copy
-      } else {
-        if (!hip(launch_copy(jb.W, cur.p, (int64_t)m * n, st))) return;  // already Theta^T col-major
-      }
-    }
-    SvdOut so = jacobi(jp, jb, eps_, cap);
-    if (so.r < 1) return;
-    const int r = so.r;
+    // The row-major m x n core is the column-major n x m matrix Y = Pi_i^T,
+    // whose right singular vectors are Pi_i's left ones.
+    const SvdPlan sp = svd_plan(n, m);
     double *un = take();
     double *nn = take();
     if (!un || !nn) return;
-    {
-      Timed tm(&timer, KC_JAC_OTHER, st);
-      if (!hip(launch_svd_write(jp, jb, r, tall, 0, 1, un, rbuf, st))) return;
-    }
+    const int r = svd(sp, cur.p, wbuf, cap, un, SVD_U);
+    if (r < 1) return;
+    // S_r V_r^T = U_r^T Pi_i  (r x n), then into the next core
+    GemmArgs h;
+    h.M = r; h.N = n; h.K = m;
+    h.A = un; h.a_rs = 1; h.a_cs = r;
+    h.B = cur.p; h.b_rs = n; h.b_cs = 1;
+    h.C = rbuf; h.c_rs1 = n; h.c_cs1 = 1;
     const int ncol = nxt.s.d * nxt.s.rr;
     {
       Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(h, st))) return;
       if (!hip(launch_gemm(gemm_rowmajor(r, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st))) return;
     }
     flops += 2.0 * r * (double)n * ncol;

@@ -6,37 +6,6 @@
 #include "../../include/ttm_testing.h"
 #include "ttm_internal.h"
 
-namespace ttm {
-namespace {
-__global__ void gather_sigma_kernel(const double *sigma, const int *perm, int n, double *out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = sigma[perm[k]];
-}
-
-JacobiBufs carve_test(double *base, const JacobiPlan &jp) {
-  JacobiBufs b;
-  double *p = base;
-  auto adv = [&](size_t nd) {
-    double *q = p;
-    p += (nd + 31) & ~(size_t)31;
-    return q;
-  };
-  b.W = adv((size_t)jp.L * jp.ncp);
-  b.Wt = adv((size_t)jp.L * jp.ncp);
-  b.V = adv((size_t)jp.ncp * jp.ncp);
-  b.Vt = adv((size_t)jp.ncp * jp.ncp);
-  b.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
-  b.conv = adv((size_t)jp.rounds * jp.pairs);
-  b.qbuf = adv(2 * (size_t)jp.pairs * 32 * 32);
-  b.flag = reinterpret_cast<int *>(adv(2 * (size_t)jp.pairs));
-  b.sigma = adv((size_t)jp.ncp);
-  b.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
-  b.result = adv(8);
-  return b;
-}
-}  // namespace
-}  // namespace ttm
-
 extern "C" {
 
 int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs, int64_t a_cs,
@@ -66,50 +35,53 @@ int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scr
 }
 
 size_t ttm_test_svd_ws_bytes(int m, int n) {
-  ttm::JacobiPlan jp = ttm::jacobi_plan(std::max(m, n), std::min(m, n));
-  return ttm::jacobi_ws_doubles(jp) * sizeof(double);
+  if (m < 1 || n < 1) return 0;
+  // the larger of the two orientations, plus a transposed copy of M
+  const size_t a = ttm::svd_ws_doubles(ttm::svd_plan(m, n));
+  const size_t b = ttm::svd_ws_doubles(ttm::svd_plan(n, m));
+  return (std::max(a, b) + (size_t)m * n + 64) * sizeof(double);
 }
 
 int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
                  int right_pow, double *left, double *right, double *sigma, int *rank,
                  int *sweeps, void *ws, size_t ws_bytes, void *stream) {
   if (m < 1 || n < 1 || !M || !left || !right || !sigma || !rank || !ws) return TTM_EINVAL;
+  if (left_pow + right_pow != 1 || left_pow < 0 || right_pow < 0) return TTM_EINVAL;
   if (ws_bytes < ttm_test_svd_ws_bytes(m, n)) return TTM_EWORKSPACE;
-  const bool tall = m >= n;
-  const int L = tall ? m : n, nc = tall ? n : m;
-  ttm::JacobiPlan jp = ttm::jacobi_plan(L, nc);
-  ttm::JacobiBufs jb = ttm::carve_test(static_cast<double *>(ws), jp);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // W = M (tall: column-major copy of M) or M^T (wide: M's row-major storage).
-  if (tall) {
-    if (ttm::launch_transpose(jb.W, M, m, n, s) != hipSuccess) return TTM_EHIP;
+  double *base = static_cast<double *>(ws);
+  double *Yt = base;                                           // M^T copy when needed
+  double *sws = base + ((((size_t)m * n) + 31) & ~(size_t)31);
+  ttm::SvdResult res;
+  if (right_pow == 0) {
+    // right factor orthonormal: Y = M (m x n), column-major copy of row-major M
+    if (ttm::launch_transpose(Yt, M, m, n, s) != hipSuccess) return TTM_EHIP;
+    const ttm::SvdPlan sp = ttm::svd_plan(m, n);
+    res = ttm::svd_oside(sp, Yt, eps, cap, forced, 60, right, ttm::SVD_U_T, sigma, sws, s, nullptr, false);
+    if (res.err == TTM_OK) {
+      ttm::GemmArgs g;  // left = M V_r
+      g.M = m; g.N = res.rank; g.K = n;
+      g.A = M; g.a_rs = n; g.a_cs = 1;
+      g.B = right; g.b_rs = 1; g.b_cs = n;
+      g.C = left; g.c_rs1 = res.rank; g.c_cs1 = 1;
+      if (ttm::launch_gemm(g, s) != hipSuccess) return TTM_EHIP;
+    }
   } else {
-    if (ttm::launch_copy(jb.W, M, (int64_t)m * n, s) != hipSuccess) return TTM_EHIP;
+    // left factor orthonormal: Y = M^T, whose column-major storage is M's
+    const ttm::SvdPlan sp = ttm::svd_plan(n, m);
+    res = ttm::svd_oside(sp, M, eps, cap, forced, 60, left, ttm::SVD_U, sigma, sws, s, nullptr, false);
+    if (res.err == TTM_OK) {
+      ttm::GemmArgs g;  // right = U_r^T M
+      g.M = res.rank; g.N = n; g.K = m;
+      g.A = left; g.a_rs = 1; g.a_cs = res.rank;
+      g.B = M; g.b_rs = n; g.b_cs = 1;
+      g.C = right; g.c_rs1 = n; g.c_cs1 = 1;
+      if (ttm::launch_gemm(g, s) != hipSuccess) return TTM_EHIP;
+    }
   }
-  if (ttm::launch_jacobi_init(jp, jb, s) != hipSuccess) return TTM_EHIP;
-  const double tol = sqrt((double)L) * 2.220446049250313e-16;
-  double res[8];
-  int sw = 0;
-  bool ok = false;
-  double prev = INFINITY;
-  for (; sw < 60;) {
-    if (ttm::launch_jacobi_sort_columns(jp, jb, s) != hipSuccess) return TTM_EHIP;
-    if (ttm::launch_jacobi_sweep(jp, jb, tol, s) != hipSuccess) return TTM_EHIP;
-    ++sw;
-    if (hipMemcpyAsync(res, jb.result, sizeof(res), hipMemcpyDeviceToHost, s) != hipSuccess) return TTM_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return TTM_EHIP;
-    if (res[3] <= tol || (res[3] < 1e3 * tol && res[3] > 0.5 * prev)) { ok = true; break; }
-    prev = res[3];
-  }
-  if (sweeps) *sweeps = sw;
-  if (!ok) return TTM_ENOCONV;
-  if (ttm::launch_jacobi_finish(jp, jb, eps, cap, forced, s) != hipSuccess) return TTM_EHIP;
-  if (hipMemcpyAsync(res, jb.result, sizeof(res), hipMemcpyDeviceToHost, s) != hipSuccess) return TTM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return TTM_EHIP;
-  const int r = (int)res[0];
-  *rank = r;
-  if (ttm::launch_svd_write(jp, jb, r, tall, left_pow, right_pow, left, right, s) != hipSuccess) return TTM_EHIP;
-  hipLaunchKernelGGL(ttm::gather_sigma_kernel, dim3((nc + 255) / 256), dim3(256), 0, s, jb.sigma, jb.perm, nc, sigma);
+  if (sweeps) *sweeps = res.sweeps;
+  if (res.err != TTM_OK) return res.err;
+  *rank = res.rank;
   return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
 }
 

@@ -96,16 +96,20 @@ hipError_t launch_sumsq(const double *x, int64_t n, double *out, hipStream_t s);
 // ------------------------------------------------------------------ QR
 // Householder QR of an m x n matrix M (element (i,j) at M + i*rs + j*cs).
 // Writes Q (m x k, k = min(m,n)) row-major with leading dimension k into q,
-// and R (k x n) row-major into r.  scratch: at least m*n + m*k + 2*n doubles.
+// and R (k x n) row-major into r.  scratch: qr_scratch_doubles(m, n).
 // q, r and scratch must not overlap M.
 hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
                      double *scratch, hipStream_t s);
 size_t qr_scratch_doubles(int m, int n);
+// In-place Householder QR of the column-major m x n matrix S (ld m), R only:
+// on return the upper trapezoid of S[0:k, :] is R and the reflectors lie
+// below it.  scratch: qr_inplace_scratch_doubles(m).
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, hipStream_t s);
+size_t qr_inplace_scratch_doubles(int m);
 
-// ------------------------------------------------------------------ SVD
-// One-sided block Jacobi SVD of an L x nc column-major matrix W (ld = L,
-// nc <= L not required) with accumulated right rotations V (ncp x ncp,
-// column-major).  Columns are padded to ncp = nblk * bw (nblk even).
+// ------------------------------------------------------------------ Jacobi
+// One-sided block Jacobi on an L x nc column-major matrix W (ld = L),
+// columns padded with zeros to ncp = nblk * bw (nblk even).
 struct JacobiPlan {
   int L = 0, nc = 0;     // rows, real columns
   int bw = 0;            // block width
@@ -113,52 +117,86 @@ struct JacobiPlan {
   int ncp = 0;           // padded columns = nblk * bw
   int rows_per_wg = 0;   // row chunk per workgroup for Gram and update
   int sw = 0;            // row chunks of W
-  int sv = 0;            // row chunks of V
   int rounds = 0;        // nblk - 1
   int pairs = 0;         // nblk / 2
 };
 JacobiPlan jacobi_plan(int L, int nc);
-// Workspace doubles for the W/V/partials/conv arrays of a plan.
+// Workspace doubles of the Jacobi buffers of a plan.
 size_t jacobi_ws_doubles(const JacobiPlan &p);
 
 // Device buffers of one Jacobi run (carved from the workspace).
 struct JacobiBufs {
   double *W = nullptr;      // L x ncp (column-major)
-  double *V = nullptr;      // ncp x ncp
-  double *Wt = nullptr;     // reordering buffers (swapped with W, V)
-  double *Vt = nullptr;
+  double *Wt = nullptr;     // reordering buffer (swapped with W)
   double *part = nullptr;   // pairs * sw * (2bw)^2 partial Grams
   double *conv = nullptr;   // rounds * pairs: scaled off-diagonal maxima
   double *sigma = nullptr;  // ncp
   int *perm = nullptr;      // ncp: perm[k] = column index of the k-th largest value
-  double *qbuf = nullptr;   // 2 * pairs * 32 * 32: rotations of two consecutive rounds
-  int *flag = nullptr;      // 2 * pairs: rotation is not the identity
+  double *qbuf = nullptr;   // pairs * 32 * 32: rotations of the current round
+  int *flag = nullptr;      // pairs: rotation is not the identity
   double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,[5]=squared Frobenius norm of W
 };
 
-// Prepare: pad W's extra columns with zeros and set V = I.
-hipError_t launch_jacobi_init(const JacobiPlan &p, const JacobiBufs &b, hipStream_t s);
 // One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
-// off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.
+// off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.  Needs
+// result[5] = ||W||_F^2.
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer = nullptr);
-// Reorder the columns of W and V by decreasing norm (swaps W/Wt, V/Vt).
+// Reorder the columns of W by decreasing norm (swaps W/Wt).
 hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStream_t s);
 // Column norms, descending order, and the rank rule of Eq. (eps):
 // r = min{k>=1 : tail_k < eps*total or tail_k == 0}, then min(r, cap) when
 // cap > 0; forced > 0 replaces the rule.  Writes result[0..2].
 hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double eps, int cap,
                                 int forced, hipStream_t s);
+// u[rowperm[j]*u_os + t*u_ts] = j-th entry of the t-th largest column of W
+// divided by its norm (j < L, t < r).
+hipError_t launch_jacobi_write_u(const JacobiPlan &p, const JacobiBufs &b, const int *rowperm, int r,
+                                 double *u, int64_t u_os, int64_t u_ts, hipStream_t s);
 
-// Write-out of a truncated factorisation Theta ~= U_r S_r V_r^T (r = rank):
-//   left  (rows_l x r, row-major): U_r * diag(s)^left_pow
-//   right (r x cols_r, row-major): diag(s)^right_pow * V_r^T
-// `w_holds_u` says whether W's columns are U*S (W was Theta, rows_l = L) or
-// V*S (W was Theta^T, cols_r = L); the other factor comes from the rotations
-// V.  left_pow/right_pow in {0,1} choose where the singular values go.
-hipError_t launch_svd_write(const JacobiPlan &p, const JacobiBufs &b, int r, bool w_holds_u,
-                            int left_pow, int right_pow, double *left, double *right,
-                            hipStream_t s);
+// Helpers shared with the SVD driver.
+hipError_t launch_column_norms(const double *W, int L, int nc, double *out, hipStream_t s);
+hipError_t launch_sort_desc(const double *v, int n, int *perm, hipStream_t s);  // n <= 8192
+hipError_t launch_gather_columns(const double *src, const int *perm, int L, int ncols, double *dst,
+                                 hipStream_t s);
+hipError_t launch_rt_from_qr(const double *S, int m, int n, int k, int ncp, double *W, hipStream_t s);
+hipError_t launch_frob_from_norms(const double *x, int n, double *result, hipStream_t s);
+
+// ------------------------------------------------------------------ truncated SVD
+// Truncated SVD Y ~= Z U_r^T of an np x no matrix Y (column-major, ld np)
+// whose factor U_r (no x r) must have orthonormal columns: U_r holds the
+// leading right singular vectors of Y and Z = Y U_r = U_Y,r S_r.
+//   1. the columns of Y are ordered by decreasing norm and copied;
+//   2. Householder QR of the copy, Y P = Q R (R only);
+//   3. one-sided Jacobi on W = R^T (no x k, k = min(np, no)) until its
+//      columns are orthogonal: W = (P^T V_Y) S, so the normalised columns,
+//      rows put back in Y's order, are the right singular vectors of Y;
+//   4. the rank rule of Eq. (eps) on the singular values;
+//   5. U_r written out; the caller forms Z = Y U_r with one product.
+// The QR step is the preconditioner of Drmac and Veselic (2008): Jacobi on
+// R^T of a column-ordered QR needs markedly fewer sweeps than on Y itself.
+struct SvdPlan {
+  int np = 0, no = 0, k = 0;
+  JacobiPlan jp;
+};
+SvdPlan svd_plan(int np, int no);
+size_t svd_ws_doubles(const SvdPlan &p);
+struct SvdResult {
+  int rank = -1;
+  double disc = 0.0, total = 0.0;
+  int sweeps = 0;
+  int err = 0;  // TTM_OK or a TTM_E* code
+};
+// Runs the SVD of Y (left intact) and writes U_r into u: as U_r^T (r x no,
+// row-major: u[t*no + o]) when u_layout == SVD_U_T, as U_r (no x r,
+// row-major: u[o*r + t]) when u_layout == SVD_U.  forced > 0 replaces the
+// rank rule.  When sigma_out is not null the k
+// singular values are written there in decreasing order.  Synchronises the
+// stream once per Jacobi sweep (convergence test) and at the end.
+enum { SVD_U_T = 0, SVD_U = 1 };
+SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
+                    double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
+                    KernelTimer *timer, bool trace);
 
 // ------------------------------------------------------------------ conventional
 // Dense transposed copy used by the variational driver:
