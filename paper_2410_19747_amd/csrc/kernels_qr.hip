@@ -12,7 +12,9 @@
 // reduction over rows is then a per-lane sum, two shuffles across the four
 // row groups of a wave and one LDS exchange across the 16 waves, and it
 // yields the sums of all 16 columns at once: one pass gives v^T x for every
-// trailing column of the panel and V^T v for the T recurrence.
+// trailing column of the panel and V^T v for T.  The column being reflected
+// is published in LDS once per step, so each lane forms v for its own rows
+// from a broadcast read; T is assembled after the last column.
 #include "ttm_internal.h"
 
 namespace ttm {
@@ -70,55 +72,57 @@ __global__ void strided_to_colmajor_kernel(double *__restrict__ S, const double 
 template <int SL>
 __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ S, int m, int j0, int jb,
                                                            double *__restrict__ Vb, double *__restrict__ T) {
-  __shared__ double red[2][16][QB];
-  __shared__ double Ts[QB][QB + 1];
-  __shared__ double sh_alpha;
-  constexpr bool kCache = SL <= 8;  // keep v in registers while they fit beside x
+  __shared__ double red[2][16][QB];     // per-wave column sums: [norm | v^T x][wave][column]
+  __shared__ double piv[2][64 * SL];    // column cc before its reflection (double-buffered)
+  __shared__ double zs[QB][QB + 1];     // zs[i][b] = v_b^T v_i, b < i
+  __shared__ double taus[QB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int mv = m - j0;
+  const int i0 = 4 * w + g;  // row of slot 0; slot s holds row i0 + 64 s
   double x[SL];
-  double vt[kCache ? SL : 1];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
-    const int i = 64 * s + 4 * w + g;
+    const int i = i0 + 64 * s;
     x[s] = (i < mv && c < jb) ? S[(int64_t)(j0 + c) * m + j0 + i] : 0.0;
   }
+  // Rows at or above a pivot (< 16) occur only in slot 0, so every row test
+  // below concerns slot 0 alone.
   for (int cc = 0; cc < jb; ++cc) {
-    const int src = (g << 4) | cc;  // lane holding column cc of this lane's rows
-    // Squared norm of every column below row cc, and the pivot x(cc, cc).
-    double p = 0.0;
+    double *pc = piv[cc & 1];
+    // Squared norm of every column below row cc; column cc is published in
+    // LDS so that every lane can form v for its own rows.
+    double p = (i0 > cc) ? x[0] * x[0] : 0.0;
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = 64 * s + 4 * w + g;
-      p = (i > cc) ? fma(x[s], x[s], p) : p;
+    for (int s = 1; s < SL; ++s) p = fma(x[s], x[s], p);
+    if (c == cc) {
+#pragma unroll
+      for (int s = 0; s < SL; ++s) pc[i0 + 64 * s] = x[s];
     }
     p += __shfl_xor(p, 16, 64);
     p += __shfl_xor(p, 32, 64);
     if (g == 0) red[0][w][c] = p;
-    if (c == cc && 4 * w + g == cc) sh_alpha = x[0];
     __syncthreads();
     double xnorm2 = 0.0;
 #pragma unroll
     for (int ww = 0; ww < 16; ++ww) xnorm2 += red[0][ww][cc];
-    const double alpha = sh_alpha;
+    const double alpha = pc[cc];
     double tau = 0.0, scale = 0.0, beta = alpha;
     if (xnorm2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
       tau = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    // Reflector v (1 at row cc, x / (alpha - beta) below) into column cc, and
-    // the partial sums of v^T x for every column of the panel.
-    double q = 0.0;
+    // Reflector v (1 at row cc, x / (alpha - beta) below) and the partial
+    // sums of v^T x for every column of the panel.
+    const double v0 = (i0 > cc) ? pc[i0] * scale : (i0 == cc ? 1.0 : 0.0);
+    double q = v0 * x[0];
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = 64 * s + 4 * w + g;
-      const double xv = __shfl(x[s], src, 64);
-      const double v = (i > cc) ? xv * scale : (i == cc ? 1.0 : 0.0);
-      if (kCache) vt[s] = v;
-      q = fma(v, x[s], q);
-      if (c == cc) x[s] = (i > cc) ? v : (i == cc ? beta : x[s]);
+    for (int s = 1; s < SL; ++s) q = fma(pc[i0 + 64 * s] * scale, x[s], q);
+    if (c == cc) {
+      x[0] = (i0 > cc) ? v0 : (i0 == cc ? beta : x[0]);
+#pragma unroll
+      for (int s = 1; s < SL; ++s) x[s] = pc[i0 + 64 * s] * scale;
     }
     q += __shfl_xor(q, 16, 64);
     q += __shfl_xor(q, 32, 64);
@@ -128,31 +132,36 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
 #pragma unroll
     for (int ww = 0; ww < 16; ++ww) tot += red[1][ww][c];
     // Columns right of cc: x <- x - tau (v^T x) v.  Columns left of cc hold
-    // earlier reflectors; their sums are V(:, 0:cc)^T v for T.
-    const double f = (c > cc) ? tau * tot : 0.0;
+    // earlier reflectors; their sums v_b^T v are kept for T.
+    if (c > cc) {
+      const double f = tau * tot;
+      x[0] = fma(-f, v0, x[0]);
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      double v;
-      if (kCache) {
-        v = vt[s];
-      } else {
-        const int i = 64 * s + 4 * w + g;
-        const double xv = __shfl(x[s], src, 64);
-        v = (i > cc) ? xv : (i == cc ? 1.0 : 0.0);
-      }
-      x[s] = fma(-f, v, x[s]);
+      for (int s = 1; s < SL; ++s) x[s] = fma(-f, pc[i0 + 64 * s] * scale, x[s]);
     }
-    // T(0:cc, cc) = -tau T(0:cc, 0:cc) (V(:, 0:cc)^T v), T(cc, cc) = tau.
-    // Lane a of wave 0 owns row a of T.
-    if (w == 0) {
-      double acc = 0.0;
-      for (int b = 0; b < cc; ++b) {
-        const double zb = __shfl(tot, b, 64);
-        if (g == 0 && b >= c) acc = fma(Ts[c][b], zb, acc);
-      }
-      if (g == 0 && c < cc) Ts[c][cc] = -tau * acc;
-      if (g == 0 && c == cc) Ts[cc][cc] = tau;
+    if (w == 0 && g == 0) {
+      if (c < cc) zs[cc][c] = tot;
+      if (c == cc) taus[cc] = tau;
     }
+  }
+  __syncthreads();
+  // T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) zs(i, 0:i)^T, column by
+  // column; lane a of wave 0 keeps row a in registers.
+  if (w == 0 && g == 0) {
+    double tr[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) tr[b] = 0.0;
+#pragma unroll
+    for (int i = 0; i < QB; ++i) {
+      if (i < jb) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < i; ++b) acc = (b >= c) ? fma(tr[b], zs[i][b], acc) : acc;
+        tr[i] = (c < i) ? -taus[i] * acc : (c == i ? taus[i] : 0.0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? tr[b] : 0.0;
   }
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
@@ -161,9 +170,6 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
       if (c < jb) S[(int64_t)(j0 + c) * m + j0 + i] = x[s];
       Vb[(int64_t)c * mv + i] = (c < jb && i >= c) ? (i == c ? 1.0 : x[s]) : 0.0;
     }
-  }
-  if (w == 0 && g == 0) {
-    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb && b >= c) ? Ts[c][b] : 0.0;
   }
 }
 
@@ -264,12 +270,22 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
   const int cb = c0 + QB * blockIdx.x;
   const int ncol = min(QB, c0 + nc - cb);
   double *A = S + (int64_t)cb * m + j0;  // A(i, j) = A[j * m + i]
+  // Each wave reduces a contiguous quarter of the rows, four MFMA steps per
+  // batch of loads.
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 4 * w; k0 < mv; k0 += 16) {
-    const int kk = k0 + q4;
-    const double va = (kk < mv) ? Vb[(int64_t)r16 * mv + kk] : 0.0;
-    const double ab = (kk < mv && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ab, acc, 0, 0, 0);
+  const int chunk = ((mv + 15) / 16) * 4;
+  const int kb = w * chunk, ke = min(mv, kb + chunk);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    double va[4], ab[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + 4 * u + q4;
+      const bool ok = kk < ke;
+      va[u] = ok ? Vb[(int64_t)r16 * mv + kk] : 0.0;
+      ab[u] = (ok && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], ab[u], acc, 0, 0, 0);
   }
   for (int t = 0; t < 4; ++t) Wp[w][4 * t + q4][r16] = acc[t];
   __syncthreads();
@@ -283,18 +299,34 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
   }
   __syncthreads();
   const double wa0 = W2[q4][r16], wa1 = W2[4 + q4][r16], wa2 = W2[8 + q4][r16], wa3 = W2[12 + q4][r16];
-  for (int i0 = 16 * w; i0 < mv; i0 += 64) {
-    const int r = i0 + r16;
-    const bool ok = r < mv;
-    dbl4 d = {0.0, 0.0, 0.0, 0.0};
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, ok ? Vb[(int64_t)q4 * mv + r] : 0.0, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa1, ok ? Vb[(int64_t)(4 + q4) * mv + r] : 0.0, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa2, ok ? Vb[(int64_t)(8 + q4) * mv + r] : 0.0, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa3, ok ? Vb[(int64_t)(12 + q4) * mv + r] : 0.0, d, 0, 0, 0);
-    if (ok) {
-      for (int t = 0; t < 4; ++t) {
-        const int col = 4 * t + q4;
-        if (col < ncol) A[(int64_t)col * m + r] -= d[t];
+  // Two 16-row tiles per iteration, every load issued before the products.
+  for (int i0 = 16 * w; i0 < mv; i0 += 128) {
+    double vv[2][4], aa[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = i0 + 64 * h + r16;
+      const bool ok = r < mv;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int col = 4 * u + q4;
+        vv[h][u] = ok ? Vb[(int64_t)col * mv + r] : 0.0;
+        aa[h][u] = (ok && col < ncol) ? A[(int64_t)col * m + r] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = i0 + 64 * h + r16;
+      dbl4 d = {0.0, 0.0, 0.0, 0.0};
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, vv[h][0], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa1, vv[h][1], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa2, vv[h][2], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa3, vv[h][3], d, 0, 0, 0);
+      if (r < mv) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int col = 4 * t + q4;
+          if (col < ncol) A[(int64_t)col * m + r] = aa[h][t] - d[t];
+        }
       }
     }
   }
