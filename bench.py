@@ -12,6 +12,11 @@ Prints one JSON line with the throughput, the roofline of the dominant
 kernel (the Jacobi block-pair solve kernel of the swap SVDs, timed with HIP events on
 the library's stream during the timed steps), and the CPU oracle's rate on a
 bounded sample of the same workload.
+
+``--sweep`` instead measures the bond-dimension sweep on the 10-site shapes
+(a 1024^3 field, d = 8, chi in --sweep-chis): one JSON line per chi with the
+product rate, the algorithmic flop rate against the FP64 MFMA peak, and the
+relative error of sampled entries against the exact product A(x) B(x).
 """
 from __future__ import annotations
 
@@ -71,6 +76,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
+    ap.add_argument("--sweep", action="store_true", help="bond-dimension sweep on the 10-site shapes")
+    ap.add_argument("--sweep-chis", default="64,128,256,512,1024")
+    ap.add_argument("--sweep-grid", type=int, default=1024)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -88,6 +96,8 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.sweep:
+        return sweep(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -215,6 +225,82 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _tt_entries(cores, idx):
+    """Entries T(x) = prod_i core_i[:, x_i, :] of a TT at the multi-indices
+    idx (S x N), by S vector-matrix chains grouped by physical value."""
+    import torch
+
+    S = idx.shape[0]
+    v = torch.ones(S, 1, dtype=torch.float64, device=idx.device)
+    for i, c in enumerate(cores):
+        nv = torch.zeros(S, c.shape[2], dtype=torch.float64, device=idx.device)
+        for e in range(c.shape[1]):
+            sel = (idx[:, i] == e).nonzero().squeeze(1)
+            if sel.numel():
+                nv[sel] = v[sel] @ c[:, e, :].contiguous()
+        v = nv
+    return v[:, 0]
+
+
+def sweep(args, dev):
+    import numpy as np
+    import torch
+
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    chis = [int(c) for c in args.sweep_chis.split(",") if c]
+    _log("generating %d^3 turbulence QTTs on the device for chi %s" % (args.sweep_grid, chis))
+    t0 = time.time()
+    qtts = I.turbulence_qtt_device(args.sweep_grid, 101, chis, dev)
+    torch.cuda.empty_cache()
+    _log("  done in %.1f s" % (time.time() - t0))
+    n_sites = len(next(iter(qtts.values())))
+    g = torch.Generator(device="cpu")
+    g.manual_seed(7)
+    idx = torch.randint(0, 8, (4096, n_sites), generator=g).to(dev)
+    for chi in chis:
+        A = T.pack(qtts[chi], dev)
+        ws = T.Workspace(dev)
+        _, cap = T.query(A, A, chi)
+        out = torch.empty(cap, dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream()
+        steps = 2 if chi <= 256 else 1
+        if chi <= 256:
+            T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            C, st = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        _, sp = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream, profile=True)
+        tot = sum(sp["kernel_ms"].values())
+        share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
+        a_cores = A.cores()
+        exact = _tt_entries(a_cores, idx) ** 2
+        got = _tt_entries(C.cores(), idx)
+        rel = float(torch.linalg.norm(got - exact) / torch.linalg.norm(exact))
+        line = {
+            "sweep": True, "chi": chi, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=8"
+            % (args.sweep_grid, n_sites), "eps": args.eps, "chi_out": chi, "chi_mid": chi,
+            "products_per_s": 1.0 / dt, "ms_per_product": 1e3 * dt, "steps": steps,
+            "model_flops": st["model_flops"], "svd_model_flops": st["svd_model_flops"],
+            "algorithmic_tflops": st["model_flops"] / dt / 1e12,
+            "fp64_mfma_frac": st["model_flops"] / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "jacobi_sweeps": st["sweeps"], "jacobi_max_sweeps": st["jacobi_max_sweeps"],
+            "max_bond": st["max_bond"], "n_svd": st["n_svd"],
+            "sampled_rel_err_vs_exact": rel, "sampled_points": int(idx.shape[0]),
+            "error_bound_abs": st["error_bound"], "kernel_time_share": share,
+            "workspace_bytes": st["peak_ws_bytes"],
+        }
+        print(json.dumps(line), flush=True)
+        _log("  chi=%d: %.1f ms per product, %.3f TFLOP/s algorithmic, %d sweeps, sampled rel err %.2e"
+             % (chi, 1e3 * dt, line["algorithmic_tflops"], st["sweeps"], rel))
+        del A, C, out, ws
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -89,15 +89,15 @@ JacobiPlan jacobi_plan(int L, int nc) {
 size_t jacobi_ws_doubles(const JacobiPlan &p) {
   const size_t b2 = 2 * (size_t)p.bw;
   size_t n = 0;
-  n += 2 * (size_t)p.L * p.ncp;           // W and its reordering buffer
-  n += (size_t)p.pairs * p.sw * b2 * b2;  // partial Grams
-  n += (size_t)p.rounds * p.pairs;        // conv
-  n += (size_t)p.pairs * MAXB2 * MAXB2;   // rotations of the current round
-  n += (size_t)p.pairs;                   // rotation flags (ints)
-  n += (size_t)p.ncp;                     // sigma
-  n += (size_t)p.ncp;                     // perm (ints, padded as doubles)
-  n += 8;                                 // result
-  return n + 9 * 32;                      // each of the 9 regions is rounded up to 32 doubles
+  n += 2 * (size_t)p.L * p.ncp;               // W and its reordering buffer
+  n += (size_t)p.pairs * p.sw * b2 * b2;      // partial Grams
+  n += (size_t)p.rounds * p.pairs;            // conv
+  n += (size_t)p.pairs * MAXB2 * MAXB2;       // rotations of the current round
+  n += (size_t)p.pairs;                       // rotation flags (ints)
+  n += (size_t)p.ncp;                         // sigma
+  n += (size_t)p.ncp;                         // perm (ints, padded as doubles)
+  n += 8;                                     // result
+  return n + 9 * 32;                          // each region is rounded up to 32 doubles
 }
 
 // ------------------------------------------------------------------ MFMA helpers
@@ -116,71 +116,81 @@ __device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
   return acc;
 }
 
-// ------------------------------------------------------------------ Gram partials
-// grid (pairs, sw).  Partial G = P^T P over rows [s*R, s*R+R) of the pair's
-// 2*bw columns (zero-padded to 32), one 16 x 16 tile per wave on MFMA.
-__global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int bw,
-                                                          int nblk, int round,
-                                                          double *__restrict__ part, int sw) {
-  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
-  const int pair = blockIdx.x, s = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int bi, bj;
-  rr_pair(nblk, round, pair, bi, bj);
-  const int b2 = 2 * bw;
-  const int r0 = s * ROWS_PER_WG;
-  const int nr = min(ROWS_PER_WG, L - r0);
-  for (int e = tid; e < ROWS_PER_WG * MAXB2; e += JNT) {
+// ------------------------------------------------------------------ pair pieces
+// LDS tile of one block pair: rows [chunk*128, chunk*128 + 128) of the 32
+// columns (block bi, then block bj), zero beyond row L.
+typedef double PairTile[ROWS_PER_WG][MAXB2 + 1];
+
+__device__ __forceinline__ int pair_col(int bi, int bj, int c) { return (c < BW) ? bi * BW + c : bj * BW + (c - BW); }
+
+__device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
+                                                PairTile &P) {
+  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
+  for (int e = threadIdx.x; e < ROWS_PER_WG * MAXB2; e += JNT) {
     const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    double v = 0.0;
-    if (c < b2 && i < nr) {
-      const int col = (c < bw) ? bi * bw + c : bj * bw + (c - bw);
-      v = W[(int64_t)col * L + r0 + i];
-    }
-    P[i][c] = v;
+    P[i][c] = (i < nr) ? W[(int64_t)pair_col(bi, bj, c) * L + r0 + i] : 0.0;
   }
-  __syncthreads();
+}
+
+// out (32 x 32, row-major) = P^T P over the tile; one 16 x 16 tile per wave.
+__device__ __forceinline__ void gram_of_tile(const PairTile &P, double *__restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ti = wave >> 1, tj = wave & 1;
   dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
                        [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
-  double *out = part + ((int64_t)pair * sw + s) * MAXB2 * MAXB2;
   for (int t = 0; t < 4; ++t) {
     const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
     out[i * MAXB2 + j] = acc[t];
   }
 }
 
+// W rows of the tile <- P Q (P, Q in LDS); 8 x 2 output tiles of 16 x 16,
+// wave w owns row tiles 2w and 2w+1.
+__device__ __forceinline__ void apply_tile(const PairTile &P, const double (*Q)[MAXB2 + 1],
+                                           double *__restrict__ W, int L, int bi, int bj, int chunk) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
+  for (int x = 0; x < 2; ++x) {
+    const int rt = 2 * wave + x;
+    for (int y = 0; y < 2; ++y) {
+      dbl4 acc = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
+                           [&](int k, int j) { return Q[k][y * 16 + j]; }, MAXB2, lane);
+      for (int t = 0; t < 4; ++t) {
+        const int i = rt * 16 + 4 * t + (lane >> 4), c = y * 16 + (lane & 15);
+        if (i < nr) W[(int64_t)pair_col(bi, bj, c) * L + r0 + i] = acc[t];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ rotate
 // Rotation (c, s) annihilating g_pq of a symmetric 2 x 2 block, or (1, 0)
-// when the pair is already orthogonal to tolerance (see the header).  The
-// hardware reciprocal / rsqrt approximations are enough for the angle; one
-// Newton step on c makes c^2 + s^2 = 1 to rounding.  Every thread that needs
-// a rotation computes it from the same inputs, so all copies agree bitwise.
+// when the pair is already orthogonal to tolerance (see the header).
+// Rutishauser's form: zeta = (g_qq - g_pp) / (2 g_pq),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t.
+// The angle only has to be close (later sweeps revisit the pair), so zeta and
+// t use the hardware FP64 reciprocal and reciprocal square root directly; c
+// gets one Newton step so that c^2 + s^2 = 1 to rounding for the t used.
+// Every thread that needs a rotation computes it from the same inputs, so all
+// copies agree bitwise.
 __device__ __forceinline__ void rot_params(double gpp, double gqq, double gpq, double thr, double tol2,
                                            double floor2, double &c, double &sn) {
   const double hi2 = fmax(gpp, gqq), lo2 = fmin(gpp, gqq);
   c = 1.0;
   sn = 0.0;
   if (hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2)) {
-    // The angle only has to be approximately right (the outer sweeps repeat
-    // every pair): zeta = (g_qq - g_pp) / (2 g_pq) and t = tan(angle) in FP32.
-    // c = 1 / sqrt(1 + t^2) is then refined in FP64 so that c^2 + s^2 = 1
-    // to rounding for the t actually used.
     const double zeta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
+    const double az = fabs(zeta);
     double t;
-    if (fabs(zeta) > 1e15) {
-      t = 0.5 * __builtin_amdgcn_rcp(zeta);
+    if (az > 1e150) {
+      t = 0.5 * __builtin_amdgcn_rcp(zeta);  // zeta^2 would overflow; t ~ 1 / (2 zeta)
     } else {
-      const float zf = (float)zeta;
-      const float az = fabsf(zf);
-      const float w = 1.0f + zf * zf;
-      const float tf = __builtin_amdgcn_rcpf(az + w * __builtin_amdgcn_rsqf(w));
-      t = copysign((double)tf, zeta);
+      const double w = fma(zeta, zeta, 1.0);
+      t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), zeta);
     }
-    const double x = 1.0 + t * t;
-    double y = (double)__builtin_amdgcn_rsqf((float)x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
+    const double x = fma(t, t, 1.0);
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
     c = y;
     sn = y * t;
   }
@@ -200,68 +210,80 @@ __device__ __forceinline__ void pair32(int st, int k, int &p, int &q) {
   q = max(a, b);
 }
 
-// grid (pairs).  One workgroup per block pair: reduce the partial Grams in a
-// fixed order, measure convergence, run one cyclic sweep of two-sided Jacobi
-// on the 32 x 32 Gram in LDS, re-orthogonalise the accumulated rotation and
-// store it (qbuf[pair], 32 x 32 row-major; flag[pair] = 1 when it is not the
-// identity).  A step rotates 16 disjoint index pairs at once; G <- J^T G J
-// splits into independent 2 x 2 blocks, one per thread, read from one copy of
-// G and written to the other, so a step needs a single barrier.
-__global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int round,
-                                                           const double *__restrict__ part, int sw,
-                                                           double *__restrict__ conv, double tol,
-                                                           const double *__restrict__ result,
-                                                           double noise2, double *__restrict__ qbuf,
-                                                           int *__restrict__ flag) {
-  __shared__ double Gb[2][MAXB2][MAXB2 + 1];
-  __shared__ double Q[MAXB2][MAXB2 + 1];
-  __shared__ double S[MAXB2][MAXB2 + 1];
-  __shared__ double redmax[JNT / 64];
-  static_assert(JNT == BW * BW, "one 2x2 block per thread");
+// Shared memory of the block-pair solve.
+struct SolveSmem {
+  double Gb[2][MAXB2][MAXB2 + 1];
+  double Q[MAXB2][MAXB2 + 1];
+  double S[MAXB2][MAXB2 + 1];
+  double redmax[JNT / 64];
+};
 
-  const int pair = blockIdx.x;
+// Solve of one block pair by its workgroup: reduce the sw partial Grams
+// (part, 32 x 32 each, consecutive) in a fixed order, measure convergence
+// (scaled off-diagonal maximum, returned in *mout in every thread), and
+// when some index pair exceeds tol run one cyclic sweep of two-sided Jacobi
+// on the 32 x 32 Gram in LDS, re-orthogonalise the accumulated rotation and
+// hand it to store(i, j, q_ij).  Returns 0 (nothing stored) when no rotation
+// is needed.  A step rotates 16 disjoint index pairs at once; G <- J^T G J
+// splits into independent 2 x 2 blocks, one per thread, read from one copy
+// of G and written to the other, so a step needs a single barrier.  Every
+// workgroup that solves the same partials computes bitwise the same result.
+template <typename Store>
+__device__ int solve_pair(const double *__restrict__ part, int sw, double tol, double thr, double floor2,
+                          SolveSmem &sm, double *mout, Store store) {
+  static_assert(JNT == BW * BW, "one 2x2 block per thread");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double thr = noise2 * result[5];
-  const double floor2 = result[5] / (double)L;  // (F / sqrt(L))^2
   const double tol2 = tol * tol;
-  // Reduce partial Grams in a fixed order.
   const int64_t pstride = (int64_t)MAXB2 * MAXB2;
-  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
-    const int i = e / MAXB2, j = e % MAXB2;
-    const double *src = part + (int64_t)pair * sw * pstride + e;
-    double acc = 0.0;
-    for (int s = 0; s < sw; ++s) acc += src[s * pstride];
-    Gb[0][i][j] = acc;
-    Q[i][j] = (i == j) ? 1.0 : 0.0;
+  // Thread tid sums entries tid + 256 j, j < 4, over the sw partials in order
+  // s = 0, 1, ...; the loads of four partials are issued before any add.
+  constexpr int EPT = MAXB2 * MAXB2 / JNT;
+  double acc[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
+  const double *src = part + tid;
+  int s0 = 0;
+  for (; s0 + 4 <= sw; s0 += 4) {
+    double v[4][EPT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) v[u][j] = src[(s0 + u) * pstride + j * JNT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) acc[j] += v[u][j];
+  }
+  for (; s0 < sw; ++s0)
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) acc[j] += src[s0 * pstride + j * JNT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + j * JNT, i = e / MAXB2, k = e % MAXB2;
+    sm.Gb[0][i][k] = acc[j];
+    sm.Q[i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-
   // Convergence measure of this visit (scaled off-diagonal, see the header).
-  {
-    double m = 0.0;
-    for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
-      const int p = e / MAXB2, q = e % MAXB2;
-      if (p < q) {
-        const double gp = Gb[0][p][p], gq = Gb[0][q][q];
-        if (gp > thr || gq > thr) {
-          const double a = sqrt(gp), b = sqrt(gq);
-          const double lo = fmin(a, b);
-          m = fmax(m, fabs(Gb[0][p][q]) / (fmax(a, b) * (lo * lo > thr ? lo : sqrt(floor2))));
-        }
+  double m = 0.0;
+  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
+    const int p = e / MAXB2, q = e % MAXB2;
+    if (p < q) {
+      const double gp = sm.Gb[0][p][p], gq = sm.Gb[0][q][q];
+      if (gp > thr || gq > thr) {
+        const double a = sqrt(gp), b = sqrt(gq);
+        const double lo = fmin(a, b);
+        m = fmax(m, fabs(sm.Gb[0][p][q]) / (fmax(a, b) * (lo * lo > thr ? lo : sqrt(floor2))));
       }
     }
-    m = wave_max(m);
-    if (lane == 0) redmax[wave] = m;
-    __syncthreads();
-    m = 0.0;
-    for (int w = 0; w < JNT / 64; ++w) m = fmax(m, redmax[w]);
-    if (tid == 0) conv[(int64_t)round * (nblk / 2) + pair] = m;
-    // No pair above tolerance: the inner sweep would rotate nothing.
-    if (!(m > tol)) {
-      if (tid == 0) flag[pair] = 0;
-      return;
-    }
   }
+  m = wave_max(m);
+  if (lane == 0) sm.redmax[wave] = m;
+  __syncthreads();
+  m = 0.0;
+  for (int w = 0; w < JNT / 64; ++w) m = fmax(m, sm.redmax[w]);
+  *mout = m;
+  if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
   // One cyclic sweep of two-sided Jacobi over the 32 indices (31 steps).
   const int u = tid >> 4, v = tid & 15;
@@ -270,8 +292,8 @@ __global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int 
     int pu, qu, pv, qv;
     pair32(step, u, pu, qu);
     pair32(step, v, pv, qv);
-    double (*Gc)[MAXB2 + 1] = Gb[cur];
-    double (*Gn)[MAXB2 + 1] = Gb[cur ^ 1];
+    double (*Gc)[MAXB2 + 1] = sm.Gb[cur];
+    double (*Gn)[MAXB2 + 1] = sm.Gb[cur ^ 1];
     double cu, su, cv, sv;
     rot_params(Gc[pu][pu], Gc[qu][qu], Gc[pu][qu], thr, tol2, floor2, cu, su);
     rot_params(Gc[pv][pv], Gc[qv][qv], Gc[pv][qv], thr, tol2, floor2, cv, sv);
@@ -287,9 +309,9 @@ __global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int 
     if (sv != 0.0) {
       for (int h = 0; h < 2; ++h) {
         const int k = 2 * u + h;
-        const double q0 = Q[k][pv], q1 = Q[k][qv];
-        Q[k][pv] = cv * q0 - sv * q1;
-        Q[k][qv] = sv * q0 + cv * q1;
+        const double q0 = sm.Q[k][pv], q1 = sm.Q[k][qv];
+        sm.Q[k][pv] = cv * q0 - sv * q1;
+        sm.Q[k][qv] = sv * q0 + cv * q1;
       }
     }
     cur ^= 1;
@@ -302,77 +324,75 @@ __global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int 
   // MFMA, one 16 x 16 tile per wave.
   const int ti = wave >> 1, tj = wave & 1;
   {
-    dbl4 acc = mfma_tile([&](int i, int k) { return Q[k][ti * 16 + i]; },
-                         [&](int k, int j) { return Q[k][tj * 16 + j]; }, MAXB2, lane);
-    for (int t = 0; t < 4; ++t) S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = acc[t];
+    dbl4 acc = mfma_tile([&](int i, int k) { return sm.Q[k][ti * 16 + i]; },
+                         [&](int k, int j) { return sm.Q[k][tj * 16 + j]; }, MAXB2, lane);
+    for (int t = 0; t < 4; ++t) sm.S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = acc[t];
   }
   __syncthreads();
   {
-    dbl4 acc = mfma_tile([&](int i, int k) { return Q[ti * 16 + i][k]; },
-                         [&](int k, int j) { return S[k][tj * 16 + j]; }, MAXB2, lane);
+    dbl4 acc = mfma_tile([&](int i, int k) { return sm.Q[ti * 16 + i][k]; },
+                         [&](int k, int j) { return sm.S[k][tj * 16 + j]; }, MAXB2, lane);
     for (int t = 0; t < 4; ++t) {
       const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-      qbuf[(int64_t)pair * MAXB2 * MAXB2 + i * MAXB2 + j] = 1.5 * Q[i][j] - 0.5 * acc[t];
+      store(i, j, 1.5 * sm.Q[i][j] - 0.5 * acc[t]);
     }
   }
-  if (tid == 0) flag[pair] = 1;
+  return 1;
 }
 
-
-// Rotate one 128-row chunk of the pair's 32 columns of X (column-major, leading
-// dimension ld, nrows rows): P (rows x 32) <- P Q, Q from qsrc (32 x 32).
-__device__ void apply_chunk(double *__restrict__ X, int ld, int nrows, int chunk, int bi, int bj,
-                            const double *__restrict__ qsrc, double (*Qn)[MAXB2 + 1],
-                            double (*P)[MAXB2 + 1]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, nrows - r0);
-  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) Qn[e / MAXB2][e % MAXB2] = qsrc[e];
-  for (int e = tid; e < ROWS_PER_WG * MAXB2; e += JNT) {
-    const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    double val = 0.0;
-    if (i < nr) {
-      const int col = (c < BW) ? bi * BW + c : bj * BW + (c - BW);
-      val = X[(int64_t)col * ld + r0 + i];
-    }
-    P[i][c] = val;
-  }
+// ------------------------------------------------------------------ one launch per stage
+// grid (pairs, sw).  Partial Gram of every block pair over one row chunk.
+__global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk,
+                                                          int round, double *__restrict__ part, int sw) {
+  __shared__ PairTile P;
+  const int pair = blockIdx.x, s = blockIdx.y;
+  int bi, bj;
+  rr_pair(nblk, round, pair, bi, bj);
+  load_pair_chunk(W, L, bi, bj, s, P);
   __syncthreads();
-  // 8 x 2 output tiles of 16 x 16; wave w owns row tiles 2w, 2w+1.
-  dbl4 acc[2][2];
-  for (int x = 0; x < 2; ++x) {
-    const int rt = 2 * wave + x;
-    for (int y = 0; y < 2; ++y)
-      acc[x][y] = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
-                            [&](int k, int j) { return Qn[k][y * 16 + j]; }, MAXB2, lane);
-  }
-  for (int x = 0; x < 2; ++x) {
-    const int rt = 2 * wave + x;
-    for (int y = 0; y < 2; ++y) {
-      for (int t = 0; t < 4; ++t) {
-        const int i = rt * 16 + 4 * t + (lane >> 4), c = y * 16 + (lane & 15);
-        if (i < nr) {
-          const int col = (c < BW) ? bi * BW + c : bj * BW + (c - BW);
-          X[(int64_t)col * ld + r0 + i] = acc[x][y][t];
-        }
-      }
-    }
+  gram_of_tile(P, part + ((int64_t)pair * sw + s) * MAXB2 * MAXB2);
+}
+
+// grid (pairs).  One workgroup per block pair: the solve, the rotation into
+// qbuf[pair] (32 x 32 row-major) and flag[pair] = 1 when it is not the identity.
+__global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int round,
+                                                           const double *__restrict__ part, int sw,
+                                                           double *__restrict__ conv, double tol,
+                                                           const double *__restrict__ result,
+                                                           double noise2, double *__restrict__ qbuf,
+                                                           int *__restrict__ flag) {
+  __shared__ SolveSmem sm;
+  const int pair = blockIdx.x;
+  const double thr = noise2 * result[5];
+  const double floor2 = result[5] / (double)L;  // (F / sqrt(L))^2
+  double *qo = qbuf + (int64_t)pair * MAXB2 * MAXB2;
+  double m;
+  const int rot = solve_pair(part + (int64_t)pair * sw * MAXB2 * MAXB2, sw, tol, thr, floor2, sm, &m,
+                             [&](int i, int j, double q) { qo[i * MAXB2 + j] = q; });
+  if (threadIdx.x == 0) {
+    conv[(int64_t)round * (nblk / 2) + pair] = m;
+    flag[pair] = rot;
   }
 }
 
-// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
-// of W.
+// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk of W.
 __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
                                                            const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
   __shared__ double Qn[MAXB2][MAXB2 + 1];
-  __shared__ double P[ROWS_PER_WG][MAXB2 + 1];
+  __shared__ PairTile P;
   const int pair = blockIdx.x, chunk = blockIdx.y;
   if (flag[pair] == 0) return;
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
-  apply_chunk(W, L, L, chunk, bi, bj, qbuf + (int64_t)pair * MAXB2 * MAXB2, Qn, P);
+  const double *qsrc = qbuf + (int64_t)pair * MAXB2 * MAXB2;
+  for (int e = threadIdx.x; e < MAXB2 * MAXB2; e += JNT) Qn[e / MAXB2][e % MAXB2] = qsrc[e];
+  load_pair_chunk(W, L, bi, bj, chunk, P);
+  __syncthreads();
+  apply_tile(P, Qn, W, L, bi, bj, chunk);
 }
 
+// result[3] = max of conv[0..n).
 __global__ void jacobi_convmax_kernel(const double *__restrict__ conv, int n, double *result) {
   __shared__ double red[JNT / 64];
   double m = 0.0;
@@ -410,8 +430,8 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
   for (int round = 0; round < p.rounds; ++round) {
     {
       Timed tm(timer, KC_JAC_GRAM, s);
-      hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.bw,
-                         p.nblk, round, b.part, p.sw);
+      hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
+                         b.part, p.sw);
     }
     {
       Timed tm(timer, KC_JAC_SOLVE, s);
@@ -420,14 +440,13 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
     }
     {
       Timed tm(timer, KC_JAC_APPLY, s);
-      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk,
-                         round, b.qbuf, b.flag);
+      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
+                         b.qbuf, b.flag);
     }
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
-    hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs,
-                       b.result);
+    hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs, b.result);
   }
   return hipGetLastError();
 }

@@ -134,12 +134,13 @@ struct JacobiBufs {
   int *perm = nullptr;      // ncp: perm[k] = column index of the k-th largest value
   double *qbuf = nullptr;   // pairs * 32 * 32: rotations of the current round
   int *flag = nullptr;      // pairs: rotation is not the identity
-  double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,[5]=squared Frobenius norm of W
+  double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,
+                            // [5]=squared Frobenius norm of W
 };
 
 // One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
 // off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.  Needs
-// result[5] = ||W||_F^2.
+// result[5] = ||W||_F^2.  Three launches per round: Gram, solve, apply.
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer = nullptr);
 // Reorder the columns of W by decreasing norm (swaps W/Wt).

@@ -258,6 +258,78 @@ def turbulence_qtt(n, seed, chi, kprime=None):
     return tt_svd(t, chi)
 
 
+def turbulence_qtt_device(n, seed, chis, device, kprime=None):
+    """QTTs of one synthetic turbulence component for grids too large for
+    the host path (1024^3: 8 GiB per field), one per bond cap in ``chis``.
+
+    The recipe of ``turbulence_component`` / ``turbulence_qtt`` run with
+    torch on ``device``: the same amplitudes and cut-off, phases from the FFT
+    of seeded real white noise (torch's generator on the device, so not the
+    host path's draws), unit RMS, the interleaved-bit order of
+    ``qtt_encode_3d``.  The left-to-right TT-SVD takes the leading
+    eigenvectors of each unfolding's Gram matrix (smaller side) instead of an
+    SVD; for an input that only has to be a TT of this field's structure at
+    bond cap chi, the squared conditioning of the Gram matrix is harmless.
+    Returns {chi: list of float64 numpy cores [r, 8, r']}.
+    """
+    import torch
+
+    if kprime is None:
+        kprime = n / 8.0
+    beta = 2.0 / kprime
+    f64 = torch.float64
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    noise = torch.randn((n, n, n), generator=g, dtype=f64, device=device)
+    phase = torch.angle(torch.fft.rfftn(noise))
+    del noise
+    k1 = torch.fft.fftfreq(n, 1.0 / n, dtype=f64, device=device)
+    kr = torch.fft.rfftfreq(n, 1.0 / n, dtype=f64, device=device)
+    k = torch.sqrt(k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    amp = torch.where(k > 1e-16, k.clamp_min(1e-16) ** (-11.0 / 6.0), torch.zeros_like(k))
+    amp = amp / (1.0 + torch.exp(torch.clamp(beta * (k - kprime), max=700.0)))
+    amp[k > n / 2.0] = 0.0
+    del k
+    uk = torch.polar(amp / np.sqrt(2.0), phase)
+    del amp, phase
+    u = torch.fft.irfftn(uk, s=(n, n, n))
+    del uk
+    u /= torch.sqrt(torch.mean(u * u))
+    L = int(round(np.log2(n)))
+    order = []
+    for s_ in range(L):
+        order += [s_, L + s_, 2 * L + s_]
+    field = u.reshape((2,) * (3 * L)).permute(order).contiguous().reshape(-1)
+    del u
+    out = {}
+    for chi in chis:
+        cores = []
+        rest = field.reshape(1, -1)
+        r_left = 1
+        for i in range(L - 1):
+            mat = rest.reshape(r_left * 8, -1)
+            m, ncol = mat.shape
+            r = min(m, ncol, chi) if chi and chi > 0 else min(m, ncol)
+            if m <= ncol:
+                _, evec = torch.linalg.eigh(mat @ mat.T)
+                U = evec[:, -r:].flip(1).contiguous()
+                cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+                rest = U.T @ mat
+            else:
+                _, evec = torch.linalg.eigh(mat.T @ mat)
+                V = evec[:, -r:].flip(1).contiguous()
+                US = mat @ V
+                s = torch.linalg.norm(US, dim=0)
+                U = US / torch.where(s > 0, s, torch.ones_like(s))
+                cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+                rest = s[:, None] * V.T
+            r_left = r
+        cores.append(rest.reshape(r_left, 8, 1).cpu().numpy())
+        out[chi] = cores
+        del rest
+    return out
+
+
 def app_a_toy_tt(n_sites, d_rest=2, chi=4, seed=0):
     """The toy TT of App. A: the first two carriages are
 
