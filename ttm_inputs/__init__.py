@@ -295,12 +295,20 @@ def turbulence_qtt_device(n, seed, chis, device, kprime=None):
     u = torch.fft.irfftn(uk, s=(n, n, n))
     del uk
     u /= torch.sqrt(torch.mean(u * u))
+    # Interleaved bit order in two passes (torch views hold at most 16
+    # dimensions): high halves of the three coordinates, then low halves.
     L = int(round(np.log2(n)))
-    order = []
-    for s_ in range(L):
-        order += [s_, L + s_, 2 * L + s_]
-    field = u.reshape((2,) * (3 * L)).permute(order).contiguous().reshape(-1)
+    h, lo = L // 2, L - L // 2
+
+    def interleave(nb):
+        return [a * nb + b for b in range(nb) for a in range(3)]
+
+    t = u.reshape(2 ** h, 2 ** lo, 2 ** h, 2 ** lo, 2 ** h, 2 ** lo).permute(0, 2, 4, 1, 3, 5).contiguous()
     del u
+    t = t.reshape((2,) * (3 * h) + (2 ** (3 * lo),)).permute(interleave(h) + [3 * h]).contiguous()
+    t = t.reshape((2 ** (3 * h),) + (2,) * (3 * lo)).permute([0] + [1 + i for i in interleave(lo)])
+    field = t.contiguous().reshape(-1)
+    del t
     out = {}
     for chi in chis:
         cores = []
