@@ -276,9 +276,11 @@ def sweep(args, dev):
             C, st = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        _, sp = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream, profile=True)
-        tot = sum(sp["kernel_ms"].values())
-        share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
+        share = None
+        if not args.no_profile:
+            _, sp = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream, profile=True)
+            tot = sum(sp["kernel_ms"].values())
+            share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
         a_cores = A.cores()
         exact = _tt_entries(a_cores, idx) ** 2
         got = _tt_entries(C.cores(), idx)

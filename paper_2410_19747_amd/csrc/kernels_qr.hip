@@ -62,16 +62,114 @@ __global__ void strided_to_colmajor_kernel(double *__restrict__ S, const double 
   }
 }
 
+// Block column pivoting for panel j0 (all PNT threads): the jb columns of
+// largest norm among positions [j0, n) (norms over rows j0.. in cnorm) move
+// to positions j0 .. j0+jb-1 in decreasing order (ties: lower position
+// first), and the columns they displace take the vacated positions.  Whole
+// columns move, since rows above j0 hold R.  perm[j] (the original index of
+// the column at position j) follows the moves.  scratch: 2 * QB * m doubles.
+constexpr int PIVOT_MAX_CAND = 8;  // candidates per thread: n - j0 <= PNT * 8
+__device__ void panel_pivot(double *__restrict__ S, int m, int n, int j0, int jb,
+                            const double *__restrict__ cnorm, int *__restrict__ perm,
+                            double *__restrict__ scratch) {
+  __shared__ double wv[PNT / 64];
+  __shared__ int wi[PNT / 64];
+  __shared__ int sel[QB], dpos[QB], vpos[QB], oldp[2 * QB];
+  __shared__ int nmove;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double cv[PIVOT_MAX_CAND];
+  int ci[PIVOT_MAX_CAND];
+#pragma unroll
+  for (int q = 0; q < PIVOT_MAX_CAND; ++q) {
+    ci[q] = j0 + tid + PNT * q;
+    cv[q] = (ci[q] < n) ? cnorm[ci[q]] : -1.0;
+  }
+  for (int t = 0; t < jb; ++t) {
+    double bv = -2.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < PIVOT_MAX_CAND; ++q)
+      if (cv[q] > bv || (cv[q] == bv && ci[q] < bi)) {
+        bv = cv[q];
+        bi = ci[q];
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[w] = bv;
+      wi[w] = bi;
+    }
+    __syncthreads();
+    double gv = wv[0];
+    int gi = wi[0];
+    for (int ww = 1; ww < PNT / 64; ++ww)
+      if (wv[ww] > gv || (wv[ww] == gv && wi[ww] < gi)) {
+        gv = wv[ww];
+        gi = wi[ww];
+      }
+    if (tid == 0) sel[t] = gi;
+#pragma unroll
+    for (int q = 0; q < PIVOT_MAX_CAND; ++q)
+      if (ci[q] == gi) cv[q] = -1.0;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int nd = 0, nv = 0;
+    bool identity = true;
+    for (int t = 0; t < jb; ++t) {
+      const int pos = j0 + t;
+      bool chosen = false;
+      for (int u = 0; u < jb; ++u) chosen |= (sel[u] == pos);
+      if (!chosen) dpos[nd++] = pos;
+      if (sel[t] >= j0 + jb) vpos[nv++] = sel[t];
+      identity &= (sel[t] == pos);
+    }
+    nmove = identity ? -1 : nd;
+    for (int t = 0; t < jb; ++t) oldp[t] = perm[sel[t]];
+    for (int d = 0; d < nd; ++d) oldp[QB + d] = perm[dpos[d]];
+  }
+  __syncthreads();
+  const int nd = nmove;
+  if (nd < 0) return;  // already in place
+  const int64_t tot = (int64_t)(jb + nd) * m;
+  for (int64_t e = tid; e < tot; e += PNT) {
+    const int c = (int)(e / m), i = (int)(e % m);
+    const int src = (c < jb) ? sel[c] : dpos[c - jb];
+    scratch[e] = S[(int64_t)src * m + i];
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < tot; e += PNT) {
+    const int c = (int)(e / m), i = (int)(e % m);
+    const int dst = (c < jb) ? j0 + c : vpos[c - jb];
+    S[(int64_t)dst * m + i] = scratch[e];
+  }
+  if (tid == 0) {
+    for (int t = 0; t < jb; ++t) perm[j0 + t] = oldp[t];
+    for (int d = 0; d < nd; ++d) perm[vpos[d]] = oldp[QB + d];
+  }
+  __syncthreads();
+}
+
 // Factor columns j0 .. j0+jb-1 of S (column-major, ld m) in place, rows
-// j0 .. m-1 (mv = m - j0 <= 64 * SL).  Each reflector is H = I - tau v v^T
+// j0 .. m-1 (mv = m - j0 <= 64 * SL), after block column pivoting when
+// cnorm is not null.  Each reflector is H = I - tau v v^T
 // with v(pivot) = 1 (LAPACK dlarfg convention); R goes on and above the
 // diagonal, v below it.  Also writes the explicit V (mv x 16, column-major,
 // unit diagonal, zero above and in columns >= jb) and T (16 x 16, row-major,
 // zero outside the leading jb x jb upper triangle) with
 // H_0 H_1 ... H_{jb-1} = I - V T V^T.
 template <int SL>
-__global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ S, int m, int j0, int jb,
-                                                           double *__restrict__ Vb, double *__restrict__ T) {
+__global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
+                                                           double *__restrict__ Vb, double *__restrict__ T,
+                                                           const double *__restrict__ cnorm, int *__restrict__ perm,
+                                                           double *__restrict__ pscratch) {
+  if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
   __shared__ double red[2][16][QB];     // per-wave column sums: [norm | v^T x][wave][column]
   __shared__ double piv[2][64 * SL];    // column cc before its reflection (double-buffered)
   __shared__ double zs[QB][QB + 1];     // zs[i][b] = v_b^T v_i, b < i
@@ -175,8 +273,11 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
 
 // The same factorisation for panels taller than the register panels: the
 // columns stay in memory and one wave updates one trailing column.
-__global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int j0, int jb,
-                                                           double *__restrict__ Vb, double *__restrict__ T) {
+__global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
+                                                           double *__restrict__ Vb, double *__restrict__ T,
+                                                           const double *__restrict__ cnorm, int *__restrict__ perm,
+                                                           double *__restrict__ pscratch) {
+  if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
   __shared__ double red[PNT / 64];
   __shared__ double Y[QB][QB + 1];
   __shared__ double Tl[QB][QB + 1];
@@ -259,10 +360,14 @@ __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ 
 //   W1 = V^T A (MFMA, the four waves split the rows), W2 = op(T) W1,
 //   A^T -= W2^T V^T (MFMA; the lanes of a row group write 16 consecutive
 //   rows of one column).
+// When cnorm is not null, cnorm[column] receives the norm of the updated
+// column over rows j0 + next .. m-1 (the next panel's candidates).
 __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, int m, int j0, int c0, int nc,
                                                         const double *__restrict__ Vb,
-                                                        const double *__restrict__ T, int trans) {
+                                                        const double *__restrict__ T, int trans,
+                                                        double *__restrict__ cnorm, int next) {
   __shared__ double Wp[4][QB][QB + 1];
+  __shared__ double nred[4][QB];
   __shared__ double W2[QB][QB + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
@@ -300,6 +405,7 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
   __syncthreads();
   const double wa0 = W2[q4][r16], wa1 = W2[4 + q4][r16], wa2 = W2[8 + q4][r16], wa3 = W2[12 + q4][r16];
   // Two 16-row tiles per iteration, every load issued before the products.
+  double nsq[4] = {0.0, 0.0, 0.0, 0.0};  // squared norms below row `next` of this lane's columns
   for (int i0 = 16 * w; i0 < mv; i0 += 128) {
     double vv[2][4], aa[2][4];
 #pragma unroll
@@ -325,10 +431,21 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int col = 4 * t + q4;
-          if (col < ncol) A[(int64_t)col * m + r] = aa[h][t] - d[t];
+          const double nv = aa[h][t] - d[t];
+          if (col < ncol) A[(int64_t)col * m + r] = nv;
+          if (r >= next) nsq[t] = fma(nv, nv, nsq[t]);
         }
       }
     }
+  }
+  if (cnorm) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      for (int o = 1; o < 16; o <<= 1) nsq[t] += __shfl_xor(nsq[t], o, 64);
+    if (r16 == 0)
+      for (int t = 0; t < 4; ++t) nred[w][4 * t + q4] = nsq[t];
+    __syncthreads();
+    if (tid < ncol) cnorm[cb + tid] = sqrt((nred[0][tid] + nred[1][tid]) + (nred[2][tid] + nred[3][tid]));
   }
 }
 
@@ -362,39 +479,62 @@ __global__ void qr_extract_v_kernel(const double *__restrict__ S, int m, int j0,
 }
 
 namespace {
-hipError_t launch_panel(double *S, int m, int j0, int jb, double *Vb, double *T, hipStream_t s) {
+struct Pivot {
+  const double *cnorm = nullptr;  // null: no pivoting
+  int *perm = nullptr;
+  double *scratch = nullptr;
+};
+
+hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *Vb, double *T, const Pivot &pv,
+                        hipStream_t s) {
   const int sl = (m - j0 + 63) / 64;
   const dim3 g(1), b(PNT);
-  if (sl <= 1) hipLaunchKernelGGL(qr_panel_reg_kernel<1>, g, b, 0, s, S, m, j0, jb, Vb, T);
-  else if (sl <= 2) hipLaunchKernelGGL(qr_panel_reg_kernel<2>, g, b, 0, s, S, m, j0, jb, Vb, T);
-  else if (sl <= 4) hipLaunchKernelGGL(qr_panel_reg_kernel<4>, g, b, 0, s, S, m, j0, jb, Vb, T);
-  else if (sl <= 8) hipLaunchKernelGGL(qr_panel_reg_kernel<8>, g, b, 0, s, S, m, j0, jb, Vb, T);
-  else if (sl <= MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_reg_kernel<16>, g, b, 0, s, S, m, j0, jb, Vb, T);
-  else hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, S, m, j0, jb, Vb, T);
+#define TTM_PANEL_ARGS S, m, n, j0, jb, Vb, T, pv.cnorm, pv.perm, pv.scratch
+  if (sl <= 1) hipLaunchKernelGGL(qr_panel_reg_kernel<1>, g, b, 0, s, TTM_PANEL_ARGS);
+  else if (sl <= 2) hipLaunchKernelGGL(qr_panel_reg_kernel<2>, g, b, 0, s, TTM_PANEL_ARGS);
+  else if (sl <= 4) hipLaunchKernelGGL(qr_panel_reg_kernel<4>, g, b, 0, s, TTM_PANEL_ARGS);
+  else if (sl <= 8) hipLaunchKernelGGL(qr_panel_reg_kernel<8>, g, b, 0, s, TTM_PANEL_ARGS);
+  else if (sl <= MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_reg_kernel<16>, g, b, 0, s, TTM_PANEL_ARGS);
+  else hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, TTM_PANEL_ARGS);
+#undef TTM_PANEL_ARGS
   return hipGetLastError();
 }
 
 hipError_t launch_update(double *S, int m, int j0, int c0, int nc, const double *Vb, const double *T,
-                         int trans, hipStream_t s) {
+                         int trans, double *cnorm, int next, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
   hipLaunchKernelGGL(qr_update_kernel, dim3((nc + QB - 1) / QB), dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T,
-                     trans);
+                     trans, cnorm, next);
   return hipGetLastError();
 }
 }  // namespace
 
-size_t qr_inplace_scratch_doubles(int m) { return (size_t)m * QB + QB * QB + 64; }
+size_t qr_inplace_scratch_doubles(int m, int n) {
+  return (size_t)m * QB + QB * QB + (size_t)n + 2 * (size_t)QB * m + 4 * 32;
+}
 
-hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, hipStream_t s) {
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipErrorInvalidValue;
+  if (perm && n > PNT * PIVOT_MAX_CAND) return hipErrorInvalidValue;
   const int k = m < n ? m : n;
-  double *Vb = scratch;
-  double *T = scratch + (((size_t)m * QB + 31) & ~(size_t)31);
+  double *p = scratch;
+  auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
+  double *Vb = adv((size_t)m * QB);
+  double *T = adv(QB * QB);
+  Pivot pv;
+  if (perm) {
+    double *cnorm = adv((size_t)n);
+    pv.cnorm = cnorm;
+    pv.perm = perm;
+    pv.scratch = adv(2 * (size_t)QB * m);
+    hipError_t e = launch_column_norms(S, m, n, cnorm, s);
+    if (e != hipSuccess) return e;
+  }
   for (int j0 = 0; j0 < k; j0 += QB) {
     const int jb = (k - j0) < QB ? (k - j0) : QB;
-    hipError_t e = launch_panel(S, m, j0, jb, Vb, T, s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, pv, s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, const_cast<double *>(pv.cnorm), jb, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -427,9 +567,9 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   for (int pi = 0; pi < np; ++pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall + (size_t)pi * QB * QB;
-    hipError_t e = launch_panel(S, m, j0, jb, Vb, T, s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, Pivot(), s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, nullptr, 0, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(qr_r_and_identity_kernel, dim3(grid_for((int64_t)k * n + (int64_t)m * k, 256)), dim3(256),
@@ -439,7 +579,7 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
                        j0, jb, Vb);
-    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, s);
+    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, s);
     if (e != hipSuccess) return e;
   }
   // q (m x k, row-major) from Qs (column-major)

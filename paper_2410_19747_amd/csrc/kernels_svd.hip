@@ -40,10 +40,8 @@
 namespace ttm {
 
 namespace {
-constexpr int JNT = 256;
-constexpr int BW = 16;        // block width
-constexpr int MAXB2 = 2 * BW; // columns of a block pair
-constexpr int ROWS_PER_WG = 128;
+constexpr int JNT = 256;           // threads of the Gram / apply / helper kernels
+constexpr int ROWS_PER_WG = 128;   // row chunk of a Gram / apply workgroup
 
 __device__ __forceinline__ void rr_pair(int n, int round, int k, int &a, int &b) {
   // Circle method over n (even) players: player n-1 fixed, the others rotate.
@@ -70,9 +68,13 @@ JacobiPlan jacobi_plan(int L, int nc) {
   JacobiPlan p;
   p.L = L;
   p.nc = nc;
-  // Fixed block width: the kernels are specialised for 2 * BW = 32 columns;
-  // narrower problems are padded with zero columns, which never rotate.
-  const int bw = BW;
+  // Block width 16: 32-column pairs and a 256-thread solve.  Wider pairs
+  // (64 columns, a 1024-thread solve) halve the rounds per sweep, but each of
+  // their twice as many inner steps moves four times the LDS bytes, and on
+  // gfx950 that costs more than the rounds saved at every size measured
+  // (1024 to 4096 columns).  Columns are padded with zeros to a whole even
+  // number of blocks; zero columns never rotate.
+  const int bw = 16;
   int nblk = (nc + bw - 1) / bw;
   if (nblk < 2) nblk = 2;
   if (nblk & 1) ++nblk;
@@ -92,7 +94,7 @@ size_t jacobi_ws_doubles(const JacobiPlan &p) {
   n += 2 * (size_t)p.L * p.ncp;               // W and its reordering buffer
   n += (size_t)p.pairs * p.sw * b2 * b2;      // partial Grams
   n += (size_t)p.rounds * p.pairs;            // conv
-  n += (size_t)p.pairs * MAXB2 * MAXB2;       // rotations of the current round
+  n += (size_t)p.pairs * b2 * b2;             // rotations of the current round
   n += (size_t)p.pairs;                       // rotation flags (ints)
   n += (size_t)p.ncp;                         // sigma
   n += (size_t)p.ncp;                         // perm (ints, padded as doubles)
@@ -117,53 +119,67 @@ __device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
 }
 
 // ------------------------------------------------------------------ pair pieces
-// LDS tile of one block pair: rows [chunk*128, chunk*128 + 128) of the 32
-// columns (block bi, then block bj), zero beyond row L.
-typedef double PairTile[ROWS_PER_WG][MAXB2 + 1];
+// A block pair is 2 BW columns: block bi, then block bj.
+template <int BW>
+struct Pair {
+  static constexpr int B2 = 2 * BW;    // columns of the pair
+  static constexpr int SNT = BW * BW;  // threads of the solve: one 2 x 2 block of the Gram each
+  typedef double Tile[ROWS_PER_WG][B2 + 1];  // rows [chunk*128, +128) of the pair, zero beyond L
+  typedef double Square[B2][B2 + 1];
+};
 
-__device__ __forceinline__ int pair_col(int bi, int bj, int c) { return (c < BW) ? bi * BW + c : bj * BW + (c - BW); }
+template <int BW>
+__device__ __forceinline__ int pair_col(int bi, int bj, int c) {
+  return (c < BW) ? bi * BW + c : bj * BW + (c - BW);
+}
 
+template <int BW>
 __device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
-                                                PairTile &P) {
+                                                typename Pair<BW>::Tile &P) {
+  constexpr int B2 = Pair<BW>::B2;
   const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
-  for (int e = threadIdx.x; e < ROWS_PER_WG * MAXB2; e += JNT) {
+  for (int e = threadIdx.x; e < ROWS_PER_WG * B2; e += JNT) {
     const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    P[i][c] = (i < nr) ? W[(int64_t)pair_col(bi, bj, c) * L + r0 + i] : 0.0;
+    P[i][c] = (i < nr) ? W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] : 0.0;
   }
 }
 
-// out (32 x 32, row-major) = P^T P over the tile; one 16 x 16 tile per wave.
-__device__ __forceinline__ void gram_of_tile(const PairTile &P, double *__restrict__ out) {
+// out (B2 x B2, row-major) = P^T P over the tile; the four waves take the
+// 16 x 16 output tiles in turn.
+template <int BW>
+__device__ __forceinline__ void gram_of_tile(const typename Pair<BW>::Tile &P, double *__restrict__ out) {
+  constexpr int B2 = Pair<BW>::B2, NT = B2 / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ti = wave >> 1, tj = wave & 1;
-  dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
-                       [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
-  for (int t = 0; t < 4; ++t) {
-    const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-    out[i * MAXB2 + j] = acc[t];
-  }
-}
-
-// W rows of the tile <- P Q (P, Q in LDS); 8 x 2 output tiles of 16 x 16,
-// wave w owns row tiles 2w and 2w+1.
-__device__ __forceinline__ void apply_tile(const PairTile &P, const double (*Q)[MAXB2 + 1],
-                                           double *__restrict__ W, int L, int bi, int bj, int chunk) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
-  for (int x = 0; x < 2; ++x) {
-    const int rt = 2 * wave + x;
-    for (int y = 0; y < 2; ++y) {
-      dbl4 acc = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
-                           [&](int k, int j) { return Q[k][y * 16 + j]; }, MAXB2, lane);
-      for (int t = 0; t < 4; ++t) {
-        const int i = rt * 16 + 4 * t + (lane >> 4), c = y * 16 + (lane & 15);
-        if (i < nr) W[(int64_t)pair_col(bi, bj, c) * L + r0 + i] = acc[t];
-      }
+  for (int t = wave; t < NT * NT; t += JNT / 64) {
+    const int ti = t / NT, tj = t % NT;
+    dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
+                         [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti * 16 + 4 * q + (lane >> 4), j = tj * 16 + (lane & 15);
+      out[i * B2 + j] = acc[q];
     }
   }
 }
 
-// ------------------------------------------------------------------ rotate
+// W rows of the tile <- P Q (P, Q in LDS); the four waves take the 16 x 16
+// output tiles in turn.
+template <int BW>
+__device__ __forceinline__ void apply_tile(const typename Pair<BW>::Tile &P, const typename Pair<BW>::Square &Q,
+                                           double *__restrict__ W, int L, int bi, int bj, int chunk) {
+  constexpr int B2 = Pair<BW>::B2, NC = B2 / 16, NR = ROWS_PER_WG / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
+  for (int t = wave; t < NR * NC; t += JNT / 64) {
+    const int rt = t / NC, y = t % NC;
+    dbl4 acc = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
+                         [&](int k, int j) { return Q[k][y * 16 + j]; }, B2, lane);
+    for (int q = 0; q < 4; ++q) {
+      const int i = rt * 16 + 4 * q + (lane >> 4), c = y * 16 + (lane & 15);
+      if (i < nr) W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] = acc[q];
+    }
+  }
+}
+
 // Rotation (c, s) annihilating g_pq of a symmetric 2 x 2 block, or (1, 0)
 // when the pair is already orthogonal to tolerance (see the header).
 // Rutishauser's form: zeta = (g_qq - g_pp) / (2 g_pq),
@@ -196,48 +212,52 @@ __device__ __forceinline__ void rot_params(double gpp, double gqq, double gpq, d
   }
 }
 
-// Pair k of step st of the round-robin over 32 indices, ordered p < q.
-__device__ __forceinline__ void pair32(int st, int k, int &p, int &q) {
+// Pair k of step st of the round-robin (circle method) over n indices,
+// ordered p < q.
+__device__ __forceinline__ void round_robin_pair(int n, int st, int k, int &p, int &q) {
   int a, b;
   if (k == 0) {
     a = st;
-    b = MAXB2 - 1;
+    b = n - 1;
   } else {
-    a = (st + k) % (MAXB2 - 1);
-    b = (st - k + (MAXB2 - 1)) % (MAXB2 - 1);
+    a = (st + k) % (n - 1);
+    b = (st - k + (n - 1)) % (n - 1);
   }
   p = min(a, b);
   q = max(a, b);
 }
 
 // Shared memory of the block-pair solve.
+template <int BW>
 struct SolveSmem {
-  double Gb[2][MAXB2][MAXB2 + 1];
-  double Q[MAXB2][MAXB2 + 1];
-  double S[MAXB2][MAXB2 + 1];
-  double redmax[JNT / 64];
+  typename Pair<BW>::Square Gb[2];
+  typename Pair<BW>::Square Q;
+  typename Pair<BW>::Square S;
+  double redmax[Pair<BW>::SNT / 64];
 };
 
-// Solve of one block pair by its workgroup: reduce the sw partial Grams
-// (part, 32 x 32 each, consecutive) in a fixed order, measure convergence
-// (scaled off-diagonal maximum, returned in *mout in every thread), and
-// when some index pair exceeds tol run one cyclic sweep of two-sided Jacobi
-// on the 32 x 32 Gram in LDS, re-orthogonalise the accumulated rotation and
-// hand it to store(i, j, q_ij).  Returns 0 (nothing stored) when no rotation
-// is needed.  A step rotates 16 disjoint index pairs at once; G <- J^T G J
-// splits into independent 2 x 2 blocks, one per thread, read from one copy
-// of G and written to the other, so a step needs a single barrier.  Every
-// workgroup that solves the same partials computes bitwise the same result.
-template <typename Store>
+// Solve of one block pair by its workgroup (BW * BW threads): reduce the sw
+// partial Grams (part, B2 x B2 each, consecutive) in a fixed order, measure
+// convergence (scaled off-diagonal maximum, returned in *mout in every
+// thread), and when some index pair exceeds tol run one cyclic sweep of
+// two-sided Jacobi on the B2 x B2 Gram in LDS, re-orthogonalise the
+// accumulated rotation and hand it to store(i, j, q_ij).  Returns 0 (nothing
+// stored) when no rotation is needed.  A step rotates BW disjoint index pairs
+// at once; G <- J^T G J splits into independent 2 x 2 blocks, one per
+// thread, read from one copy of G and written to the other, so a step needs a
+// single barrier.  Every workgroup that solves the same partials computes
+// bitwise the same result.
+template <int BW, typename Store>
 __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, double thr, double floor2,
-                          SolveSmem &sm, double *mout, Store store) {
-  static_assert(JNT == BW * BW, "one 2x2 block per thread");
+                          SolveSmem<BW> &sm, double *mout, Store store) {
+  constexpr int B2 = Pair<BW>::B2, SNT = Pair<BW>::SNT, NT = B2 / 16;
+  static_assert(NT * NT == SNT / 64, "one 16 x 16 tile of the Newton-Schulz products per wave");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double tol2 = tol * tol;
-  const int64_t pstride = (int64_t)MAXB2 * MAXB2;
-  // Thread tid sums entries tid + 256 j, j < 4, over the sw partials in order
+  const int64_t pstride = (int64_t)B2 * B2;
+  // Thread tid sums entries tid + SNT j, j < 4, over the sw partials in order
   // s = 0, 1, ...; the loads of four partials are issued before any add.
-  constexpr int EPT = MAXB2 * MAXB2 / JNT;
+  constexpr int EPT = B2 * B2 / SNT;
   double acc[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
@@ -248,7 +268,7 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) v[u][j] = src[(s0 + u) * pstride + j * JNT];
+      for (int j = 0; j < EPT; ++j) v[u][j] = src[(s0 + u) * pstride + j * SNT];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -256,18 +276,18 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   }
   for (; s0 < sw; ++s0)
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) acc[j] += src[s0 * pstride + j * JNT];
+    for (int j = 0; j < EPT; ++j) acc[j] += src[s0 * pstride + j * SNT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    const int e = tid + j * JNT, i = e / MAXB2, k = e % MAXB2;
+    const int e = tid + j * SNT, i = e / B2, k = e % B2;
     sm.Gb[0][i][k] = acc[j];
     sm.Q[i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
   // Convergence measure of this visit (scaled off-diagonal, see the header).
   double m = 0.0;
-  for (int e = tid; e < MAXB2 * MAXB2; e += JNT) {
-    const int p = e / MAXB2, q = e % MAXB2;
+  for (int e = tid; e < B2 * B2; e += SNT) {
+    const int p = e / B2, q = e % B2;
     if (p < q) {
       const double gp = sm.Gb[0][p][p], gq = sm.Gb[0][q][q];
       if (gp > thr || gq > thr) {
@@ -281,19 +301,19 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   if (lane == 0) sm.redmax[wave] = m;
   __syncthreads();
   m = 0.0;
-  for (int w = 0; w < JNT / 64; ++w) m = fmax(m, sm.redmax[w]);
+  for (int w = 0; w < SNT / 64; ++w) m = fmax(m, sm.redmax[w]);
   *mout = m;
   if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
-  // One cyclic sweep of two-sided Jacobi over the 32 indices (31 steps).
-  const int u = tid >> 4, v = tid & 15;
+  // One cyclic sweep of two-sided Jacobi over the B2 indices (B2 - 1 steps).
+  const int u = tid / BW, v = tid % BW;
   int cur = 0;
-  for (int step = 0; step < MAXB2 - 1; ++step) {
+  for (int step = 0; step < B2 - 1; ++step) {
     int pu, qu, pv, qv;
-    pair32(step, u, pu, qu);
-    pair32(step, v, pv, qv);
-    double (*Gc)[MAXB2 + 1] = sm.Gb[cur];
-    double (*Gn)[MAXB2 + 1] = sm.Gb[cur ^ 1];
+    round_robin_pair(B2, step, u, pu, qu);
+    round_robin_pair(B2, step, v, pv, qv);
+    double (*Gc)[B2 + 1] = sm.Gb[cur];
+    double (*Gn)[B2 + 1] = sm.Gb[cur ^ 1];
     double cu, su, cv, sv;
     rot_params(Gc[pu][pu], Gc[qu][qu], Gc[pu][qu], thr, tol2, floor2, cu, su);
     rot_params(Gc[pv][pv], Gc[qv][qv], Gc[pv][qv], thr, tol2, floor2, cv, sv);
@@ -320,55 +340,58 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 
   // One Newton-Schulz step, Q <- Q (3I - Q^T Q) / 2, restores orthogonality
   // to rounding level; without it the O(u) drift of every visit accumulates
-  // over the thousands of visits a column receives.  32 x 32 products on
+  // over the thousands of visits a column receives.  B2 x B2 products on
   // MFMA, one 16 x 16 tile per wave.
-  const int ti = wave >> 1, tj = wave & 1;
+  const int ti = wave / NT, tj = wave % NT;
   {
-    dbl4 acc = mfma_tile([&](int i, int k) { return sm.Q[k][ti * 16 + i]; },
-                         [&](int k, int j) { return sm.Q[k][tj * 16 + j]; }, MAXB2, lane);
-    for (int t = 0; t < 4; ++t) sm.S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = acc[t];
+    dbl4 a4 = mfma_tile([&](int i, int k) { return sm.Q[k][ti * 16 + i]; },
+                        [&](int k, int j) { return sm.Q[k][tj * 16 + j]; }, B2, lane);
+    for (int t = 0; t < 4; ++t) sm.S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = a4[t];
   }
   __syncthreads();
   {
-    dbl4 acc = mfma_tile([&](int i, int k) { return sm.Q[ti * 16 + i][k]; },
-                         [&](int k, int j) { return sm.S[k][tj * 16 + j]; }, MAXB2, lane);
+    dbl4 a4 = mfma_tile([&](int i, int k) { return sm.Q[ti * 16 + i][k]; },
+                        [&](int k, int j) { return sm.S[k][tj * 16 + j]; }, B2, lane);
     for (int t = 0; t < 4; ++t) {
       const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-      store(i, j, 1.5 * sm.Q[i][j] - 0.5 * acc[t]);
+      store(i, j, 1.5 * sm.Q[i][j] - 0.5 * a4[t]);
     }
   }
   return 1;
 }
 
-// ------------------------------------------------------------------ one launch per stage
+// ------------------------------------------------------------------ kernels of a round
 // grid (pairs, sw).  Partial Gram of every block pair over one row chunk.
+template <int BW>
 __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk,
                                                           int round, double *__restrict__ part, int sw) {
-  __shared__ PairTile P;
+  __shared__ typename Pair<BW>::Tile P;
+  constexpr int B2 = Pair<BW>::B2;
   const int pair = blockIdx.x, s = blockIdx.y;
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
-  load_pair_chunk(W, L, bi, bj, s, P);
+  load_pair_chunk<BW>(W, L, bi, bj, s, P);
   __syncthreads();
-  gram_of_tile(P, part + ((int64_t)pair * sw + s) * MAXB2 * MAXB2);
+  gram_of_tile<BW>(P, part + ((int64_t)pair * sw + s) * B2 * B2);
 }
 
 // grid (pairs).  One workgroup per block pair: the solve, the rotation into
-// qbuf[pair] (32 x 32 row-major) and flag[pair] = 1 when it is not the identity.
-__global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int round,
-                                                           const double *__restrict__ part, int sw,
-                                                           double *__restrict__ conv, double tol,
-                                                           const double *__restrict__ result,
-                                                           double noise2, double *__restrict__ qbuf,
-                                                           int *__restrict__ flag) {
-  __shared__ SolveSmem sm;
+// qbuf[pair] (B2 x B2 row-major) and flag[pair] = 1 when it is not the identity.
+template <int BW>
+__global__ __launch_bounds__(BW *BW) void jacobi_solve_kernel(int L, int nblk, int round,
+                                                              const double *__restrict__ part, int sw,
+                                                              double *__restrict__ conv, double tol,
+                                                              const double *__restrict__ result, double noise2,
+                                                              double *__restrict__ qbuf, int *__restrict__ flag) {
+  __shared__ SolveSmem<BW> sm;
+  constexpr int B2 = Pair<BW>::B2;
   const int pair = blockIdx.x;
   const double thr = noise2 * result[5];
   const double floor2 = result[5] / (double)L;  // (F / sqrt(L))^2
-  double *qo = qbuf + (int64_t)pair * MAXB2 * MAXB2;
+  double *qo = qbuf + (int64_t)pair * B2 * B2;
   double m;
-  const int rot = solve_pair(part + (int64_t)pair * sw * MAXB2 * MAXB2, sw, tol, thr, floor2, sm, &m,
-                             [&](int i, int j, double q) { qo[i * MAXB2 + j] = q; });
+  const int rot = solve_pair<BW>(part + (int64_t)pair * sw * B2 * B2, sw, tol, thr, floor2, sm, &m,
+                                 [&](int i, int j, double q) { qo[i * B2 + j] = q; });
   if (threadIdx.x == 0) {
     conv[(int64_t)round * (nblk / 2) + pair] = m;
     flag[pair] = rot;
@@ -376,20 +399,22 @@ __global__ __launch_bounds__(JNT) void jacobi_solve_kernel(int L, int nblk, int 
 }
 
 // grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk of W.
+template <int BW>
 __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
                                                            const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
-  __shared__ double Qn[MAXB2][MAXB2 + 1];
-  __shared__ PairTile P;
+  __shared__ typename Pair<BW>::Square Qn;
+  __shared__ typename Pair<BW>::Tile P;
+  constexpr int B2 = Pair<BW>::B2;
   const int pair = blockIdx.x, chunk = blockIdx.y;
   if (flag[pair] == 0) return;
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
-  const double *qsrc = qbuf + (int64_t)pair * MAXB2 * MAXB2;
-  for (int e = threadIdx.x; e < MAXB2 * MAXB2; e += JNT) Qn[e / MAXB2][e % MAXB2] = qsrc[e];
-  load_pair_chunk(W, L, bi, bj, chunk, P);
+  const double *qsrc = qbuf + (int64_t)pair * B2 * B2;
+  for (int e = threadIdx.x; e < B2 * B2; e += JNT) Qn[e / B2][e % B2] = qsrc[e];
+  load_pair_chunk<BW>(W, L, bi, bj, chunk, P);
   __syncthreads();
-  apply_tile(P, Qn, W, L, bi, bj, chunk);
+  apply_tile<BW>(P, Qn, W, L, bi, bj, chunk);
 }
 
 // result[3] = max of conv[0..n).
@@ -423,27 +448,34 @@ __global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restr
   }
 }
 
+namespace {
+template <int BW>
+void launch_round(const JacobiPlan &p, const JacobiBufs &b, int round, double tol, double noise2, hipStream_t s,
+                  KernelTimer *timer) {
+  {
+    Timed tm(timer, KC_JAC_GRAM, s);
+    hipLaunchKernelGGL(jacobi_gram_kernel<BW>, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
+                       b.part, p.sw);
+  }
+  {
+    Timed tm(timer, KC_JAC_SOLVE, s);
+    hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(BW * BW), 0, s, p.L, p.nblk, round, b.part,
+                       p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
+  }
+  {
+    Timed tm(timer, KC_JAC_APPLY, s);
+    hipLaunchKernelGGL(jacobi_apply_kernel<BW>, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
+                       b.qbuf, b.flag);
+  }
+}
+}  // namespace
+
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer) {
   const double ns = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;
   const double noise2 = ns * ns;
-  for (int round = 0; round < p.rounds; ++round) {
-    {
-      Timed tm(timer, KC_JAC_GRAM, s);
-      hipLaunchKernelGGL(jacobi_gram_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
-                         b.part, p.sw);
-    }
-    {
-      Timed tm(timer, KC_JAC_SOLVE, s);
-      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(p.pairs), dim3(JNT), 0, s, p.L, p.nblk, round, b.part,
-                         p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
-    }
-    {
-      Timed tm(timer, KC_JAC_APPLY, s);
-      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
-                         b.qbuf, b.flag);
-    }
-  }
+  if (p.bw != 16) return hipErrorInvalidValue;
+  for (int round = 0; round < p.rounds; ++round) launch_round<16>(p, b, round, tol, noise2, s, timer);
   {
     Timed tm(timer, KC_JAC_OTHER, s);
     hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs, b.result);

@@ -281,7 +281,7 @@ struct Runner {
   double *wbuf = nullptr, *qrbuf = nullptr, *rbuf = nullptr;
   int *flags = nullptr;
   int64_t max_core = 0;
-  bool trace = false;
+  int trace = 0;  // TTM_TRACE: 1 = one line per step, 2 = also one per Jacobi sweep
   // stats
   int n_contract = 0, n_swap = 0, n_qr = 0, n_svd = 0, n_trace = 0, max_bond = 1;
   int jac_sweeps = 0, jac_max = 0;
@@ -291,7 +291,8 @@ struct Runner {
   KernelTimer timer;
 
   Runner(hipStream_t s, const Options &opt) : st(s), o(opt) {
-    trace = getenv("TTM_TRACE") != nullptr;
+    const char *tv = getenv("TTM_TRACE");
+    trace = tv ? (atoi(tv) > 0 ? atoi(tv) : 1) : 0;
     timer.on = opt.profile != 0;
   }
   // synchronise the stream and read the event timers

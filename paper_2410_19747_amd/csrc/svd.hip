@@ -32,14 +32,14 @@ SvdBufs carve(const SvdPlan &p, double *base) {
   };
   const JacobiPlan &jp = p.jp;
   b.S = adv((size_t)p.np * p.no);
-  b.qr = adv(qr_inplace_scratch_doubles(p.np));
+  b.qr = adv(qr_inplace_scratch_doubles(p.np, p.no));
   b.ynorm = adv((size_t)p.no);
   b.perm0 = reinterpret_cast<int *>(adv((size_t)p.no));
   b.jb.W = adv((size_t)jp.L * jp.ncp);
   b.jb.Wt = adv((size_t)jp.L * jp.ncp);
   b.jb.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
   b.jb.conv = adv((size_t)jp.rounds * jp.pairs);
-  b.jb.qbuf = adv((size_t)jp.pairs * 32 * 32);
+  b.jb.qbuf = adv((size_t)jp.pairs * 4 * jp.bw * jp.bw);
   b.jb.flag = reinterpret_cast<int *>(adv((size_t)jp.pairs));
   b.jb.sigma = adv((size_t)jp.ncp);
   b.jb.perm = reinterpret_cast<int *>(adv((size_t)jp.ncp));
@@ -67,12 +67,12 @@ size_t svd_ws_doubles(const SvdPlan &p) {
   const JacobiPlan &jp = p.jp;
   size_t n = 0;
   n += r32((size_t)p.np * p.no);
-  n += r32(qr_inplace_scratch_doubles(p.np));
+  n += r32(qr_inplace_scratch_doubles(p.np, p.no));
   n += 2 * r32((size_t)p.no);
   n += 2 * r32((size_t)jp.L * jp.ncp);
   n += r32((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
   n += r32((size_t)jp.rounds * jp.pairs);
-  n += r32((size_t)jp.pairs * 32 * 32);
+  n += r32((size_t)jp.pairs * 4 * jp.bw * jp.bw);
   n += r32((size_t)jp.pairs);
   n += 2 * r32((size_t)jp.ncp);
   n += r32(8);
@@ -81,7 +81,7 @@ size_t svd_ws_doubles(const SvdPlan &p) {
 
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, bool trace) {
+                    KernelTimer *timer, int trace) {
   SvdResult out;
   SvdBufs b = carve(p, ws);
   const JacobiPlan &jp = p.jp;
@@ -108,7 +108,10 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   }
   {
     Timed tm(timer, KC_QR, s);
-    if (!ok(launch_qr_inplace(b.S, p.np, p.no, b.qr, s))) return out;
+    // Block column pivoting in the QR saves Jacobi sweeps (the rows of R come
+    // out graded); its selection step pays off once a sweep is expensive.
+    int *pivot = (p.no >= 2048) ? b.perm0 : nullptr;
+    if (!ok(launch_qr_inplace(b.S, p.np, p.no, b.qr, pivot, s))) return out;
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
@@ -129,7 +132,7 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
     if (!ok(hipMemcpyAsync(res, b.jb.result, sizeof(res), hipMemcpyDeviceToHost, s))) return out;
     if (!sync()) return out;
     const double off = res[3];
-    if (trace) fprintf(stderr, "[ttm]   jacobi %dx%d sweep %d off=%.3e tol=%.3e\n", jp.L, jp.nc, sw, off, tol);
+    if (trace >= 2) fprintf(stderr, "[ttm]   jacobi %dx%d sweep %d off=%.3e tol=%.3e\n", jp.L, jp.nc, sw, off, tol);
     if (!(off == off)) break;  // NaN
     if (off <= tol) {
       conv = true;

@@ -57,7 +57,7 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
     // right factor orthonormal: Y = M (m x n), column-major copy of row-major M
     if (ttm::launch_transpose(Yt, M, m, n, s) != hipSuccess) return TTM_EHIP;
     const ttm::SvdPlan sp = ttm::svd_plan(m, n);
-    res = ttm::svd_oside(sp, Yt, eps, cap, forced, 60, right, ttm::SVD_U_T, sigma, sws, s, nullptr, false);
+    res = ttm::svd_oside(sp, Yt, eps, cap, forced, 60, right, ttm::SVD_U_T, sigma, sws, s, nullptr, 0);
     if (res.err == TTM_OK) {
       ttm::GemmArgs g;  // left = M V_r
       g.M = m; g.N = res.rank; g.K = n;
@@ -69,7 +69,7 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
   } else {
     // left factor orthonormal: Y = M^T, whose column-major storage is M's
     const ttm::SvdPlan sp = ttm::svd_plan(n, m);
-    res = ttm::svd_oside(sp, M, eps, cap, forced, 60, left, ttm::SVD_U, sigma, sws, s, nullptr, false);
+    res = ttm::svd_oside(sp, M, eps, cap, forced, 60, left, ttm::SVD_U, sigma, sws, s, nullptr, 0);
     if (res.err == TTM_OK) {
       ttm::GemmArgs g;  // right = U_r^T M
       g.M = res.rank; g.N = n; g.K = m;

@@ -103,9 +103,13 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
 size_t qr_scratch_doubles(int m, int n);
 // In-place Householder QR of the column-major m x n matrix S (ld m), R only:
 // on return the upper trapezoid of S[0:k, :] is R and the reflectors lie
-// below it.  scratch: qr_inplace_scratch_doubles(m).
-hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, hipStream_t s);
-size_t qr_inplace_scratch_doubles(int m);
+// below it.  With perm (device, n ints) not null the factorisation uses
+// block column pivoting: before each 16-column panel the 16 columns of
+// largest remaining norm are moved into it (n <= 8192), so that S P = Q R,
+// and perm is permuted along (perm[j] = the column held at position j).
+// scratch: qr_inplace_scratch_doubles(m, n).
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, hipStream_t s);
+size_t qr_inplace_scratch_doubles(int m, int n);
 
 // ------------------------------------------------------------------ Jacobi
 // One-sided block Jacobi on an L x nc column-major matrix W (ld = L),
@@ -132,7 +136,7 @@ struct JacobiBufs {
   double *conv = nullptr;   // rounds * pairs: scaled off-diagonal maxima
   double *sigma = nullptr;  // ncp
   int *perm = nullptr;      // ncp: perm[k] = column index of the k-th largest value
-  double *qbuf = nullptr;   // pairs * 32 * 32: rotations of the current round
+  double *qbuf = nullptr;   // pairs * (2bw)^2: rotations of the current round
   int *flag = nullptr;      // pairs: rotation is not the identity
   double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,
                             // [5]=squared Frobenius norm of W
@@ -193,11 +197,12 @@ struct SvdResult {
 // row-major: u[o*r + t]) when u_layout == SVD_U.  forced > 0 replaces the
 // rank rule.  When sigma_out is not null the k
 // singular values are written there in decreasing order.  Synchronises the
-// stream once per Jacobi sweep (convergence test) and at the end.
+// stream once per Jacobi sweep (convergence test) and at the end.  trace > 0
+// prints one line per SVD to stderr, trace > 1 also one per sweep.
 enum { SVD_U_T = 0, SVD_U = 1 };
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, bool trace);
+                    KernelTimer *timer, int trace);
 
 // ------------------------------------------------------------------ conventional
 // Dense transposed copy used by the variational driver:

@@ -116,7 +116,8 @@ def _svd(torch, L, M, eps=0.0, cap=0, forced=0, left_pow=1, right_pow=0):
             ds.cpu().numpy(), r, sweeps.value)
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (1, 5), (2, 2), (3, 3), (9, 3), (50, 30), (30, 50), (200, 200)])
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (1, 5), (2, 2), (3, 3), (9, 3), (50, 30), (30, 50), (200, 200),
+                                 (300, 290), (700, 520), (257, 1100)])
 def test_svd_full_rank(m, n):
     torch, L = _env()
     _say("svd %d %d" % (m, n))
@@ -155,6 +156,28 @@ def test_svd_power_law_truncated():
     assert r2 == 17
     _, _, _, r3, _ = _svd(torch, L, M, eps=1e-10, forced=5)
     assert r3 == 5
+
+
+def test_svd_swap_size_2048_power_law():
+    """An SVD at the largest swap size of chi = 256 (2048 x 2048, 64-column
+    Jacobi blocks) against LAPACK: singular values, the rank rule with a cap,
+    and the truncated factorisation against the best rank-r approximation."""
+    torch, L = _env()
+    _say("svd power law 2048x2048")
+    rng = np.random.default_rng(21)
+    n = 2048
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = (1.0 + np.arange(n)) ** -1.5
+    M = (U * s) @ V.T
+    ref = np.linalg.svd(M, compute_uv=False)
+    left, right, sv, r, sw = _svd(torch, L, M, eps=1e-14, cap=256)
+    assert r == 256
+    assert np.allclose(sv, ref, rtol=1e-11, atol=1e-14 * ref[0])
+    best = (U[:, :r] * s[:r]) @ V[:, :r].T
+    assert np.linalg.norm(left @ right - best) <= 1e-11 * np.linalg.norm(M)
+    assert np.abs(right @ right.T - np.eye(r)).max() < 1e-12
+    _say("  sweeps %d" % sw)
 
 
 def test_svd_rank_deficient_and_zero():

@@ -144,6 +144,22 @@ def test_gpu_config2_turbulence_vs_oracle(chi):
     assert st2["max_bond"] == o.max_bond
 
 
+def test_gpu_ten_sites_1024_turbulence_vs_oracle():
+    """The 10-site, d = 8 shapes of the bond-dimension sweep (a 1024^3 field,
+    generated on the device) at chi = 64 against the oracle."""
+    torch = _torch()
+    _say("case: 1024^3 turbulence N=10 chi=64")
+    chi = 64
+    q = I.turbulence_qtt_device(1024, 101, [chi], torch.device("cuda", 0))[chi]
+    torch.cuda.empty_cache()
+    assert len(q) == 10 and max(c.shape[2] for c in q) == chi
+    o = O.ttm(q, q, chi, 1e-14)
+    C, st = _run(q, q, chi, 1e-14)
+    assert st["ranks"] == o.ranks
+    assert O.rel_frob(C, o.cores) <= TOL
+    assert st["n_swap"] == 45 and st["n_contract"] == 10
+
+
 def test_gpu_error_codes():
     import paper_2410_19747_amd as T
     _say("case: error codes")
