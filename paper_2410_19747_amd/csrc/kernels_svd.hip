@@ -68,13 +68,15 @@ JacobiPlan jacobi_plan(int L, int nc) {
   JacobiPlan p;
   p.L = L;
   p.nc = nc;
-  // Block width 16: 32-column pairs and a 256-thread solve.  Wider pairs
-  // (64 columns, a 1024-thread solve) halve the rounds per sweep, but each of
-  // their twice as many inner steps moves four times the LDS bytes, and on
-  // gfx950 that costs more than the rounds saved at every size measured
-  // (1024 to 4096 columns).  Columns are padded with zeros to a whole even
-  // number of blocks; zero columns never rotate.
-  const int bw = 16;
+  // Block width 16 (32-column pairs, 256-thread solve), or 32 (64-column
+  // pairs, 1024-thread solve) from 8192 rows and 256 columns up.  Every
+  // round streams W through the Gram and apply kernels, so wider pairs, with
+  // half the rounds per sweep, halve that traffic; but each of their twice
+  // as many inner steps moves four times the LDS bytes, which costs more
+  // than the rounds saved until W is large enough for the rounds to be HBM
+  // bound.  Columns are padded with zeros to a whole even number of blocks;
+  // zero columns never rotate.
+  const int bw = (L >= 8192 && nc > 256) ? 32 : 16;
   int nblk = (nc + bw - 1) / bw;
   if (nblk < 2) nblk = 2;
   if (nblk & 1) ++nblk;
@@ -474,8 +476,13 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
                                KernelTimer *timer) {
   const double ns = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;
   const double noise2 = ns * ns;
-  if (p.bw != 16) return hipErrorInvalidValue;
-  for (int round = 0; round < p.rounds; ++round) launch_round<16>(p, b, round, tol, noise2, s, timer);
+  if (p.bw != 16 && p.bw != 32) return hipErrorInvalidValue;
+  for (int round = 0; round < p.rounds; ++round) {
+    if (p.bw == 32)
+      launch_round<32>(p, b, round, tol, noise2, s, timer);
+    else
+      launch_round<16>(p, b, round, tol, noise2, s, timer);
+  }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
     hipLaunchKernelGGL(jacobi_convmax_kernel, dim3(1), dim3(JNT), 0, s, b.conv, p.rounds * p.pairs, b.result);

@@ -117,7 +117,7 @@ def _svd(torch, L, M, eps=0.0, cap=0, forced=0, left_pow=1, right_pow=0):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (1, 5), (2, 2), (3, 3), (9, 3), (50, 30), (30, 50), (200, 200),
-                                 (300, 290), (700, 520), (257, 1100)])
+                                 (300, 290), (700, 520), (257, 1100), (300, 8192)])
 def test_svd_full_rank(m, n):
     torch, L = _env()
     _say("svd %d %d" % (m, n))
