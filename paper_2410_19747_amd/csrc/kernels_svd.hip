@@ -236,6 +236,8 @@ struct SolveSmem {
   typename Pair<BW>::Square Q;
   typename Pair<BW>::Square S;
   double redmax[Pair<BW>::SNT / 64];
+  double cs[BW][2];                            // rotations of the current step
+  unsigned short pq[Pair<BW>::B2 - 1][BW];     // index pairs of every step: p | q << 8
 };
 
 // Solve of one block pair by its workgroup (BW * BW threads): reduce the sw
@@ -308,18 +310,35 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
   // One cyclic sweep of two-sided Jacobi over the B2 indices (B2 - 1 steps).
+  // Per step: every thread loads its 2 x 2 block of G and its two entries of
+  // Q's rows; meanwhile threads 0 .. BW-1 compute the step's BW rotations
+  // into LDS; after one barrier each thread applies its two rotations.
+  for (int e = tid; e < (B2 - 1) * BW; e += SNT) {
+    int p, q;
+    round_robin_pair(B2, e / BW, e % BW, p, q);
+    sm.pq[e / BW][e % BW] = (unsigned short)(p | (q << 8));
+  }
+  __syncthreads();
   const int u = tid / BW, v = tid % BW;
   int cur = 0;
   for (int step = 0; step < B2 - 1; ++step) {
-    int pu, qu, pv, qv;
-    round_robin_pair(B2, step, u, pu, qu);
-    round_robin_pair(B2, step, v, pv, qv);
+    const unsigned pqu = sm.pq[step][u], pqv = sm.pq[step][v];
+    const int pu = pqu & 255, qu = pqu >> 8, pv = pqv & 255, qv = pqv >> 8;
     double (*Gc)[B2 + 1] = sm.Gb[cur];
     double (*Gn)[B2 + 1] = sm.Gb[cur ^ 1];
-    double cu, su, cv, sv;
-    rot_params(Gc[pu][pu], Gc[qu][qu], Gc[pu][qu], thr, tol2, floor2, cu, su);
-    rot_params(Gc[pv][pv], Gc[qv][qv], Gc[pv][qv], thr, tol2, floor2, cv, sv);
     const double g00 = Gc[pu][pv], g01 = Gc[pu][qv], g10 = Gc[qu][pv], g11 = Gc[qu][qv];
+    const double q00 = sm.Q[2 * u][pv], q01 = sm.Q[2 * u][qv];
+    const double q10 = sm.Q[2 * u + 1][pv], q11 = sm.Q[2 * u + 1][qv];
+    if (tid < BW) {
+      const unsigned pq = sm.pq[step][tid];
+      const int p = pq & 255, q = pq >> 8;
+      double c, sn;
+      rot_params(Gc[p][p], Gc[q][q], Gc[p][q], thr, tol2, floor2, c, sn);
+      sm.cs[tid][0] = c;
+      sm.cs[tid][1] = sn;
+    }
+    __syncthreads();
+    const double cu = sm.cs[u][0], su = sm.cs[u][1], cv = sm.cs[v][0], sv = sm.cs[v][1];
     // rows (J_u^T), then columns (J_v)
     const double h00 = cu * g00 - su * g10, h01 = cu * g01 - su * g11;
     const double h10 = su * g00 + cu * g10, h11 = su * g01 + cu * g11;
@@ -329,12 +348,10 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
     Gn[qu][qv] = sv * h10 + cv * h11;
     // Q <- Q J_v on rows 2u, 2u + 1
     if (sv != 0.0) {
-      for (int h = 0; h < 2; ++h) {
-        const int k = 2 * u + h;
-        const double q0 = sm.Q[k][pv], q1 = sm.Q[k][qv];
-        sm.Q[k][pv] = cv * q0 - sv * q1;
-        sm.Q[k][qv] = sv * q0 + cv * q1;
-      }
+      sm.Q[2 * u][pv] = cv * q00 - sv * q01;
+      sm.Q[2 * u][qv] = sv * q00 + cv * q01;
+      sm.Q[2 * u + 1][pv] = cv * q10 - sv * q11;
+      sm.Q[2 * u + 1][qv] = sv * q10 + cv * q11;
     }
     cur ^= 1;
     __syncthreads();
