@@ -135,14 +135,22 @@ __device__ __forceinline__ int pair_col(int bi, int bj, int c) {
   return (c < BW) ? bi * BW + c : bj * BW + (c - BW);
 }
 
+// Every load of the thread is issued before the first LDS store.
 template <int BW>
 __device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
                                                 typename Pair<BW>::Tile &P) {
-  constexpr int B2 = Pair<BW>::B2;
+  constexpr int B2 = Pair<BW>::B2, PER = ROWS_PER_WG * B2 / JNT;
   const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
-  for (int e = threadIdx.x; e < ROWS_PER_WG * B2; e += JNT) {
-    const int c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
-    P[i][c] = (i < nr) ? W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] : 0.0;
+  double v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * JNT, c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
+    v[q] = (i < nr) ? W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * JNT;
+    P[e % ROWS_PER_WG][e / ROWS_PER_WG] = v[q];
   }
 }
 
