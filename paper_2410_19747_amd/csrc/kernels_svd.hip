@@ -425,21 +425,31 @@ __global__ __launch_bounds__(BW *BW) void jacobi_solve_kernel(int L, int nblk, i
   }
 }
 
-// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk of W.
+// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
+// of W.  The flag, the rotation and the chunk are loaded together; a pair
+// that did not rotate stores nothing.
 template <int BW>
 __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
                                                            const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
   __shared__ typename Pair<BW>::Square Qn;
   __shared__ typename Pair<BW>::Tile P;
-  constexpr int B2 = Pair<BW>::B2;
+  constexpr int B2 = Pair<BW>::B2, QPER = B2 * B2 / JNT;
   const int pair = blockIdx.x, chunk = blockIdx.y;
-  if (flag[pair] == 0) return;
+  const int rot = flag[pair];
   int bi, bj;
   rr_pair(nblk, round, pair, bi, bj);
   const double *qsrc = qbuf + (int64_t)pair * B2 * B2;
-  for (int e = threadIdx.x; e < B2 * B2; e += JNT) Qn[e / B2][e % B2] = qsrc[e];
+  double qv[QPER];
+#pragma unroll
+  for (int q = 0; q < QPER; ++q) qv[q] = qsrc[threadIdx.x + q * JNT];
   load_pair_chunk<BW>(W, L, bi, bj, chunk, P);
+#pragma unroll
+  for (int q = 0; q < QPER; ++q) {
+    const int e = threadIdx.x + q * JNT;
+    Qn[e / B2][e % B2] = qv[q];
+  }
+  if (rot == 0) return;  // uniform over the workgroup
   __syncthreads();
   apply_tile<BW>(P, Qn, W, L, bi, bj, chunk);
 }
