@@ -333,3 +333,30 @@ def test_ttm_turbulence_t16_exact():
     ref = O.brute_force(A, B)
     res = O.ttm(A, B, 64, 1e-28, chi_mid=0)
     assert O.rel_frob(res.cores, ref) <= 1e-12
+
+
+def test_device_turbulence_generator_on_host():
+    """The device-side turbulence generator (run here with torch on the CPU):
+    unit RMS, the interleaved bit order of qtt_encode_3d, and an exact TT at
+    the structural bonds (a 16^3 field has bonds 8, 64, 8)."""
+    torch = pytest.importorskip("torch")
+    out = I.turbulence_qtt_device(16, 5, [64, 8], torch.device("cpu"))
+    exact = O.dense(out[64])
+    assert [c.shape for c in out[64]] == [(1, 8, 8), (8, 8, 64), (64, 8, 8), (8, 8, 1)]
+    assert abs(np.sqrt(np.mean(exact ** 2)) - 1.0) < 1e-12
+    # the chi = 8 train is the leading part of the same field
+    assert O.rel_frob(out[8], exact) < 0.2
+    # decoding the interleaved order gives a field whose spectrum has no k = 0 mode and
+    # nothing beyond the cut-off |k| > n/2
+    n = 16
+    t = exact.reshape((2,) * 12)
+    order = [0] * 12
+    for s in range(4):
+        for a in range(3):
+            order[a * 4 + s] = 3 * s + a
+    u = t.transpose(order).reshape(n, n, n)
+    uk = np.fft.fftn(u)
+    assert abs(uk[0, 0, 0]) < 1e-9 * np.abs(uk).max()
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kk = np.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
+    assert np.abs(uk[kk > n / 2]).max() < 1e-9 * np.abs(uk).max()
