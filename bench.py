@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--no-conventional", action="store_true", help="skip timing the conventional product")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--sweep", action="store_true", help="bond-dimension sweep on the 10-site shapes")
@@ -182,6 +183,25 @@ def main():
             roofline["traffic_gbs"] = roofline["traffic"] / avg_launch_s / 1e9
         kernel_share = {k: sum(s["kernel_ms"][k] for s in pstats) / tot_ms for k in st["kernel_ms"]}
 
+    # The conventional chi^4 variational product of the same inputs (config 2 compares the two):
+    # time per call, sweeps, and its distance from the TTM result.
+    conv = None
+    if not args.no_conventional:
+        cws = T.Workspace(dev)
+        _, ccap = T.conventional_query(A, B, args.chi)
+        cout = torch.empty(ccap, dtype=torch.float64, device=dev)
+        T.conventional(A, B, args.chi, 1e-12, max_sweeps=10, workspace=cws, out=cout, stream=stream)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(args.steps):
+            Cc, stc = T.conventional(A, B, args.chi, 1e-12, max_sweeps=10, workspace=cws, out=cout,
+                                     stream=stream)
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - tc) / args.steps
+        conv = {"ms_per_product": 1e3 * tc, "products_per_s": 1.0 / tc, "sweeps": stc["sweeps"],
+                "tol": 1e-12, "max_sweeps": 10, "model_flops": stc["model_flops"]}
+        _log("  conventional: %.1f ms per product, %d sweeps" % (1e3 * tc, stc["sweeps"]))
+
     rel_err = None
     cpu = None
     if not args.no_cpu:
@@ -192,6 +212,8 @@ def main():
         dt = time.perf_counter() - t0
         cores = [c.detach().cpu().numpy() for c in C.cores()]
         rel_err = O.rel_frob(cores, ref.cores)
+        if conv is not None:
+            conv["rel_diff_vs_ttm"] = O.rel_frob([c.detach().cpu().numpy() for c in Cc.cores()], cores)
         cpu = {"value": 1.0 / dt, "unit": "TT products/s", "cores": _cpu_threads(), "kind": "oracle",
                "sample": "one full product (%d^3 u_x*u_x, chi=%d, eps=%g), %.1f s" % (args.grid, args.chi,
                                                                                        args.eps, dt)}
@@ -221,6 +243,7 @@ def main():
         "max_bond": st["max_bond"],
         "rel_err_vs_oracle": rel_err,
         "kernel_time_share": kernel_share,
+        "conventional": conv,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

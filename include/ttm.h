@@ -97,17 +97,27 @@ typedef struct ttm_options {
   double *discard_trace;   /* host [trace_cap]: discarded weight sum_{i>r} lambda_i^2, or NULL */
   int32_t profile;         /* 1: time every kernel launch with HIP events on the stream and
                               report per-class totals in ttm_stats (default 0) */
+  int32_t contract_precision; /* arithmetic of the contractions (Eq. (contract) and the swap
+                              merges): TTM_PREC_F64 (default), TTM_PREC_F32, TTM_PREC_BF16 or
+                              TTM_PREC_BF16X3, the last three with FP32 accumulation on the
+                              matrix cores; QR, SVD and truncation stay FP64 */
 } ttm_options;
+
+/* Values of ttm_options.contract_precision: operands of the contractions in
+ * FP64; rounded to FP32; rounded to BF16; or each split into three BF16
+ * terms of which the six leading products are accumulated (about FP32
+ * accuracy on the BF16 matrix cores). */
+enum { TTM_PREC_F64 = 0, TTM_PREC_F32 = 1, TTM_PREC_BF16 = 2, TTM_PREC_BF16X3 = 3 };
 
 /* Kernel classes of ttm_stats.kernel_ms / kernel_launches. */
 enum {
   TTM_KC_GEMM = 0,         /* contractions, merges, R and S V^T products          */
-  TTM_KC_QR = 1,           /* Householder QR of gauge moves                        */
+  TTM_KC_QR = 1,           /* Householder QR: gauge moves and the SVDs' preconditioner */
   TTM_KC_JAC_GRAM = 2,     /* Jacobi SVD: partial Gram matrices of block pairs     */
   TTM_KC_JAC_SOLVE = 3,    /* Jacobi SVD: diagonalisation of each block-pair Gram  */
-  TTM_KC_JAC_OTHER = 4,    /* Jacobi SVD: set-up, convergence, norms, sort, write  */
+  TTM_KC_JAC_OTHER = 4,    /* SVD: ordering, R^T, convergence, norms, sort, write  */
   TTM_KC_OTHER = 5,        /* copies, reversal, transposes, checks                 */
-  TTM_KC_JAC_APPLY = 6,    /* Jacobi SVD: rotation of the column blocks and of V   */
+  TTM_KC_JAC_APPLY = 6,    /* Jacobi SVD: rotation of the column blocks            */
   TTM_KC_COUNT = 7
 };
 
@@ -127,11 +137,14 @@ typedef struct ttm_stats {
   double svd_model_flops;  /* the part of model_flops spent in SVDs            */
   size_t peak_ws_bytes;    /* workspace bytes the call used                    */
   double kernel_ms[TTM_KC_COUNT];        /* with opt.profile: summed event time per class */
-  int64_t kernel_launches[TTM_KC_COUNT]; /* with opt.profile: launches per class          */
+  int64_t kernel_launches[TTM_KC_COUNT]; /* with opt.profile: timed regions per class: one launch
+                                            each, except a whole QR or a column reordering,
+                                            which are timed as one region */
 } ttm_stats;
 
 /* Defaults: chi_mid = -1 (same as chi_out), final_round = 1, max_sweeps = 10,
- * svd_max_sweeps = 40, seed = 12345, no forced ranks, no traces. */
+ * svd_max_sweeps = 40, seed = 12345, no forced ranks, no traces, FP64
+ * contractions. */
 void ttm_default_options(ttm_options *opt);
 
 /* Sizes for ttm_multiply (host only, no GPU work).  Writes the workspace

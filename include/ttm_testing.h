@@ -27,6 +27,12 @@ int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs,
                   double *C, int64_t c_bs, int c_rdiv, int c_cdiv, int64_t c_rs1, int64_t c_rs0,
                   int64_t c_cs1, int64_t c_cs0, void *stream);
 
+/* As ttm_test_gemm, in the arithmetic `prec` (a TTM_PREC_* value of ttm.h):
+ * operands rounded to FP32 / BF16 / three BF16 terms with FP32 accumulation. */
+int ttm_test_gemm_prec(int prec, int M, int N, int K, const double *A, int64_t a_rs, int64_t a_cs,
+                       const double *B, int64_t b_rs, int64_t b_cs, double *C, int64_t c_rs,
+                       void *stream);
+
 /* Householder QR of the m x n row-major matrix M (device): Q (m x k,
  * row-major, k = min(m,n)) and R (k x n, row-major).  scratch: device,
  * ttm_test_qr_scratch(m, n) doubles. */

@@ -124,9 +124,12 @@ _DEFAULT_WS = {}
 
 
 def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, seed=12345,
-             forced_ranks=None, trace_cap=0, profile=False):
+             forced_ranks=None, trace_cap=0, profile=False, contract_precision="f64"):
+    from ._abi import PRECISIONS
     o = TtmOptions()
     lib().ttm_default_options(ctypes.byref(o))
+    o.contract_precision = (PRECISIONS[contract_precision] if isinstance(contract_precision, str)
+                            else int(contract_precision))
     o.chi_mid = -1 if chi_mid is None else int(chi_mid)
     o.final_round = 1 if final_round else 0
     o.max_sweeps = int(max_sweeps)
@@ -223,7 +226,10 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
 
 
 def multiply(A, B, chi_out, tol, **opts):
-    """C = A * B elementwise by TTM.  Returns (PackedTT, stats dict)."""
+    """C = A * B elementwise by TTM.  Returns (PackedTT, stats dict).
+
+    Options: chi_mid, final_round, svd_max_sweeps, forced_ranks, trace_cap,
+    profile, contract_precision ("f64", "f32", "bf16" or "bf16x3")."""
     return _run("ttm", A, B, chi_out, tol, **opts)
 
 

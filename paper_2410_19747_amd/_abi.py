@@ -53,6 +53,7 @@ class TtmOptions(ctypes.Structure):
         ("rank_trace", I32P),
         ("discard_trace", F64P),
         ("profile", ctypes.c_int32),
+        ("contract_precision", ctypes.c_int32),
     ]
 
 
@@ -75,6 +76,9 @@ class TtmStats(ctypes.Structure):
         ("kernel_launches", ctypes.c_int64 * 7),
     ]
 
+
+TTM_PREC_F64, TTM_PREC_F32, TTM_PREC_BF16, TTM_PREC_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"f64": TTM_PREC_F64, "f32": TTM_PREC_F32, "bf16": TTM_PREC_BF16, "bf16x3": TTM_PREC_BF16X3}
 
 KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_solve", "jacobi_other", "other", "jacobi_apply"]
 
@@ -115,6 +119,7 @@ TESTING_PROTOTYPES = {
     "ttm_test_gemm": (ctypes.c_int, [ctypes.c_int] * 4 + [_VP, _I64, _I64, _I64, _VP, _I64, _I64, _I64,
                                                           _VP, _I64, ctypes.c_int, ctypes.c_int,
                                                           _I64, _I64, _I64, _I64, _VP]),
+    "ttm_test_gemm_prec": (ctypes.c_int, [ctypes.c_int] * 4 + [_VP, _I64, _I64, _VP, _I64, _I64, _VP, _I64, _VP]),
     "ttm_test_qr_scratch": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "ttm_test_qr": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP]),
     "ttm_test_svd_ws_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),

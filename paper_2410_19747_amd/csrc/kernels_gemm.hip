@@ -1,5 +1,9 @@
-// FP64 batched strided GEMM on the gfx950 matrix cores
-// (v_mfma_f64_16x16x4_f64), with a split-stride epilogue.
+// Batched strided GEMM on the gfx950 matrix cores with a split-stride
+// epilogue.  FP64 (v_mfma_f64_16x16x4_f64) throughout, or, for the
+// contractions of a mixed-precision product, operands rounded to FP32
+// (v_mfma_f32_16x16x4_f32), to BF16 (v_mfma_f32_16x16x16_bf16) or split into
+// three BF16 terms (six BF16 products, about FP32 accuracy), all with FP32
+// accumulation; inputs and outputs stay FP64 in memory.
 //
 // Used for every contraction of the TTM sweep: the COPY-tensor contraction
 // of Eq. (contract) is a batch of d products sharing the physical index; the
@@ -100,6 +104,135 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
   }
 }
 
+// ------------------------------------------------------------------ reduced-precision operands
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short shr4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  __bf16 h = (__bf16)x;  // round to nearest even
+  return __builtin_bit_cast(short, h);
+}
+__device__ __forceinline__ float bf16_value(short b) { return (float)__builtin_bit_cast(__bf16, b); }
+
+// The same tiling with operands rounded to FP32 or BF16 in LDS and FP32
+// accumulation.  PREC: 1 = FP32 (16x16x4 f32 MFMA, 4 k per step), 2 = BF16
+// (16x16x16 bf16 MFMA, 16 k per step), 3 = BF16 x 3: x = hi + mid + lo with
+// each term BF16, and A B ~ hi hi + hi mid + mid hi + hi lo + mid mid + lo hi
+// (the six terms above 2^-24 relative).  Operand layouts: f32 as for f64
+// (lane l: A[l%16][l/16], B[l/16][l%16]); bf16 lane l: A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16], j < 4.  Accumulator register t of lane l holds
+// D[4(l/16) + t][l%16] for both (checked on gfx950 by the GEMM tests).
+template <int PREC>
+__global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
+  constexpr int NS = (PREC == 3) ? 3 : 1;  // BF16 terms per operand
+  __shared__ float As[NS][BK][BM + 1];
+  __shared__ float Bs[NS][BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tile_m = blockIdx.y * BM;
+  const int tile_n = blockIdx.x * BN;
+  const int64_t bz = blockIdx.z;
+  const double *A = g.A + bz * g.a_bs;
+  const double *B = g.B + bz * g.b_bs;
+  const bool a_kfast = (g.a_cs == 1);
+  const bool b_jfast = (g.b_cs == 1);
+  // Rounded terms of one operand value: FP32, one BF16, or three BF16.
+  auto put = [&](float (*dst)[BK][BM + 1], int k, int i, double x) {
+    if (PREC == 1) {
+      dst[0][k][i] = (float)x;
+    } else {
+      const float f = (float)x;
+      const float hi = bf16_value(bf16_bits(f));
+      dst[0][k][i] = hi;
+      if (PREC == 3) {
+        const float r = (float)(x - (double)hi);
+        const float mid = bf16_value(bf16_bits(r));
+        dst[1][k][i] = mid;
+        dst[2][k][i] = bf16_value(bf16_bits((float)(x - (double)hi - (double)mid)));
+      }
+    }
+  };
+
+  flt4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += NT) {
+      int i, k;
+      if (a_kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
+      const int gi = tile_m + i, gk = k0 + k;
+      put(As, k, i, (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0);
+    }
+    for (int e = tid; e < BK * BN; e += NT) {
+      int j, k;
+      if (b_jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+      const int gj = tile_n + j, gk = k0 + k;
+      put(Bs, k, j, (gj < g.N && gk < g.K) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0);
+    }
+    __syncthreads();
+    if (PREC == 1) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        const float a0 = As[0][kr][wr * 32 + (lane & 15)], a1 = As[0][kr][wr * 32 + 16 + (lane & 15)];
+        const float b0 = Bs[0][kr][wc * 32 + (lane & 15)], b1 = Bs[0][kr][wc * 32 + 16 + (lane & 15)];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+      // one 16-deep step: lane l takes k = 4 (l/16) + j, j < 4
+      shr4 a[NS][2], b[NS][2];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int kr = 4 * (lane >> 4) + j;
+          a[s][0][j] = bf16_bits(As[s][kr][wr * 32 + (lane & 15)]);
+          a[s][1][j] = bf16_bits(As[s][kr][wr * 32 + 16 + (lane & 15)]);
+          b[s][0][j] = bf16_bits(Bs[s][kr][wc * 32 + (lane & 15)]);
+          b[s][1][j] = bf16_bits(Bs[s][kr][wc * 32 + 16 + (lane & 15)]);
+        }
+      // term pairs (sa, sb) with sa + sb <= 2: hi hi, hi mid, mid hi, hi lo, mid mid, lo hi
+#pragma unroll
+      for (int sa = 0; sa < NS; ++sa)
+#pragma unroll
+        for (int sb = 0; sb < NS; ++sb) {
+          if (sa + sb > 2) continue;
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[sa][x], b[sb][y], acc[x][y], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  double *C = g.C + bz * g.c_bs;
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = tile_m + wr * 32 + x * 16 + 4 * (lane >> 4) + t;
+        const int j = tile_n + wc * 32 + y * 16 + (lane & 15);
+        if (i < g.M && j < g.N) {
+          const int64_t o = out_index(g, i, j);
+          double v = g.alpha * (double)acc[x][y][t];
+          if (g.beta != 0.0) v += g.beta * C[o];
+          C[o] = v;
+        }
+      }
+    }
+  }
+}
+
 GemmArgs gemm_rowmajor(int M, int N, int K, const double *A, int64_t lda, const double *B,
                        int64_t ldb, double *C, int64_t ldc) {
   GemmArgs g;
@@ -119,7 +252,13 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
   }
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, g);
+  switch (g.prec) {
+    case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, g); break;
+    case GEMM_F32: hipLaunchKernelGGL(gemm_lowp_kernel<1>, grid, dim3(NT), 0, s, g); break;
+    case GEMM_BF16: hipLaunchKernelGGL(gemm_lowp_kernel<2>, grid, dim3(NT), 0, s, g); break;
+    case GEMM_BF16X3: hipLaunchKernelGGL(gemm_lowp_kernel<3>, grid, dim3(NT), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -72,11 +72,23 @@ constexpr int PIVOT_MAX_CAND = 8;  // candidates per thread: n - j0 <= PNT * 8
 __device__ void panel_pivot(double *__restrict__ S, int m, int n, int j0, int jb,
                             const double *__restrict__ cnorm, int *__restrict__ perm,
                             double *__restrict__ scratch) {
-  __shared__ double wv[PNT / 64];
-  __shared__ int wi[PNT / 64];
+  __shared__ double fv[PNT / 64][QB];  // each wave's top jb: values
+  __shared__ int fi[PNT / 64][QB];     // and positions
   __shared__ int sel[QB], dpos[QB], vpos[QB], oldp[2 * QB];
   __shared__ int nmove;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // Order: larger norm first, then lower position; taken candidates get -1.
+  auto better = [](double v1, int i1, double v2, int i2) { return v1 > v2 || (v1 == v2 && i1 < i2); };
+  auto wave_best = [&](double &bv, int &bi) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (better(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+  };
   double cv[PIVOT_MAX_CAND];
   int ci[PIVOT_MAX_CAND];
 #pragma unroll
@@ -84,41 +96,55 @@ __device__ void panel_pivot(double *__restrict__ S, int m, int n, int j0, int jb
     ci[q] = j0 + tid + PNT * q;
     cv[q] = (ci[q] < n) ? cnorm[ci[q]] : -1.0;
   }
+  // Every wave: its own jb best candidates, by jb rounds of a wave arg-max.
   for (int t = 0; t < jb; ++t) {
     double bv = -2.0;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int q = 0; q < PIVOT_MAX_CAND; ++q)
-      if (cv[q] > bv || (cv[q] == bv && ci[q] < bi)) {
+      if (better(cv[q], ci[q], bv, bi)) {
         bv = cv[q];
         bi = ci[q];
       }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      wv[w] = bv;
-      wi[w] = bi;
-    }
-    __syncthreads();
-    double gv = wv[0];
-    int gi = wi[0];
-    for (int ww = 1; ww < PNT / 64; ++ww)
-      if (wv[ww] > gv || (wv[ww] == gv && wi[ww] < gi)) {
-        gv = wv[ww];
-        gi = wi[ww];
-      }
-    if (tid == 0) sel[t] = gi;
+    wave_best(bv, bi);
 #pragma unroll
     for (int q = 0; q < PIVOT_MAX_CAND; ++q)
-      if (ci[q] == gi) cv[q] = -1.0;
-    __syncthreads();
+      if (ci[q] == bi) cv[q] = -1.0;
+    if (lane == 0) {
+      fv[w][t] = bv;
+      fi[w][t] = bi;
+    }
   }
+  __syncthreads();
+  // Wave 0: the jb best of the 16 waves' finalists (each global top-jb
+  // column is among its wave's top jb).
+  if (w == 0) {
+    constexpr int PER = (PNT / 64) * QB / 64;  // finalists per lane
+    double gv[PER];
+    int gi[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int f = lane + 64 * q, ww = f / QB, t = f % QB;
+      gv[q] = (t < jb) ? fv[ww][t] : -2.0;
+      gi[q] = (t < jb) ? fi[ww][t] : 0x7fffffff;
+    }
+    for (int t = 0; t < jb; ++t) {
+      double bv = -2.0;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (better(gv[q], gi[q], bv, bi)) {
+          bv = gv[q];
+          bi = gi[q];
+        }
+      wave_best(bv, bi);
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (gi[q] == bi) gv[q] = -3.0;
+      if (lane == 0) sel[t] = bi;
+    }
+  }
+  __syncthreads();
   if (tid == 0) {
     int nd = 0, nv = 0;
     bool identity = true;

@@ -50,6 +50,7 @@ struct Options {
   int32_t *rank_trace = nullptr;
   double *discard_trace = nullptr;
   int profile = 0;
+  int contract_prec = GEMM_F64;
 };
 
 int64_t sat_mul(int64_t a, int64_t b) {
@@ -110,6 +111,8 @@ int resolve_options(const ttm_options *o, int chi_out, Options &r) {
   r.discard_trace = o->discard_trace;
   if (o->profile != 0 && o->profile != 1) return TTM_EINVAL;
   r.profile = o->profile;
+  if (o->contract_precision < TTM_PREC_F64 || o->contract_precision > TTM_PREC_BF16X3) return TTM_EINVAL;
+  r.contract_prec = o->contract_precision;  // TTM_PREC_* and GemmPrec share their values
   return TTM_OK;
 }
 
@@ -335,6 +338,7 @@ struct Runner {
     g.A = k.p; g.a_rs = (int64_t)k.s.d * k.s.rr; g.a_cs = 1; g.a_bs = k.s.rr;
     g.B = m.p; g.b_rs = (int64_t)m.s.d * m.s.rr; g.b_cs = 1; g.b_bs = m.s.rr;
     g.C = out.p; g.c_rs1 = (int64_t)k.s.d * m.s.rr; g.c_cs1 = 1; g.c_bs = m.s.rr;
+    g.prec = o.contract_prec;
     {
       Timed tm(&timer, KC_GEMM, st);
       hip(launch_gemm(g, st));
@@ -435,6 +439,7 @@ struct Runner {
     g.C = Y;
     g.c_rdiv = dp; g.c_cdiv = Dr;
     g.c_rs1 = dx; g.c_rs0 = (int64_t)m * Dr; g.c_cs1 = 1; g.c_cs0 = m;
+    g.prec = o.contract_prec;
     {
       Timed tm(&timer, KC_GEMM, st);
       if (!hip(launch_gemm(g, st))) return;

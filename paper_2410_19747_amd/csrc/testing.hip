@@ -25,6 +25,22 @@ int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs,
   return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
 }
 
+int ttm_test_gemm_prec(int prec, int M, int N, int K, const double *A, int64_t a_rs, int64_t a_cs,
+                       const double *B, int64_t b_rs, int64_t b_cs, double *C, int64_t c_rs,
+                       void *stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return TTM_EINVAL;
+  if (prec < TTM_PREC_F64 || prec > TTM_PREC_BF16X3) return TTM_EINVAL;
+  ttm::GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.a_rs = a_rs; g.a_cs = a_cs;
+  g.B = B; g.b_rs = b_rs; g.b_cs = b_cs;
+  g.C = C; g.c_rs1 = c_rs; g.c_cs1 = 1;
+  g.prec = prec;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ttm::launch_gemm(g, s) != hipSuccess) return TTM_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
+}
+
 size_t ttm_test_qr_scratch(int m, int n) { return ttm::qr_scratch_doubles(m, n); }
 
 int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scratch, void *stream) {

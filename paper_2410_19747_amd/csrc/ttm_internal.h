@@ -58,7 +58,10 @@ struct Timed {
 //   C[i][j] at C + b*c_bs + (i / c_rdiv)*c_rs1 + (i % c_rdiv)*c_rs0
 //                         + (j / c_cdiv)*c_cs1 + (j % c_cdiv)*c_cs0
 // The split output mapping lets a product write a permuted layout (the
-// leg exchange of a swap) directly.  beta == 0 never reads C.
+// leg exchange of a swap) directly.  beta == 0 never reads C.  prec selects
+// the arithmetic: FP64, or operands rounded to FP32, BF16 or three BF16 terms
+// with FP32 accumulation (inputs and output FP64 in memory either way).
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3 };
 struct GemmArgs {
   int M = 0, N = 0, K = 0, batch = 1;
   const double *A = nullptr;
@@ -70,6 +73,7 @@ struct GemmArgs {
   int c_rdiv = 1, c_cdiv = 1;
   int64_t c_rs1 = 0, c_rs0 = 0, c_cs1 = 0, c_cs0 = 0;
   double alpha = 1.0, beta = 0.0;
+  int prec = GEMM_F64;
 };
 
 // Plain row-major helper: C[M x N] (ldc) = A[M x K] (lda) * B[K x N] (ldb).

@@ -122,6 +122,14 @@ def test_validation_codes(L):
     L.ttm_default_options(ctypes.byref(o))
     o.trace_cap = 4      # arrays missing
     assert _query(L, good, good, 4, o)[0] == _abi.TTM_EINVAL
+    L.ttm_default_options(ctypes.byref(o))
+    assert o.contract_precision == _abi.TTM_PREC_F64
+    for bad in (-1, 4):
+        o.contract_precision = bad
+        assert _query(L, good, good, 4, o)[0] == _abi.TTM_EINVAL
+    for ok in (_abi.TTM_PREC_F32, _abi.TTM_PREC_BF16, _abi.TTM_PREC_BF16X3):
+        o.contract_precision = ok
+        assert _query(L, good, good, 4, o)[0] == _abi.TTM_OK
 
 
 def test_multiply_rejects_before_gpu_work(L):

@@ -44,6 +44,37 @@ def test_gemm_rowmajor_batched(M, N, K, batch):
     assert np.allclose(C, A @ B, rtol=1e-13, atol=1e-13)
 
 
+# Error of a reduced-precision product against the exact one, relative to
+# |A| |B| (entrywise), for operands rounded to FP32 (unit roundoff 2^-24), to
+# BF16 (2^-8) and split into three BF16 terms (about 2^-24), with FP32
+# accumulation.  The bounds are a few unit roundoffs times sqrt(K).
+PREC_BOUND = {1: 4e-7, 2: 2e-2, 3: 4e-7}
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 16), (70, 45, 33), (130, 129, 200)])
+def test_gemm_reduced_precision(prec, M, N, K):
+    """FP32, BF16 and 3 x BF16 operands with FP32 accumulation on the matrix
+    cores (also checks the operand and accumulator lane layouts: a wrong one
+    gives errors of order one)."""
+    torch, L = _env()
+    _say("gemm prec %d: %d %d %d" % (prec, M, N, K))
+    rng = np.random.default_rng(M * 7 + N * 3 + K + prec)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    dA, dB = _dev(torch, A), _dev(torch, B)
+    dC = torch.zeros(M * N, dtype=torch.float64, device="cuda")
+    rc = L.ttm_test_gemm_prec(prec, M, N, K, _ptr(dA), K, 1, _ptr(dB), N, 1, _ptr(dC), N, None)
+    assert rc == 0
+    C = dC.cpu().numpy().reshape(M, N)
+    scale = np.abs(A) @ np.abs(B)
+    err = np.abs(C - A @ B) / scale
+    assert err.max() <= PREC_BOUND[prec] * np.sqrt(K), err.max()
+    if prec == 2:
+        # BF16 really rounds: far above the FP32 level
+        assert K < 8 or err.max() > 1e-5
+
+
 def test_gemm_strided_operands_and_split_output():
     """Merge of a swap pair: theta[(a,e),(w,b)] stored as Theta[(a,w),(e,b)] column-major."""
     torch, L = _env()

@@ -160,6 +160,22 @@ def test_gpu_ten_sites_1024_turbulence_vs_oracle():
     assert st["n_swap"] == 45 and st["n_contract"] == 10
 
 
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("bf16x3", 1e-5), ("bf16", 5e-2)])
+def test_gpu_mixed_precision_contractions_vs_fp64_oracle(prec, bound):
+    """Contractions with FP32 / 3 x BF16 / BF16 operands (FP32 accumulation),
+    QR, SVD and truncation in FP64, against the FP64 oracle on the 256^3
+    chi = 64 product; the bound is the precision's level, not 1e-12."""
+    _say("case: 256^3 turbulence chi=64, contractions in %s" % prec)
+    chi = 64
+    A = I.turbulence_qtt(256, 101, chi)
+    o = O.ttm(A, A, chi, 1e-14)
+    C, st = _run(A, A, chi, 1e-14, contract_precision=prec)
+    err = O.rel_frob(C, o.cores)
+    _say("  relative error vs FP64 oracle: %.3e" % err)
+    assert err <= bound
+    assert st["n_swap"] == 28
+
+
 def test_gpu_error_codes():
     import paper_2410_19747_amd as T
     _say("case: error codes")
