@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="bond-dimension sweep on the 10-site shapes")
     ap.add_argument("--sweep-chis", default="64,128,256,512,1024")
     ap.add_argument("--sweep-grid", type=int, default=1024)
+    ap.add_argument("--sweep-precisions", default="f64",
+                    help="contraction arithmetic per sweep point, e.g. f64,f32,bf16x3,bf16 (f64 first)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -308,6 +310,23 @@ def sweep(args, dev):
         exact = _tt_entries(a_cores, idx) ** 2
         got = _tt_entries(C.cores(), idx)
         rel = float(torch.linalg.norm(got - exact) / torch.linalg.norm(exact))
+        # Mixed-precision contractions at the same point: time and the relative
+        # difference of the sampled entries from the FP64 product's.
+        mixed = {}
+        for prec in [q for q in args.sweep_precisions.split(",") if q and q != "f64"]:
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            Cm, stm = T.multiply(A, A, chi, args.eps, workspace=ws, out=torch.empty_like(out), stream=stream,
+                                 contract_precision=prec)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - tm
+            gm = _tt_entries(Cm.cores(), idx)
+            mixed[prec] = {"ms_per_product": 1e3 * tm,
+                           "sampled_rel_diff_vs_f64": float(torch.linalg.norm(gm - got) / torch.linalg.norm(got)),
+                           "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"]}
+            _log("    %s contractions: %.1f ms, sampled rel diff vs FP64 %.2e"
+                 % (prec, 1e3 * tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
+            del Cm
         line = {
             "sweep": True, "chi": chi, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=8"
             % (args.sweep_grid, n_sites), "eps": args.eps, "chi_out": chi, "chi_mid": chi,
@@ -319,6 +338,7 @@ def sweep(args, dev):
             "max_bond": st["max_bond"], "n_svd": st["n_svd"],
             "sampled_rel_err_vs_exact": rel, "sampled_points": int(idx.shape[0]),
             "error_bound_abs": st["error_bound"], "kernel_time_share": share,
+            "mixed_precision": mixed or None,
             "workspace_bytes": st["peak_ws_bytes"],
         }
         print(json.dumps(line), flush=True)

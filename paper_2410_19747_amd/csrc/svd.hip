@@ -3,7 +3,6 @@
 // write-out (the steps are listed with svd_oside in ttm_internal.h).
 #include <math.h>
 #include <stdio.h>
-#include <stdlib.h>
 
 #include <algorithm>
 
@@ -111,7 +110,7 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
     Timed tm(timer, KC_QR, s);
     // Block column pivoting in the QR saves Jacobi sweeps (the rows of R come
     // out graded); its selection step pays off once a sweep is expensive.
-    int *pivot = (p.no >= (getenv("TTM_AB_PIVOT_ALL") ? 1 : 2048)) ? b.perm0 : nullptr;  // AB-TEMP
+    int *pivot = (p.no >= 2048) ? b.perm0 : nullptr;
     if (!ok(launch_qr_inplace(b.S, p.np, p.no, b.qr, pivot, s))) return out;
   }
   {
