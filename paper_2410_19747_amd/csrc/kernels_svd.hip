@@ -191,61 +191,63 @@ __device__ __forceinline__ void apply_tile(const typename Pair<BW>::Tile &P, con
 }
 
 // Rotation (c, s) annihilating g_pq of a symmetric 2 x 2 block, or (1, 0)
-// when the pair is already orthogonal to tolerance (see the header).
-// Rutishauser's form: zeta = (g_qq - g_pp) / (2 g_pq),
-// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t.
-// The angle only has to be close (later sweeps revisit the pair), so zeta and
-// t use the hardware FP64 reciprocal and reciprocal square root directly; c
-// gets one Newton step so that c^2 + s^2 = 1 to rounding for the t used.
-// Every thread that needs a rotation computes it from the same inputs, so all
-// copies agree bitwise.
+// when the pair is already orthogonal to tolerance (see the header).  With
+// d = g_qq - g_pp and r = sqrt(d^2 + 4 g_pq^2), the smaller root of the
+// rotation's quadratic is t = 2 g_pq sign(d) / (|d| + r) (Rutishauser's
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / (2 g_pq),
+// multiplied through by |2 g_pq|), and c = 1 / sqrt(1 + t^2), s = c t.  t is
+// invariant under a common scaling of d and g_pq, so both are first brought
+// to [1/2, 1) by a power of two (no overflow or underflow in d^2).  The angle
+// only has to be close (later sweeps revisit the pair), so r and t use the
+// hardware FP64 reciprocal square root and reciprocal directly; c gets one
+// Newton step so that c^2 + s^2 = 1 to rounding for the t used.  No branch:
+// the identity is selected afterwards.  Every thread that computes a
+// rotation from the same inputs gets bitwise the same result.
 __device__ __forceinline__ void rot_params(double gpp, double gqq, double gpq, double thr, double tol2,
                                            double floor2, double &c, double &sn) {
   const double hi2 = fmax(gpp, gqq), lo2 = fmin(gpp, gqq);
-  c = 1.0;
-  sn = 0.0;
-  if (hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2)) {
-    const double zeta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
-    const double az = fabs(zeta);
-    double t;
-    if (az > 1e150) {
-      t = 0.5 * __builtin_amdgcn_rcp(zeta);  // zeta^2 would overflow; t ~ 1 / (2 zeta)
-    } else {
-      const double w = fma(zeta, zeta, 1.0);
-      t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), zeta);
-    }
-    const double x = fma(t, t, 1.0);
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    c = y;
-    sn = y * t;
-  }
+  const bool on = hi2 > thr && gpq * gpq > tol2 * hi2 * (lo2 > thr ? lo2 : floor2);
+  const double d0 = gqq - gpp, g0 = 2.0 * gpq;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d0), fabs(g0)));
+  const double d = __builtin_amdgcn_ldexp(d0, -e), g2 = __builtin_amdgcn_ldexp(g0, -e);
+  const double r2 = fma(d, d, g2 * g2);
+  const double r = r2 * __builtin_amdgcn_rsq(r2);
+  const double t = (d >= 0.0 ? g2 : -g2) * __builtin_amdgcn_rcp(fabs(d) + r);
+  const double x = fma(t, t, 1.0);
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  c = on ? y : 1.0;
+  sn = on ? y * t : 0.0;
 }
 
-// Pair k of step st of the round-robin (circle method) over n indices,
-// ordered p < q.
-__device__ __forceinline__ void round_robin_pair(int n, int st, int k, int &p, int &q) {
-  int a, b;
-  if (k == 0) {
-    a = st;
-    b = n - 1;
-  } else {
-    a = (st + k) % (n - 1);
-    b = (st - k + (n - 1)) % (n - 1);
-  }
-  p = min(a, b);
-  q = max(a, b);
+// Slot permutation of the circle-method tournament over n (even) indices.
+// If step st pairs slots (2k, 2k + 1), k < n/2, holding the indices
+// (st, n-1) for k = 0 and ((st + k) mod (n-1), (st - k) mod (n-1)) for
+// k >= 1, then the index in slot a at step st sits in slot slot_next(a) at
+// step st + 1: 0 -> 3, 1 -> 1, 2 -> 0, 2k -> 2k - 2, 2k + 1 -> 2k + 3,
+// n - 1 -> n - 2.  It is one cycle over the n - 1 slots other than 1, so
+// n - 1 steps bring every index back to its starting slot.  Moving the data
+// by this fixed permutation after each step, with the indices starting in
+// slot order, lets every step pair the same slots (2k, 2k + 1): all LDS
+// addresses of a thread are loop invariant.
+__device__ __forceinline__ int slot_next(int a, int n) {
+  if (a == 0) return 3;
+  if (a == 1) return 1;
+  if (a == 2) return 0;
+  if (a == n - 1) return n - 2;
+  return (a & 1) ? a + 2 : a - 2;
 }
 
-// Shared memory of the block-pair solve.
+// Shared memory of the block-pair solve: G and the accumulated rotation Q
+// double-buffered (a step reads one copy and writes the other at permuted
+// positions), rows padded to keep 16-byte alignment for paired loads.
 template <int BW>
 struct SolveSmem {
-  typename Pair<BW>::Square Gb[2];
-  typename Pair<BW>::Square Q;
-  typename Pair<BW>::Square S;
-  double redmax[Pair<BW>::SNT / 64];
-  double cs[BW][2];                            // rotations of the current step
-  unsigned short pq[Pair<BW>::B2 - 1][BW];     // index pairs of every step: p | q << 8
+  static constexpr int LD = 2 * BW + 2;
+  double Gb[2][2 * BW][LD];
+  double Qb[2][2 * BW][LD];
+  double redmax[BW * BW / 64];
+  double cs[BW][2];  // rotations of the current step
 };
 
 // Solve of one block pair by its workgroup (BW * BW threads): reduce the sw
@@ -256,9 +258,8 @@ struct SolveSmem {
 // accumulated rotation and hand it to store(i, j, q_ij).  Returns 0 (nothing
 // stored) when no rotation is needed.  A step rotates BW disjoint index pairs
 // at once; G <- J^T G J splits into independent 2 x 2 blocks, one per
-// thread, read from one copy of G and written to the other, so a step needs a
-// single barrier.  Every workgroup that solves the same partials computes
-// bitwise the same result.
+// thread, read from one copy of G and written to the other.  Every workgroup
+// that solves the same partials computes bitwise the same result.
 template <int BW, typename Store>
 __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, double thr, double floor2,
                           SolveSmem<BW> &sm, double *mout, Store store) {
@@ -293,7 +294,7 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   for (int j = 0; j < EPT; ++j) {
     const int e = tid + j * SNT, i = e / B2, k = e % B2;
     sm.Gb[0][i][k] = acc[j];
-    sm.Q[i][k] = (i == k) ? 1.0 : 0.0;
+    sm.Qb[0][i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
   // Convergence measure of this visit (scaled off-diagonal, see the header).
@@ -317,53 +318,53 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   *mout = m;
   if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
-  // One cyclic sweep of two-sided Jacobi over the B2 indices (B2 - 1 steps).
-  // Per step: every thread loads its 2 x 2 block of G and its two entries of
-  // Q's rows; meanwhile threads 0 .. BW-1 compute the step's BW rotations
-  // into LDS; after one barrier each thread applies its two rotations.
-  for (int e = tid; e < (B2 - 1) * BW; e += SNT) {
-    int p, q;
-    round_robin_pair(B2, e / BW, e % BW, p, q);
-    sm.pq[e / BW][e % BW] = (unsigned short)(p | (q << 8));
-  }
-  __syncthreads();
+  // One cyclic sweep of two-sided Jacobi over the B2 indices (B2 - 1 steps),
+  // slots (2k, 2k + 1) paired at every step (see slot_next).  Thread (u, v)
+  // owns the 2 x 2 block of G at slot pairs (u, v) and rows 2u, 2u + 1 of Q
+  // at slot pair v.  Per step: every thread loads its blocks of G and Q while
+  // threads 0 .. BW-1 compute the step's rotations into LDS; after one
+  // barrier each thread applies J_u^T (.) J_v to its G block and J_v to its
+  // Q block and writes both to the other buffer at the slots of the next step.
+  typedef double d2 __attribute__((ext_vector_type(2)));
   const int u = tid / BW, v = tid % BW;
+  const int nu0 = slot_next(2 * u, B2), nu1 = slot_next(2 * u + 1, B2);
+  const int nv0 = slot_next(2 * v, B2), nv1 = slot_next(2 * v + 1, B2);
   int cur = 0;
   for (int step = 0; step < B2 - 1; ++step) {
-    const unsigned pqu = sm.pq[step][u], pqv = sm.pq[step][v];
-    const int pu = pqu & 255, qu = pqu >> 8, pv = pqv & 255, qv = pqv >> 8;
-    double (*Gc)[B2 + 1] = sm.Gb[cur];
-    double (*Gn)[B2 + 1] = sm.Gb[cur ^ 1];
-    const double g00 = Gc[pu][pv], g01 = Gc[pu][qv], g10 = Gc[qu][pv], g11 = Gc[qu][qv];
-    const double q00 = sm.Q[2 * u][pv], q01 = sm.Q[2 * u][qv];
-    const double q10 = sm.Q[2 * u + 1][pv], q11 = sm.Q[2 * u + 1][qv];
+    double (*Gc)[SolveSmem<BW>::LD] = sm.Gb[cur];
+    double (*Gn)[SolveSmem<BW>::LD] = sm.Gb[cur ^ 1];
+    double (*Qc)[SolveSmem<BW>::LD] = sm.Qb[cur];
+    double (*Qn)[SolveSmem<BW>::LD] = sm.Qb[cur ^ 1];
+    const d2 ga = *(const d2 *)&Gc[2 * u][2 * v], gb = *(const d2 *)&Gc[2 * u + 1][2 * v];
+    const d2 qa = *(const d2 *)&Qc[2 * u][2 * v], qb = *(const d2 *)&Qc[2 * u + 1][2 * v];
     if (tid < BW) {
-      const unsigned pq = sm.pq[step][tid];
-      const int p = pq & 255, q = pq >> 8;
+      const d2 dg = *(const d2 *)&Gc[2 * tid][2 * tid];
       double c, sn;
-      rot_params(Gc[p][p], Gc[q][q], Gc[p][q], thr, tol2, floor2, c, sn);
-      sm.cs[tid][0] = c;
-      sm.cs[tid][1] = sn;
+      rot_params(dg.x, Gc[2 * tid + 1][2 * tid + 1], dg.y, thr, tol2, floor2, c, sn);
+      const d2 cs = {c, sn};
+      *(d2 *)&sm.cs[tid][0] = cs;
     }
     __syncthreads();
-    const double cu = sm.cs[u][0], su = sm.cs[u][1], cv = sm.cs[v][0], sv = sm.cs[v][1];
+    const d2 ru = *(const d2 *)&sm.cs[u][0], rv = *(const d2 *)&sm.cs[v][0];
+    const double cu = ru.x, su = ru.y, cv = rv.x, sv = rv.y;
     // rows (J_u^T), then columns (J_v)
-    const double h00 = cu * g00 - su * g10, h01 = cu * g01 - su * g11;
-    const double h10 = su * g00 + cu * g10, h11 = su * g01 + cu * g11;
-    Gn[pu][pv] = cv * h00 - sv * h01;
-    Gn[pu][qv] = sv * h00 + cv * h01;
-    Gn[qu][pv] = cv * h10 - sv * h11;
-    Gn[qu][qv] = sv * h10 + cv * h11;
-    // Q <- Q J_v on rows 2u, 2u + 1
-    if (sv != 0.0) {
-      sm.Q[2 * u][pv] = cv * q00 - sv * q01;
-      sm.Q[2 * u][qv] = sv * q00 + cv * q01;
-      sm.Q[2 * u + 1][pv] = cv * q10 - sv * q11;
-      sm.Q[2 * u + 1][qv] = sv * q10 + cv * q11;
-    }
+    const double h00 = cu * ga.x - su * gb.x, h01 = cu * ga.y - su * gb.y;
+    const double h10 = su * ga.x + cu * gb.x, h11 = su * ga.y + cu * gb.y;
+    Gn[nu0][nv0] = cv * h00 - sv * h01;
+    Gn[nu0][nv1] = sv * h00 + cv * h01;
+    Gn[nu1][nv0] = cv * h10 - sv * h11;
+    Gn[nu1][nv1] = sv * h10 + cv * h11;
+    Qn[2 * u][nv0] = cv * qa.x - sv * qa.y;
+    Qn[2 * u][nv1] = sv * qa.x + cv * qa.y;
+    Qn[2 * u + 1][nv0] = cv * qb.x - sv * qb.y;
+    Qn[2 * u + 1][nv1] = sv * qb.x + cv * qb.y;
     cur ^= 1;
     __syncthreads();
   }
+  // B2 - 1 steps have returned every index to its own slot: Q is in index
+  // order.  G is no longer needed; its other buffer holds Q^T Q below.
+  double (*Qf)[SolveSmem<BW>::LD] = sm.Qb[cur];
+  double (*Sq)[SolveSmem<BW>::LD] = sm.Gb[0];
 
   // One Newton-Schulz step, Q <- Q (3I - Q^T Q) / 2, restores orthogonality
   // to rounding level; without it the O(u) drift of every visit accumulates
@@ -371,17 +372,17 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   // MFMA, one 16 x 16 tile per wave.
   const int ti = wave / NT, tj = wave % NT;
   {
-    dbl4 a4 = mfma_tile([&](int i, int k) { return sm.Q[k][ti * 16 + i]; },
-                        [&](int k, int j) { return sm.Q[k][tj * 16 + j]; }, B2, lane);
-    for (int t = 0; t < 4; ++t) sm.S[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = a4[t];
+    dbl4 a4 = mfma_tile([&](int i, int k) { return Qf[k][ti * 16 + i]; },
+                        [&](int k, int j) { return Qf[k][tj * 16 + j]; }, B2, lane);
+    for (int t = 0; t < 4; ++t) Sq[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = a4[t];
   }
   __syncthreads();
   {
-    dbl4 a4 = mfma_tile([&](int i, int k) { return sm.Q[ti * 16 + i][k]; },
-                        [&](int k, int j) { return sm.S[k][tj * 16 + j]; }, B2, lane);
+    dbl4 a4 = mfma_tile([&](int i, int k) { return Qf[ti * 16 + i][k]; },
+                        [&](int k, int j) { return Sq[k][tj * 16 + j]; }, B2, lane);
     for (int t = 0; t < 4; ++t) {
       const int i = ti * 16 + 4 * t + (lane >> 4), j = tj * 16 + (lane & 15);
-      store(i, j, 1.5 * sm.Q[i][j] - 0.5 * a4[t]);
+      store(i, j, 1.5 * Qf[i][j] - 0.5 * a4[t]);
     }
   }
   return 1;
