@@ -13,8 +13,9 @@
 // row groups of a wave and one LDS exchange across the 16 waves, and it
 // yields the sums of all 16 columns at once: one pass gives v^T x for every
 // trailing column of the panel and V^T v for T.  The column being reflected
-// is published in LDS once per step, so each lane forms v for its own rows
-// from a broadcast read; T is assembled after the last column.
+// reaches every lane at its own rows by a DPP row broadcast (the 16 lanes
+// of a row group hold the 16 columns at the same rows); T is assembled
+// after the last column.
 #include "ttm_internal.h"
 
 namespace ttm {
@@ -182,6 +183,90 @@ __device__ void panel_pivot(double *__restrict__ S, int m, int n, int j0, int jb
   __syncthreads();
 }
 
+// Lane K of each row of 16 lanes to the whole row (DPP row broadcast).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + K, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + K, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Shared state of a register panel.
+struct PanelSmem {
+  double red[2][PNT / 64][QB];  // per-wave sums d_c (double-buffered by column parity)
+  double xrow[2][QB];           // row CC of every column (same buffering)
+  double zs[QB][QB + 1];        // zs[i][b] = v_b^T v_i, b < i
+  double taus[QB];
+};
+
+// Column CC of a register panel (see qr_panel_reg_kernel), one barrier.
+// The row group of 16 lanes that holds a set of rows holds all 16 columns
+// there, so lane (g, c) gets column CC at its own rows by a row broadcast
+// from lane (g, CC).  One pass forms d_c = sum over rows below CC of
+// x_CC x_c for every column c (d_CC is the squared norm below the pivot);
+// with v = (1 at row CC, x_CC scale below), v^T x_c = x_c(CC) + scale d_c.
+// Row sums: per lane over slots, two shuffles over the four row groups,
+// one LDS value per (wave, column); a lane reads four of the sixteen
+// waves' values and two shuffles finish the sum, so every lane of a column
+// gets bitwise the same total.
+template <int SL, int CC>
+__device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int w, int g, int c, int i0) {
+  constexpr int B = CC & 1;
+  // Rows at or above the pivot (< 16) occur only in slot 0.
+  double b[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) b[s] = row_bcast<CC>(x[s]);
+  double d = (i0 > CC) ? b[0] * x[0] : 0.0;
+#pragma unroll
+  for (int s = 1; s < SL; ++s) d = fma(b[s], x[s], d);
+  d += __shfl_xor(d, 16, 64);
+  d += __shfl_xor(d, 32, 64);
+  if (g == 0) sm.red[B][w][c] = d;
+  if (i0 == CC) sm.xrow[B][c] = x[0];
+  __syncthreads();
+  double dc = (sm.red[B][g][c] + sm.red[B][4 + g][c]) + (sm.red[B][8 + g][c] + sm.red[B][12 + g][c]);
+  dc += __shfl_xor(dc, 16, 64);
+  dc += __shfl_xor(dc, 32, 64);
+  const double xnorm2 = row_bcast<CC>(dc);
+  const double alpha = sm.xrow[B][CC], xc = sm.xrow[B][c];
+  double tau = 0.0, scale = 0.0, beta = alpha;
+  if (xnorm2 > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  const double tot = fma(scale, dc, xc);  // v^T x_c
+  // Reflector v (1 at row CC, x_CC scale below) into b.
+  b[0] = (i0 > CC) ? b[0] * scale : (i0 == CC ? 1.0 : 0.0);
+#pragma unroll
+  for (int s = 1; s < SL; ++s) b[s] *= scale;
+  if (c == CC) {
+    x[0] = (i0 > CC) ? b[0] : (i0 == CC ? beta : x[0]);
+#pragma unroll
+    for (int s = 1; s < SL; ++s) x[s] = b[s];
+  } else if (c > CC) {
+    // x <- x - tau (v^T x) v
+    const double f = tau * tot;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) x[s] = fma(-f, b[s], x[s]);
+  }
+  // Columns left of CC hold earlier reflectors; their sums v_b^T v are kept for T.
+  if (w == 0 && g == 0) {
+    if (c < CC) sm.zs[CC][c] = tot;
+    if (c == CC) sm.taus[CC] = tau;
+  }
+}
+
+template <int SL, int CC = 0>
+__device__ __forceinline__ void panel_columns(double (&x)[SL], PanelSmem &sm, int jb, int w, int g, int c, int i0) {
+  if constexpr (CC < QB) {
+    if (CC < jb) {
+      panel_column<SL, CC>(x, sm, w, g, c, i0);
+      panel_columns<SL, CC + 1>(x, sm, jb, w, g, c, i0);
+    }
+  }
+}
+
 // Factor columns j0 .. j0+jb-1 of S (column-major, ld m) in place, rows
 // j0 .. m-1 (mv = m - j0 <= 64 * SL), after block column pivoting when
 // cnorm is not null.  Each reflector is H = I - tau v v^T
@@ -196,10 +281,7 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
                                                            const double *__restrict__ cnorm, int *__restrict__ perm,
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
-  __shared__ double red[2][16][QB];     // per-wave column sums: [norm | v^T x][wave][column]
-  __shared__ double piv[2][64 * SL];    // column cc before its reflection (double-buffered)
-  __shared__ double zs[QB][QB + 1];     // zs[i][b] = v_b^T v_i, b < i
-  __shared__ double taus[QB];
+  __shared__ PanelSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int mv = m - j0;
@@ -210,64 +292,7 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
     const int i = i0 + 64 * s;
     x[s] = (i < mv && c < jb) ? S[(int64_t)(j0 + c) * m + j0 + i] : 0.0;
   }
-  // Rows at or above a pivot (< 16) occur only in slot 0, so every row test
-  // below concerns slot 0 alone.
-  for (int cc = 0; cc < jb; ++cc) {
-    double *pc = piv[cc & 1];
-    // Squared norm of every column below row cc; column cc is published in
-    // LDS so that every lane can form v for its own rows.
-    double p = (i0 > cc) ? x[0] * x[0] : 0.0;
-#pragma unroll
-    for (int s = 1; s < SL; ++s) p = fma(x[s], x[s], p);
-    if (c == cc) {
-#pragma unroll
-      for (int s = 0; s < SL; ++s) pc[i0 + 64 * s] = x[s];
-    }
-    p += __shfl_xor(p, 16, 64);
-    p += __shfl_xor(p, 32, 64);
-    if (g == 0) red[0][w][c] = p;
-    __syncthreads();
-    double xnorm2 = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < 16; ++ww) xnorm2 += red[0][ww][cc];
-    const double alpha = pc[cc];
-    double tau = 0.0, scale = 0.0, beta = alpha;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // Reflector v (1 at row cc, x / (alpha - beta) below) and the partial
-    // sums of v^T x for every column of the panel.
-    const double v0 = (i0 > cc) ? pc[i0] * scale : (i0 == cc ? 1.0 : 0.0);
-    double q = v0 * x[0];
-#pragma unroll
-    for (int s = 1; s < SL; ++s) q = fma(pc[i0 + 64 * s] * scale, x[s], q);
-    if (c == cc) {
-      x[0] = (i0 > cc) ? v0 : (i0 == cc ? beta : x[0]);
-#pragma unroll
-      for (int s = 1; s < SL; ++s) x[s] = pc[i0 + 64 * s] * scale;
-    }
-    q += __shfl_xor(q, 16, 64);
-    q += __shfl_xor(q, 32, 64);
-    if (g == 0) red[1][w][c] = q;
-    __syncthreads();
-    double tot = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < 16; ++ww) tot += red[1][ww][c];
-    // Columns right of cc: x <- x - tau (v^T x) v.  Columns left of cc hold
-    // earlier reflectors; their sums v_b^T v are kept for T.
-    if (c > cc) {
-      const double f = tau * tot;
-      x[0] = fma(-f, v0, x[0]);
-#pragma unroll
-      for (int s = 1; s < SL; ++s) x[s] = fma(-f, pc[i0 + 64 * s] * scale, x[s]);
-    }
-    if (w == 0 && g == 0) {
-      if (c < cc) zs[cc][c] = tot;
-      if (c == cc) taus[cc] = tau;
-    }
-  }
+  panel_columns<SL>(x, sm, jb, w, g, c, i0);
   __syncthreads();
   // T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) zs(i, 0:i)^T, column by
   // column; lane a of wave 0 keeps row a in registers.
@@ -280,8 +305,8 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
       if (i < jb) {
         double acc = 0.0;
 #pragma unroll
-        for (int b = 0; b < i; ++b) acc = (b >= c) ? fma(tr[b], zs[i][b], acc) : acc;
-        tr[i] = (c < i) ? -taus[i] * acc : (c == i ? taus[i] : 0.0);
+        for (int b = 0; b < i; ++b) acc = (b >= c) ? fma(tr[b], sm.zs[i][b], acc) : acc;
+        tr[i] = (c < i) ? -sm.taus[i] * acc : (c == i ? sm.taus[i] : 0.0);
       }
     }
 #pragma unroll
