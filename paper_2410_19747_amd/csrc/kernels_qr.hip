@@ -564,14 +564,14 @@ size_t qr_inplace_scratch_doubles(int m, int n) {
   return (size_t)m * QB + QB * QB + (size_t)n + 2 * (size_t)QB * m + 4 * 32;
 }
 
-hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, hipStream_t s) {
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipErrorInvalidValue;
   if (perm && n > PNT * PIVOT_MAX_CAND) return hipErrorInvalidValue;
   const int k = m < n ? m : n;
   double *p = scratch;
   auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
   double *Vb = adv((size_t)m * QB);
-  double *T = adv(QB * QB);
+  double *T1 = adv(QB * QB);
   Pivot pv;
   if (perm) {
     double *cnorm = adv((size_t)n);
@@ -583,12 +583,28 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   }
   for (int j0 = 0; j0 < k; j0 += QB) {
     const int jb = (k - j0) < QB ? (k - j0) : QB;
+    double *T = Tall ? Tall + (size_t)(j0 / QB) * QB * QB : T1;
     hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, pv, s);
     if (e != hipSuccess) return e;
     e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, const_cast<double *>(pv.cnorm), jb, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_apply_q(const double *S, int m, int k, const double *Tall, double *X, int nc, double *scratch,
+                          hipStream_t s) {
+  if (m <= 0 || k <= 0 || nc <= 0) return hipSuccess;
+  double *Vb = scratch;
+  // Q X = H_0 ... H_{k-1} X: block reflectors from the last panel to the first.
+  for (int pi = (k - 1) / QB; pi >= 0; --pi) {
+    const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
+    hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
+                       j0, jb, Vb);
+    hipError_t e = launch_update(X, m, j0, 0, nc, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
 }
 
 size_t qr_scratch_doubles(int m, int n) {

@@ -674,8 +674,8 @@ hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStr
 // ------------------------------------------------------------------ write-out
 // u[rowperm[j] * u_os + t * u_ts] = W[:, perm[t]](j) / sigma[perm[t]] for
 // j < L, t < r: the leading r columns of W normalised, their rows put back
-// in the caller's order (rowperm[j] = original index of row j).  Zero
-// singular values give zero vectors.
+// in the caller's order (rowperm[j] = original index of row j; a null
+// rowperm keeps the order).  Zero singular values give zero vectors.
 __global__ void jacobi_write_u_kernel(const double *__restrict__ W, const double *__restrict__ sigma,
                                       const int *__restrict__ perm, const int *__restrict__ rowperm, int L,
                                       int r, double *__restrict__ u, int64_t u_os, int64_t u_ts) {
@@ -686,7 +686,8 @@ __global__ void jacobi_write_u_kernel(const double *__restrict__ W, const double
     const int c = perm[t];
     const double sg = sigma[c];
     const double v = W[(int64_t)c * L + j];
-    u[(int64_t)rowperm[j] * u_os + (int64_t)t * u_ts] = (sg > 0.0) ? v / sg : 0.0;
+    const int row = rowperm ? rowperm[j] : j;
+    u[(int64_t)row * u_os + (int64_t)t * u_ts] = (sg > 0.0) ? v / sg : 0.0;
   }
 }
 

@@ -1,6 +1,6 @@
 // Truncated SVD driver for the swap and rounding steps: column ordering,
-// Householder QR preconditioning, one-sided Jacobi on R^T, rank rule and
-// write-out (the steps are listed with svd_oside in ttm_internal.h).
+// two Householder QRs as preconditioner, one-sided Jacobi on R2^T, rank rule
+// and write-out (the steps are listed with svd_oside in ttm_internal.h).
 #include <math.h>
 #include <stdio.h>
 
@@ -11,16 +11,23 @@
 namespace ttm {
 namespace {
 constexpr double kUnitRoundoff = 2.220446049250313e-16;
+constexpr int kPanel = 16;  // QR panel width (T factors of 16 x 16 per panel)
 
 size_t r32(size_t n) { return (n + 31) & ~(size_t)31; }
 
 struct SvdBufs {
-  double *S = nullptr;      // np x no: ordered copy of Y, factored in place
-  double *qr = nullptr;     // QR scratch
-  double *ynorm = nullptr;  // no column norms of Y
-  int *perm0 = nullptr;     // no: ordered position -> column of Y
+  double *Xt = nullptr;    // no x np: X = Y^T; later R1^T (np x k), then U_r (no x r)
+  double *S = nullptr;     // no x np: ordered copy of X, factored in place (Q1, R1)
+  double *qr = nullptr;    // QR scratch (both factorisations)
+  double *Tall = nullptr;  // T factors of the first QR
+  double *xnorm = nullptr; // np column norms of X
+  int *perm1 = nullptr;    // np: ordered position -> column of X
   JacobiBufs jb;
 };
+
+size_t qr_ws(const SvdPlan &p) {
+  return std::max(qr_inplace_scratch_doubles(p.no, p.np), qr_inplace_scratch_doubles(p.np, p.k));
+}
 
 SvdBufs carve(const SvdPlan &p, double *base) {
   SvdBufs b;
@@ -31,10 +38,12 @@ SvdBufs carve(const SvdPlan &p, double *base) {
     return x;
   };
   const JacobiPlan &jp = p.jp;
+  b.Xt = adv((size_t)p.np * p.no);
   b.S = adv((size_t)p.np * p.no);
-  b.qr = adv(qr_inplace_scratch_doubles(p.np, p.no));
-  b.ynorm = adv((size_t)p.no);
-  b.perm0 = reinterpret_cast<int *>(adv((size_t)p.no));
+  b.qr = adv(qr_ws(p));
+  b.Tall = adv((size_t)((p.k + kPanel - 1) / kPanel) * kPanel * kPanel);
+  b.xnorm = adv((size_t)p.np);
+  b.perm1 = reinterpret_cast<int *>(adv((size_t)p.np));
   b.jb.W = adv((size_t)jp.L * jp.ncp);
   b.jb.Wt = adv((size_t)jp.L * jp.ncp);
   b.jb.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
@@ -59,16 +68,17 @@ SvdPlan svd_plan(int np, int no) {
   p.np = np;
   p.no = no;
   p.k = std::min(np, no);
-  p.jp = jacobi_plan(no, p.k);
+  p.jp = jacobi_plan(p.k, p.k);
   return p;
 }
 
 size_t svd_ws_doubles(const SvdPlan &p) {
   const JacobiPlan &jp = p.jp;
   size_t n = 0;
-  n += r32((size_t)p.np * p.no);
-  n += r32(qr_inplace_scratch_doubles(p.np, p.no));
-  n += 2 * r32((size_t)p.no);
+  n += 2 * r32((size_t)p.np * p.no);
+  n += r32(qr_ws(p));
+  n += r32((size_t)((p.k + kPanel - 1) / kPanel) * kPanel * kPanel);
+  n += 2 * r32((size_t)p.np);
   n += 2 * r32((size_t)jp.L * jp.ncp);
   n += r32((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
   n += r32((size_t)jp.rounds * jp.pairs);
@@ -98,24 +108,34 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
     if (timer && timer->on) timer->collect();
     return true;
   };
-  // 1-2. column order, copy, ||Y||_F^2, QR
+  // 1. X = Y^T, its columns in decreasing norm order, ||Y||_F^2
   {
     Timed tm(timer, KC_JAC_OTHER, s);
-    if (!ok(launch_column_norms(Y, p.np, p.no, b.ynorm, s))) return out;
-    if (!ok(launch_sort_desc(b.ynorm, p.no, b.perm0, s))) return out;
-    if (!ok(launch_gather_columns(Y, b.perm0, p.np, p.no, b.S, s))) return out;
-    if (!ok(launch_frob_from_norms(b.ynorm, p.no, b.jb.result, s))) return out;
+    if (!ok(launch_transpose(b.Xt, Y, p.no, p.np, s))) return out;
+    if (!ok(launch_column_norms(b.Xt, p.no, p.np, b.xnorm, s))) return out;
+    if (!ok(launch_sort_desc(b.xnorm, p.np, b.perm1, s))) return out;
+    if (!ok(launch_gather_columns(b.Xt, b.perm1, p.no, p.np, b.S, s))) return out;
+    if (!ok(launch_frob_from_norms(b.xnorm, p.np, b.jb.result, s))) return out;
+  }
+  // 2. X P = Q1 R1, then R1^T = Q2 R2
+  {
+    Timed tm(timer, KC_QR, s);
+    // Block column pivoting saves sweeps once a sweep is expensive enough
+    // to pay for the selection step.
+    int *pivot = (p.np >= 2048) ? b.perm1 : nullptr;
+    if (!ok(launch_qr_inplace(b.S, p.no, p.np, b.qr, pivot, b.Tall, s))) return out;
+  }
+  {
+    Timed tm(timer, KC_JAC_OTHER, s);
+    if (!ok(launch_rt_from_qr(b.S, p.no, p.np, p.k, p.k, b.Xt, s))) return out;
   }
   {
     Timed tm(timer, KC_QR, s);
-    // Block column pivoting in the QR saves Jacobi sweeps (the rows of R come
-    // out graded); its selection step pays off once a sweep is expensive.
-    int *pivot = (p.no >= 2048) ? b.perm0 : nullptr;
-    if (!ok(launch_qr_inplace(b.S, p.np, p.no, b.qr, pivot, s))) return out;
+    if (!ok(launch_qr_inplace(b.Xt, p.np, p.k, b.qr, nullptr, nullptr, s))) return out;
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);
-    if (!ok(launch_rt_from_qr(b.S, p.np, p.no, p.k, jp.ncp, b.jb.W, s))) return out;
+    if (!ok(launch_rt_from_qr(b.Xt, p.np, p.k, p.k, jp.ncp, b.jb.W, s))) return out;
   }
   // 3. Jacobi sweeps until the columns of W are orthogonal
   const double tol = sqrt((double)std::max(jp.L, 1)) * kUnitRoundoff;
@@ -164,12 +184,22 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   out.rank = (int)res[0];
   out.disc = res[1];
   out.total = res[2];
-  // 5. U_r in the caller's layout
+  // 5. U_r = Q1 [U_W,r; 0] (no x r, column-major), then the caller's layout.
+  // U_r^T row-major is that column-major matrix, so SVD_U_T is formed in u.
+  const int r = out.rank;
+  double *ucm = (u_layout == SVD_U_T) ? u : b.Xt;
   {
     Timed tm(timer, KC_JAC_OTHER, s);
-    const int64_t u_os = (u_layout == SVD_U) ? out.rank : 1;
-    const int64_t u_ts = (u_layout == SVD_U) ? 1 : p.no;
-    if (!ok(launch_jacobi_write_u(jp, b.jb, b.perm0, out.rank, u, u_os, u_ts, s))) return out;
+    if (p.k < p.no && !ok(launch_fill(ucm, 0.0, (int64_t)p.no * r, s))) return out;
+    if (!ok(launch_jacobi_write_u(jp, b.jb, nullptr, r, ucm, 1, p.no, s))) return out;
+  }
+  {
+    Timed tm(timer, KC_QR, s);
+    if (!ok(launch_apply_q(b.S, p.no, p.k, b.Tall, ucm, r, b.qr, s))) return out;
+  }
+  {
+    Timed tm(timer, KC_JAC_OTHER, s);
+    if (u_layout == SVD_U && !ok(launch_transpose(u, ucm, r, p.no, s))) return out;
     if (sigma_out) {
       hipLaunchKernelGGL(sorted_sigma_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s, b.jb.sigma, b.jb.perm,
                          p.k, sigma_out);

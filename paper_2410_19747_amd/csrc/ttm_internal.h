@@ -111,9 +111,16 @@ size_t qr_scratch_doubles(int m, int n);
 // block column pivoting: before each 16-column panel the 16 columns of
 // largest remaining norm are moved into it (n <= 8192), so that S P = Q R,
 // and perm is permuted along (perm[j] = the column held at position j).
-// scratch: qr_inplace_scratch_doubles(m, n).
-hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, hipStream_t s);
+// scratch: qr_inplace_scratch_doubles(m, n).  With Tall not null the
+// triangular factor T of panel i (16 x 16, row-major) is kept at
+// Tall + 256 i, ceil(k / 16) panels, for launch_apply_q.
+hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s);
 size_t qr_inplace_scratch_doubles(int m, int n);
+// X <- Q X for the m x nc column-major X (ld m), Q = H_0 ... H_{k-1} the
+// orthogonal factor of a launch_qr_inplace factorisation of S (m rows, its
+// T factors in Tall).  scratch: 16 m doubles.
+hipError_t launch_apply_q(const double *S, int m, int k, const double *Tall, double *X, int nc, double *scratch,
+                          hipStream_t s);
 
 // ------------------------------------------------------------------ Jacobi
 // One-sided block Jacobi on an L x nc column-major matrix W (ld = L),
@@ -174,16 +181,21 @@ hipError_t launch_frob_from_norms(const double *x, int n, double *result, hipStr
 // ------------------------------------------------------------------ truncated SVD
 // Truncated SVD Y ~= Z U_r^T of an np x no matrix Y (column-major, ld np)
 // whose factor U_r (no x r) must have orthonormal columns: U_r holds the
-// leading right singular vectors of Y and Z = Y U_r = U_Y,r S_r.
-//   1. the columns of Y are ordered by decreasing norm and copied;
-//   2. Householder QR of the copy, Y P = Q R (R only);
-//   3. one-sided Jacobi on W = R^T (no x k, k = min(np, no)) until its
-//      columns are orthogonal: W = (P^T V_Y) S, so the normalised columns,
-//      rows put back in Y's order, are the right singular vectors of Y;
+// leading right singular vectors of Y and Z = Y U_r = U_Y,r S_r.  With
+// X = Y^T (no x np):
+//   1. the columns of X are ordered by decreasing norm (block-pivoted in the
+//      QR from 2048 columns) and copied;
+//   2. Householder QR of the copy, X P = Q1 R1 (reflectors and T factors
+//      kept), then QR of R1^T = Q2 R2 (R2 only, k x k, k = min(np, no));
+//   3. one-sided Jacobi on W = R2^T until its columns are orthogonal: then
+//      X P = Q1 W Q2^T with W = U_W S, so the leading right singular vectors
+//      of Y are U_r = Q1 U_W,r;
 //   4. the rank rule of Eq. (eps) on the singular values;
-//   5. U_r written out; the caller forms Z = Y U_r with one product.
-// The QR step is the preconditioner of Drmac and Veselic (2008): Jacobi on
-// R^T of a column-ordered QR needs markedly fewer sweeps than on Y itself.
+//   5. U_W,r written out and multiplied by Q1 (block reflectors); the
+//      caller forms Z = Y U_r with one product.
+// The two QRs are the preconditioner of Drmac and Veselic (2008): Jacobi on
+// R2^T needs markedly fewer sweeps than on R1^T, which needs fewer than on
+// Y itself.
 struct SvdPlan {
   int np = 0, no = 0, k = 0;
   JacobiPlan jp;
