@@ -191,6 +191,31 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum of v over the four row groups of a wave (lanes c, c + 16, c + 32,
+// c + 48) by the gfx950 lane swaps, which exchange rows of 16 lanes
+// (permlane16) or halves of the wave (permlane32) between two registers.
+// Every lane adds the same two operands in the same order, so the four
+// lanes of a column get bitwise the same sum.
+__device__ __forceinline__ double rowgroup_sum(double v) {
+  unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+// 1 / x from the hardware reciprocal and two Newton steps (x finite, nonzero).
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
 // Shared state of a register panel.
 struct PanelSmem {
   double red[2][PNT / 64][QB];  // per-wave sums d_c (double-buffered by column parity)
@@ -219,37 +244,31 @@ __device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int
   double d = (i0 > CC) ? b[0] * x[0] : 0.0;
 #pragma unroll
   for (int s = 1; s < SL; ++s) d = fma(b[s], x[s], d);
-  d += __shfl_xor(d, 16, 64);
-  d += __shfl_xor(d, 32, 64);
+  d = rowgroup_sum(d);
   if (g == 0) sm.red[B][w][c] = d;
   if (i0 == CC) sm.xrow[B][c] = x[0];
   __syncthreads();
-  double dc = (sm.red[B][g][c] + sm.red[B][4 + g][c]) + (sm.red[B][8 + g][c] + sm.red[B][12 + g][c]);
-  dc += __shfl_xor(dc, 16, 64);
-  dc += __shfl_xor(dc, 32, 64);
+  const double dc = rowgroup_sum((sm.red[B][g][c] + sm.red[B][4 + g][c]) + (sm.red[B][8 + g][c] + sm.red[B][12 + g][c]));
   const double xnorm2 = row_bcast<CC>(dc);
   const double alpha = sm.xrow[B][CC], xc = sm.xrow[B][c];
   double tau = 0.0, scale = 0.0, beta = alpha;
   if (xnorm2 > 0.0) {
     beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-    tau = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+    tau = (beta - alpha) * recip(beta);
+    scale = recip(alpha - beta);
   }
   const double tot = fma(scale, dc, xc);  // v^T x_c
   // Reflector v (1 at row CC, x_CC scale below) into b.
   b[0] = (i0 > CC) ? b[0] * scale : (i0 == CC ? 1.0 : 0.0);
 #pragma unroll
   for (int s = 1; s < SL; ++s) b[s] *= scale;
-  if (c == CC) {
-    x[0] = (i0 > CC) ? b[0] : (i0 == CC ? beta : x[0]);
+  // Column CC becomes (R entries, beta, v); columns right of it
+  // x <- x - tau (v^T x) v; columns left of it (earlier reflectors) stay.
+  const bool piv = (c == CC);
+  const double f = (c > CC) ? tau * tot : 0.0;
+  x[0] = piv ? ((i0 > CC) ? b[0] : (i0 == CC ? beta : x[0])) : fma(-f, b[0], x[0]);
 #pragma unroll
-    for (int s = 1; s < SL; ++s) x[s] = b[s];
-  } else if (c > CC) {
-    // x <- x - tau (v^T x) v
-    const double f = tau * tot;
-#pragma unroll
-    for (int s = 0; s < SL; ++s) x[s] = fma(-f, b[s], x[s]);
-  }
+  for (int s = 1; s < SL; ++s) x[s] = piv ? b[s] : fma(-f, b[s], x[s]);
   // Columns left of CC hold earlier reflectors; their sums v_b^T v are kept for T.
   if (w == 0 && g == 0) {
     if (c < CC) sm.zs[CC][c] = tot;
@@ -500,6 +519,116 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
   }
 }
 
+// The same update with the rows split over workgroups, for when no column
+// norms are wanted: a tall block reflector applied by one workgroup per 16
+// columns is a long serial walk over the rows.  Rows j0 .. m-1 are cut into
+// chunks of URC; grid (column blocks, chunks) for both kernels.
+//   qr_update_part_kernel:  part[cb][ch] = V_ch^T A_ch (16 x 16, row-major);
+//   qr_update_apply_kernel: W1 = sum over ch of part[cb][ch] (fixed order,
+//     so every chunk of a column block gets bitwise the same W1),
+//     W2 = op(T) W1, A_ch -= V_ch W2.
+constexpr int URC = 128;
+
+static inline int update_chunks(int mv) { return (mv + URC - 1) / URC; }
+
+__global__ __launch_bounds__(UNT) void qr_update_part_kernel(const double *__restrict__ S, int m, int j0, int c0,
+                                                             int nc, const double *__restrict__ Vb,
+                                                             double *__restrict__ part) {
+  __shared__ double Wp[4][QB][QB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mv = m - j0;
+  const int cb = c0 + QB * blockIdx.x, ch = blockIdx.y;
+  const int ncol = min(QB, c0 + nc - cb);
+  const double *A = S + (int64_t)cb * m + j0;
+  // Each wave reduces URC / 4 rows of the chunk, all loads issued first.
+  constexpr int KS = URC / 16;  // MFMA k-steps of 4 rows per wave
+  const int kb = ch * URC + w * (URC / 4);
+  double va[KS], ab[KS];
+#pragma unroll
+  for (int u = 0; u < KS; ++u) {
+    const int kk = kb + 4 * u + q4;
+    const bool ok = kk < mv;
+    va[u] = ok ? Vb[(int64_t)r16 * mv + kk] : 0.0;
+    ab[u] = (ok && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
+  }
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < KS; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], ab[u], acc, 0, 0, 0);
+  for (int t = 0; t < 4; ++t) Wp[w][4 * t + q4][r16] = acc[t];
+  __syncthreads();
+  const int ti = tid >> 4, tj = tid & 15;
+  part[((int64_t)blockIdx.x * gridDim.y + ch) * QB * QB + ti * QB + tj] =
+      (Wp[0][ti][tj] + Wp[1][ti][tj]) + (Wp[2][ti][tj] + Wp[3][ti][tj]);
+}
+
+__global__ __launch_bounds__(UNT) void qr_update_apply_kernel(double *__restrict__ S, int m, int j0, int c0, int nc,
+                                                              const double *__restrict__ Vb,
+                                                              const double *__restrict__ T, int trans,
+                                                              const double *__restrict__ part) {
+  __shared__ double W1[QB][QB + 1];
+  __shared__ double W2[QB][QB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mv = m - j0;
+  const int cb = c0 + QB * blockIdx.x, ch = blockIdx.y, nch = gridDim.y;
+  const int ncol = min(QB, c0 + nc - cb);
+  double *A = S + (int64_t)cb * m + j0;
+  // This chunk's rows of V and A (two 16-row tiles per wave), loaded first.
+  double vv[2][4], aa[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = ch * URC + 16 * w + 64 * h + r16;
+    const bool ok = r < mv;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int col = 4 * u + q4;
+      vv[h][u] = ok ? Vb[(int64_t)col * mv + r] : 0.0;
+      aa[h][u] = (ok && col < ncol) ? A[(int64_t)col * m + r] : 0.0;
+    }
+  }
+  const int ti = tid >> 4, tj = tid & 15;
+  {
+    const double *pp = part + (int64_t)blockIdx.x * nch * QB * QB + ti * QB + tj;
+    double sum = 0.0;
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+      const double p0 = pp[(c + 0) * QB * QB], p1 = pp[(c + 1) * QB * QB];
+      const double p2 = pp[(c + 2) * QB * QB], p3 = pp[(c + 3) * QB * QB];
+      sum += p0;
+      sum += p1;
+      sum += p2;
+      sum += p3;
+    }
+    for (; c < nch; ++c) sum += pp[c * QB * QB];
+    W1[ti][tj] = sum;
+  }
+  __syncthreads();
+  {
+    double t2 = 0.0;
+    for (int b = 0; b < QB; ++b) t2 = fma(trans ? T[b * QB + ti] : T[ti * QB + b], W1[b][tj], t2);
+    W2[ti][tj] = t2;
+  }
+  __syncthreads();
+  const double wa0 = W2[q4][r16], wa1 = W2[4 + q4][r16], wa2 = W2[8 + q4][r16], wa3 = W2[12 + q4][r16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = ch * URC + 16 * w + 64 * h + r16;
+    dbl4 d = {0.0, 0.0, 0.0, 0.0};
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, vv[h][0], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa1, vv[h][1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa2, vv[h][2], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(wa3, vv[h][3], d, 0, 0, 0);
+    if (r < mv) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 4 * t + q4;
+        if (col < ncol) A[(int64_t)col * m + r] = aa[h][t] - d[t];
+      }
+    }
+  }
+}
+
 // R (k x n, row-major) = upper triangle of S[0:k, :]; Qs = first k columns of I.
 __global__ void qr_r_and_identity_kernel(const double *__restrict__ S, int m, int n, int k,
                                          double *__restrict__ r, double *__restrict__ Qs) {
@@ -552,16 +681,28 @@ hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *Vb, dou
 }
 
 hipError_t launch_update(double *S, int m, int j0, int c0, int nc, const double *Vb, const double *T,
-                         int trans, double *cnorm, int next, hipStream_t s) {
+                         int trans, double *cnorm, int next, double *part, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(qr_update_kernel, dim3((nc + QB - 1) / QB), dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T,
-                     trans, cnorm, next);
+  const int ncb = (nc + QB - 1) / QB;
+  if (cnorm == nullptr && part != nullptr) {
+    const dim3 grid(ncb, update_chunks(m - j0));
+    hipLaunchKernelGGL(qr_update_part_kernel, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, part);
+    hipLaunchKernelGGL(qr_update_apply_kernel, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T, trans, part);
+  } else {
+    hipLaunchKernelGGL(qr_update_kernel, dim3(ncb), dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T, trans, cnorm,
+                       next);
+  }
   return hipGetLastError();
 }
 }  // namespace
 
+// Partial products of the split update over nc columns of an m-row block.
+static size_t update_part_doubles(int m, int nc) {
+  return (size_t)((nc + QB - 1) / QB) * update_chunks(m) * QB * QB;
+}
+
 size_t qr_inplace_scratch_doubles(int m, int n) {
-  return (size_t)m * QB + QB * QB + (size_t)n + 2 * (size_t)QB * m + 4 * 32;
+  return (size_t)m * QB + QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + 5 * 32;
 }
 
 hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s) {
@@ -572,6 +713,7 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
   double *Vb = adv((size_t)m * QB);
   double *T1 = adv(QB * QB);
+  double *part = adv(update_part_doubles(m, n));
   Pivot pv;
   if (perm) {
     double *cnorm = adv((size_t)n);
@@ -586,22 +728,27 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
     double *T = Tall ? Tall + (size_t)(j0 / QB) * QB * QB : T1;
     hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, pv, s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, const_cast<double *>(pv.cnorm), jb, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, const_cast<double *>(pv.cnorm), jb, part, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+size_t qr_apply_q_scratch_doubles(int m, int nc) {
+  return (((size_t)m * QB + 31) & ~(size_t)31) + update_part_doubles(m, nc) + 32;
 }
 
 hipError_t launch_apply_q(const double *S, int m, int k, const double *Tall, double *X, int nc, double *scratch,
                           hipStream_t s) {
   if (m <= 0 || k <= 0 || nc <= 0) return hipSuccess;
   double *Vb = scratch;
+  double *part = scratch + (((size_t)m * QB + 31) & ~(size_t)31);
   // Q X = H_0 ... H_{k-1} X: block reflectors from the last panel to the first.
   for (int pi = (k - 1) / QB; pi >= 0; --pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
                        j0, jb, Vb);
-    hipError_t e = launch_update(X, m, j0, 0, nc, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, s);
+    hipError_t e = launch_update(X, m, j0, 0, nc, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -615,7 +762,8 @@ size_t qr_scratch_doubles(int m, int n) {
   t += (size_t)m * QB;         // Vb
   t += (size_t)np * QB * QB;   // T per panel
   t += (size_t)m * k;          // Qs
-  return t + 4 * 32;
+  t += update_part_doubles(m, n);  // split-update partials
+  return t + 5 * 32;
 }
 
 hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
@@ -629,6 +777,7 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   double *Vb = adv((size_t)m * QB);
   double *Tall = adv((size_t)np * QB * QB);
   double *Qs = adv((size_t)m * k);
+  double *part = adv(update_part_doubles(m, n));
   const int64_t tot = (int64_t)m * n;
   hipLaunchKernelGGL(strided_to_colmajor_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, S, M, m, n, rs, cs);
   for (int pi = 0; pi < np; ++pi) {
@@ -636,7 +785,7 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
     double *T = Tall + (size_t)pi * QB * QB;
     hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, Pivot(), s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, nullptr, 0, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(qr_r_and_identity_kernel, dim3(grid_for((int64_t)k * n + (int64_t)m * k, 256)), dim3(256),
@@ -646,7 +795,7 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
                        j0, jb, Vb);
-    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, s);
+    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   // q (m x k, row-major) from Qs (column-major)

@@ -26,7 +26,8 @@ struct SvdBufs {
 };
 
 size_t qr_ws(const SvdPlan &p) {
-  return std::max(qr_inplace_scratch_doubles(p.no, p.np), qr_inplace_scratch_doubles(p.np, p.k));
+  return std::max({qr_inplace_scratch_doubles(p.no, p.np), qr_inplace_scratch_doubles(p.np, p.k),
+                   qr_apply_q_scratch_doubles(p.no, p.k)});
 }
 
 SvdBufs carve(const SvdPlan &p, double *base) {

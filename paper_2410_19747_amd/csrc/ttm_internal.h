@@ -118,7 +118,8 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
 size_t qr_inplace_scratch_doubles(int m, int n);
 // X <- Q X for the m x nc column-major X (ld m), Q = H_0 ... H_{k-1} the
 // orthogonal factor of a launch_qr_inplace factorisation of S (m rows, its
-// T factors in Tall).  scratch: 16 m doubles.
+// T factors in Tall).  scratch: qr_apply_q_scratch_doubles(m, nc).
+size_t qr_apply_q_scratch_doubles(int m, int nc);
 hipError_t launch_apply_q(const double *S, int m, int k, const double *Tall, double *X, int nc, double *scratch,
                           hipStream_t s);
 
