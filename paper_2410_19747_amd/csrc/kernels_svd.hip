@@ -268,28 +268,24 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double tol2 = tol * tol;
   const int64_t pstride = (int64_t)B2 * B2;
-  // Thread tid sums entries tid + SNT j, j < 4, over the sw partials in order
-  // s = 0, 1, ...; the loads of four partials are issued before any add.
-  constexpr int EPT = B2 * B2 / SNT;
+  // Thread tid sums entries tid + SNT j, j < EPT, over the sw partials in
+  // order s = 0, 1, ...; the loads of eight partials are issued before any add.
+  constexpr int EPT = B2 * B2 / SNT, KB = 8;
   double acc[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
   const double *src = part + tid;
-  int s0 = 0;
-  for (; s0 + 4 <= sw; s0 += 4) {
-    double v[4][EPT];
+  for (int s0 = 0; s0 < sw; s0 += KB) {
+    double v[KB][EPT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < KB; ++u)
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) v[u][j] = src[(s0 + u) * pstride + j * SNT];
+      for (int j = 0; j < EPT; ++j) v[u][j] = (s0 + u < sw) ? src[(s0 + u) * pstride + j * SNT] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < KB; ++u)
 #pragma unroll
       for (int j = 0; j < EPT; ++j) acc[j] += v[u][j];
   }
-  for (; s0 < sw; ++s0)
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) acc[j] += src[s0 * pstride + j * SNT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int e = tid + j * SNT, i = e / B2, k = e % B2;
@@ -297,24 +293,22 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
     sm.Qb[0][i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Convergence measure of this visit (scaled off-diagonal, see the header).
-  double m = 0.0;
-  for (int e = tid; e < B2 * B2; e += SNT) {
-    const int p = e / B2, q = e % B2;
-    if (p < q) {
-      const double gp = sm.Gb[0][p][p], gq = sm.Gb[0][q][q];
-      if (gp > thr || gq > thr) {
-        const double a = sqrt(gp), b = sqrt(gq);
-        const double lo = fmin(a, b);
-        m = fmax(m, fabs(sm.Gb[0][p][q]) / (fmax(a, b) * (lo * lo > thr ? lo : sqrt(floor2))));
-      }
-    }
+  // Convergence measure of this visit (scaled off-diagonal, see the header),
+  // squared: g_pq^2 / (hi^2 (lo^2 > thr ? lo^2 : floor2)), one root at the end.
+  double m2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + j * SNT, p = e / B2, q = e % B2;
+    const double gp = sm.Gb[0][p][p], gq = sm.Gb[0][q][q];
+    const double hi2 = fmax(gp, gq), lo2 = fmin(gp, gq);
+    if (p < q && hi2 > thr) m2 = fmax(m2, acc[j] * acc[j] / (hi2 * (lo2 > thr ? lo2 : floor2)));
   }
-  m = wave_max(m);
-  if (lane == 0) sm.redmax[wave] = m;
+  m2 = wave_max(m2);
+  if (lane == 0) sm.redmax[wave] = m2;
   __syncthreads();
-  m = 0.0;
-  for (int w = 0; w < SNT / 64; ++w) m = fmax(m, sm.redmax[w]);
+  m2 = 0.0;
+  for (int w = 0; w < SNT / 64; ++w) m2 = fmax(m2, sm.redmax[w]);
+  const double m = sqrt(m2);
   *mout = m;
   if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
