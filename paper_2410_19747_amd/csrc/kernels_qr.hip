@@ -230,12 +230,16 @@ struct PanelSmem {
 // from lane (g, CC).  One pass forms d_c = sum over rows below CC of
 // x_CC x_c for every column c (d_CC is the squared norm below the pivot);
 // with v = (1 at row CC, x_CC scale below), v^T x_c = x_c(CC) + scale d_c.
-// Row sums: per lane over slots, two shuffles over the four row groups,
-// one LDS value per (wave, column); a lane reads four of the sixteen
-// waves' values and two shuffles finish the sum, so every lane of a column
-// gets bitwise the same total.
+// A reflected column is left unscaled in registers: its lane keeps scale
+// and beta, the scale is folded into the update coefficient of the columns
+// to its right and into v_c^T v_CC, and the write-out applies it once.  Row
+// sums: per lane over slots, the lane swaps over the four row groups, one
+// LDS value per (wave, column); a lane reads four of the sixteen waves'
+// values and the lane swaps finish the sum, so every lane of a column gets
+// bitwise the same total.
 template <int SL, int CC>
-__device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int w, int g, int c, int i0) {
+__device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int w, int g, int c, int i0,
+                                             double &myscale, double &mybeta) {
   constexpr int B = CC & 1;
   // Rows at or above the pivot (< 16) occur only in slot 0.
   double b[SL];
@@ -257,31 +261,31 @@ __device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int
     tau = (beta - alpha) * recip(beta);
     scale = recip(alpha - beta);
   }
-  const double tot = fma(scale, dc, xc);  // v^T x_c
-  // Reflector v (1 at row CC, x_CC scale below) into b.
-  b[0] = (i0 > CC) ? b[0] * scale : (i0 == CC ? 1.0 : 0.0);
+  // v^T x_c for the column as stored (for c < CC: v_CC^T v_c / scale_c).
+  const double tot = fma(scale, dc, xc);
+  // Columns right of CC: x <- x - tau (v^T x) v, v = (1 at CC, b scale below).
+  const double f = (c > CC) ? tau * tot : 0.0, fs = f * scale;
+  x[0] = (i0 > CC) ? fma(-fs, b[0], x[0]) : (i0 == CC ? x[0] - f : x[0]);
 #pragma unroll
-  for (int s = 1; s < SL; ++s) b[s] *= scale;
-  // Column CC becomes (R entries, beta, v); columns right of it
-  // x <- x - tau (v^T x) v; columns left of it (earlier reflectors) stay.
-  const bool piv = (c == CC);
-  const double f = (c > CC) ? tau * tot : 0.0;
-  x[0] = piv ? ((i0 > CC) ? b[0] : (i0 == CC ? beta : x[0])) : fma(-f, b[0], x[0]);
-#pragma unroll
-  for (int s = 1; s < SL; ++s) x[s] = piv ? b[s] : fma(-f, b[s], x[s]);
-  // Columns left of CC hold earlier reflectors; their sums v_b^T v are kept for T.
+  for (int s = 1; s < SL; ++s) x[s] = fma(-fs, b[s], x[s]);
+  if (c == CC) {
+    myscale = scale;
+    mybeta = beta;
+  }
+  // Sums v_b^T v_CC of the earlier reflectors, kept for T.
   if (w == 0 && g == 0) {
-    if (c < CC) sm.zs[CC][c] = tot;
+    if (c < CC) sm.zs[CC][c] = myscale * tot;
     if (c == CC) sm.taus[CC] = tau;
   }
 }
 
 template <int SL, int CC = 0>
-__device__ __forceinline__ void panel_columns(double (&x)[SL], PanelSmem &sm, int jb, int w, int g, int c, int i0) {
+__device__ __forceinline__ void panel_columns(double (&x)[SL], PanelSmem &sm, int jb, int w, int g, int c, int i0,
+                                              double &myscale, double &mybeta) {
   if constexpr (CC < QB) {
     if (CC < jb) {
-      panel_column<SL, CC>(x, sm, w, g, c, i0);
-      panel_columns<SL, CC + 1>(x, sm, jb, w, g, c, i0);
+      panel_column<SL, CC>(x, sm, w, g, c, i0, myscale, mybeta);
+      panel_columns<SL, CC + 1>(x, sm, jb, w, g, c, i0, myscale, mybeta);
     }
   }
 }
@@ -311,7 +315,8 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
     const int i = i0 + 64 * s;
     x[s] = (i < mv && c < jb) ? S[(int64_t)(j0 + c) * m + j0 + i] : 0.0;
   }
-  panel_columns<SL>(x, sm, jb, w, g, c, i0);
+  double myscale = 0.0, mybeta = 0.0;  // of this lane's column once reflected
+  panel_columns<SL>(x, sm, jb, w, g, c, i0, myscale, mybeta);
   __syncthreads();
   // T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) zs(i, 0:i)^T, column by
   // column; lane a of wave 0 keeps row a in registers.
@@ -331,12 +336,14 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
 #pragma unroll
     for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? tr[b] : 0.0;
   }
+  // Column c: R above row c, beta at row c, v = x scale below.
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
     const int i = 64 * s + 4 * w + g;
     if (i < mv) {
-      if (c < jb) S[(int64_t)(j0 + c) * m + j0 + i] = x[s];
-      Vb[(int64_t)c * mv + i] = (c < jb && i >= c) ? (i == c ? 1.0 : x[s]) : 0.0;
+      const double v = x[s] * myscale;
+      if (c < jb) S[(int64_t)(j0 + c) * m + j0 + i] = (i > c) ? v : (i == c ? mybeta : x[s]);
+      Vb[(int64_t)c * mv + i] = (c < jb && i >= c) ? (i == c ? 1.0 : v) : 0.0;
     }
   }
 }
