@@ -183,12 +183,10 @@ __device__ void panel_pivot(double *__restrict__ S, int m, int n, int j0, int jb
   __syncthreads();
 }
 
-// Lane K of each row of 16 lanes to the whole row (DPP row broadcast).
+// Lane K of each row of 16 lanes to the whole row (64-bit DPP row broadcast).
 template <int K>
 __device__ __forceinline__ double row_bcast(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + K, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + K, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, false);
 }
 
 // Sum of v over the four row groups of a wave (lanes c, c + 16, c + 32,
@@ -222,7 +220,21 @@ struct PanelSmem {
   double xrow[2][QB];           // row CC of every column (same buffering)
   double zs[QB][QB + 1];        // zs[i][b] = v_b^T v_i, b < i
   double taus[QB];
+  double Tl[QB][QB + 1];        // T, row r kept by lane r of row group 0 of wave 0
 };
+
+// Column I of the compact-WY factor T by lane c (row c of T):
+// T(I, I) = tau_I, T(r, I) = -tau_I sum over r <= b < I of T(r, b) zs(I, b).
+// Each lane reads and writes only its own row, so no barrier is needed
+// between columns; zs(I, :) and tau_I must be visible.
+__device__ __forceinline__ void t_column(PanelSmem &sm, int I, int c) {
+  double a0 = 0.0, a1 = 0.0;
+  for (int b = c; b < I; b += 2) {
+    a0 = fma(sm.Tl[c][b], sm.zs[I][b], a0);
+    if (b + 1 < I) a1 = fma(sm.Tl[c][b + 1], sm.zs[I][b + 1], a1);
+  }
+  sm.Tl[c][I] = (c < I) ? -sm.taus[I] * (a0 + a1) : (c == I ? sm.taus[I] : 0.0);
+}
 
 // Column CC of a register panel (see qr_panel_reg_kernel), one barrier.
 // The row group of 16 lanes that holds a set of rows holds all 16 columns
@@ -245,10 +257,12 @@ __device__ __forceinline__ void panel_column(double (&x)[SL], PanelSmem &sm, int
   double b[SL];
 #pragma unroll
   for (int s = 0; s < SL; ++s) b[s] = row_bcast<CC>(x[s]);
-  double d = (i0 > CC) ? b[0] * x[0] : 0.0;
+  double dp[4] = {(i0 > CC) ? b[0] * x[0] : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int s = 1; s < SL; ++s) d = fma(b[s], x[s], d);
-  d = rowgroup_sum(d);
+  for (int s = 1; s < SL; ++s) dp[s & 3] = fma(b[s], x[s], dp[s & 3]);
+  // T column CC - 2 (its zs and tau became visible at the last barrier).
+  if (CC >= 2 && w == 0 && g == 0) t_column(sm, CC - 2, c);
+  double d = rowgroup_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
   if (g == 0) sm.red[B][w][c] = d;
   if (i0 == CC) sm.xrow[B][c] = x[0];
   __syncthreads();
@@ -305,45 +319,52 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
   __shared__ PanelSmem sm;
+  // The panel passes through LDS on the way in and out, so that global
+  // loads and stores run along the columns.
+  constexpr int RT = 64 * SL;
+  __shared__ double tile[QB][RT + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int mv = m - j0;
   const int i0 = 4 * w + g;  // row of slot 0; slot s holds row i0 + 64 s
   double x[SL];
 #pragma unroll
-  for (int s = 0; s < SL; ++s) {
-    const int i = i0 + 64 * s;
-    x[s] = (i < mv && c < jb) ? S[(int64_t)(j0 + c) * m + j0 + i] : 0.0;
+  for (int q = 0; q < SL; ++q) {
+    const int e = tid + PNT * q, cc = e / RT, i = e % RT;
+    x[q] = (i < mv && cc < jb) ? S[(int64_t)(j0 + cc) * m + j0 + i] : 0.0;
   }
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    const int e = tid + PNT * q;
+    tile[e / RT][e % RT] = x[q];
+  }
+  if (w == 0 && g == 0)
+    for (int b = 0; b < QB; ++b) sm.Tl[c][b] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SL; ++s) x[s] = tile[c][i0 + 64 * s];
   double myscale = 0.0, mybeta = 0.0;  // of this lane's column once reflected
   panel_columns<SL>(x, sm, jb, w, g, c, i0, myscale, mybeta);
-  __syncthreads();
-  // T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) zs(i, 0:i)^T, column by
-  // column; lane a of wave 0 keeps row a in registers.
-  if (w == 0 && g == 0) {
-    double tr[QB];
-#pragma unroll
-    for (int b = 0; b < QB; ++b) tr[b] = 0.0;
-#pragma unroll
-    for (int i = 0; i < QB; ++i) {
-      if (i < jb) {
-        double acc = 0.0;
-#pragma unroll
-        for (int b = 0; b < i; ++b) acc = (b >= c) ? fma(tr[b], sm.zs[i][b], acc) : acc;
-        tr[i] = (c < i) ? -sm.taus[i] * acc : (c == i ? sm.taus[i] : 0.0);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? tr[b] : 0.0;
-  }
   // Column c: R above row c, beta at row c, v = x scale below.
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
-    const int i = 64 * s + 4 * w + g;
+    const int i = i0 + 64 * s;
+    tile[c][i] = (i > c) ? x[s] * myscale : (i == c ? mybeta : x[s]);
+  }
+  __syncthreads();
+  // The last two columns of T, then T out.
+  if (w == 0 && g == 0) {
+    if (jb >= 2) t_column(sm, jb - 2, c);
+    t_column(sm, jb - 1, c);
+    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? sm.Tl[c][b] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    const int e = tid + PNT * q, cc = e / RT, i = e % RT;
     if (i < mv) {
-      const double v = x[s] * myscale;
-      if (c < jb) S[(int64_t)(j0 + c) * m + j0 + i] = (i > c) ? v : (i == c ? mybeta : x[s]);
-      Vb[(int64_t)c * mv + i] = (c < jb && i >= c) ? (i == c ? 1.0 : v) : 0.0;
+      const double val = tile[cc][i];
+      if (cc < jb) S[(int64_t)(j0 + cc) * m + j0 + i] = val;
+      Vb[(int64_t)cc * mv + i] = (cc < jb && i >= cc) ? (i == cc ? 1.0 : val) : 0.0;
     }
   }
 }
