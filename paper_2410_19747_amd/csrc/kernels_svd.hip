@@ -125,7 +125,11 @@ __device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
 template <int BW>
 struct Pair {
   static constexpr int B2 = 2 * BW;    // columns of the pair
-  static constexpr int SNT = BW * BW;  // threads of the solve: one 2 x 2 block of the Gram each
+  static constexpr int SNT = BW * BW;  // solve threads that own a 2 x 2 block of the Gram
+  // 32-column pairs add SNT threads that accumulate the rotation in
+  // registers (see solve_pair); 64-column pairs keep it in LDS.
+  static constexpr bool QREG = (BW == 16);
+  static constexpr int THREADS = QREG ? 2 * SNT : SNT;
   typedef double Tile[ROWS_PER_WG][B2 + 1];  // rows [chunk*128, +128) of the pair, zero beyond L
   typedef double Square[B2][B2 + 1];
 };
@@ -271,11 +275,12 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   // Thread tid sums entries tid + SNT j, j < EPT, over the sw partials in
   // order s = 0, 1, ...; the loads of eight partials are issued before any add.
   constexpr int EPT = B2 * B2 / SNT, KB = 8;
+  const bool gt = tid < SNT;  // a Gram thread
   double acc[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
-  const double *src = part + tid;
-  for (int s0 = 0; s0 < sw; s0 += KB) {
+  const double *src = part + (gt ? tid : 0);
+  for (int s0 = 0; gt && s0 < sw; s0 += KB) {
     double v[KB][EPT];
 #pragma unroll
     for (int u = 0; u < KB; ++u)
@@ -289,8 +294,10 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int e = tid + j * SNT, i = e / B2, k = e % B2;
-    sm.Gb[0][i][k] = acc[j];
-    sm.Qb[0][i][k] = (i == k) ? 1.0 : 0.0;
+    if (gt) {
+      sm.Gb[0][i][k] = acc[j];
+      sm.Qb[0][i][k] = (i == k) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   // Convergence measure of this visit (scaled off-diagonal, see the header),
@@ -298,13 +305,13 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   double m2 = 0.0;
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    const int e = tid + j * SNT, p = e / B2, q = e % B2;
+    const int e = (gt ? tid : 0) + j * SNT, p = e / B2, q = e % B2;
     const double gp = sm.Gb[0][p][p], gq = sm.Gb[0][q][q];
     const double hi2 = fmax(gp, gq), lo2 = fmin(gp, gq);
-    if (p < q && hi2 > thr) m2 = fmax(m2, acc[j] * acc[j] / (hi2 * (lo2 > thr ? lo2 : floor2)));
+    if (gt && p < q && hi2 > thr) m2 = fmax(m2, acc[j] * acc[j] / (hi2 * (lo2 > thr ? lo2 : floor2)));
   }
   m2 = wave_max(m2);
-  if (lane == 0) sm.redmax[wave] = m2;
+  if (gt && lane == 0) sm.redmax[wave] = m2;
   __syncthreads();
   m2 = 0.0;
   for (int w = 0; w < SNT / 64; ++w) m2 = fmax(m2, sm.redmax[w]);
@@ -313,24 +320,46 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   if (!(m > tol)) return 0;  // no index pair above tolerance: nothing would rotate
 
   // One cyclic sweep of two-sided Jacobi over the B2 indices (B2 - 1 steps),
-  // slots (2k, 2k + 1) paired at every step (see slot_next).  Thread (u, v)
-  // owns the 2 x 2 block of G at slot pairs (u, v) and rows 2u, 2u + 1 of Q
-  // at slot pair v.  Per step: every thread loads its blocks of G and Q while
-  // threads 0 .. BW-1 compute the step's rotations into LDS; after one
-  // barrier each thread applies J_u^T (.) J_v to its G block and J_v to its
-  // Q block and writes both to the other buffer at the slots of the next step.
+  // slots (2k, 2k + 1) paired at every step (see slot_next).  Gram thread
+  // (u, v) owns the 2 x 2 block of G at slot pairs (u, v).  Per step: every
+  // Gram thread loads its block while threads 0 .. BW-1 compute the step's
+  // rotations into LDS; after one barrier each applies J_u^T (.) J_v to its
+  // block and writes it to the other buffer at the slots of the next step.
+  // The accumulated rotation Q (rows: the pair's columns, columns: slots):
+  //  * 32-column pairs: thread SNT + 8 i + t holds Q(i, 4t .. 4t+3) in
+  //    registers, applies the step's rotations of slot pairs 2t, 2t + 1 after
+  //    the same barrier and moves its values to the next step's slots with
+  //    two row shifts (slot_next moves one slot a lane down, one a lane up);
+  //    it adds no LDS traffic to the Gram threads' critical path;
+  //  * 64-column pairs: Gram thread (u, v) also owns rows 2u, 2u + 1 of Q at
+  //    slot pair v, double-buffered in LDS like G.
   typedef double d2 __attribute__((ext_vector_type(2)));
   const int u = tid / BW, v = tid % BW;
   const int nu0 = slot_next(2 * u, B2), nu1 = slot_next(2 * u + 1, B2);
   const int nv0 = slot_next(2 * v, B2), nv1 = slot_next(2 * v + 1, B2);
+  const int qi = (tid - SNT) >> 3, qt = (tid - SNT) & 7;  // register-Q row and slot quad
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+  if (Pair<BW>::QREG && !gt) {
+    q0 = (qi == 4 * qt) ? 1.0 : 0.0;
+    q1 = (qi == 4 * qt + 1) ? 1.0 : 0.0;
+    q2 = (qi == 4 * qt + 2) ? 1.0 : 0.0;
+    q3 = (qi == 4 * qt + 3) ? 1.0 : 0.0;
+  }
   int cur = 0;
   for (int step = 0; step < B2 - 1; ++step) {
     double (*Gc)[SolveSmem<BW>::LD] = sm.Gb[cur];
     double (*Gn)[SolveSmem<BW>::LD] = sm.Gb[cur ^ 1];
     double (*Qc)[SolveSmem<BW>::LD] = sm.Qb[cur];
     double (*Qn)[SolveSmem<BW>::LD] = sm.Qb[cur ^ 1];
-    const d2 ga = *(const d2 *)&Gc[2 * u][2 * v], gb = *(const d2 *)&Gc[2 * u + 1][2 * v];
-    const d2 qa = *(const d2 *)&Qc[2 * u][2 * v], qb = *(const d2 *)&Qc[2 * u + 1][2 * v];
+    d2 ga = {0.0, 0.0}, gb = {0.0, 0.0}, qa = {0.0, 0.0}, qb = {0.0, 0.0};
+    if (gt) {
+      ga = *(const d2 *)&Gc[2 * u][2 * v];
+      gb = *(const d2 *)&Gc[2 * u + 1][2 * v];
+      if (!Pair<BW>::QREG) {
+        qa = *(const d2 *)&Qc[2 * u][2 * v];
+        qb = *(const d2 *)&Qc[2 * u + 1][2 * v];
+      }
+    }
     if (tid < BW) {
       const d2 dg = *(const d2 *)&Gc[2 * tid][2 * tid];
       double c, sn;
@@ -339,39 +368,64 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
       *(d2 *)&sm.cs[tid][0] = cs;
     }
     __syncthreads();
-    const d2 ru = *(const d2 *)&sm.cs[u][0], rv = *(const d2 *)&sm.cs[v][0];
-    const double cu = ru.x, su = ru.y, cv = rv.x, sv = rv.y;
-    // rows (J_u^T), then columns (J_v)
-    const double h00 = cu * ga.x - su * gb.x, h01 = cu * ga.y - su * gb.y;
-    const double h10 = su * ga.x + cu * gb.x, h11 = su * ga.y + cu * gb.y;
-    Gn[nu0][nv0] = cv * h00 - sv * h01;
-    Gn[nu0][nv1] = sv * h00 + cv * h01;
-    Gn[nu1][nv0] = cv * h10 - sv * h11;
-    Gn[nu1][nv1] = sv * h10 + cv * h11;
-    Qn[2 * u][nv0] = cv * qa.x - sv * qa.y;
-    Qn[2 * u][nv1] = sv * qa.x + cv * qa.y;
-    Qn[2 * u + 1][nv0] = cv * qb.x - sv * qb.y;
-    Qn[2 * u + 1][nv1] = sv * qb.x + cv * qb.y;
+    if (gt) {
+      const d2 ru = *(const d2 *)&sm.cs[u][0], rv = *(const d2 *)&sm.cs[v][0];
+      const double cu = ru.x, su = ru.y, cv = rv.x, sv = rv.y;
+      // rows (J_u^T), then columns (J_v)
+      const double h00 = cu * ga.x - su * gb.x, h01 = cu * ga.y - su * gb.y;
+      const double h10 = su * ga.x + cu * gb.x, h11 = su * ga.y + cu * gb.y;
+      Gn[nu0][nv0] = cv * h00 - sv * h01;
+      Gn[nu0][nv1] = sv * h00 + cv * h01;
+      Gn[nu1][nv0] = cv * h10 - sv * h11;
+      Gn[nu1][nv1] = sv * h10 + cv * h11;
+      if (!Pair<BW>::QREG) {
+        Qn[2 * u][nv0] = cv * qa.x - sv * qa.y;
+        Qn[2 * u][nv1] = sv * qa.x + cv * qa.y;
+        Qn[2 * u + 1][nv0] = cv * qb.x - sv * qb.y;
+        Qn[2 * u + 1][nv1] = sv * qb.x + cv * qb.y;
+      }
+    } else if (Pair<BW>::QREG) {
+      const d2 r0 = *(const d2 *)&sm.cs[2 * qt][0], r1 = *(const d2 *)&sm.cs[2 * qt + 1][0];
+      const double n0 = r0.x * q0 - r0.y * q1, n1 = r0.y * q0 + r0.x * q1;
+      const double n2 = r1.x * q2 - r1.y * q3, n3 = r1.y * q2 + r1.x * q3;
+      // Slot 4t + 3 of the lane below moves to slot 4t + 1 here, slot 4t of
+      // the lane above to slot 4t + 2 (row shifts by one lane); at the ends
+      // of a row of Q (t = 0, t = 7) the moves stay within the lane.
+      const double from_below = __builtin_amdgcn_mov_dpp(n3, 0x111, 0xf, 0xf, false);  // row_shr:1
+      const double from_above = __builtin_amdgcn_mov_dpp(n0, 0x101, 0xf, 0xf, false);  // row_shl:1
+      q0 = n2;
+      q1 = (qt == 0) ? n1 : from_below;
+      q2 = (qt == 7) ? n3 : from_above;
+      q3 = (qt == 0) ? n0 : n1;
+    }
     cur ^= 1;
     __syncthreads();
   }
   // B2 - 1 steps have returned every index to its own slot: Q is in index
   // order.  G is no longer needed; its other buffer holds Q^T Q below.
-  double (*Qf)[SolveSmem<BW>::LD] = sm.Qb[cur];
+  double (*Qf)[SolveSmem<BW>::LD] = Pair<BW>::QREG ? sm.Qb[0] : sm.Qb[cur];
   double (*Sq)[SolveSmem<BW>::LD] = sm.Gb[0];
+  if (Pair<BW>::QREG) {
+    if (!gt) {
+      const d2 a = {q0, q1}, b = {q2, q3};
+      *(d2 *)&Qf[qi][4 * qt] = a;
+      *(d2 *)&Qf[qi][4 * qt + 2] = b;
+    }
+    __syncthreads();
+  }
 
   // One Newton-Schulz step, Q <- Q (3I - Q^T Q) / 2, restores orthogonality
   // to rounding level; without it the O(u) drift of every visit accumulates
   // over the thousands of visits a column receives.  B2 x B2 products on
   // MFMA, one 16 x 16 tile per wave.
   const int ti = wave / NT, tj = wave % NT;
-  {
+  if (gt) {
     dbl4 a4 = mfma_tile([&](int i, int k) { return Qf[k][ti * 16 + i]; },
                         [&](int k, int j) { return Qf[k][tj * 16 + j]; }, B2, lane);
     for (int t = 0; t < 4; ++t) Sq[ti * 16 + 4 * t + (lane >> 4)][tj * 16 + (lane & 15)] = a4[t];
   }
   __syncthreads();
-  {
+  if (gt) {
     dbl4 a4 = mfma_tile([&](int i, int k) { return Qf[ti * 16 + i][k]; },
                         [&](int k, int j) { return Sq[k][tj * 16 + j]; }, B2, lane);
     for (int t = 0; t < 4; ++t) {
@@ -400,7 +454,7 @@ __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restri
 // grid (pairs).  One workgroup per block pair: the solve, the rotation into
 // qbuf[pair] (B2 x B2 row-major) and flag[pair] = 1 when it is not the identity.
 template <int BW>
-__global__ __launch_bounds__(BW *BW) void jacobi_solve_kernel(int L, int nblk, int round,
+__global__ __launch_bounds__(Pair<BW>::THREADS) void jacobi_solve_kernel(int L, int nblk, int round,
                                                               const double *__restrict__ part, int sw,
                                                               double *__restrict__ conv, double tol,
                                                               const double *__restrict__ result, double noise2,
@@ -491,7 +545,7 @@ void launch_round(const JacobiPlan &p, const JacobiBufs &b, int round, double to
   }
   {
     Timed tm(timer, KC_JAC_SOLVE, s);
-    hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(BW * BW), 0, s, p.L, p.nblk, round, b.part,
+    hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(Pair<BW>::THREADS), 0, s, p.L, p.nblk, round, b.part,
                        p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
   }
   {
