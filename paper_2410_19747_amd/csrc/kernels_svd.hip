@@ -597,64 +597,84 @@ __global__ __launch_bounds__(JNT) void jacobi_sort_kernel(const double *__restri
   const int c = blockIdx.x * JNT + threadIdx.x;
   if (c >= nc) return;
   const double me = sv[c];
-  int pos = 0;
-  for (int j = 0; j < nc; ++j) {
-    const double o = sv[j];
-    pos += (o > me) || (o == me && j < c);
+  // Position = number of values ahead of this one (larger, or equal at a
+  // lower index); LDS read in pairs, eight values per iteration.
+  auto ahead = [&](double o, int j) { return (int)((o > me) | ((o == me) & (j < c))); };
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 *s2 = reinterpret_cast<const d2 *>(sv);
+  int pos = 0, j = 0;
+  for (; j + 8 <= nc; j += 8) {
+    const d2 a = s2[j / 2], b = s2[j / 2 + 1], e = s2[j / 2 + 2], f = s2[j / 2 + 3];
+    pos += (ahead(a.x, j) + ahead(a.y, j + 1)) + (ahead(b.x, j + 2) + ahead(b.y, j + 3)) +
+           (ahead(e.x, j + 4) + ahead(e.y, j + 5)) + (ahead(f.x, j + 6) + ahead(f.y, j + 7));
   }
+  for (; j < nc; ++j) pos += ahead(sv[j], j);
   perm[pos] = c;
 }
 
-// Rule of Eq. (eps) on the sorted values: tails summed from the smallest up.
-// One workgroup: thread t owns the contiguous index range of chunk t.
+// Rule of Eq. (eps) on the sorted values.  One workgroup of 1024 threads:
+// thread t owns the contiguous index range of chunk t (at most RANK_PER
+// values, kept in registers); tails are suffix sums, within a chunk from its
+// smallest value up, the chunk totals combined by a suffix scan.
+constexpr int RANK_PER = 8;  // n <= 8192
 __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restrict__ sigma,
                                                            const int *__restrict__ perm, int n,
                                                            double eps, int cap, int forced,
                                                            double *__restrict__ result) {
-  __shared__ double csum[1024];
+  __shared__ double csum[2][1024];
   __shared__ int best;
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n + nt - 1) / nt;
   const int lo = min(n, t * per), hi = min(n, lo + per);
+  double suf[RANK_PER];  // suf[j] = sum over lo + j <= i < hi of s_i^2
   double local = 0.0;
-  for (int k = hi - 1; k >= lo; --k) {
-    const double s = sigma[perm[k]];
-    local += s * s;
+#pragma unroll
+  for (int j = RANK_PER - 1; j >= 0; --j) {
+    if (lo + j < hi) {
+      const double s = sigma[perm[lo + j]];
+      local += s * s;
+    }
+    suf[j] = local;
   }
-  csum[t] = local;
+  csum[0][t] = local;
   if (t == 0) best = n;
   __syncthreads();
-  // suffix: weight of every chunk after this one, summed from the end
-  double after = 0.0;
-  for (int u = nt - 1; u > t; --u) after += csum[u];
-  double total = 0.0;
-  for (int u = nt - 1; u >= 0; --u) total += csum[u];
-  // tails[k] = sum_{i >= k} s_i^2 ; the kept count k needs tails[k]
-  double tail = after;
+  // Inclusive suffix scan of the chunk totals (fixed order: Hillis-Steele).
+  int src = 0;
+  for (int d = 1; d < nt; d <<= 1) {
+    const double v = csum[src][t] + ((t + d < nt) ? csum[src][t + d] : 0.0);
+    csum[src ^ 1][t] = v;
+    src ^= 1;
+    __syncthreads();
+  }
+  const double after = (t + 1 < nt) ? csum[src][t + 1] : 0.0;  // sum over i >= hi
+  const double total = csum[src][0];
+  // The smallest kept count r < n whose tail (sum over i >= r) is zero or
+  // below eps * total; the tail of kept = k + 1 is suf[k + 1 - lo] + after
+  // inside the chunk and `after` at its end.
   int mine = n;
-  for (int k = hi - 1; k >= lo; --k) {
-    // tail currently = tails[k+1]
-    const int kept = k + 1;
-    if (kept >= 1 && (tail <= 0.0 || tail < eps * total)) mine = kept;
-    const double s = sigma[perm[k]];
-    tail += s * s;
+#pragma unroll
+  for (int j = RANK_PER - 1; j >= 0; --j) {
+    const int kept = lo + j + 1;
+    if (lo + j < hi && kept < n) {
+      const double tail = (j + 1 < RANK_PER && kept < hi) ? suf[j + 1] + after : after;
+      if (tail <= 0.0 || tail < eps * total) mine = kept;
+    }
   }
   if (mine < n) atomicMin(&best, mine);
   __syncthreads();
+  int r = best;
+  if (r < 1) r = 1;
+  if (cap > 0 && r > cap) r = cap;
+  if (forced > 0) r = forced;
+  if (r > n) r = n;
+  // Discarded weight: the tail at r, written by the chunk that holds r.
+#pragma unroll
+  for (int j = 0; j < RANK_PER; ++j)
+    if (lo + j < hi && lo + j == r) result[1] = suf[j] + after;
   if (t == 0) {
-    int r = best;
-    if (r < 1) r = 1;
-    if (cap > 0 && r > cap) r = cap;
-    if (forced > 0) r = forced;
-    if (r > n) r = n;
-    // discarded weight tails[r], summed from the smallest up
-    double disc = 0.0;
-    for (int k = n - 1; k >= r; --k) {
-      const double s = sigma[perm[k]];
-      disc += s * s;
-    }
+    if (r == n) result[1] = 0.0;
     result[0] = (double)r;
-    result[1] = disc;
     result[2] = total;
     result[4] = isfinite(total) ? 0.0 : 1.0;
   }
@@ -668,6 +688,7 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
   if (shm > 64 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(jacobi_sort_kernel, dim3((nc + JNT - 1) / JNT), dim3(JNT), shm, s, b.sigma, nc,
                      b.perm);
+  if (nc > 1024 * RANK_PER) return hipErrorInvalidValue;
   hipLaunchKernelGGL(jacobi_rank_kernel, dim3(1), dim3(1024), 0, s, b.sigma, b.perm, nc, eps, cap,
                      forced, b.result);
   return hipGetLastError();
