@@ -41,7 +41,8 @@ namespace ttm {
 
 namespace {
 constexpr int JNT = 256;           // threads of the Gram / apply / helper kernels
-constexpr int ROWS_PER_WG = 128;   // row chunk of a Gram / apply workgroup
+constexpr int ROWS_PER_WG = 128;   // row chunk of a Gram / apply workgroup (circle pairing)
+constexpr int ROWS_XOR = 64;       // row chunk with XOR pairing
 
 __device__ __forceinline__ void rr_pair(int n, int round, int k, int &a, int &b) {
   // Circle method over n (even) players: player n-1 fixed, the others rotate.
@@ -52,6 +53,25 @@ __device__ __forceinline__ void rr_pair(int n, int round, int k, int &a, int &b)
     a = (round + k) % (n - 1);
     b = (round - k + (n - 1)) % (n - 1);
   }
+}
+
+// XOR pairing over n = 2^k blocks: round r pairs block i with i ^ (r + 1).
+// Pair `pair` of the round is the `pair`-th block i < i ^ m (m = r + 1),
+// i.e. `pair` with a zero bit inserted at the highest set bit h of m.
+__device__ __forceinline__ int insert_zero_bit(int x, int b) { return ((x >> b) << (b + 1)) | (x & ((1 << b) - 1)); }
+__device__ __forceinline__ int remove_bit(int x, int b) { return ((x >> (b + 1)) << b) | (x & ((1 << b) - 1)); }
+__device__ __forceinline__ int high_bit(int m) { return 31 - __clz(m); }
+__device__ __forceinline__ void xor_pair(int round, int pair, int &a, int &b) {
+  const int m = round + 1;
+  a = insert_zero_bit(pair, high_bit(m));
+  b = a ^ m;
+}
+// Blocks of pair `pair` in round `round` under the plan's pairing.
+__device__ __forceinline__ void pair_blocks(int xs, int n, int round, int pair, int &a, int &b) {
+  if (xs)
+    xor_pair(round, pair, a, b);
+  else
+    rr_pair(n, round, pair, a, b);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -83,8 +103,13 @@ JacobiPlan jacobi_plan(int L, int nc) {
   p.bw = bw;
   p.nblk = nblk;
   p.ncp = nblk * bw;
-  p.rows_per_wg = ROWS_PER_WG;
-  p.sw = (L + ROWS_PER_WG - 1) / ROWS_PER_WG;
+  // XOR pairing for 32-column pairs when the block count is a power of two
+  // (4 or more): consecutive rounds then exchange blocks within groups of
+  // four, and one pass per round applies the rotations and forms the next
+  // Grams (jacobi_xor_round_kernel).
+  p.xs = (bw == 16 && nblk >= 4 && (nblk & (nblk - 1)) == 0) ? 1 : 0;
+  p.rows_per_wg = p.xs ? ROWS_XOR : ROWS_PER_WG;
+  p.sw = (L + p.rows_per_wg - 1) / p.rows_per_wg;
   p.rounds = nblk - 1;
   p.pairs = nblk / 2;
   return p;
@@ -130,7 +155,8 @@ struct Pair {
   // registers (see solve_pair); 64-column pairs keep it in LDS.
   static constexpr bool QREG = (BW == 16);
   static constexpr int THREADS = QREG ? 2 * SNT : SNT;
-  typedef double Tile[ROWS_PER_WG][B2 + 1];  // rows [chunk*128, +128) of the pair, zero beyond L
+  template <int RC>
+  using Tile = double[RC][B2 + 1];  // one row chunk of the pair, zero beyond L
   typedef double Square[B2][B2 + 1];
 };
 
@@ -140,34 +166,34 @@ __device__ __forceinline__ int pair_col(int bi, int bj, int c) {
 }
 
 // Every load of the thread is issued before the first LDS store.
-template <int BW>
+template <int BW, int RC>
 __device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
-                                                typename Pair<BW>::Tile &P) {
-  constexpr int B2 = Pair<BW>::B2, PER = ROWS_PER_WG * B2 / JNT;
-  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
+                                                typename Pair<BW>::template Tile<RC> &P) {
+  constexpr int B2 = Pair<BW>::B2, PER = RC * B2 / JNT;
+  const int r0 = chunk * RC, nr = min(RC, L - r0);
   double v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * JNT, c = e / ROWS_PER_WG, i = e % ROWS_PER_WG;
+    const int e = threadIdx.x + q * JNT, c = e / RC, i = e % RC;
     v[q] = (i < nr) ? W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * JNT;
-    P[e % ROWS_PER_WG][e / ROWS_PER_WG] = v[q];
+    P[e % RC][e / RC] = v[q];
   }
 }
 
 // out (B2 x B2, row-major) = P^T P over the tile; the four waves take the
 // 16 x 16 output tiles in turn.
-template <int BW>
-__device__ __forceinline__ void gram_of_tile(const typename Pair<BW>::Tile &P, double *__restrict__ out) {
+template <int BW, int RC>
+__device__ __forceinline__ void gram_of_tile(const typename Pair<BW>::template Tile<RC> &P, double *__restrict__ out) {
   constexpr int B2 = Pair<BW>::B2, NT = B2 / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int t = wave; t < NT * NT; t += JNT / 64) {
     const int ti = t / NT, tj = t % NT;
     dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
-                         [&](int k, int j) { return P[k][tj * 16 + j]; }, ROWS_PER_WG, lane);
+                         [&](int k, int j) { return P[k][tj * 16 + j]; }, RC, lane);
     for (int q = 0; q < 4; ++q) {
       const int i = ti * 16 + 4 * q + (lane >> 4), j = tj * 16 + (lane & 15);
       out[i * B2 + j] = acc[q];
@@ -177,12 +203,13 @@ __device__ __forceinline__ void gram_of_tile(const typename Pair<BW>::Tile &P, d
 
 // W rows of the tile <- P Q (P, Q in LDS); the four waves take the 16 x 16
 // output tiles in turn.
-template <int BW>
-__device__ __forceinline__ void apply_tile(const typename Pair<BW>::Tile &P, const typename Pair<BW>::Square &Q,
-                                           double *__restrict__ W, int L, int bi, int bj, int chunk) {
-  constexpr int B2 = Pair<BW>::B2, NC = B2 / 16, NR = ROWS_PER_WG / 16;
+template <int BW, int RC>
+__device__ __forceinline__ void apply_tile(const typename Pair<BW>::template Tile<RC> &P,
+                                           const typename Pair<BW>::Square &Q, double *__restrict__ W, int L, int bi,
+                                           int bj, int chunk) {
+  constexpr int B2 = Pair<BW>::B2, NC = B2 / 16, NR = RC / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = chunk * ROWS_PER_WG, nr = min(ROWS_PER_WG, L - r0);
+  const int r0 = chunk * RC, nr = min(RC, L - r0);
   for (int t = wave; t < NR * NC; t += JNT / 64) {
     const int rt = t / NC, y = t % NC;
     dbl4 acc = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
@@ -273,8 +300,8 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
   const double tol2 = tol * tol;
   const int64_t pstride = (int64_t)B2 * B2;
   // Thread tid sums entries tid + SNT j, j < EPT, over the sw partials in
-  // order s = 0, 1, ...; the loads of eight partials are issued before any add.
-  constexpr int EPT = B2 * B2 / SNT, KB = 8;
+  // order s = 0, 1, ...; the loads of KB partials are issued before any add.
+  constexpr int EPT = B2 * B2 / SNT, KB = (BW == 16) ? 16 : 8;
   const bool gt = tid < SNT;  // a Gram thread
   double acc[EPT];
 #pragma unroll
@@ -438,17 +465,17 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 
 // ------------------------------------------------------------------ kernels of a round
 // grid (pairs, sw).  Partial Gram of every block pair over one row chunk.
-template <int BW>
-__global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk,
+template <int BW, int RC>
+__global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk, int xs,
                                                           int round, double *__restrict__ part, int sw) {
-  __shared__ typename Pair<BW>::Tile P;
+  __shared__ typename Pair<BW>::template Tile<RC> P;
   constexpr int B2 = Pair<BW>::B2;
   const int pair = blockIdx.x, s = blockIdx.y;
   int bi, bj;
-  rr_pair(nblk, round, pair, bi, bj);
-  load_pair_chunk<BW>(W, L, bi, bj, s, P);
+  pair_blocks(xs, nblk, round, pair, bi, bj);
+  load_pair_chunk<BW, RC>(W, L, bi, bj, s, P);
   __syncthreads();
-  gram_of_tile<BW>(P, part + ((int64_t)pair * sw + s) * B2 * B2);
+  gram_of_tile<BW, RC>(P, part + ((int64_t)pair * sw + s) * B2 * B2);
 }
 
 // grid (pairs).  One workgroup per block pair: the solve, the rotation into
@@ -477,22 +504,22 @@ __global__ __launch_bounds__(Pair<BW>::THREADS) void jacobi_solve_kernel(int L, 
 // grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
 // of W.  The flag, the rotation and the chunk are loaded together; a pair
 // that did not rotate stores nothing.
-template <int BW>
-__global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int round,
-                                                           const double *__restrict__ qbuf,
+template <int BW, int RC>
+__global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int xs,
+                                                           int round, const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
   __shared__ typename Pair<BW>::Square Qn;
-  __shared__ typename Pair<BW>::Tile P;
+  __shared__ typename Pair<BW>::template Tile<RC> P;
   constexpr int B2 = Pair<BW>::B2, QPER = B2 * B2 / JNT;
   const int pair = blockIdx.x, chunk = blockIdx.y;
   const int rot = flag[pair];
   int bi, bj;
-  rr_pair(nblk, round, pair, bi, bj);
+  pair_blocks(xs, nblk, round, pair, bi, bj);
   const double *qsrc = qbuf + (int64_t)pair * B2 * B2;
   double qv[QPER];
 #pragma unroll
   for (int q = 0; q < QPER; ++q) qv[q] = qsrc[threadIdx.x + q * JNT];
-  load_pair_chunk<BW>(W, L, bi, bj, chunk, P);
+  load_pair_chunk<BW, RC>(W, L, bi, bj, chunk, P);
 #pragma unroll
   for (int q = 0; q < QPER; ++q) {
     const int e = threadIdx.x + q * JNT;
@@ -500,7 +527,115 @@ __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ 
   }
   if (rot == 0) return;  // uniform over the workgroup
   __syncthreads();
-  apply_tile<BW>(P, Qn, W, L, bi, bj, chunk);
+  apply_tile<BW, RC>(P, Qn, W, L, bi, bj, chunk);
+}
+
+// grid (nblk / 4, sw), XOR pairing, 32-column pairs, in place.  Round
+// `round` (mask m = round + 1) and the next (m' = round + 2) pair the four
+// blocks {i, i^m, i^m', i^m^m'} among themselves: (i, i^m) and
+// (i^m', i^m^m') now, (i, i^m') and (i^m, i^m^m') next.  One workgroup per
+// such group and ROWS_XOR-row chunk applies both rotations of the round to
+// its rows of the four blocks, writes them back and forms the two partial
+// Grams of the next round over those rows: W is read and written once per
+// round.  No LDS staging: the columns are loaded in the MFMA operand layout
+// (lane l: row l % 16 of the wave's 16-row tile, column 4 k + l / 16 of the
+// pair) and the accumulator layout of the rotation product (lane l,
+// register t: row 4 t + l / 16, column l % 16) is the operand layout of the
+// Gram product over those rows.  A pair that did not rotate goes through
+// the identity (exact in FP64).
+__global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restrict__ W, int L, int round,
+                                                               const double *__restrict__ qbuf,
+                                                               const int *__restrict__ flag,
+                                                               double *__restrict__ part, int sw) {
+  constexpr int BW = 16, B2 = 32, KS = B2 / 4;
+  __shared__ double red[JNT / 64][2][3][16][17];  // per wave: two pairs' Gram tiles (0,0), (0,1), (1,1)
+  __shared__ double tw[JNT / 64][4 * 16][17];     // per wave: its 16 rows of the four new blocks, transposed
+  const int chunk = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, q4 = lane >> 4;
+  const int m = round + 1, mn = round + 2;
+  // Group representative: zero bits at two positions that the span of m and
+  // m' covers one-to-one (the highest bit of m, and of m' reduced by m).
+  const int h1 = high_bit(m), mr = ((mn >> h1) & 1) ? (mn ^ m) : mn, h2 = high_bit(mr);
+  const int blo = min(h1, h2), bhi = max(h1, h2);
+  const int i0 = insert_zero_bit(insert_zero_bit(blockIdx.x, blo), bhi);
+  const int blk[4] = {i0, i0 ^ m, i0 ^ mn, i0 ^ m ^ mn};
+  const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
+  // The round's two pairs: (blk[0], blk[1]) and (blk[2], blk[3]), each as
+  // (lower block, higher block) = columns 0..15, 16..31 of its rotation.
+  dbl4 nb[4];
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const int x = blk[2 * pp], y = blk[2 * pp + 1];
+    const int lo = min(x, y), hi = max(x, y);
+    const int pr = remove_bit(lo, h1);
+    const int rot = flag[pr];
+    const double *Q = qbuf + (int64_t)pr * B2 * B2;
+    double wv[KS], qv[2][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + q4;
+      const int col = (k < BW) ? lo * BW + k : hi * BW + (k - BW);
+      wv[ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) qv[ct][ks] = rot ? Q[k * B2 + ct * BW + r16] : (k == ct * BW + r16 ? 1.0 : 0.0);
+    }
+    dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[ks], qv[0][ks], d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[ks], qv[1][ks], d1, 0, 0, 0);
+    }
+    // d0 is block lo, d1 block hi
+    nb[2 * pp] = (x == lo) ? d0 : d1;
+    nb[2 * pp + 1] = (x == lo) ? d1 : d0;
+  }
+  // The next round's pairs: (blk[0], blk[2]) and (blk[1], blk[3]).
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const int xa = blk[pp], xb = blk[pp + 2];
+    const dbl4 A = (xa < xb) ? nb[pp] : nb[pp + 2], B = (xa < xb) ? nb[pp + 2] : nb[pp];
+    dbl4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = {0.0, 0.0, 0.0, 0.0}, g11 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], A[t], g00, 0, 0, 0);
+      g01 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], g01, 0, 0, 0);
+      g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(B[t], B[t], g11, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      red[w][pp][0][4 * t + q4][r16] = g00[t];
+      red[w][pp][1][4 * t + q4][r16] = g01[t];
+      red[w][pp][2][4 * t + q4][r16] = g11[t];
+    }
+  }
+  // New columns back in place through LDS, so that a store covers 16
+  // consecutive rows of a column (rows beyond L were zero, not stored).
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) tw[w][b * BW + r16][4 * t + q4] = nb[b][t];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int c = 4 * e + q4, r = chunk * ROWS_XOR + 16 * w + r16;  // column c of the four blocks
+    if (r < L) W[(int64_t)(blk[c >> 4] * BW + (c & 15)) * L + r] = tw[w][c][r16];
+  }
+  // Sum over the waves (fixed order); tile (1,0) is the transpose of (0,1).
+  const int ii = threadIdx.x >> 4, jj = threadIdx.x & 15;
+  const int h1n = high_bit(mn);
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const int lo = min(blk[pp], blk[pp + 2]);
+    double *out = part + ((int64_t)remove_bit(lo, h1n) * sw + chunk) * B2 * B2;
+    double v[3];
+#pragma unroll
+    for (int tl = 0; tl < 3; ++tl)
+      v[tl] = (red[0][pp][tl][ii][jj] + red[1][pp][tl][ii][jj]) + (red[2][pp][tl][ii][jj] + red[3][pp][tl][ii][jj]);
+    out[ii * B2 + jj] = v[0];
+    out[ii * B2 + BW + jj] = v[1];
+    out[(BW + jj) * B2 + ii] = v[1];
+    out[(BW + ii) * B2 + BW + jj] = v[2];
+  }
 }
 
 // result[3] = max of conv[0..n).
@@ -535,23 +670,28 @@ __global__ __launch_bounds__(1024) void jacobi_frob_kernel(const double *__restr
 }
 
 namespace {
-template <int BW>
+template <int BW, int RC>
 void launch_round(const JacobiPlan &p, const JacobiBufs &b, int round, double tol, double noise2, hipStream_t s,
-                  KernelTimer *timer) {
-  {
+                  KernelTimer *timer, bool gram, bool apply) {
+  if (gram) {
     Timed tm(timer, KC_JAC_GRAM, s);
-    hipLaunchKernelGGL(jacobi_gram_kernel<BW>, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
-                       b.part, p.sw);
+    hipLaunchKernelGGL((jacobi_gram_kernel<BW, RC>), dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, p.xs,
+                       round, b.part, p.sw);
   }
   {
     Timed tm(timer, KC_JAC_SOLVE, s);
-    hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(Pair<BW>::THREADS), 0, s, p.L, p.nblk, round, b.part,
-                       p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
+    hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(Pair<BW>::THREADS), 0, s, p.L, p.nblk, round,
+                       b.part, p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
   }
-  {
+  if (apply) {
     Timed tm(timer, KC_JAC_APPLY, s);
-    hipLaunchKernelGGL(jacobi_apply_kernel<BW>, dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, round,
-                       b.qbuf, b.flag);
+    hipLaunchKernelGGL((jacobi_apply_kernel<BW, RC>), dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, p.xs,
+                       round, b.qbuf, b.flag);
+  } else {
+    // this round's rotations and the next round's Grams in one pass
+    Timed tm(timer, KC_JAC_APPLY, s);
+    hipLaunchKernelGGL(jacobi_xor_round_kernel, dim3(p.nblk / 4, p.sw), dim3(JNT), 0, s, b.W, p.L, round, b.qbuf,
+                       b.flag, b.part, p.sw);
   }
 }
 }  // namespace
@@ -562,10 +702,15 @@ hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double 
   const double noise2 = ns * ns;
   if (p.bw != 16 && p.bw != 32) return hipErrorInvalidValue;
   for (int round = 0; round < p.rounds; ++round) {
-    if (p.bw == 32)
-      launch_round<32>(p, b, round, tol, noise2, s, timer);
-    else
-      launch_round<16>(p, b, round, tol, noise2, s, timer);
+    if (p.bw == 32) {
+      launch_round<32, ROWS_PER_WG>(p, b, round, tol, noise2, s, timer, true, true);
+    } else if (p.xs) {
+      // the Gram of round 0 alone; later Grams come with the previous
+      // round's rotations; the last round's apply alone
+      launch_round<16, ROWS_XOR>(p, b, round, tol, noise2, s, timer, round == 0, round + 1 == p.rounds);
+    } else {
+      launch_round<16, ROWS_PER_WG>(p, b, round, tol, noise2, s, timer, true, true);
+    }
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);

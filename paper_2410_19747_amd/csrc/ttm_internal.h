@@ -131,6 +131,7 @@ struct JacobiPlan {
   int bw = 0;            // block width
   int nblk = 0;          // number of blocks (even)
   int ncp = 0;           // padded columns = nblk * bw
+  int xs = 0;            // 1: XOR pairing (round r pairs blocks i and i ^ (r + 1)), else circle method
   int rows_per_wg = 0;   // row chunk per workgroup for Gram and update
   int sw = 0;            // row chunks of W
   int rounds = 0;        // nblk - 1
@@ -156,7 +157,8 @@ struct JacobiBufs {
 
 // One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
 // off-diagonal |g_pq| / sqrt(g_pp g_qq) over every visited pair.  Needs
-// result[5] = ||W||_F^2.  Three launches per round: Gram, solve, apply.
+// result[5] = ||W||_F^2.  Per round a Gram, a solve and an apply launch;
+// with XOR pairing a round's apply and the next round's Grams are one launch.
 hipError_t launch_jacobi_sweep(const JacobiPlan &p, const JacobiBufs &b, double tol, hipStream_t s,
                                KernelTimer *timer = nullptr);
 // Reorder the columns of W by decreasing norm (swaps W/Wt).
