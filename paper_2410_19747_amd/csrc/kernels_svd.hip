@@ -550,6 +550,7 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
   constexpr int BW = 16, B2 = 32, KS = B2 / 4;
   __shared__ double red[JNT / 64][2][3][16][17];  // per wave: two pairs' Gram tiles (0,0), (0,1), (1,1)
   __shared__ double tw[JNT / 64][4 * 16][17];     // per wave: its 16 rows of the four new blocks, transposed
+  __shared__ double qs[2][B2][B2 + 1];            // the round's two rotations
   const int chunk = blockIdx.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, q4 = lane >> 4;
   const int m = round + 1, mn = round + 2;
@@ -560,30 +561,55 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
   const int i0 = insert_zero_bit(insert_zero_bit(blockIdx.x, blo), bhi);
   const int blk[4] = {i0, i0 ^ m, i0 ^ mn, i0 ^ m ^ mn};
   const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
+  // The round's two rotations into LDS once (identity for a pair that did
+  // not rotate), loaded with the columns.
+  double wv[2][KS];
+  {
+    double qg[2][B2 * B2 / JNT];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      const int lo = min(blk[2 * pp], blk[2 * pp + 1]), hi = max(blk[2 * pp], blk[2 * pp + 1]);
+      const int pr = remove_bit(lo, h1);
+      const int rot = flag[pr];
+      const double *Q = qbuf + (int64_t)pr * B2 * B2;
+#pragma unroll
+      for (int e = 0; e < B2 * B2 / JNT; ++e) {
+        const int idx = threadIdx.x + JNT * e;
+        qg[pp][e] = rot ? Q[idx] : ((idx / B2 == idx % B2) ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + q4;
+        const int col = (k < BW) ? lo * BW + k : hi * BW + (k - BW);
+        wv[pp][ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int e = 0; e < B2 * B2 / JNT; ++e) {
+        const int idx = threadIdx.x + JNT * e;
+        qs[pp][idx / B2][idx % B2] = qg[pp][e];
+      }
+  }
+  __syncthreads();
   // The round's two pairs: (blk[0], blk[1]) and (blk[2], blk[3]), each as
   // (lower block, higher block) = columns 0..15, 16..31 of its rotation.
   dbl4 nb[4];
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int x = blk[2 * pp], y = blk[2 * pp + 1];
-    const int lo = min(x, y), hi = max(x, y);
-    const int pr = remove_bit(lo, h1);
-    const int rot = flag[pr];
-    const double *Q = qbuf + (int64_t)pr * B2 * B2;
-    double wv[KS], qv[2][KS];
+    const int lo = min(x, y);
+    double qv[2][KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + q4;
-      const int col = (k < BW) ? lo * BW + k : hi * BW + (k - BW);
-      wv[ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) qv[ct][ks] = rot ? Q[k * B2 + ct * BW + r16] : (k == ct * BW + r16 ? 1.0 : 0.0);
-    }
+      for (int ct = 0; ct < 2; ++ct) qv[ct][ks] = qs[pp][4 * ks + q4][ct * BW + r16];
     dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[ks], qv[0][ks], d0, 0, 0, 0);
-      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[ks], qv[1][ks], d1, 0, 0, 0);
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[0][ks], d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[1][ks], d1, 0, 0, 0);
     }
     // d0 is block lo, d1 block hi
     nb[2 * pp] = (x == lo) ? d0 : d1;
