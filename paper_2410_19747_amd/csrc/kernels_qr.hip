@@ -370,23 +370,33 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
 }
 
 // The same factorisation for panels taller than the register panels: the
-// columns stay in memory and one wave updates one trailing column.
+// columns stay in memory (L2) and one wave handles one other column of the
+// panel per step; every row loop keeps four independent rows in flight.
+// The sums v_j^T v_c of the earlier reflectors come out of the same dot
+// products (c < j), and row r of T is built by lane r of wave 0.
 __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
                                                            double *__restrict__ Vb, double *__restrict__ T,
                                                            const double *__restrict__ cnorm, int *__restrict__ perm,
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
   __shared__ double red[PNT / 64];
-  __shared__ double Y[QB][QB + 1];
+  __shared__ double zs[QB][QB + 1];  // zs[i][b] = v_b^T v_i, b < i
+  __shared__ double taus[QB];
   __shared__ double Tl[QB][QB + 1];
-  __shared__ double tl[QB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mv = m - j0;
-  for (int j = j0; j < j0 + jb; ++j) {
+  for (int jj = 0; jj < jb; ++jj) {
+    const int j = j0 + jj;
     double *col = S + (int64_t)j * m;
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < m; i += PNT) part += col[i] * col[i];
-    const double xnorm2 = block_sum(part, red);
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = j + 1 + tid; i < m; i += 4 * PNT) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (i + u * PNT < m) ? col[i + u * PNT] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = fma(v[u], v[u], p[u]);
+    }
+    const double xnorm2 = block_sum((p[0] + p[1]) + (p[2] + p[3]), red);
     const double alpha = col[j];
     double t = 0.0, scale = 0.0, beta = alpha;
     if (xnorm2 > 0.0) {
@@ -396,58 +406,76 @@ __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ 
     }
     __syncthreads();
     if (xnorm2 > 0.0)
-      for (int i = j + 1 + tid; i < m; i += PNT) col[i] *= scale;
+      for (int i = j + 1 + tid; i < m; i += 4 * PNT) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (i + u * PNT < m) ? col[i + u * PNT] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + u * PNT < m) col[i + u * PNT] = v[u] * scale;
+      }
     if (tid == 0) {
       col[j] = beta;
-      tl[j - j0] = t;
+      taus[jj] = t;
     }
     __syncthreads();
-    if (t != 0.0) {
-      for (int c = j + 1 + wave; c < j0 + jb; c += PNT / 64) {
-        double *x = S + (int64_t)c * m;
-        double w = 0.0;
-        for (int i = j + 1 + lane; i < m; i += 64) w += col[i] * x[i];
-        w = wave_sum(w) + x[j];
+    // Wave c (c != jj): w = v_j^T x_c (v_j = 1 at row j, scaled below).
+    // Right of j: x_c <- x_c - t w v_j; left of j: x_c holds v_c, and w is
+    // the sum v_c^T v_j that T needs.
+    if (wave < jb && wave != jj) {
+      double *x = S + (int64_t)(j0 + wave) * m;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = j + 1 + lane; i < m; i += 4 * 64) {
+        double cv[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = i + u * 64 < m;
+          cv[u] = ok ? col[i + u * 64] : 0.0;
+          xv[u] = ok ? x[i + u * 64] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = fma(cv[u], xv[u], a[u]);
+      }
+      const double w = wave_sum((a[0] + a[1]) + (a[2] + a[3])) + x[j];
+      if (wave > jj) {
         const double tw = t * w;
-        if (lane == 0) x[j] -= tw;
-        for (int i = j + 1 + lane; i < m; i += 64) x[i] -= tw * col[i];
+        if (tw != 0.0) {
+          for (int i = j + 1 + lane; i < m; i += 4 * 64) {
+            double cv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool ok = i + u * 64 < m;
+              cv[u] = ok ? col[i + u * 64] : 0.0;
+              xv[u] = ok ? x[i + u * 64] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (i + u * 64 < m) x[i + u * 64] = fma(-tw, cv[u], xv[u]);
+          }
+          if (lane == 0) x[j] -= tw;
+        }
+      } else if (lane == 0) {
+        zs[jj][wave] = w;
       }
     }
     __syncthreads();
+  }
+  // T(i, i) = tau_i, T(r, i) = -tau_i sum over r <= b < i of T(r, b) zs(i, b):
+  // lane r of wave 0 builds row r.
+  if (wave == 0 && lane < QB) {
+    const int r = lane;
+    for (int b = 0; b < QB; ++b) Tl[r][b] = 0.0;
+    for (int i = 0; i < jb; ++i) {
+      double acc = 0.0;
+      for (int b = r; b < i; ++b) acc = fma(Tl[r][b], zs[i][b], acc);
+      Tl[r][i] = (r < i) ? -taus[i] * acc : (r == i ? taus[i] : 0.0);
+    }
+    for (int b = 0; b < QB; ++b) T[r * QB + b] = (r < jb && b < jb) ? Tl[r][b] : 0.0;
   }
   for (int64_t e = tid; e < (int64_t)mv * QB; e += PNT) {
     const int i = (int)(e % mv), c = (int)(e / mv);
     Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : S[(int64_t)(j0 + c) * m + j0 + i]) : 0.0;
   }
-  __syncthreads();
-  {  // Y = V^T V: 4 threads per entry, rows split four ways
-    const int ent = tid >> 2, quarter = tid & 3;
-    const int a = ent / QB, b = ent % QB;
-    double acc = 0.0;
-    if (a < jb && b < jb) {
-      const double *va = Vb + (int64_t)a * mv, *vb = Vb + (int64_t)b * mv;
-      for (int i = quarter; i < mv; i += 4) acc += va[i] * vb[i];
-    }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    if (quarter == 0 && a < jb && b < jb) Y[a][b] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < QB; ++i)
-      for (int r = 0; r < QB; ++r) Tl[r][i] = 0.0;
-    for (int i = 0; i < jb; ++i) {
-      const double ti = tl[i];
-      Tl[i][i] = ti;
-      for (int r = 0; r < i; ++r) {
-        double acc = 0.0;
-        for (int c = r; c < i; ++c) acc += Tl[r][c] * Y[c][i];
-        Tl[r][i] = -ti * acc;
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < QB * QB; e += PNT) T[e] = Tl[e / QB][e % QB];
 }
 
 // A <- (I - V op(T) V^T) A for the rows j0 .. m-1 of columns c0 .. c0+nc-1

@@ -110,7 +110,7 @@ def test_gemm_strided_operands_and_split_output():
     assert np.allclose(dC.cpu().numpy().reshape(30, 11), At.T @ dB.cpu().numpy(), rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (3, 3), (37, 11), (11, 37), (300, 64), (1024, 128)])
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 3), (37, 11), (11, 37), (300, 64), (1024, 128), (2500, 40)])
 def test_qr(m, n):
     torch, L = _env()
     _say("qr %d %d" % (m, n))
