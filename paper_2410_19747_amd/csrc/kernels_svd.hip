@@ -548,9 +548,17 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
                                                                const int *__restrict__ flag,
                                                                double *__restrict__ part, int sw) {
   constexpr int BW = 16, B2 = 32, KS = B2 / 4;
-  __shared__ double red[JNT / 64][2][3][16][17];  // per wave: two pairs' Gram tiles (0,0), (0,1), (1,1)
-  __shared__ double tw[JNT / 64][4 * 16][17];     // per wave: its 16 rows of the four new blocks, transposed
-  __shared__ double qs[2][B2][B2 + 1];            // the round's two rotations
+  // One LDS region for three phases (52 KB, so that three workgroups fit
+  // on a CU): the round's two rotations; then each wave's 16 rows of the
+  // four new blocks, transposed for the stores; then each wave's Gram tiles.
+  typedef double QsT[2][B2][B2 + 1];
+  typedef double TwT[JNT / 64][4 * 16][17];
+  typedef double RedT[JNT / 64][2][3][16][17];
+  __shared__ double lds[sizeof(RedT) / sizeof(double)];
+  static_assert(sizeof(RedT) >= sizeof(TwT) && sizeof(RedT) >= sizeof(QsT), "LDS phases");
+  QsT &qs = *reinterpret_cast<QsT *>(lds);
+  TwT &tw = *reinterpret_cast<TwT *>(lds);
+  RedT &red = *reinterpret_cast<RedT *>(lds);
   const int chunk = blockIdx.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, q4 = lane >> 4;
   const int m = round + 1, mn = round + 2;
@@ -616,6 +624,7 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
     nb[2 * pp + 1] = (x == lo) ? d1 : d0;
   }
   // The next round's pairs: (blk[0], blk[2]) and (blk[1], blk[3]).
+  dbl4 gt[2][3];
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int xa = blk[pp], xb = blk[pp + 2];
@@ -627,15 +636,13 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
       g01 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], g01, 0, 0, 0);
       g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(B[t], B[t], g11, 0, 0, 0);
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      red[w][pp][0][4 * t + q4][r16] = g00[t];
-      red[w][pp][1][4 * t + q4][r16] = g01[t];
-      red[w][pp][2][4 * t + q4][r16] = g11[t];
-    }
+    gt[pp][0] = g00;
+    gt[pp][1] = g01;
+    gt[pp][2] = g11;
   }
   // New columns back in place through LDS, so that a store covers 16
   // consecutive rows of a column (rows beyond L were zero, not stored).
+  __syncthreads();  // every wave is done with the rotations in LDS
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -646,6 +653,14 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
     const int c = 4 * e + q4, r = chunk * ROWS_XOR + 16 * w + r16;  // column c of the four blocks
     if (r < L) W[(int64_t)(blk[c >> 4] * BW + (c & 15)) * L + r] = tw[w][c][r16];
   }
+  __syncthreads();  // the transposed rows have been read out
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+    for (int tl = 0; tl < 3; ++tl)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[w][pp][tl][4 * t + q4][r16] = gt[pp][tl][t];
+  __syncthreads();
   // Sum over the waves (fixed order); tile (1,0) is the transpose of (0,1).
   const int ii = threadIdx.x >> 4, jj = threadIdx.x & 15;
   const int h1n = high_bit(mn);
