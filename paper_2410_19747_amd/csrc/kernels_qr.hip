@@ -369,93 +369,123 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
   }
 }
 
-// The same factorisation for panels taller than the register panels: the
-// columns stay in memory (L2) and one wave handles one other column of the
-// panel per step; every row loop keeps four independent rows in flight.
-// The sums v_j^T v_c of the earlier reflectors come out of the same dot
-// products (c < j), and row r of T is built by lane r of wave 0.
+// Sum over the 64 lanes of a wave of each of 16 values: after the call lane
+// l holds (bitwise the same in the four lanes of its quad) the wave total of
+// value col(l) = 8 [l & 32] + 4 [l & 16] + 2 [l & 8] + [l & 4]: at each
+// halving step a lane keeps the half of its values its partner sends away.
+__device__ __forceinline__ double wave_sum16(const double (&d)[QB], int lane) {
+  double e[8], f[4], g[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const bool hi = lane & 32;
+    e[k] = (hi ? d[k + 8] : d[k]) + __shfl_xor(hi ? d[k] : d[k + 8], 32, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool hi = lane & 16;
+    f[k] = (hi ? e[k + 4] : e[k]) + __shfl_xor(hi ? e[k] : e[k + 4], 16, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const bool hi = lane & 8;
+    g[k] = (hi ? f[k + 2] : f[k]) + __shfl_xor(hi ? f[k] : f[k + 2], 8, 64);
+  }
+  const bool hi = lane & 4;
+  double h = (hi ? g[1] : g[0]) + __shfl_xor(hi ? g[0] : g[1], 4, 64);
+  h += __shfl_xor(h, 2, 64);
+  h += __shfl_xor(h, 1, 64);
+  return h;
+}
+
+// The same factorisation for panels taller than the register panels, with
+// the panel in memory (L2).  Per column, all threads stream their rows
+// (thread t: rows t + PNT q) of all 16 columns at once, two rows at a time:
+// one pass forms d_c = x_CC^T x_c below the pivot for every column (d_CC is
+// the squared norm) and publishes row CC; with v = (1 at CC, x_CC scale
+// below), v^T x_c = x_c(CC) + scale d_c, so a second pass updates the
+// columns right of CC and writes v (scaled) and beta into column CC.  For
+// columns left of CC, v^T x_c is the sum v_CC^T v_c that T needs; row r of T
+// is built by lane r of wave 0 at the end.
 __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
                                                            double *__restrict__ Vb, double *__restrict__ T,
                                                            const double *__restrict__ cnorm, int *__restrict__ perm,
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
-  __shared__ double red[PNT / 64];
+  __shared__ double red[PNT / 64][QB];
+  __shared__ double dsum[QB], xrow[QB];
   __shared__ double zs[QB][QB + 1];  // zs[i][b] = v_b^T v_i, b < i
   __shared__ double taus[QB];
   __shared__ double Tl[QB][QB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mv = m - j0;
-  for (int jj = 0; jj < jb; ++jj) {
-    const int j = j0 + jj;
-    double *col = S + (int64_t)j * m;
-    double p[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = j + 1 + tid; i < m; i += 4 * PNT) {
-      double v[4];
+  double *P = S + (int64_t)j0 * m + j0;  // P(i, c) = P[c * m + i], i < mv, c < 16
+  const int col_l = ((lane & 32) ? 8 : 0) + ((lane & 16) ? 4 : 0) + ((lane & 8) ? 2 : 0) + ((lane & 4) ? 1 : 0);
+  for (int cc = 0; cc < jb; ++cc) {
+    const double *pc = P + (int64_t)cc * m;
+    // Pass 1: d_c for every column over rows below cc; row cc published.
+    double d[QB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = (i + u * PNT < m) ? col[i + u * PNT] : 0.0;
+    for (int c = 0; c < QB; ++c) d[c] = 0.0;
+    for (int i0 = tid; i0 < mv; i0 += 2 * PNT) {
+      double v[2][QB], b[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) p[u] = fma(v[u], v[u], p[u]);
+      for (int r = 0; r < 2; ++r) {
+        const int i = i0 + r * PNT;
+        const bool ok = i < mv;
+        b[r] = (ok && i > cc) ? pc[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < QB; ++c) v[r][c] = (ok && c < jb) ? P[(int64_t)c * m + i] : 0.0;
+      }
+      if (i0 == cc)
+#pragma unroll
+        for (int c = 0; c < QB; ++c) xrow[c] = v[0][c];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < QB; ++c) d[c] = fma(b[r], v[r][c], d[c]);
     }
-    const double xnorm2 = block_sum((p[0] + p[1]) + (p[2] + p[3]), red);
-    const double alpha = col[j];
-    double t = 0.0, scale = 0.0, beta = alpha;
+    const double wsum = wave_sum16(d, lane);
+    if ((lane & 3) == 0) red[wave][col_l] = wsum;
+    __syncthreads();
+    if (tid < QB) {
+      double t = 0.0;
+      for (int w = 0; w < PNT / 64; ++w) t += red[w][tid];
+      dsum[tid] = t;
+    }
+    __syncthreads();
+    const double xnorm2 = dsum[cc], alpha = xrow[cc];
+    double tau = 0.0, scale = 0.0, beta = alpha;
     if (xnorm2 > 0.0) {
       beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
+      tau = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    __syncthreads();
-    if (xnorm2 > 0.0)
-      for (int i = j + 1 + tid; i < m; i += 4 * PNT) {
-        double v[4];
+    double f[QB];  // tau v^T x_c for the columns right of cc
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (i + u * PNT < m) ? col[i + u * PNT] : 0.0;
+    for (int c = 0; c < QB; ++c) f[c] = (c > cc && c < jb) ? tau * fma(scale, dsum[c], xrow[c]) : 0.0;
+    if (tid < QB && tid < cc) zs[cc][tid] = fma(scale, dsum[tid], xrow[tid]);
+    if (tid == 0) taus[cc] = tau;
+    // Pass 2: columns right of cc updated, column cc becomes (beta, v).
+    for (int i0 = tid; i0 < mv; i0 += 2 * PNT) {
+      double v[2][QB], b[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (i + u * PNT < m) col[i + u * PNT] = v[u] * scale;
+      for (int r = 0; r < 2; ++r) {
+        const int i = i0 + r * PNT;
+        const bool ok = i < mv && i >= cc;
+        b[r] = ok ? pc[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < QB; ++c) v[r][c] = (ok && c > cc && c < jb) ? P[(int64_t)c * m + i] : 0.0;
       }
-    if (tid == 0) {
-      col[j] = beta;
-      taus[jj] = t;
-    }
-    __syncthreads();
-    // Wave c (c != jj): w = v_j^T x_c (v_j = 1 at row j, scaled below).
-    // Right of j: x_c <- x_c - t w v_j; left of j: x_c holds v_c, and w is
-    // the sum v_c^T v_j that T needs.
-    if (wave < jb && wave != jj) {
-      double *x = S + (int64_t)(j0 + wave) * m;
-      double a[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i = j + 1 + lane; i < m; i += 4 * 64) {
-        double cv[4], xv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = i + u * 64 < m;
-          cv[u] = ok ? col[i + u * 64] : 0.0;
-          xv[u] = ok ? x[i + u * 64] : 0.0;
+      for (int r = 0; r < 2; ++r) {
+        const int i = i0 + r * PNT;
+        if (i < mv && i >= cc) {
+          const double vi = (i == cc) ? 1.0 : b[r] * scale;
+#pragma unroll
+          for (int c = 0; c < QB; ++c)
+            if (c > cc && c < jb) P[(int64_t)c * m + i] = fma(-f[c], vi, v[r][c]);
+          P[(int64_t)cc * m + i] = (i == cc) ? beta : vi;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = fma(cv[u], xv[u], a[u]);
-      }
-      const double w = wave_sum((a[0] + a[1]) + (a[2] + a[3])) + x[j];
-      if (wave > jj) {
-        const double tw = t * w;
-        if (tw != 0.0) {
-          for (int i = j + 1 + lane; i < m; i += 4 * 64) {
-            double cv[4], xv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const bool ok = i + u * 64 < m;
-              cv[u] = ok ? col[i + u * 64] : 0.0;
-              xv[u] = ok ? x[i + u * 64] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (i + u * 64 < m) x[i + u * 64] = fma(-tw, cv[u], xv[u]);
-          }
-          if (lane == 0) x[j] -= tw;
-        }
-      } else if (lane == 0) {
-        zs[jj][wave] = w;
       }
     }
     __syncthreads();
@@ -474,7 +504,7 @@ __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ 
   }
   for (int64_t e = tid; e < (int64_t)mv * QB; e += PNT) {
     const int i = (int)(e % mv), c = (int)(e / mv);
-    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : S[(int64_t)(j0 + c) * m + j0 + i]) : 0.0;
+    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : P[(int64_t)c * m + i]) : 0.0;
   }
 }
 
