@@ -308,13 +308,12 @@ __device__ __forceinline__ void panel_columns(double (&x)[SL], PanelSmem &sm, in
 // j0 .. m-1 (mv = m - j0 <= 64 * SL), after block column pivoting when
 // cnorm is not null.  Each reflector is H = I - tau v v^T
 // with v(pivot) = 1 (LAPACK dlarfg convention); R goes on and above the
-// diagonal, v below it.  Also writes the explicit V (mv x 16, column-major,
-// unit diagonal, zero above and in columns >= jb) and T (16 x 16, row-major,
-// zero outside the leading jb x jb upper triangle) with
-// H_0 H_1 ... H_{jb-1} = I - V T V^T.
+// diagonal, v below it (the V that the updates read in place).  Also
+// writes T (16 x 16, row-major, zero outside the leading jb x jb upper
+// triangle) with H_0 H_1 ... H_{jb-1} = I - V T V^T.
 template <int SL>
 __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
-                                                           double *__restrict__ Vb, double *__restrict__ T,
+                                                           double *__restrict__ T,
                                                            const double *__restrict__ cnorm, int *__restrict__ perm,
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
@@ -364,7 +363,6 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
     if (i < mv) {
       const double val = tile[cc][i];
       if (cc < jb) S[(int64_t)(j0 + cc) * m + j0 + i] = val;
-      Vb[(int64_t)cc * mv + i] = (cc < jb && i >= cc) ? (i == cc ? 1.0 : val) : 0.0;
     }
   }
 }
@@ -407,7 +405,7 @@ __device__ __forceinline__ double wave_sum16(const double (&d)[QB], int lane) {
 // columns left of CC, v^T x_c is the sum v_CC^T v_c that T needs; row r of T
 // is built by lane r of wave 0 at the end.
 __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
-                                                           double *__restrict__ Vb, double *__restrict__ T,
+                                                           double *__restrict__ T,
                                                            const double *__restrict__ cnorm, int *__restrict__ perm,
                                                            double *__restrict__ pscratch) {
   if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
@@ -502,24 +500,27 @@ __global__ __launch_bounds__(PNT) void qr_panel_mem_kernel(double *__restrict__ 
     }
     for (int b = 0; b < QB; ++b) T[r * QB + b] = (r < jb && b < jb) ? Tl[r][b] : 0.0;
   }
-  for (int64_t e = tid; e < (int64_t)mv * QB; e += PNT) {
-    const int i = (int)(e % mv), c = (int)(e / mv);
-    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : P[(int64_t)c * m + i]) : 0.0;
-  }
+}
+
+// Entry (i, c) of the panel's V (unit lower trapezoidal, zero beyond jb
+// columns) read from the factored panel Vs (= S + j0 m + j0, ld m).
+__device__ __forceinline__ double vload(const double *Vs, int m, int jb, int c, int i) {
+  return (c < jb && i >= c) ? (i == c ? 1.0 : Vs[(int64_t)c * m + i]) : 0.0;
 }
 
 // A <- (I - V op(T) V^T) A for the rows j0 .. m-1 of columns c0 .. c0+nc-1
 // of the column-major S (ld m), with op(T) = T^T when `trans` (applying
 // Q^T: the trailing update of the factorisation) and T otherwise (forming
-// Q).  V: mv x 16 column-major, T: 16 x 16 row-major, both zero-padded.
+// Q).  V: the panel's reflectors read in place from the factored panel Vs
+// (vload), T: 16 x 16 row-major, zero-padded.
 // One workgroup per 16 columns:
 //   W1 = V^T A (MFMA, the four waves split the rows), W2 = op(T) W1,
 //   A^T -= W2^T V^T (MFMA; the lanes of a row group write 16 consecutive
 //   rows of one column).
 // When cnorm is not null, cnorm[column] receives the norm of the updated
 // column over rows j0 + next .. m-1 (the next panel's candidates).
-__global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, int m, int j0, int c0, int nc,
-                                                        const double *__restrict__ Vb,
+__global__ __launch_bounds__(UNT) void qr_update_kernel(double *S, int m, int j0, int c0, int nc,
+                                                        const double *Vs, int jb,
                                                         const double *__restrict__ T, int trans,
                                                         double *__restrict__ cnorm, int next) {
   __shared__ double Wp[4][QB][QB + 1];
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
     for (int u = 0; u < 4; ++u) {
       const int kk = k0 + 4 * u + q4;
       const bool ok = kk < ke;
-      va[u] = ok ? Vb[(int64_t)r16 * mv + kk] : 0.0;
+      va[u] = ok ? vload(Vs, m, jb, r16, kk) : 0.0;
       ab[u] = (ok && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
     }
 #pragma unroll
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(UNT) void qr_update_kernel(double *__restrict__ S, 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int col = 4 * u + q4;
-        vv[h][u] = ok ? Vb[(int64_t)col * mv + r] : 0.0;
+        vv[h][u] = ok ? vload(Vs, m, jb, col, r) : 0.0;
         aa[h][u] = (ok && col < ncol) ? A[(int64_t)col * m + r] : 0.0;
       }
     }
@@ -617,9 +618,8 @@ constexpr int URC = 128;
 
 static inline int update_chunks(int mv) { return (mv + URC - 1) / URC; }
 
-__global__ __launch_bounds__(UNT) void qr_update_part_kernel(const double *__restrict__ S, int m, int j0, int c0,
-                                                             int nc, const double *__restrict__ Vb,
-                                                             double *__restrict__ part) {
+__global__ __launch_bounds__(UNT) void qr_update_part_kernel(const double *S, int m, int j0, int c0, int nc,
+                                                             const double *Vs, int jb, double *__restrict__ part) {
   __shared__ double Wp[4][QB][QB + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(UNT) void qr_update_part_kernel(const double *__res
   for (int u = 0; u < KS; ++u) {
     const int kk = kb + 4 * u + q4;
     const bool ok = kk < mv;
-    va[u] = ok ? Vb[(int64_t)r16 * mv + kk] : 0.0;
+    va[u] = ok ? vload(Vs, m, jb, r16, kk) : 0.0;
     ab[u] = (ok && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
   }
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -648,8 +648,8 @@ __global__ __launch_bounds__(UNT) void qr_update_part_kernel(const double *__res
       (Wp[0][ti][tj] + Wp[1][ti][tj]) + (Wp[2][ti][tj] + Wp[3][ti][tj]);
 }
 
-__global__ __launch_bounds__(UNT) void qr_update_apply_kernel(double *__restrict__ S, int m, int j0, int c0, int nc,
-                                                              const double *__restrict__ Vb,
+__global__ __launch_bounds__(UNT) void qr_update_apply_kernel(double *S, int m, int j0, int c0, int nc,
+                                                              const double *Vs, int jb,
                                                               const double *__restrict__ T, int trans,
                                                               const double *__restrict__ part) {
   __shared__ double W1[QB][QB + 1];
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(UNT) void qr_update_apply_kernel(double *__restrict
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int col = 4 * u + q4;
-      vv[h][u] = ok ? Vb[(int64_t)col * mv + r] : 0.0;
+      vv[h][u] = ok ? vload(Vs, m, jb, col, r) : 0.0;
       aa[h][u] = (ok && col < ncol) ? A[(int64_t)col * m + r] : 0.0;
     }
   }
@@ -732,18 +732,6 @@ __global__ void qr_r_and_identity_kernel(const double *__restrict__ S, int m, in
   }
 }
 
-// Explicit V of the panel starting at column j0 (rows j0..m-1, 16 columns,
-// zero-padded) rebuilt from the factored S.
-__global__ void qr_extract_v_kernel(const double *__restrict__ S, int m, int j0, int jb,
-                                    double *__restrict__ Vb) {
-  const int mv = m - j0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)mv * QB;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % mv), c = (int)(e / mv);
-    Vb[e] = (c < jb && i >= c) ? (i == c ? 1.0 : S[(int64_t)(j0 + c) * m + j0 + i]) : 0.0;
-  }
-}
-
 namespace {
 struct Pivot {
   const double *cnorm = nullptr;  // null: no pivoting
@@ -751,11 +739,11 @@ struct Pivot {
   double *scratch = nullptr;
 };
 
-hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *Vb, double *T, const Pivot &pv,
+hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *T, const Pivot &pv,
                         hipStream_t s) {
   const int sl = (m - j0 + 63) / 64;
   const dim3 g(1), b(PNT);
-#define TTM_PANEL_ARGS S, m, n, j0, jb, Vb, T, pv.cnorm, pv.perm, pv.scratch
+#define TTM_PANEL_ARGS S, m, n, j0, jb, T, pv.cnorm, pv.perm, pv.scratch
   if (sl <= 1) hipLaunchKernelGGL(qr_panel_reg_kernel<1>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= 2) hipLaunchKernelGGL(qr_panel_reg_kernel<2>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= 4) hipLaunchKernelGGL(qr_panel_reg_kernel<4>, g, b, 0, s, TTM_PANEL_ARGS);
@@ -766,16 +754,19 @@ hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *Vb, dou
   return hipGetLastError();
 }
 
-hipError_t launch_update(double *S, int m, int j0, int c0, int nc, const double *Vb, const double *T,
+// A <- (I - V op(T) V^T) A with V the reflectors of the panel at j0 (jb
+// columns) of the factored Sf (ld m); A may be Sf itself (trailing update).
+hipError_t launch_update(double *A, int m, int j0, int c0, int nc, const double *Sf, int jb, const double *T,
                          int trans, double *cnorm, int next, double *part, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
+  const double *Vs = Sf + (int64_t)j0 * m + j0;
   const int ncb = (nc + QB - 1) / QB;
   if (cnorm == nullptr && part != nullptr) {
     const dim3 grid(ncb, update_chunks(m - j0));
-    hipLaunchKernelGGL(qr_update_part_kernel, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, part);
-    hipLaunchKernelGGL(qr_update_apply_kernel, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T, trans, part);
+    hipLaunchKernelGGL(qr_update_part_kernel, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, part);
+    hipLaunchKernelGGL(qr_update_apply_kernel, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, T, trans, part);
   } else {
-    hipLaunchKernelGGL(qr_update_kernel, dim3(ncb), dim3(UNT), 0, s, S, m, j0, c0, nc, Vb, T, trans, cnorm,
+    hipLaunchKernelGGL(qr_update_kernel, dim3(ncb), dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, T, trans, cnorm,
                        next);
   }
   return hipGetLastError();
@@ -788,7 +779,7 @@ static size_t update_part_doubles(int m, int nc) {
 }
 
 size_t qr_inplace_scratch_doubles(int m, int n) {
-  return (size_t)m * QB + QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + 5 * 32;
+  return QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + 4 * 32;
 }
 
 hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s) {
@@ -797,7 +788,6 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   const int k = m < n ? m : n;
   double *p = scratch;
   auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
-  double *Vb = adv((size_t)m * QB);
   double *T1 = adv(QB * QB);
   double *part = adv(update_part_doubles(m, n));
   Pivot pv;
@@ -812,29 +802,24 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   for (int j0 = 0; j0 < k; j0 += QB) {
     const int jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall ? Tall + (size_t)(j0 / QB) * QB * QB : T1;
-    hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, pv, s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, T, pv, s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, const_cast<double *>(pv.cnorm), jb, part, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), S, jb, T, 1, const_cast<double *>(pv.cnorm), jb, part, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-size_t qr_apply_q_scratch_doubles(int m, int nc) {
-  return (((size_t)m * QB + 31) & ~(size_t)31) + update_part_doubles(m, nc) + 32;
-}
+size_t qr_apply_q_scratch_doubles(int m, int nc) { return update_part_doubles(m, nc) + 32; }
 
 hipError_t launch_apply_q(const double *S, int m, int k, const double *Tall, double *X, int nc, double *scratch,
                           hipStream_t s) {
   if (m <= 0 || k <= 0 || nc <= 0) return hipSuccess;
-  double *Vb = scratch;
-  double *part = scratch + (((size_t)m * QB + 31) & ~(size_t)31);
+  double *part = scratch;
   // Q X = H_0 ... H_{k-1} X: block reflectors from the last panel to the first.
   for (int pi = (k - 1) / QB; pi >= 0; --pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
-    hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
-                       j0, jb, Vb);
-    hipError_t e = launch_update(X, m, j0, 0, nc, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
+    hipError_t e = launch_update(X, m, j0, 0, nc, S, jb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -845,11 +830,10 @@ size_t qr_scratch_doubles(int m, int n) {
   const int np = (k + QB - 1) / QB;
   size_t t = 0;
   t += (size_t)m * n;          // S
-  t += (size_t)m * QB;         // Vb
   t += (size_t)np * QB * QB;   // T per panel
   t += (size_t)m * k;          // Qs
   t += update_part_doubles(m, n);  // split-update partials
-  return t + 5 * 32;
+  return t + 4 * 32;
 }
 
 hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
@@ -860,7 +844,6 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   double *p = scratch;
   auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
   double *S = adv((size_t)m * n);
-  double *Vb = adv((size_t)m * QB);
   double *Tall = adv((size_t)np * QB * QB);
   double *Qs = adv((size_t)m * k);
   double *part = adv(update_part_doubles(m, n));
@@ -869,9 +852,9 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   for (int pi = 0; pi < np; ++pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall + (size_t)pi * QB * QB;
-    hipError_t e = launch_panel(S, m, n, j0, jb, Vb, T, Pivot(), s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, T, Pivot(), s);
     if (e != hipSuccess) return e;
-    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), Vb, T, 1, nullptr, 0, part, s);
+    e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), S, jb, T, 1, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(qr_r_and_identity_kernel, dim3(grid_for((int64_t)k * n + (int64_t)m * k, 256)), dim3(256),
@@ -879,9 +862,7 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   // Q = H_0 ... H_{np-1} applied to [I_k; 0], panels in reverse order.
   for (int pi = np - 1; pi >= 0; --pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
-    hipLaunchKernelGGL(qr_extract_v_kernel, dim3(grid_for((int64_t)(m - j0) * QB, 256)), dim3(256), 0, s, S, m,
-                       j0, jb, Vb);
-    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, Vb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
+    hipError_t e = launch_update(Qs, m, j0, j0, k - j0, S, jb, Tall + (size_t)pi * QB * QB, 0, nullptr, 0, part, s);
     if (e != hipSuccess) return e;
   }
   // q (m x k, row-major) from Qs (column-major)
