@@ -17,6 +17,11 @@ bounded sample of the same workload.
 (a 1024^3 field, d = 8, chi in --sweep-chis): one JSON line per chi with the
 product rate, the algorithmic flop rate against the FP64 MFMA peak, and the
 relative error of sampled entries against the exact product A(x) B(x).
+
+``--batched`` measures the nine advective products u_j * d_j u_i of a
+synthetic velocity field (1024^3, 10 sites, d = 8) at uneven bonds, one
+after another and in single ttm_multiply_batch calls (FP64 and FP32
+contractions): one JSON line per run.
 """
 from __future__ import annotations
 
@@ -82,6 +87,14 @@ def main():
     ap.add_argument("--sweep-grid", type=int, default=1024)
     ap.add_argument("--sweep-precisions", default="f64",
                     help="contraction arithmetic per sweep point, e.g. f64,f32,bf16x3,bf16 (f64 first)")
+    ap.add_argument("--batched", action="store_true",
+                    help="the nine advective products u_j * d_j u_i at uneven bonds, serial and batched")
+    ap.add_argument("--batch-grid", type=int, default=1024)
+    ap.add_argument("--batch-chis", default="", help="nine bonds (comma list); default: the fixed uneven set")
+    ap.add_argument("--batch-streams", default="4",
+                    help="products in flight (streams) for the batched runs, comma list")
+    ap.add_argument("--batch-precisions", default="f64,f32",
+                    help="contraction arithmetic of the batched runs (f64 first)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -101,6 +114,8 @@ def main():
     dev = torch.device("cuda", 0)
     if args.sweep:
         return sweep(args, dev)
+    if args.batched:
+        return batched(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -346,6 +361,90 @@ def sweep(args, dev):
              % (chi, 1e3 * dt, line["algorithmic_tflops"], st["sweeps"], rel))
         del A, C, out, ws
         torch.cuda.empty_cache()
+
+
+def batched(args, dev):
+    """Nine products u_j * d_j u_i (i, j in x, y, z) of a synthetic velocity
+    field, operands compressed at the uneven bonds ADVECTIVE_CHIS, chi_out =
+    chi_mid = the product's bond: one after another (FP64), then in one
+    ttm_multiply_batch call per worker count and contraction precision.
+    Prints one JSON line per run."""
+    import torch
+
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    chis = [int(c) for c in args.batch_chis.split(",") if c] or list(I.ADVECTIVE_CHIS)
+    assert len(chis) == 9
+    _log("generating the advective operands on a %d^3 grid, chis %s" % (args.batch_grid, chis))
+    t0 = time.time()
+    prods = I.advective_qtts_device(args.batch_grid, 201, chis=chis, device=dev)
+    torch.cuda.empty_cache()
+    _log("  done in %.1f s" % (time.time() - t0))
+    n_sites = len(prods[0][0])
+    pairs = [(T.pack(A, dev), T.pack(B, dev)) for A, B, _ in prods]
+    g = torch.Generator(device="cpu")
+    g.manual_seed(7)
+    idx = torch.randint(0, 8, (4096, n_sites), generator=g).to(dev)
+    exact = [_tt_entries(A.cores(), idx) * _tt_entries(B.cores(), idx) for A, B in pairs]
+    workload = ("9 advective products u_j*d_j u_i, 3D turbulence QTTs, %d^3 grid, N=%d sites, d=8, chi %s"
+                % (args.batch_grid, n_sites, chis))
+    wss = [T.Workspace(dev) for _ in pairs]
+
+    def sampled(results):
+        out = []
+        for (C, _), ex in zip(results, exact):
+            got = _tt_entries(C.cores(), idx)
+            out.append(float(torch.linalg.norm(got - ex) / torch.linalg.norm(ex)))
+        return out
+
+    # Serial FP64: one ttm_multiply after another on one stream.
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    serial = []
+    per = []
+    for (A, B), chi, w in zip(pairs, chis, wss):
+        tp = time.perf_counter()
+        serial.append(T.multiply(A, B, chi, args.eps, workspace=w))
+        per.append(1e3 * (time.perf_counter() - tp))
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t
+    ref = [_tt_entries(C.cores(), idx) for C, _ in serial]
+    line = {"batched": False, "workload": workload, "precision": "f64", "products": len(pairs),
+            "ms_per_batch": 1e3 * t_serial, "products_per_s": len(pairs) / t_serial,
+            "ms_per_product": per, "sampled_rel_err_vs_exact": sampled(serial),
+            "model_flops": sum(st["model_flops"] for _, st in serial)}
+    print(json.dumps(line), flush=True)
+    _log("  serial f64: %.1f ms for %d products (%s)" % (1e3 * t_serial, len(pairs),
+                                                           ", ".join("%.0f" % x for x in per)))
+    for prec in [q for q in args.batch_precisions.split(",") if q]:
+        for nstreams in [int(x) for x in args.batch_streams.split(",") if x]:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = T.multiply_batch([(A, B) for A, B in pairs], chis, args.eps, streams=nstreams,
+                                   workspaces=wss, contract_precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            same = None
+            diffs = []
+            for (C, _), r in zip(res, ref):
+                got = _tt_entries(C.cores(), idx)
+                diffs.append(float(torch.linalg.norm(got - r) / torch.linalg.norm(r)))
+            if prec == "f64":
+                same = all(
+                    torch.equal(C.data[:sum(C.bonds[i] * C.phys[i] * C.bonds[i + 1] for i in range(C.n_sites))],
+                                Cs.data[:sum(Cs.bonds[i] * Cs.phys[i] * Cs.bonds[i + 1] for i in range(Cs.n_sites))])
+                    for (C, _), (Cs, _) in zip(res, serial))
+            line = {"batched": True, "workload": workload, "precision": prec, "streams": nstreams,
+                    "products": len(pairs), "ms_per_batch": 1e3 * dt, "products_per_s": len(pairs) / dt,
+                    "speedup_vs_serial_f64": t_serial / dt, "identical_to_serial": same,
+                    "sampled_rel_diff_vs_serial_f64": diffs, "sampled_rel_err_vs_exact": sampled(res),
+                    "jacobi_sweeps": [st["sweeps"] for _, st in res]}
+            print(json.dumps(line), flush=True)
+            _log("  batched %s, %d streams: %.1f ms (x%.2f vs serial f64), max sampled diff vs f64 %.2e"
+                 % (prec, nstreams, 1e3 * dt, t_serial / dt, max(diffs)))
+            del res
+    return None
 
 
 if __name__ == "__main__":

@@ -166,6 +166,36 @@ int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double to
                     ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
                     const ttm_options *opt, ttm_stats *stats);
 
+/* n independent products C[i] = A[i] * B[i] by TTM (Sec. II.B) in one call,
+ * for workloads of many products at uneven bonds, such as the nine terms
+ * u_j d_j u_i of the advection term that motivates the method (Sec. I).
+ * Product i takes chi_out[i], tol[i], options opt[i] (opt NULL: defaults for
+ * all), workspace ws[i] of ws_bytes[i] >= ttm_query's size and output C[i];
+ * stats (NULL or n entries) receives each product's statistics.  Arrays are
+ * host arrays of n entries.
+ * Scheduling: the library creates min(n, n_streams) streams of its own
+ * (1 <= n_streams <= 64), each of which first waits for the work already
+ * enqueued on `stream` (the caller's hipStream_t, which produced the
+ * inputs), and drives each from a host thread that takes products from a
+ * queue ordered by decreasing estimated cost (swap count times the cube of
+ * the swap-matrix side) and runs them as ttm_multiply_ex would.  A product
+ * is a chain of small dependent launches, so products overlap only on
+ * distinct hardware queues; the streams are created with a CU mask of every
+ * CU, which gives each a hardware queue of its own rather than one of the
+ * runtime's shared default queues.  Each product's result is the one
+ * ttm_multiply_ex gives for the same arguments.
+ * Checks: every product is validated (as ttm_query, plus the workspace and
+ * output sizes and a finite tol >= 0) before any starts, and workspaces and
+ * outputs must not overlap one another (TTM_EINVAL).  The call returns when
+ * every product has finished and its streams are destroyed: 0 if all
+ * succeeded, else the code of the lowest-index failure; status (NULL or n
+ * entries) receives every product's code, and a failed product does not
+ * stop the others.  The HIP device current in the calling thread is used. */
+int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, const int32_t *chi_out,
+                       const double *tol, ttm_tt_out *C, void *const *ws, const size_t *ws_bytes,
+                       const ttm_options *opt, ttm_stats *stats, int32_t n_streams, void *stream,
+                       int32_t *status);
+
 /* Sizes for conventional_multiply (host only). */
 int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
                        size_t *ws_bytes, int64_t *out_capacity);

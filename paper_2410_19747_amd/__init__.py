@@ -7,6 +7,7 @@ The functions mirror the C entry points of ``include/ttm.h``:
     multiply(A, B, chi_out, tol, **options)       -> ttm_multiply_ex
     conventional(A, B, chi_out, tol, **options)   -> conventional_multiply_ex
     query(A, B, chi_out, **options)               -> ttm_query
+    multiply_batch(pairs, chi_out, tol, ...)      -> ttm_multiply_batch
 
 A tensor train is a list of float64 CUDA tensors, core i of shape
 [r_i, d_i, r_{i+1}] (r_0 = r_N = 1), or a ``PackedTT``.
@@ -23,7 +24,7 @@ from ._abi import (  # noqa: F401
 )
 
 __all__ = [
-    "TTMError", "PackedTT", "pack", "multiply", "conventional", "query", "conventional_query",
+    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "conventional", "query", "conventional_query",
     "Workspace", "lib",
 ]
 
@@ -213,6 +214,12 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
     if rc != TTM_OK:
         raise TTMError(rc, mfn.__name__)
     res = PackedTT(out, [A.phys[i] for i in range(n)], list(bonds), list(offs))
+    stats = _stats_dict(st, o)
+    del keep
+    return res, stats
+
+
+def _stats_dict(st, o):
     from ._abi import KERNEL_CLASSES
     stats = {f: getattr(st, f) for f, _ in TtmStats._fields_ if f not in ("kernel_ms", "kernel_launches")}
     stats["kernel_ms"] = dict(zip(KERNEL_CLASSES, list(st.kernel_ms)))
@@ -221,8 +228,7 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
     if o.trace_cap:
         stats["ranks"] = [o.rank_trace[i] for i in range(nt)]
         stats["discards"] = [o.discard_trace[i] for i in range(nt)]
-    del keep
-    return res, stats
+    return stats
 
 
 def multiply(A, B, chi_out, tol, **opts):
@@ -236,3 +242,76 @@ def multiply(A, B, chi_out, tol, **opts):
 def conventional(A, B, chi_out, tol, **opts):
     """C ~ A * B by the variational baseline.  Returns (PackedTT, stats dict)."""
     return _run("conv", A, B, chi_out, tol, **opts)
+
+
+def multiply_batch(pairs, chi_out, tol, streams=4, workspaces=None, options=None, raise_errors=True,
+                   stream=None, **opts):
+    """Products C_k = A_k * B_k for every (A_k, B_k) in ``pairs`` by one call of
+    ttm_multiply_batch.  ``chi_out`` and ``tol`` are a value for all or a list.
+    ``streams`` is the number of products in flight, each on a stream the
+    library creates; they start after the work on ``stream`` (default: the
+    current torch stream).
+    ``workspaces`` (a list of Workspace, one per product) is created when not
+    given; ``options`` (a list of dicts, one per product) overrides the shared
+    keyword options per product.  Returns a list of (PackedTT, stats dict).
+    A failed product raises TTMError with the lowest-index failure's code,
+    naming every failed product; with ``raise_errors=False`` the call returns
+    (results, codes) instead, a failed product's result being None."""
+    import torch
+
+    n = len(pairs)
+    if n == 0:
+        return [] if raise_errors else ([], [])
+    packed = [(pack(a), pack(b)) for a, b in pairs]
+    chis = [int(chi_out)] * n if isinstance(chi_out, int) else [int(c) for c in chi_out]
+    tols = [float(tol)] * n if isinstance(tol, (int, float)) else [float(t) for t in tol]
+    assert len(chis) == n and len(tols) == n
+    dev = packed[0][0].data.device
+    trace_cap = opts.pop("trace_cap", None)
+    L = lib()
+    opt_arr = (TtmOptions * n)()
+    keep, outs, wbufs, bonds, offs = [], [], [], [], []
+    if workspaces is None:
+        workspaces = [Workspace(dev) for _ in range(n)]
+    assert len(workspaces) == n and int(streams) >= 1
+    if options is None:
+        options = [{}] * n
+    assert len(options) == n
+    couts = (TtmTTOut * n)()
+    for k, (A, B) in enumerate(packed):
+        tc = trace_cap if trace_cap is not None else 4 * A.n_sites * A.n_sites + 16
+        o, kp = _options(trace_cap=tc, **dict(opts, **options[k]))
+        keep.append(kp)
+        opt_arr[k] = o
+        ws_bytes, cap = _query(L.ttm_query, A, B, chis[k], o)
+        wbufs.append(workspaces[k].get(ws_bytes))
+        outs.append(torch.empty(max(cap, 1), dtype=torch.float64, device=dev))
+        nb = A.n_sites
+        bonds.append((ctypes.c_int32 * (nb + 1))())
+        offs.append((ctypes.c_int64 * nb)())
+        couts[k] = TtmTTOut(ctypes.cast(bonds[k], ctypes.POINTER(ctypes.c_int32)),
+                            ctypes.cast(offs[k], ctypes.POINTER(ctypes.c_int64)),
+                            ctypes.c_void_p(outs[k].data_ptr()), outs[k].numel())
+    a_arr = (TtmTT * n)(*[A.view for A, _ in packed])
+    b_arr = (TtmTT * n)(*[B.view for _, B in packed])
+    chi_arr = (ctypes.c_int32 * n)(*chis)
+    tol_arr = (ctypes.c_double * n)(*tols)
+    ws_arr = (ctypes.c_void_p * n)(*[w.data_ptr() for w in wbufs])
+    wsb_arr = (ctypes.c_size_t * n)(*[w.numel() for w in wbufs])
+    stats_arr = (TtmStats * n)()
+    status = (ctypes.c_int32 * n)()
+    rc = L.ttm_multiply_batch(n, a_arr, b_arr, chi_arr, tol_arr, couts, ws_arr, wsb_arr, opt_arr, stats_arr,
+                              int(streams), _stream_handle(stream), status)
+    codes = [int(status[k]) for k in range(n)]
+    if rc != TTM_OK and (raise_errors or all(c == TTM_OK for c in codes)):
+        bad = [k for k in range(n) if codes[k] != TTM_OK]
+        raise TTMError(rc, "ttm_multiply_batch (products %s)" % bad)
+    res = []
+    for k, (A, _) in enumerate(packed):
+        if codes[k] != TTM_OK:
+            res.append(None)
+            continue
+        c = PackedTT(outs[k], list(A.phys), list(bonds[k]), list(offs[k]))
+        res.append((c, _stats_dict(stats_arr[k], opt_arr[k])))
+    del keep
+    return res if raise_errors else (res, codes)

@@ -96,6 +96,11 @@ PROTOTYPES = {
                                        ctypes.c_double, ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(TtmOptions),
                                        ctypes.POINTER(TtmStats)]),
+    "ttm_multiply_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT),
+                                          I32P, F64P, ctypes.POINTER(TtmTTOut),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats),
+                                          ctypes.c_int32, ctypes.c_void_p, I32P]),
     "conventional_query": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
                                           ctypes.POINTER(TtmOptions), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_int64)]),

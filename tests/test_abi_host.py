@@ -170,3 +170,53 @@ def test_conventional_query_sizes(L):
     bad = _TT([8] * 8, b8, data_ptr=0)
     assert L.conventional_query(ctypes.byref(bad.view), ctypes.byref(A.view), 64, None, ctypes.byref(ws),
                                 ctypes.byref(cap)) == _abi.TTM_EINVAL
+
+
+def test_batch_rejects_before_gpu_work(L):
+    """ttm_multiply_batch checks every product, and that no two products share
+    workspace or output memory, before any HIP call."""
+    A = _TT([2] * 4, [1, 2, 4, 2, 1])
+    n = 3
+    rc, need, cap = _query(L, A, A, 4)
+    assert rc == 0
+    bonds = [(ctypes.c_int32 * 5)() for _ in range(n)]
+    offs = [(ctypes.c_int64 * 4)() for _ in range(n)]
+
+    def outs(caps, bases=(0x10000000, 0x20000000, 0x30000000)):
+        arr = (_abi.TtmTTOut * n)()
+        for k in range(n):
+            arr[k] = _abi.TtmTTOut(ctypes.cast(bonds[k], _abi.I32P), ctypes.cast(offs[k], _abi.I64P),
+                                   ctypes.c_void_p(bases[k]), caps[k])
+        return arr
+
+    As = (_abi.TtmTT * n)(*([A.view] * n))
+    chis = (ctypes.c_int32 * n)(4, 4, 4)
+    tols = (ctypes.c_double * n)(1e-12, 1e-12, 1e-12)
+    status = (ctypes.c_int32 * n)()
+
+    def call(ws_ptrs, ws_sizes, out_arr, tol_arr=tols, chi_arr=chis, count=n, n_streams=2):
+        wp = (ctypes.c_void_p * n)(*ws_ptrs)
+        wb = (ctypes.c_size_t * n)(*ws_sizes)
+        return L.ttm_multiply_batch(count, As, As, chi_arr, tol_arr, out_arr, wp, wb, None, None, n_streams,
+                                    None, status)
+
+    base = [0x40000000, 0x50000000, 0x60000000]
+    assert call(base, [need] * n, outs([cap] * n), count=0) == _abi.TTM_OK
+    assert call(base, [need] * n, outs([cap] * n), count=-1) == _abi.TTM_EINVAL
+    assert call(base, [need] * n, outs([cap] * n), n_streams=0) == _abi.TTM_EINVAL
+    assert call(base, [need] * n, outs([cap] * n), n_streams=65) == _abi.TTM_EINVAL
+    assert L.ttm_multiply_batch(n, As, As, chis, tols, None, None, None, None, None, 2, None,
+                                status) == _abi.TTM_EINVAL
+    # one product's workspace too small, one product's output too small
+    assert call(base, [need, need - 8, need], outs([cap] * n)) == _abi.TTM_EWORKSPACE
+    assert call(base, [need] * n, outs([cap, cap, cap - 1])) == _abi.TTM_ECAPACITY
+    # one bad tolerance, one bad chi_out
+    bad_tol = (ctypes.c_double * n)(1e-12, float("nan"), 1e-12)
+    assert call(base, [need] * n, outs([cap] * n), tol_arr=bad_tol) == _abi.TTM_EINVAL
+    bad_chi = (ctypes.c_int32 * n)(4, 4, 0)
+    assert call(base, [need] * n, outs([cap] * n), chi_arr=bad_chi) == _abi.TTM_EINVAL
+    # overlapping workspaces, overlapping outputs, a workspace over another product's output
+    assert call([base[0], base[0] + 8, base[2]], [need] * n, outs([cap] * n)) == _abi.TTM_EINVAL
+    assert call(base, [need] * n, outs([cap] * n, (0x10000000, 0x10000000 + 8, 0x30000000))) == _abi.TTM_EINVAL
+    assert call([0x10000000 + 8, base[1], base[2]], [need] * n,
+                outs([cap] * n, (0x70000000, 0x10000000, 0x30000000))) == _abi.TTM_EINVAL

@@ -1,0 +1,112 @@
+"""GPU tests of ttm_multiply_batch: many products in one call, through the C ABI.
+
+Each product of a batch must be the product ttm_multiply_ex gives for the
+same arguments (bit for bit: the kernels of one product do not depend on
+what runs beside them), and so match the oracle at the FP64 bound.  The
+workload is the one that motivates the method (Sec. I): the nine products
+u_j * d_j u_i of a synthetic turbulence velocity field at uneven bonds.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import ttm_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _host(packed):
+    return [c.detach().cpu().numpy() for c in packed.cores()]
+
+
+def _random_pairs():
+    """Nine pairs of 8-site trains with d = 2, 3 or 4 and uneven bonds."""
+    pairs, chis = [], []
+    for k in range(9):
+        d = (2, 3, 4)[k % 3]
+        chi = (2, 16, 4, 8, 16, 2, 8, 4, 16)[k]
+        pairs.append((I.random_tt(8, d, chi, 500 + 2 * k), I.random_tt(8, d, chi, 501 + 2 * k)))
+        chis.append(chi)
+    return pairs, chis
+
+
+def test_gpu_batch_equals_single_products():
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: batch of 9 random products, uneven bonds, vs single calls")
+    pairs, chis = _random_pairs()
+    single = [T.multiply(A, B, c, 1e-14) for (A, B), c in zip(pairs, chis)]
+    for streams in (4, 1, 3, 9):
+        _say("  streams=%d" % streams)
+        batch = T.multiply_batch(pairs, chis, 1e-14, streams=streams)
+        for k, ((Cb, sb), (Cs, ss)) in enumerate(zip(batch, single)):
+            assert Cb.bonds == Cs.bonds, k
+            assert sb["ranks"] == ss["ranks"], k
+            for x, y in zip(_host(Cb), _host(Cs)):
+                assert np.array_equal(x, y), (k, float(np.abs(x - y).max()))
+    # and one of them against the oracle
+    (A, B), c = pairs[1], chis[1]
+    o = O.ttm(A, B, c, 1e-14)
+    assert single[1][1]["ranks"] == o.ranks
+    assert O.rel_frob(_host(single[1][0]), o.cores) <= TOL
+
+
+def test_gpu_batch_advective_products_vs_oracle():
+    """The nine advective products of a 64^3 field (6 sites, d = 8) at
+    uneven bonds, FP64, against the oracle; then with FP32 contractions
+    against the same oracle products at the mixed-precision bound."""
+    import paper_2410_19747_amd as T
+    torch = _torch()
+    chis = (32, 8, 16, 24, 8, 32, 16, 24, 8)
+    _say("case: advective products 64^3, chis %s" % (chis,))
+    prods = I.advective_qtts_device(64, 11, chis=chis, device=torch.device("cuda", 0))
+    torch.cuda.empty_cache()
+    pairs = [(A, B) for A, B, _ in prods]
+    res = T.multiply_batch(pairs, list(chis), 1e-14)
+    ref = []
+    for k, ((A, B, chi), (C, st)) in enumerate(zip(prods, res)):
+        o = O.ttm(A, B, chi, 1e-14)
+        ref.append(o)
+        err = O.rel_frob(_host(C), o.cores)
+        _say("  product %d chi=%d rel err %.3e" % (k, chi, err))
+        assert st["ranks"] == o.ranks, k
+        assert err <= TOL, k
+    res32 = T.multiply_batch(pairs, list(chis), 1e-14, contract_precision="f32")
+    for k, ((C, st), o) in enumerate(zip(res32, ref)):
+        err = O.rel_frob(_host(C), o.cores)
+        assert err <= 1e-5, (k, err)
+
+
+def test_gpu_batch_failure_is_per_product():
+    """A product that fails (here: an SVD sweep limit of 1) reports its own
+    code; the other products of the batch still finish correctly."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: batch with one failing product")
+    pairs = [(I.random_tt(8, 8, 64, 1), I.random_tt(8, 8, 64, 2)),
+             (I.random_tt(6, 2, 4, 3), I.random_tt(6, 2, 4, 4)),
+             (I.random_tt(6, 3, 4, 5), I.random_tt(6, 3, 4, 6))]
+    options = [{"svd_max_sweeps": 1}, {"chi_mid": 0}, {"chi_mid": 0}]
+    res, codes = T.multiply_batch(pairs, [64, 16, 16], 1e-28, options=options, raise_errors=False)
+    assert codes[0] == T.TTM_ENOCONV and codes[1:] == [T.TTM_OK, T.TTM_OK]
+    assert res[0] is None
+    for (A, B), (C, _) in zip(pairs[1:], res[1:]):
+        assert O.rel_frob(_host(C), O.brute_force(A, B)) <= TOL
+    with pytest.raises(T.TTMError) as ei:
+        T.multiply_batch(pairs, [64, 16, 16], 1e-28, options=options)
+    assert ei.value.code == T.TTM_ENOCONV

@@ -27,6 +27,9 @@ __all__ = [
     "qtt_encode_3d",
     "tt_svd",
     "turbulence_qtt",
+    "turbulence_qtt_device",
+    "advective_qtts_device",
+    "ADVECTIVE_CHIS",
     "app_a_toy_tt",
 ]
 
@@ -258,20 +261,10 @@ def turbulence_qtt(n, seed, chi, kprime=None):
     return tt_svd(t, chi)
 
 
-def turbulence_qtt_device(n, seed, chis, device, kprime=None):
-    """QTTs of one synthetic turbulence component for grids too large for
-    the host path (1024^3: 8 GiB per field), one per bond cap in ``chis``.
-
-    The recipe of ``turbulence_component`` / ``turbulence_qtt`` run with
-    torch on ``device``: the same amplitudes and cut-off, phases from the FFT
-    of seeded real white noise (torch's generator on the device, so not the
-    host path's draws), unit RMS, the interleaved-bit order of
-    ``qtt_encode_3d``.  The left-to-right TT-SVD takes the leading
-    eigenvectors of each unfolding's Gram matrix (smaller side) instead of an
-    SVD; for an input that only has to be a TT of this field's structure at
-    bond cap chi, the squared conditioning of the Gram matrix is harmless.
-    Returns {chi: list of float64 numpy cores [r, 8, r']}.
-    """
+def _spectrum_device(n, seed, kprime, device):
+    """Random-phase spectrum of one component (the recipe of
+    ``turbulence_component``, on ``device`` with torch's generator) and the
+    rfft wave-number axes.  Returns (uk, k1, kr)."""
     import torch
 
     if kprime is None:
@@ -291,12 +284,14 @@ def turbulence_qtt_device(n, seed, chis, device, kprime=None):
     amp[k > n / 2.0] = 0.0
     del k
     uk = torch.polar(amp / np.sqrt(2.0), phase)
-    del amp, phase
-    u = torch.fft.irfftn(uk, s=(n, n, n))
-    del uk
-    u /= torch.sqrt(torch.mean(u * u))
-    # Interleaved bit order in two passes (torch views hold at most 16
-    # dimensions): high halves of the three coordinates, then low halves.
+    return uk, k1, kr
+
+
+def _interleave_device(u):
+    """An n^3 device field in the interleaved-bit order of ``qtt_encode_3d``,
+    flattened, in two passes (torch views hold at most 16 dimensions): high
+    halves of the three coordinates, then low halves."""
+    n = u.shape[0]
     L = int(round(np.log2(n)))
     h, lo = L // 2, L - L // 2
 
@@ -304,37 +299,130 @@ def turbulence_qtt_device(n, seed, chis, device, kprime=None):
         return [a * nb + b for b in range(nb) for a in range(3)]
 
     t = u.reshape(2 ** h, 2 ** lo, 2 ** h, 2 ** lo, 2 ** h, 2 ** lo).permute(0, 2, 4, 1, 3, 5).contiguous()
-    del u
     t = t.reshape((2,) * (3 * h) + (2 ** (3 * lo),)).permute(interleave(h) + [3 * h]).contiguous()
     t = t.reshape((2 ** (3 * h),) + (2,) * (3 * lo)).permute([0] + [1 + i for i in interleave(lo)])
-    field = t.contiguous().reshape(-1)
-    del t
-    out = {}
-    for chi in chis:
-        cores = []
-        rest = field.reshape(1, -1)
-        r_left = 1
-        for i in range(L - 1):
-            mat = rest.reshape(r_left * 8, -1)
-            m, ncol = mat.shape
-            r = min(m, ncol, chi) if chi and chi > 0 else min(m, ncol)
-            if m <= ncol:
-                _, evec = torch.linalg.eigh(mat @ mat.T)
-                U = evec[:, -r:].flip(1).contiguous()
-                cores.append(U.reshape(r_left, 8, r).cpu().numpy())
-                rest = U.T @ mat
-            else:
-                _, evec = torch.linalg.eigh(mat.T @ mat)
-                V = evec[:, -r:].flip(1).contiguous()
-                US = mat @ V
-                s = torch.linalg.norm(US, dim=0)
-                U = US / torch.where(s > 0, s, torch.ones_like(s))
-                cores.append(U.reshape(r_left, 8, r).cpu().numpy())
-                rest = s[:, None] * V.T
-            r_left = r
-        cores.append(rest.reshape(r_left, 8, 1).cpu().numpy())
-        out[chi] = cores
-        del rest
+    return t.contiguous().reshape(-1)
+
+
+def _tt_compress_device(field, L, chi):
+    """Left-to-right TT-SVD (d = 8 per site) of a flattened interleaved field
+    with at most ``chi`` values per bond, via the leading eigenvectors of each
+    unfolding's Gram matrix on its smaller side."""
+    import torch
+
+    cores = []
+    rest = field.reshape(1, -1)
+    r_left = 1
+    for i in range(L - 1):
+        mat = rest.reshape(r_left * 8, -1)
+        m, ncol = mat.shape
+        r = min(m, ncol, chi) if chi and chi > 0 else min(m, ncol)
+        if m <= ncol:
+            _, evec = torch.linalg.eigh(mat @ mat.T)
+            U = evec[:, -r:].flip(1).contiguous()
+            cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+            rest = U.T @ mat
+        else:
+            _, evec = torch.linalg.eigh(mat.T @ mat)
+            V = evec[:, -r:].flip(1).contiguous()
+            US = mat @ V
+            s = torch.linalg.norm(US, dim=0)
+            U = US / torch.where(s > 0, s, torch.ones_like(s))
+            cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+            rest = s[:, None] * V.T
+        r_left = r
+    cores.append(rest.reshape(r_left, 8, 1).cpu().numpy())
+    return cores
+
+
+def turbulence_qtt_device(n, seed, chis, device, kprime=None):
+    """QTTs of one synthetic turbulence component for grids too large for
+    the host path (1024^3: 8 GiB per field), one per bond cap in ``chis``.
+
+    The recipe of ``turbulence_component`` / ``turbulence_qtt`` run with
+    torch on ``device``: the same amplitudes and cut-off, phases from the FFT
+    of seeded real white noise (torch's generator on the device, so not the
+    host path's draws), unit RMS, the interleaved-bit order of
+    ``qtt_encode_3d``.  The left-to-right TT-SVD takes the leading
+    eigenvectors of each unfolding's Gram matrix (smaller side) instead of an
+    SVD; for an input that only has to be a TT of this field's structure at
+    bond cap chi, the squared conditioning of the Gram matrix is harmless.
+    Returns {chi: list of float64 numpy cores [r, 8, r']}.
+    """
+    import torch
+
+    uk, _, _ = _spectrum_device(n, seed, kprime, device)
+    u = torch.fft.irfftn(uk, s=(n, n, n))
+    del uk
+    u /= torch.sqrt(torch.mean(u * u))
+    field = _interleave_device(u)
+    del u
+    L = int(round(np.log2(n)))
+    return {chi: _tt_compress_device(field, L, chi) for chi in chis}
+
+
+ADVECTIVE_CHIS = (512, 128, 64, 256, 32, 128, 64, 256, 32)
+
+
+def advective_qtts_device(n, seed, chis=ADVECTIVE_CHIS, device="cuda", kprime=None):
+    """Operands of the nine products u_j * d_j u_i (i, j in {x, y, z}; the
+    sum over j is the advection term (u . grad) u_i of the momentum equation)
+    for a synthetic turbulence velocity field on an n^3 grid.
+
+    Component c in (x, y, z) is the field of ``turbulence_qtt_device`` drawn
+    with seed ``seed + c``, scaled to unit RMS; its derivative along axis j
+    is spectral, the inverse transform of i k_j u_c(k) with the same scale
+    (the Nyquist plane of axis j set to zero so the result is real and the
+    derivative exact for the band-limited field).  Product p = 3 i + j is
+    compressed at bond cap ``chis[p]`` (both operands).  Returns a list of
+    nine (A cores, B cores, chi): A = QTT of u_j, B = QTT of d_j u_i.
+    """
+    import torch
+
+    L = int(round(np.log2(n)))
+    cache = {}
+
+    def compressed(key, chi, make):
+        if (key, chi) not in cache:
+            field = make()
+            cache[(key, chi)] = _tt_compress_device(field, L, chi)
+            del field
+        return cache[(key, chi)]
+
+    spectra = []
+    scales = []
+    for c in range(3):
+        uk, k1, kr = _spectrum_device(n, seed + c, kprime, device)
+        u = torch.fft.irfftn(uk, s=(n, n, n))
+        scales.append(float(torch.sqrt(torch.mean(u * u))))
+        del u
+        spectra.append(uk)
+    kz = kr.clone()
+    kxy = k1.clone()
+    kxy[n // 2] = 0.0
+    if n % 2 == 0:
+        kz[-1] = 0.0
+    axes = [kxy[:, None, None], kxy[None, :, None], kz[None, None, :]]
+
+    def velocity(c):
+        def make():
+            u = torch.fft.irfftn(spectra[c], s=(n, n, n)) / scales[c]
+            return _interleave_device(u)
+        return make
+
+    def derivative(c, j):
+        def make():
+            du = torch.fft.irfftn(spectra[c] * (1j * axes[j]), s=(n, n, n)) / scales[c]
+            return _interleave_device(du)
+        return make
+
+    out = []
+    for i in range(3):
+        for j in range(3):
+            chi = int(chis[3 * i + j])
+            A = compressed(("u", j), chi, velocity(j))
+            B = compressed(("du", i, j), chi, derivative(i, j))
+            out.append((A, B, chi))
     return out
 
 
