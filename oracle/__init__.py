@@ -16,6 +16,8 @@ ttm           The TTM algorithm of Sec. II.B: concatenation (Eq. tensor),
 conventional  The conventional product of Sec. II.A: Kronecker cores
               (Eq. carriageXi) with rounding, and the single-site variational
               fit of A*B.
+adjoint       Gradient of <W, A*B> with respect to the cores of A and B by
+              three-train environments (the paper has no gradients).
 """
 from .tt import (  # noqa: F401
     dense,
@@ -42,3 +44,4 @@ from .conventional import (  # noqa: F401
     splitmix64_uniform,
     initial_guess,
 )
+from .adjoint import inner3_grad, left_envs, right_envs  # noqa: F401,E402
