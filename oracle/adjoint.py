@@ -21,10 +21,17 @@ import numpy as np
 
 
 def left_envs(W, A, B):
-    """E_0 .. E_N (E_k has shape [rw_k, ra_k, rb_k])."""
+    """E_0 .. E_N (E_k has shape [rw_k, ra_k, rb_k]); the sum over the
+    physical index s is a loop, each term three tensordots."""
     envs = [np.ones((1, 1, 1))]
     for w, a, b in zip(W, A, B):
-        envs.append(np.einsum("wab,wsx,asy,bsz->xyz", envs[-1], w, a, b, optimize=True))
+        E = envs[-1]
+        nxt = np.zeros((w.shape[2], a.shape[2], b.shape[2]))
+        for s in range(w.shape[1]):
+            t = np.tensordot(E, w[:, s, :], axes=(0, 0))      # [a, b, w']
+            t = np.tensordot(t, a[:, s, :], axes=(0, 0))      # [b, w', a']
+            nxt += np.tensordot(t, b[:, s, :], axes=(0, 0))   # [w', a', b']
+        envs.append(nxt)
     return envs
 
 
@@ -34,7 +41,13 @@ def right_envs(W, A, B):
     envs = [None] * (n + 1)
     envs[n] = np.ones((1, 1, 1))
     for k in range(n - 1, -1, -1):
-        envs[k] = np.einsum("wsx,asy,bsz,xyz->wab", W[k], A[k], B[k], envs[k + 1], optimize=True)
+        w, a, b, F = W[k], A[k], B[k], envs[k + 1]
+        cur = np.zeros((w.shape[0], a.shape[0], b.shape[0]))
+        for s in range(w.shape[1]):
+            t = np.tensordot(w[:, s, :], F, axes=(1, 0))      # [w, a', b']
+            t = np.tensordot(t, a[:, s, :], axes=(1, 1))      # [w, b', a]
+            cur += np.tensordot(t, b[:, s, :], axes=(1, 1))   # [w, a, b]
+        envs[k] = cur
     return envs
 
 
@@ -45,6 +58,15 @@ def inner3_grad(W, A, B):
     F = right_envs(W, A, B)
     dA, dB = [], []
     for k in range(len(A)):
-        dA.append(np.einsum("wab,wsx,bsz,xyz->asy", E[k], W[k], B[k], F[k + 1], optimize=True))
-        dB.append(np.einsum("wab,wsx,asy,xyz->bsz", E[k], W[k], A[k], F[k + 1], optimize=True))
+        w, a, b, El, Fr = W[k], A[k], B[k], E[k], F[k + 1]
+        ga = np.zeros(a.shape)
+        gb = np.zeros(b.shape)
+        for s in range(w.shape[1]):
+            t = np.tensordot(El, w[:, s, :], axes=(0, 0))                      # [a, b, w']
+            ua = np.tensordot(t, b[:, s, :], axes=(1, 0))                      # [a, w', b']
+            ga[:, s, :] = np.tensordot(ua, Fr, axes=([1, 2], [0, 2]))          # [a, a']
+            ub = np.tensordot(t, a[:, s, :], axes=(0, 0))                      # [b, w', a']
+            gb[:, s, :] = np.tensordot(ub, Fr, axes=([1, 2], [0, 1]))          # [b, b']
+        dA.append(ga)
+        dB.append(gb)
     return float(E[-1][0, 0, 0]), dA, dB
