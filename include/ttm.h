@@ -196,6 +196,30 @@ int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, const int32_
                        const ttm_options *opt, ttm_stats *stats, int32_t n_streams, void *stream,
                        int32_t *status);
 
+/* Gradient of the loss L = <W, A*B> = sum_x W(x) A(x) B(x) with respect to
+ * the cores of A and B: the elementwise product of Sec. II followed by the
+ * inner product with a fixed train W (the paper has no gradients).  L is
+ * linear in every core, so dL/dA_k contracts all other cores: the left
+ * environment of the sites before k, cores k of W and B, and the right
+ * environment of the sites after k (three-train environments).  Wherever the
+ * truncations of TTM (Sec. II.B) drop nothing, TTM(A, B) is A*B and this is
+ * the gradient of <W, TTM(A, B)>; where they do drop weight it is the
+ * gradient of the exact product that TTM approximates, with the truncation
+ * held fixed.
+ * The environments are recomputed on every call: a right-to-left sweep
+ * keeps the right ones in ws, then one left-to-right sweep forms both
+ * gradients at each site and the next left environment.
+ * W, A, B: same N and physical dimensions, any bonds (r_0 = r_N = 1).
+ * contract_precision: TTM_PREC_* for the environment contractions (FP64
+ * storage either way).  value: host, receives L.  dA, dB: device buffers
+ * laid out like A's and B's data (core k of the gradient at the same offset
+ * as core k of the train), or NULL to skip; with both NULL only L is formed
+ * and the right sweep is skipped.  ws: ttm_inner_grad_query's bytes.
+ * Blocking like the other entry points; TTM_ENONFINITE if L is not finite. */
+int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size_t *ws_bytes);
+int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
+                   double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream);
+
 /* Sizes for conventional_multiply (host only). */
 int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
                        size_t *ws_bytes, int64_t *out_capacity);

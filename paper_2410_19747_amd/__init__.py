@@ -8,6 +8,9 @@ The functions mirror the C entry points of ``include/ttm.h``:
     conventional(A, B, chi_out, tol, **options)   -> conventional_multiply_ex
     query(A, B, chi_out, **options)               -> ttm_query
     multiply_batch(pairs, chi_out, tol, ...)      -> ttm_multiply_batch
+    inner_grad(W, A, B)                           -> ttm_inner_grad
+    ttm_inner_loss(W, A, B, chi_out, tol)         -> torch.autograd.Function over
+                                                     ttm_multiply_ex + ttm_inner_grad
 
 A tensor train is a list of float64 CUDA tensors, core i of shape
 [r_i, d_i, r_{i+1}] (r_0 = r_N = 1), or a ``PackedTT``.
@@ -24,7 +27,8 @@ from ._abi import (  # noqa: F401
 )
 
 __all__ = [
-    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "conventional", "query", "conventional_query",
+    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "inner_grad", "ttm_inner_loss",
+    "conventional", "query", "conventional_query",
     "Workspace", "lib",
 ]
 
@@ -315,3 +319,88 @@ def multiply_batch(pairs, chi_out, tol, streams=4, workspaces=None, options=None
         res.append((c, _stats_dict(stats_arr[k], opt_arr[k])))
     del keep
     return res if raise_errors else (res, codes)
+
+
+def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, stream=None):
+    """L = <W, A*B> and, with ``grads``, dL/dA and dL/dB as PackedTTs laid
+    out like A and B, by one call of ttm_inner_grad.  Returns (L, dA, dB)
+    (dA, dB None without ``grads``)."""
+    import torch
+    from ._abi import PRECISIONS
+
+    W, A, B = pack(W), pack(A), pack(B)
+    L = lib()
+    need = ctypes.c_size_t(0)
+    rc = L.ttm_inner_grad_query(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view),
+                                ctypes.byref(need))
+    if rc != TTM_OK:
+        raise TTMError(rc, "ttm_inner_grad_query")
+    if workspace is None:
+        dev = A.data.device
+        workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
+    wbuf = workspace.get(need.value)
+    dA = torch.empty_like(A.data) if grads else None
+    dB = torch.empty_like(B.data) if grads else None
+    value = ctypes.c_double(0.0)
+    prec = PRECISIONS[contract_precision] if isinstance(contract_precision, str) else int(contract_precision)
+    rc = L.ttm_inner_grad(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view), prec,
+                          ctypes.byref(value), ctypes.c_void_p(dA.data_ptr() if grads else None),
+                          ctypes.c_void_p(dB.data_ptr() if grads else None), ctypes.c_void_p(wbuf.data_ptr()),
+                          ctypes.c_size_t(wbuf.numel()), _stream_handle(stream))
+    if rc != TTM_OK:
+        raise TTMError(rc, "ttm_inner_grad")
+    if not grads:
+        return value.value, None, None
+    return (value.value, PackedTT(dA, A.phys, A.bonds, A.offsets), PackedTT(dB, B.phys, B.bonds, B.offsets))
+
+
+def _ones_like_train(T):
+    """The all-ones train (every bond 1) with T's physical dimensions."""
+    import torch
+
+    offs, pos = [], 0
+    for p in T.phys:
+        offs.append(pos)
+        pos += p
+    data = torch.ones(pos, dtype=torch.float64, device=T.data.device)
+    return PackedTT(data, T.phys, [1] * (len(T.phys) + 1), offs)
+
+
+def _make_inner_loss_function():
+    import torch
+
+    class TTMInnerLoss(torch.autograd.Function):
+        """loss = <W, TTM(A, B)> with W fixed.  Forward: the TTM product
+        (ttm_multiply_ex), then <W, C> (ttm_inner_grad against the all-ones
+        train).  Backward: dL/dA, dL/dB of <W, A*B> by ttm_inner_grad, the
+        environments recomputed from W, A and B (nothing kept from the
+        forward pass but the inputs)."""
+
+        @staticmethod
+        def forward(ctx, a_data, b_data, A, B, W, chi_out, tol, prec, opts):
+            C, _ = multiply(A, B, chi_out, tol, contract_precision=prec, **opts)
+            value, _, _ = inner_grad(W, C, _ones_like_train(C), contract_precision=prec, grads=False)
+            ctx.trains = (A, B, W, prec)
+            return torch.tensor(value, dtype=torch.float64, device=a_data.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            A, B, W, prec = ctx.trains
+            _, dA, dB = inner_grad(W, A, B, contract_precision=prec)
+            return g * dA.data, g * dB.data, None, None, None, None, None, None, None
+
+    return TTMInnerLoss
+
+
+_INNER_LOSS = None
+
+
+def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
+    """0-d tensor <W, TTM(A, B)> whose backward gives dL/dA.data and
+    dL/dB.data (PackedTT data tensors with requires_grad) through the
+    adjoint environments of ttm_inner_grad.  W is a constant train."""
+    global _INNER_LOSS
+    if _INNER_LOSS is None:
+        _INNER_LOSS = _make_inner_loss_function()
+    W, A, B = pack(W), pack(A), pack(B)
+    return _INNER_LOSS.apply(A.data, B.data, A, B, W, int(chi_out), float(tol), contract_precision, opts)

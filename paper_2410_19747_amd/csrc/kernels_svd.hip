@@ -802,13 +802,18 @@ __global__ __launch_bounds__(JNT) void jacobi_sort_kernel(const double *__restri
 // thread t owns the contiguous index range of chunk t (at most RANK_PER
 // values, kept in registers); tails are suffix sums, within a chunk from its
 // smallest value up, the chunk totals combined by a suffix scan.
+// Values at or below the rounding-noise level nz = noise * ||W||_F are
+// numerically zero: the sweeps neither rotate nor converge pairs of such
+// columns, so their normalised columns are not orthonormal singular vectors
+// and are never kept (r <= the count of values above nz), whatever eps; with
+// eps at or above the square of that level the rule drops them anyway.
 constexpr int RANK_PER = 8;  // n <= 8192
 __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restrict__ sigma,
                                                            const int *__restrict__ perm, int n,
-                                                           double eps, int cap, int forced,
+                                                           double eps, double noise, int cap, int forced,
                                                            double *__restrict__ result) {
   __shared__ double csum[2][1024];
-  __shared__ int best;
+  __shared__ int best, nsig;
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n + nt - 1) / nt;
   const int lo = min(n, t * per), hi = min(n, lo + per);
@@ -823,7 +828,10 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
     suf[j] = local;
   }
   csum[0][t] = local;
-  if (t == 0) best = n;
+  if (t == 0) {
+    best = n;
+    nsig = 0;
+  }
   __syncthreads();
   // Inclusive suffix scan of the chunk totals (fixed order: Hillis-Steele).
   int src = 0;
@@ -848,8 +856,18 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
     }
   }
   if (mine < n) atomicMin(&best, mine);
+  // values above the noise level (sorted, so they are the leading ones)
+  const double nz2 = noise * noise * total;
+  int above = 0;
+#pragma unroll
+  for (int j = 0; j < RANK_PER; ++j)
+    if (lo + j < hi) {
+      const double sv = sigma[perm[lo + j]];
+      above += (sv * sv > nz2) ? 1 : 0;
+    }
+  if (above) atomicAdd(&nsig, above);
   __syncthreads();
-  int r = best;
+  int r = min(best, nsig);
   if (r < 1) r = 1;
   if (cap > 0 && r > cap) r = cap;
   if (forced > 0) r = forced;
@@ -875,7 +893,8 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
   hipLaunchKernelGGL(jacobi_sort_kernel, dim3((nc + JNT - 1) / JNT), dim3(JNT), shm, s, b.sigma, nc,
                      b.perm);
   if (nc > 1024 * RANK_PER) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_rank_kernel, dim3(1), dim3(1024), 0, s, b.sigma, b.perm, nc, eps, cap,
+  const double noise = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;  // as in the sweeps
+  hipLaunchKernelGGL(jacobi_rank_kernel, dim3(1), dim3(1024), 0, s, b.sigma, b.perm, nc, eps, noise, cap,
                      forced, b.result);
   return hipGetLastError();
 }

@@ -220,3 +220,27 @@ def test_batch_rejects_before_gpu_work(L):
     assert call(base, [need] * n, outs([cap] * n, (0x10000000, 0x10000000 + 8, 0x30000000))) == _abi.TTM_EINVAL
     assert call([0x10000000 + 8, base[1], base[2]], [need] * n,
                 outs([cap] * n, (0x70000000, 0x10000000, 0x30000000))) == _abi.TTM_EINVAL
+
+
+def test_inner_grad_rejects_before_gpu_work(L):
+    """ttm_inner_grad sizes its workspace from shapes and rejects bad
+    arguments before any HIP call."""
+    W = _TT([2, 3, 2], [1, 2, 2, 1])
+    A = _TT([2, 3, 2], [1, 2, 3, 1])
+    B = _TT([2, 3, 2], [1, 2, 1, 1])
+    ws = ctypes.c_size_t(0)
+    assert L.ttm_inner_grad_query(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view),
+                                  ctypes.byref(ws)) == 0
+    # right environments (bonds 1,2x2x2,2x3x1,1) + two left ones + three scratch tensors, 32-aligned
+    assert ws.value >= 8 * (1 + 8 + 6 + 1)
+    Bad = _TT([2, 2, 2], [1, 2, 1, 1])
+    assert L.ttm_inner_grad_query(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(Bad.view),
+                                  ctypes.byref(ws)) == _abi.TTM_ESHAPE
+    v = ctypes.c_double(0.0)
+    args = (ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view))
+    assert L.ttm_inner_grad(*args, 0, None, None, None, ctypes.c_void_p(0x1000), 1 << 20, None) == _abi.TTM_EINVAL
+    assert L.ttm_inner_grad(*args, 7, ctypes.byref(v), None, None, ctypes.c_void_p(0x1000), 1 << 20,
+                            None) == _abi.TTM_EINVAL
+    assert L.ttm_inner_grad(*args, 0, ctypes.byref(v), None, None, None, 1 << 20, None) == _abi.TTM_EWORKSPACE
+    assert L.ttm_inner_grad(*args, 0, ctypes.byref(v), None, None, ctypes.c_void_p(0x1000), 16,
+                            None) == _abi.TTM_EWORKSPACE

@@ -194,3 +194,19 @@ def test_gpu_error_codes():
     # the library stays usable after errors
     C, _ = _run(A, B, 16, 1e-28, chi_mid=0)
     assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
+
+
+def test_gpu_eps_zero_keeps_only_resolved_values():
+    """eps = 0 with no cap: every swap matrix here is rank deficient (rank
+    12 of 27 at the middle bonds), so its trailing singular values are
+    rounding noise whose vectors the SVD does not resolve.  They are dropped
+    (ranks at most the oracle's), and the product stays exact."""
+    _say("case: eps = 0, rank-deficient swaps")
+    n, d = 6, 3
+    A, B = I.random_tt(n, d, 3, 12), I.random_tt(n, d, 2, 13)
+    C, st = _run(A, B, 6, 0.0, chi_mid=0)
+    assert O.rel_frob(C, O.brute_force(A, B)) <= TOL
+    o = O.ttm(A, B, 6, 0.0, chi_mid=0)
+    assert len(st["ranks"]) == len(o.ranks)
+    assert all(g <= r for g, r in zip(st["ranks"], o.ranks))
+    assert max(st["ranks"]) < max(o.ranks)
