@@ -22,6 +22,9 @@ relative error of sampled entries against the exact product A(x) B(x).
 synthetic velocity field (1024^3, 10 sites, d = 8) at uneven bonds, one
 after another and in single ttm_multiply_batch calls (FP64 and FP32
 contractions): one JSON line per run.
+
+``--adjoint`` measures the gradient of <W, A*B> with respect to the cores
+of A and B (ttm_inner_grad) on the 1024^3 chi = 128 QTTs.
 """
 from __future__ import annotations
 
@@ -95,6 +98,8 @@ def main():
                     help="products in flight (streams) for the batched runs, comma list")
     ap.add_argument("--batch-precisions", default="f64,f32",
                     help="contraction arithmetic of the batched runs (f64 first)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,6 +121,8 @@ def main():
         return sweep(args, dev)
     if args.batched:
         return batched(args, dev)
+    if args.adjoint:
+        return adjoint(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -444,6 +451,78 @@ def batched(args, dev):
             _log("  batched %s, %d streams: %.1f ms (x%.2f vs serial f64), max sampled diff vs f64 %.2e"
                  % (prec, nstreams, 1e3 * dt, t_serial / dt, max(diffs)))
             del res
+    return None
+
+
+def _inner_grad_flops(W, A, B):
+    """Algorithmic flops of one ttm_inner_grad call with gradients: the
+    right sweep's three contractions per site (sites 1..N-1) and the left
+    sweep's six (two for the environment, four for the gradients)."""
+    f = 0.0
+    n = len(A)
+    for k in range(n):
+        rw, d, rw2 = W[k].shape
+        ra, _, ra2 = A[k].shape
+        rb, _, rb2 = B[k].shape
+        if k >= 1:
+            f += 2.0 * (rw * d * ra2 * rb2 * rw2 + ra * rw * rb2 * ra2 * d + rw * ra * d * rb2 * rb)
+        f += 2.0 * (ra * rb * d * rw2 * rw + rb * rw2 * ra2 * ra * d + rb * d * rb2 * rw2 * ra2
+                    + rb * rw2 * ra2 * rb2 * d + ra * ra2 * rb * rw2 * d + rw2 * ra2 * rb2 * rb * d)
+    return f
+
+
+def adjoint(args, dev):
+    """Gradient of <W, A*B> with respect to the cores of A and B (A, B: the
+    1024^3 turbulence QTTs u_x, u_y at chi = 128, 10 sites, d = 8; W a random
+    train at chi = 32), FP64 and FP32 contractions, against the oracle's
+    gradient, which is also timed on the host.  One JSON line per precision."""
+    import numpy as np
+    import torch
+
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    _log("generating 1024^3 turbulence QTTs at chi 128 on the device")
+    qa = I.turbulence_qtt_device(1024, 101, [128], dev)[128]
+    qb = I.turbulence_qtt_device(1024, 102, [128], dev)[128]
+    torch.cuda.empty_cache()
+    W = I.random_tt(10, 8, 32, 77)
+    A, B, Wp = T.pack(qa, dev), T.pack(qb, dev), T.pack(W, dev)
+    flops = _inner_grad_flops(W, qa, qb)
+    ref = None
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        t = time.perf_counter()
+        ref = O.inner3_grad(W, qa, qb)
+        cpu = time.perf_counter() - t
+    ws = T.Workspace(dev)
+    for prec in ("f64", "f32"):
+        for _ in range(max(args.warmup, 1)):
+            T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            v, dA, dB = T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        err = None
+        if ref is not None:
+            gA = [c.detach().cpu().numpy() for c in dA.cores()]
+            gB = [c.detach().cpu().numpy() for c in dB.cores()]
+            num = sum(np.sum((x - y) ** 2) for x, y in zip(gA + gB, ref[1] + ref[2]))
+            den = sum(np.sum(y ** 2) for y in ref[1] + ref[2])
+            err = float(np.sqrt(num / den))
+        line = {"adjoint": True, "workload": "grad of <W, A*B>: 1024^3 turbulence QTTs u_x, u_y at chi 128 "
+                "(N=10, d=8), W random at chi 32", "precision": prec, "ms_per_gradient": 1e3 * dt,
+                "gradients_per_s": 1.0 / dt, "algorithmic_flops": flops,
+                "algorithmic_tflops": flops / dt / 1e12,
+                "fp64_mfma_frac": flops / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                "rel_err_vs_oracle_gradient": err, "value": v,
+                "cpu_oracle_s": cpu, "cpu_cores": _cpu_threads() if cpu is not None else None}
+        print(json.dumps(line), flush=True)
+        _log("  %s: %.2f ms per gradient, %.2f TFLOP/s algorithmic, rel err vs oracle %s"
+             % (prec, 1e3 * dt, flops / dt / 1e12, "%.2e" % err if err is not None else "-"))
     return None
 
 
