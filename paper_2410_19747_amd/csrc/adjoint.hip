@@ -18,6 +18,7 @@ namespace ttm {
 namespace {
 
 size_t r32(size_t n) { return (n + 31) & ~(size_t)31; }
+constexpr int64_t kSplitSlices = 16;  // split-K scratch: up to 16 partial outputs per contraction
 
 int check_train(const ttm_tt *t) {
   if (!t) return TTM_EINVAL;
@@ -51,6 +52,7 @@ struct GradPlan {
   int64_t x_max = 0;  // T1 (left sweep) / U1 (right sweep)
   int64_t y_max = 0;  // T2 / U2
   int64_t v_max = 0;  // V
+  int64_t part = 0;   // split-K partial tiles of the skinny contractions
   size_t ws_doubles = 0;
   bool fits = true;
 };
@@ -72,13 +74,16 @@ GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
     p.x_max = std::max({p.x_max, d * ra * rb * rw2, d * ra2 * rw * rb2});
     p.y_max = std::max({p.y_max, rb * d * rw2 * ra2, rw * ra * d * rb2});
     p.v_max = std::max(p.v_max, d * rb * rw2 * ra2);
+    p.part = std::max({p.part, d * ra * ra2, d * rb * rb2, rw2 * ra2 * rb2, rw * ra * rb});
     // GEMM extents are ints; the largest are ra*rb, rw2*ra2, d*rw2 and d*ra2*rb2.
     const int64_t lim = (int64_t)1 << 30;
     if (ra * rb > lim || rw2 * ra2 > lim || d * rw2 > lim || ra2 * rb2 > lim || rw * ra > lim ||
         rw * d > lim || rb * d > lim || rb * rw2 > lim || rw * rb2 > lim || d * rb2 > lim)
       p.fits = false;
   }
-  p.ws_doubles = (size_t)p.env_total + 2 * r32(p.env_max) + r32(p.x_max) + r32(p.y_max) + r32(p.v_max) + 32;
+  p.part *= kSplitSlices;
+  p.ws_doubles = (size_t)p.env_total + 2 * r32(p.env_max) + r32(p.x_max) + r32(p.y_max) + r32(p.v_max) +
+                 r32(p.part) + 32;
   return p;
 }
 
@@ -141,7 +146,13 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
   double *X = Ln + r32(p.env_max);
   double *Y = X + r32(p.x_max);
   double *V = Y + r32(p.y_max);
+  double *P = V + r32(p.v_max);  // split-K partial tiles
   const bool grads = dA || dB;
+  auto gemm = [&](GemmArgs g) {
+    g.part = P;
+    g.part_doubles = p.part;
+    return launch_gemm(g, st);
+  };
   const int n = p.n;
   auto fail = [&](hipError_t h) {
     (void)hipStreamSynchronize(st);
@@ -166,8 +177,8 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
       // F_k[w][a][b] = sum_{s,b'} U2[w][a][s][b'] B[b,s,b']  (rows w*ra+a, K = s*rb2+b')
       GemmArgs g3 = strided(rw * ra, rb, d * rb2, 1, Y, (int64_t)d * rb2, 1, 0, core(B, k), 1, (int64_t)d * rb2, 0,
                             R + p.env_off[k], 0, 1, rb, 0, 1, 1, 0, gp);
-      if ((h = launch_gemm(g1, st)) != hipSuccess || (h = launch_gemm(g2, st)) != hipSuccess ||
-          (h = launch_gemm(g3, st)) != hipSuccess)
+      if ((h = gemm(g1)) != hipSuccess || (h = gemm(g2)) != hipSuccess ||
+          (h = gemm(g3)) != hipSuccess)
         return fail(h);
     }
   }
@@ -183,14 +194,14 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
     GemmArgs t2 = strided(rb * rw2, ra2, ra, d, X, 1, (int64_t)rb * rw2, (int64_t)ra * rb * rw2, core(A, k),
                           (int64_t)d * ra2, 1, ra2, Y, (int64_t)rw2 * ra2, rw2, (int64_t)d * rw2 * ra2, ra2, 1, 1,
                           0, gp);
-    if ((h = launch_gemm(t1, st)) != hipSuccess || (h = launch_gemm(t2, st)) != hipSuccess) return fail(h);
+    if ((h = gemm(t1)) != hipSuccess || (h = gemm(t2)) != hipSuccess) return fail(h);
     if (grads) {
       const double *Rn = R + p.env_off[k + 1];
       if (dB) {
         // dB_k[b,s,b'] = sum_{w',a'} T2[b][s][w'][a'] F_{k+1}[w'][a'][b']  (rows b*d+s)
         GemmArgs gb = strided(rb * d, rb2, rw2 * ra2, 1, Y, (int64_t)rw2 * ra2, 1, 0, Rn, rb2, 1, 0,
                               dB + B->offsets[k], 0, 1, rb2, 0, 1, 1, 0, gp);
-        if ((h = launch_gemm(gb, st)) != hipSuccess) return fail(h);
+        if ((h = gemm(gb)) != hipSuccess) return fail(h);
       }
       if (dA) {
         // V[s][b][w'][a'] = sum_b' B[b,s,b'] F_{k+1}[w'][a'][b']  (batch s; rows b, columns w'*ra2+a')
@@ -200,13 +211,13 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
         GemmArgs ga = strided(ra, ra2, rb * rw2, d, X, (int64_t)rb * rw2, 1, (int64_t)ra * rb * rw2, V, ra2, 1,
                               (int64_t)rb * rw2 * ra2, dA + A->offsets[k], ra2, 1, (int64_t)d * ra2, 0, 1, 1,
                               0, gp);
-        if ((h = launch_gemm(gv, st)) != hipSuccess || (h = launch_gemm(ga, st)) != hipSuccess) return fail(h);
+        if ((h = gemm(gv)) != hipSuccess || (h = gemm(ga)) != hipSuccess) return fail(h);
       }
     }
     // E_{k+1}[w'][a'][b'] = sum_{b,s} T2[b][s][w'][a'] B[b,s,b']  (rows w'*ra2+a', K = b*d+s)
     GemmArgs t3 = strided(rw2 * ra2, rb2, rb * d, 1, Y, 1, (int64_t)rw2 * ra2, 0, core(B, k), rb2, 1, 0, Ln, 0, 1,
                           rb2, 0, 1, 1, 0, gp);
-    if ((h = launch_gemm(t3, st)) != hipSuccess) return fail(h);
+    if ((h = gemm(t3)) != hipSuccess) return fail(h);
     std::swap(Lc, Ln);
   }
   if ((h = hipMemcpyAsync(value, Lc, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return fail(h);

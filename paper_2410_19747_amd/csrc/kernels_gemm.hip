@@ -10,6 +10,8 @@
 // merge of a swap pair is one product whose epilogue stores the leg-exchanged
 // unfolding; the R (or S V^T) factor of a gauge move is multiplied into the
 // next carriage; the variational baseline's environment contractions.
+#include <algorithm>
+
 #include "ttm_internal.h"
 
 namespace ttm {
@@ -21,6 +23,7 @@ constexpr int BM = 64;
 constexpr int BN = 64;
 constexpr int BK = 16;
 constexpr int NT = 256;  // 4 waves of 64 lanes, 2 x 2 over the 64 x 64 tile
+constexpr int64_t kSplitTarget = 512;  // workgroups a split product aims for (two per CU)
 
 __device__ __forceinline__ int64_t out_index(const GemmArgs &g, int i, int j) {
   int64_t oi = (g.c_rdiv == 1) ? (int64_t)i * g.c_rs1
@@ -45,7 +48,9 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int tile_m = blockIdx.y * BM;
   const int tile_n = blockIdx.x * BN;
-  const int64_t bz = blockIdx.z;
+  const int64_t bz = blockIdx.z / g.ksplit;
+  const int kbeg = (g.ksplit > 1) ? (int)(blockIdx.z % g.ksplit) * g.kchunk : 0;
+  const int kend = (g.ksplit > 1) ? min(g.K, kbeg + g.kchunk) : g.K;
   const double *A = g.A + bz * g.a_bs;
   const double *B = g.B + bz * g.b_bs;
   const bool a_kfast = (g.a_cs == 1);
@@ -55,18 +60,18 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     for (int e = tid; e < BM * BK; e += NT) {
       int i, k;
       if (a_kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
       const int gi = tile_m + i, gk = k0 + k;
-      As[k][i] = (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0;
+      As[k][i] = (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0;
     }
     for (int e = tid; e < BK * BN; e += NT) {
       int j, k;
       if (b_jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
       const int gj = tile_n + j, gk = k0 + k;
-      Bs[k][j] = (gj < g.N && gk < g.K) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0;
+      Bs[k][j] = (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -94,6 +99,10 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
         const int i = tile_m + wr * 32 + x * 16 + 4 * t + (lane >> 4);
         const int j = tile_n + wc * 32 + y * 16 + (lane & 15);
         if (i < g.M && j < g.N) {
+          if (g.ksplit > 1) {
+            g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = acc[x][y][t];
+            continue;
+          }
           const int64_t o = out_index(g, i, j);
           double v = g.alpha * acc[x][y][t];
           if (g.beta != 0.0) v += g.beta * C[o];
@@ -101,6 +110,26 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
         }
       }
     }
+  }
+}
+
+// Sum of the K slices of a split product, slice 0 first, then the epilogue
+// of the unsplit kernel (alpha, beta, split-stride output).
+__global__ __launch_bounds__(256) void gemm_splitk_reduce_kernel(GemmArgs g) {
+  const int64_t mn = (int64_t)g.M * g.N;
+  const int64_t total = mn * g.batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / mn, r = e % mn;
+    const double *p = g.part + b * g.ksplit * mn + r;
+    double sum = 0.0;
+    for (int s = 0; s < g.ksplit; ++s) sum += p[s * mn];
+    const int i = (int)(r / g.N), j = (int)(r % g.N);
+    double *C = g.C + b * g.c_bs;
+    const int64_t o = out_index(g, i, j);
+    double v = g.alpha * sum;
+    if (g.beta != 0.0) v += g.beta * C[o];
+    C[o] = v;
   }
 }
 
@@ -133,7 +162,9 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int tile_m = blockIdx.y * BM;
   const int tile_n = blockIdx.x * BN;
-  const int64_t bz = blockIdx.z;
+  const int64_t bz = blockIdx.z / g.ksplit;
+  const int kbeg = (g.ksplit > 1) ? (int)(blockIdx.z % g.ksplit) * g.kchunk : 0;
+  const int kend = (g.ksplit > 1) ? min(g.K, kbeg + g.kchunk) : g.K;
   const double *A = g.A + bz * g.a_bs;
   const double *B = g.B + bz * g.b_bs;
   const bool a_kfast = (g.a_cs == 1);
@@ -159,18 +190,18 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     for (int e = tid; e < BM * BK; e += NT) {
       int i, k;
       if (a_kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
       const int gi = tile_m + i, gk = k0 + k;
-      put(As, k, i, (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0);
+      put(As, k, i, (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0);
     }
     for (int e = tid; e < BK * BN; e += NT) {
       int j, k;
       if (b_jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
       const int gj = tile_n + j, gk = k0 + k;
-      put(Bs, k, j, (gj < g.N && gk < g.K) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0);
+      put(Bs, k, j, (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0);
     }
     __syncthreads();
     if (PREC == 1) {
@@ -223,6 +254,10 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
         const int i = tile_m + wr * 32 + x * 16 + 4 * (lane >> 4) + t;
         const int j = tile_n + wc * 32 + y * 16 + (lane & 15);
         if (i < g.M && j < g.N) {
+          if (g.ksplit > 1) {
+            g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = (double)acc[x][y][t];
+            continue;
+          }
           const int64_t o = out_index(g, i, j);
           double v = g.alpha * (double)acc[x][y][t];
           if (g.beta != 0.0) v += g.beta * C[o];
@@ -250,8 +285,37 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     // (every bond is >= 1); rejected rather than special-cased.
     return hipErrorInvalidValue;
   }
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+  GemmArgs h = g;
+  h.ksplit = 1;
+  h.kchunk = 0;
+  const int64_t tiles = (int64_t)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * g.batch;
+  const int64_t outs = (int64_t)g.M * g.N * g.batch;
+  // Split K only when the output tiles leave the device under-filled, and
+  // with at least 4 k-steps per slice.
+  if (g.part && tiles < kSplitTarget && g.K >= 8 * BK) {
+    int64_t ks = std::min<int64_t>((kSplitTarget + tiles - 1) / tiles, g.K / (4 * BK));
+    ks = std::min<int64_t>(ks, g.part_doubles / outs);
+    ks = std::min<int64_t>(ks, 65535 / g.batch);
+    if (ks > 1) {
+      const int kchunk = (int)(((g.K + ks - 1) / ks + BK - 1) / BK * BK);
+      h.kchunk = kchunk;
+      h.ksplit = (g.K + kchunk - 1) / kchunk;
+    }
+  }
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * h.ksplit);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
+  if (h.ksplit > 1) {
+    switch (g.prec) {
+      case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, h); break;
+      case GEMM_F32: hipLaunchKernelGGL(gemm_lowp_kernel<1>, grid, dim3(NT), 0, s, h); break;
+      case GEMM_BF16: hipLaunchKernelGGL(gemm_lowp_kernel<2>, grid, dim3(NT), 0, s, h); break;
+      case GEMM_BF16X3: hipLaunchKernelGGL(gemm_lowp_kernel<3>, grid, dim3(NT), 0, s, h); break;
+      default: return hipErrorInvalidValue;
+    }
+    const int64_t blocks = std::min<int64_t>((outs + 255) / 256, 4096);
+    hipLaunchKernelGGL(gemm_splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, h);
+    return hipGetLastError();
+  }
   switch (g.prec) {
     case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, g); break;
     case GEMM_F32: hipLaunchKernelGGL(gemm_lowp_kernel<1>, grid, dim3(NT), 0, s, g); break;

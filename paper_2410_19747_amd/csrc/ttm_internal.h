@@ -74,6 +74,14 @@ struct GemmArgs {
   int64_t c_rs1 = 0, c_rs0 = 0, c_cs1 = 0, c_cs0 = 0;
   double alpha = 1.0, beta = 0.0;
   int prec = GEMM_F64;
+  // Optional split-K scratch: with part set, launch_gemm may split K over
+  // slices when the output has too few tiles to fill the device; each slice
+  // writes its partial tile to part and a second kernel sums the slices in a
+  // fixed order (deterministic, but a different rounding order from the
+  // unsplit product).  ksplit and kchunk are set by launch_gemm.
+  double *part = nullptr;
+  int64_t part_doubles = 0;
+  int ksplit = 1, kchunk = 0;
 };
 
 // Plain row-major helper: C[M x N] (ldc) = A[M x K] (lda) * B[K x N] (ldb).
