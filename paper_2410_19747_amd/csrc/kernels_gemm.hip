@@ -25,6 +25,19 @@ constexpr int BK = 16;
 constexpr int NT = 256;  // 4 waves of 64 lanes, 2 x 2 over the 64 x 64 tile
 constexpr int64_t kSplitTarget = 512;  // workgroups a split product aims for (two per CU)
 
+constexpr int EA = BM * BK / NT;  // A-tile elements per thread
+constexpr int EB = BK * BN / NT;  // B-tile elements per thread
+
+// Tile coordinates of element e of a thread's share: the fast index follows
+// the operand's unit stride so that neighbouring lanes read neighbouring
+// addresses.
+__device__ __forceinline__ void a_coords(int e, bool kfast, int &i, int &k) {
+  if (kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
+}
+__device__ __forceinline__ void b_coords(int e, bool jfast, int &j, int &k) {
+  if (jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+}
+
 __device__ __forceinline__ int64_t out_index(const GemmArgs &g, int i, int j) {
   int64_t oi = (g.c_rdiv == 1) ? (int64_t)i * g.c_rs1
                                : (int64_t)(i / g.c_rdiv) * g.c_rs1 + (int64_t)(i % g.c_rdiv) * g.c_rs0;
@@ -60,20 +73,41 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmArgs g) {
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += NT) {
+  // The next k-tile's operands are loaded into registers while the current
+  // one is multiplied, then stored to LDS after the barrier.
+  double ra[EA], rb[EB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
       int i, k;
-      if (a_kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
+      a_coords(tid + q * NT, a_kfast, i, k);
       const int gi = tile_m + i, gk = k0 + k;
-      As[k][i] = (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0;
+      ra[q] = (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0;
     }
-    for (int e = tid; e < BK * BN; e += NT) {
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
       int j, k;
-      if (b_jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+      b_coords(tid + q * NT, b_jfast, j, k);
       const int gj = tile_n + j, gk = k0 + k;
-      Bs[k][j] = (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0;
+      rb[q] = (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      int i, k;
+      a_coords(tid + q * NT, a_kfast, i, k);
+      As[k][i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      int j, k;
+      b_coords(tid + q * NT, b_jfast, j, k);
+      Bs[k][j] = rb[q];
     }
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -190,20 +224,39 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += NT) {
+  double ra[EA], rb[EB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
       int i, k;
-      if (a_kfast) { k = e % BK; i = e / BK; } else { i = e % BM; k = e / BM; }
+      a_coords(tid + q * NT, a_kfast, i, k);
       const int gi = tile_m + i, gk = k0 + k;
-      put(As, k, i, (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0);
+      ra[q] = (gi < g.M && gk < kend) ? A[(int64_t)gi * g.a_rs + (int64_t)gk * g.a_cs] : 0.0;
     }
-    for (int e = tid; e < BK * BN; e += NT) {
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
       int j, k;
-      if (b_jfast) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+      b_coords(tid + q * NT, b_jfast, j, k);
       const int gj = tile_n + j, gk = k0 + k;
-      put(Bs, k, j, (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0);
+      rb[q] = (gj < g.N && gk < kend) ? B[(int64_t)gk * g.b_rs + (int64_t)gj * g.b_cs] : 0.0;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      int i, k;
+      a_coords(tid + q * NT, a_kfast, i, k);
+      put(As, k, i, ra[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      int j, k;
+      b_coords(tid + q * NT, b_jfast, j, k);
+      put(Bs, k, j, rb[q]);
     }
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
     if (PREC == 1) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
