@@ -145,3 +145,21 @@ def test_gpu_inner_grad_error_codes():
     with pytest.raises(T.TTMError) as ei:
         T.inner_grad(W, bad, W)
     assert ei.value.code == T.TTM_ENONFINITE
+
+
+def test_gpu_inner_grad_wide_w_and_fp32():
+    """W with larger bonds than A and B, mixed physical dimensions; FP32
+    contractions at the mixed-precision bound."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: inner_grad wide W, FP32")
+    d = [4, 2, 5, 3, 4, 2, 3]
+    W = I.random_tt(7, d, 40, 31)
+    A = I.random_tt(7, d, 6, 32)
+    B = I.random_tt(7, d, 9, 33)
+    vo, dAo, dBo = O.inner3_grad(W, A, B)
+    v, dA, dB = T.inner_grad(W, A, B)
+    assert abs(v - vo) <= TOL * abs(vo)
+    assert _rel(_host(dA), dAo) <= TOL and _rel(_host(dB), dBo) <= TOL
+    v32, dA32, dB32 = T.inner_grad(W, A, B, contract_precision="f32")
+    assert _rel(_host(dA32), dAo) <= 1e-5 and _rel(_host(dB32), dBo) <= 1e-5

@@ -110,3 +110,27 @@ def test_gpu_batch_failure_is_per_product():
     with pytest.raises(T.TTMError) as ei:
         T.multiply_batch(pairs, [64, 16, 16], 1e-28, options=options)
     assert ei.value.code == T.TTM_ENOCONV
+
+
+def test_gpu_batch_mixed_shapes_and_precisions():
+    """Products of different lengths and physical dimensions in one batch,
+    per-product options (uncapped swaps, FP32 contractions): each equals the
+    single call with the same options, bit for bit."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: batch of mixed shapes and options")
+    pairs = [(I.random_tt(4, 3, 4, 900), I.random_tt(4, 3, 4, 901)),
+             (I.random_tt(7, 2, 8, 902), I.random_tt(7, 2, 8, 903)),
+             (I.random_tt(5, [2, 5, 3, 5, 2], 6, 904), I.random_tt(5, [2, 5, 3, 5, 2], 6, 905)),
+             (I.random_tt(1, 6, 1, 906), I.random_tt(1, 6, 1, 907))]
+    chis = [16, 8, 12, 1]
+    options = [{"chi_mid": 0}, {"contract_precision": "f32"}, {"contract_precision": "bf16x3"}, {}]
+    single = [T.multiply(A, B, c, 1e-14, **o) for (A, B), c, o in zip(pairs, chis, options)]
+    batch = T.multiply_batch(pairs, chis, 1e-14, streams=3, options=options)
+    for k, ((Cb, sb), (Cs, ss)) in enumerate(zip(batch, single)):
+        assert Cb.bonds == Cs.bonds and sb["ranks"] == ss["ranks"], k
+        for x, y in zip(_host(Cb), _host(Cs)):
+            assert np.array_equal(x, y), k
+    # the exact one against brute force
+    (A, B) = pairs[0]
+    assert O.rel_frob(_host(batch[0][0]), O.brute_force(A, B)) <= TOL
