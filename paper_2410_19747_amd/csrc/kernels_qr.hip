@@ -367,6 +367,145 @@ __global__ __launch_bounds__(PNT) void qr_panel_reg_kernel(double *__restrict__ 
   }
 }
 
+// Panels of 1024 < mv <= 2048 rows: rows 0 .. 1023 of the panel in
+// registers as in qr_panel_reg_kernel<16>, rows 1024 .. 2047 in LDS
+// (ext[c][r] = row 1024 + r of column c, 128 KB), both handled by the lane
+// that owns the register rows r = i0 + 64 s.  Column CC's values at the LDS
+// rows are read by all 16 lanes of a row group from one address
+// (broadcast); only columns right of CC change, and the lane that writes
+// ext[c][r] is in the wave that reads it at the next column, after its own
+// write in program order.
+constexpr int EXT_ROWS = 64 * MAX_REG_SLOTS;  // rows held in LDS
+template <int CC>
+__device__ __forceinline__ void panel_column_ext(double (&x)[MAX_REG_SLOTS], double (*ext)[EXT_ROWS + 1],
+                                                 PanelSmem &sm, int w, int g, int c, int i0, double &myscale,
+                                                 double &mybeta) {
+  constexpr int SL = MAX_REG_SLOTS;
+  constexpr int B = CC & 1;
+  // LDS rows first, in short groups so that few loads are live at once.
+  double dl[2] = {0.0, 0.0};
+#pragma unroll 2
+  for (int s = 0; s < SL; ++s) {
+    const int r = i0 + 64 * s;
+    dl[s & 1] = fma(ext[CC][r], ext[c][r], dl[s & 1]);
+  }
+  double b[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) b[s] = row_bcast<CC>(x[s]);
+  double dp[4] = {(i0 > CC) ? b[0] * x[0] : 0.0, dl[0], dl[1], 0.0};
+#pragma unroll
+  for (int s = 1; s < SL; ++s) dp[s & 3] = fma(b[s], x[s], dp[s & 3]);
+  if (CC >= 2 && w == 0 && g == 0) t_column(sm, CC - 2, c);
+  double d = rowgroup_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
+  if (g == 0) sm.red[B][w][c] = d;
+  if (i0 == CC) sm.xrow[B][c] = x[0];
+  __syncthreads();
+  const double dc = rowgroup_sum((sm.red[B][g][c] + sm.red[B][4 + g][c]) + (sm.red[B][8 + g][c] + sm.red[B][12 + g][c]));
+  const double xnorm2 = row_bcast<CC>(dc);
+  const double alpha = sm.xrow[B][CC], xc = sm.xrow[B][c];
+  double tau = 0.0, scale = 0.0, beta = alpha;
+  if (xnorm2 > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+    tau = (beta - alpha) * recip(beta);
+    scale = recip(alpha - beta);
+  }
+  const double tot = fma(scale, dc, xc);
+  const double f = (c > CC) ? tau * tot : 0.0, fs = f * scale;
+  x[0] = (i0 > CC) ? fma(-fs, b[0], x[0]) : (i0 == CC ? x[0] - f : x[0]);
+#pragma unroll
+  for (int s = 1; s < SL; ++s) x[s] = fma(-fs, b[s], x[s]);
+  if (c > CC) {
+#pragma unroll 2
+    for (int s = 0; s < SL; ++s) {
+      const int r = i0 + 64 * s;
+      ext[c][r] = fma(-fs, ext[CC][r], ext[c][r]);
+    }
+  }
+  if (c == CC) {
+    myscale = scale;
+    mybeta = beta;
+  }
+  if (w == 0 && g == 0) {
+    if (c < CC) sm.zs[CC][c] = myscale * tot;
+    if (c == CC) sm.taus[CC] = tau;
+  }
+}
+
+template <int CC = 0>
+__device__ __forceinline__ void panel_columns_ext(double (&x)[MAX_REG_SLOTS], double (*ext)[EXT_ROWS + 1],
+                                                  PanelSmem &sm, int jb, int w, int g, int c, int i0,
+                                                  double &myscale, double &mybeta) {
+  if constexpr (CC < QB) {
+    if (CC < jb) {
+      panel_column_ext<CC>(x, ext, sm, w, g, c, i0, myscale, mybeta);
+      panel_columns_ext<CC + 1>(x, ext, sm, jb, w, g, c, i0, myscale, mybeta);
+    }
+  }
+}
+
+// As qr_panel_reg_kernel<16> for 1024 < mv <= 2048 rows (see
+// panel_column_ext).  Loads and stores run along the columns through the
+// LDS block: rows 0 .. 1023 pass through it into and out of registers
+// first, then it holds rows 1024 .. 2047 for the factorisation.
+__global__ __launch_bounds__(PNT) void qr_panel_ext_kernel(double *__restrict__ S, int m, int n, int j0, int jb,
+                                                           double *__restrict__ T,
+                                                           const double *__restrict__ cnorm,
+                                                           int *__restrict__ perm, double *__restrict__ pscratch) {
+  if (cnorm) panel_pivot(S, m, n, j0, jb, cnorm, perm, pscratch);
+  __shared__ PanelSmem sm;
+  __shared__ double ext[QB][EXT_ROWS + 1];
+  constexpr int SL = MAX_REG_SLOTS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int mv = m - j0;
+  const int i0 = 4 * w + g;
+  auto load_rows = [&](int base) {
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      const int e = tid + PNT * q, cc = e / EXT_ROWS, r = e % EXT_ROWS;
+      ext[cc][r] = (base + r < mv && cc < jb) ? S[(int64_t)(j0 + cc) * m + j0 + base + r] : 0.0;
+    }
+  };
+  auto store_rows = [&](int base) {
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      const int e = tid + PNT * q, cc = e / EXT_ROWS, r = e % EXT_ROWS;
+      if (base + r < mv && cc < jb) S[(int64_t)(j0 + cc) * m + j0 + base + r] = ext[cc][r];
+    }
+  };
+  double x[SL];
+  load_rows(0);
+  if (w == 0 && g == 0)
+    for (int b = 0; b < QB; ++b) sm.Tl[c][b] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SL; ++s) x[s] = ext[c][i0 + 64 * s];
+  __syncthreads();
+  load_rows(EXT_ROWS);
+  __syncthreads();
+  double myscale = 0.0, mybeta = 0.0;
+  panel_columns_ext(x, ext, sm, jb, w, g, c, i0, myscale, mybeta);
+  // LDS rows: v = x scale (every row there is below the diagonal).
+#pragma unroll
+  for (int s = 0; s < SL; ++s) ext[c][i0 + 64 * s] *= myscale;
+  __syncthreads();
+  if (w == 0 && g == 0) {
+    if (jb >= 2) t_column(sm, jb - 2, c);
+    t_column(sm, jb - 1, c);
+    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? sm.Tl[c][b] : 0.0;
+  }
+  store_rows(EXT_ROWS);
+  __syncthreads();
+  // Register rows: R above row c, beta at row c, v = x scale below.
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int i = i0 + 64 * s;
+    ext[c][i] = (i > c) ? x[s] * myscale : (i == c ? mybeta : x[s]);
+  }
+  __syncthreads();
+  store_rows(0);
+}
+
 // Sum over the 64 lanes of a wave of each of 16 values: after the call lane
 // l holds (bitwise the same in the four lanes of its quad) the wave total of
 // value col(l) = 8 [l & 32] + 4 [l & 16] + 2 [l & 8] + [l & 4]: at each
@@ -749,6 +888,7 @@ hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *T, cons
   else if (sl <= 4) hipLaunchKernelGGL(qr_panel_reg_kernel<4>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= 8) hipLaunchKernelGGL(qr_panel_reg_kernel<8>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_reg_kernel<16>, g, b, 0, s, TTM_PANEL_ARGS);
+  else if (sl <= 2 * MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_ext_kernel, g, b, 0, s, TTM_PANEL_ARGS);
   else hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, TTM_PANEL_ARGS);
 #undef TTM_PANEL_ARGS
   return hipGetLastError();

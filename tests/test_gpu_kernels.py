@@ -110,7 +110,8 @@ def test_gemm_strided_operands_and_split_output():
     assert np.allclose(dC.cpu().numpy().reshape(30, 11), At.T @ dB.cpu().numpy(), rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (3, 3), (37, 11), (11, 37), (300, 64), (1024, 128), (2500, 40)])
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 3), (37, 11), (11, 37), (300, 64), (1024, 128), (1100, 100),
+                                 (1500, 40), (2048, 48), (2500, 40)])
 def test_qr(m, n):
     torch, L = _env()
     _say("qr %d %d" % (m, n))
@@ -148,7 +149,7 @@ def _svd(torch, L, M, eps=0.0, cap=0, forced=0, left_pow=1, right_pow=0):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (1, 5), (2, 2), (3, 3), (9, 3), (50, 30), (30, 50), (200, 200),
-                                 (300, 290), (700, 520), (257, 1100), (300, 8192)])
+                                 (300, 290), (700, 520), (257, 1100), (300, 8192), (2100, 1500), (1500, 2100)])
 def test_svd_full_rank(m, n):
     torch, L = _env()
     _say("svd %d %d" % (m, n))
