@@ -39,6 +39,19 @@ int ttm_test_gemm_prec(int prec, int M, int N, int K, const double *A, int64_t a
 size_t ttm_test_qr_scratch(int m, int n);
 int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scratch, void *stream);
 
+/* In-place Householder QR with block column pivoting of the m x n
+ * column-major matrix S (device, ld m), n <= 8192: before each 16-column
+ * panel the 16 remaining columns of largest norm (over the rows not yet
+ * reduced) move into it in decreasing order.  On return the upper trapezoid
+ * of S is R with S_in P = Q R; perm (device, n ints) is permuted along with
+ * the columns (perm[j] = the entry that was at position j of the input
+ * array), so starting from the identity it gives P.  The SVD path does not
+ * pivot (the presorted column order costs less overall); this hook keeps
+ * the option tested.  scratch: device, ttm_test_qr_pivoted_scratch(m, n)
+ * doubles. */
+size_t ttm_test_qr_pivoted_scratch(int m, int n);
+int ttm_test_qr_pivoted(double *S, int m, int n, int *perm, double *scratch, void *stream);
+
 /* Truncated SVD of the m x n row-major matrix M (device) by the swap's SVD
  * path (column ordering, Householder QR, one-sided block Jacobi on R^T) and
  * the rule of Eq. (eps) (cap > 0 caps the rank, forced > 0 replaces the

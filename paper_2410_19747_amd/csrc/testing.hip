@@ -50,6 +50,18 @@ int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scr
   return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
 }
 
+size_t ttm_test_qr_pivoted_scratch(int m, int n) {
+  if (m < 1 || n < 1) return 0;
+  return ttm::qr_inplace_scratch_doubles(m, n);
+}
+
+int ttm_test_qr_pivoted(double *S, int m, int n, int *perm, double *scratch, void *stream) {
+  if (m < 1 || n < 1 || !S || !perm || !scratch) return TTM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ttm::launch_qr_inplace(S, m, n, scratch, perm, nullptr, s) != hipSuccess) return TTM_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
+}
+
 size_t ttm_test_svd_ws_bytes(int m, int n) {
   if (m < 1 || n < 1) return 0;
   // the larger of the two orientations, plus a transposed copy of M

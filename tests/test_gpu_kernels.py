@@ -223,3 +223,28 @@ def test_svd_rank_deficient_and_zero():
     Z = np.zeros((6, 4))
     left, right, s, r, _ = _svd(torch, L, Z, eps=1e-12)
     assert r == 1 and np.all(s == 0.0)
+
+
+@pytest.mark.parametrize("m,n", [(300, 200), (1500, 1100), (2500, 600)])
+def test_qr_block_pivoting(m, n):
+    """launch_qr_inplace with block column pivoting (register, register + LDS
+    and memory panels): S P = Q R, so R^T R equals the Gram matrix of the
+    permuted columns, and the first pivot is the column of largest norm."""
+    torch, L = _env()
+    _say("qr pivoted %d %d" % (m, n))
+    rng = np.random.default_rng(m + 3 * n)
+    M = rng.standard_normal((m, n)) * np.exp(rng.uniform(-6, 6, n))[None, :]
+    dS = torch.tensor(M.T.copy().reshape(-1), dtype=torch.float64, device="cuda")  # column-major
+    perm = torch.arange(n, dtype=torch.int32, device="cuda")
+    scratch = torch.zeros(int(L.ttm_test_qr_pivoted_scratch(m, n)), dtype=torch.float64, device="cuda")
+    assert L.ttm_test_qr_pivoted(_ptr(dS), m, n, _ptr(perm), _ptr(scratch), None) == 0
+    S = dS.cpu().numpy().reshape(n, m).T
+    P = perm.cpu().numpy()
+    assert sorted(P.tolist()) == list(range(n))
+    k = min(m, n)
+    R = np.triu(S[:k, :])
+    MP = M[:, P]
+    G = MP.T @ MP
+    assert np.abs(R.T @ R - G).max() <= 1e-12 * np.abs(G).max()
+    norms = np.linalg.norm(M, axis=0)
+    assert abs(abs(R[0, 0]) - norms.max()) <= 1e-12 * norms.max()
