@@ -207,7 +207,7 @@ def main():
             roofline["traffic_gbs"] = roofline["traffic"] / avg_launch_s / 1e9
         kernel_share = {k: sum(s["kernel_ms"][k] for s in pstats) / tot_ms for k in st["kernel_ms"]}
 
-    # The conventional chi^4 variational product of the same inputs (config 2 compares the two):
+    # The conventional chi^4 variational product of the same inputs, for comparison:
     # time per call, sweeps, and its distance from the TTM result.
     conv = None
     if not args.no_conventional:
