@@ -775,27 +775,30 @@ __global__ __launch_bounds__(JNT) void jacobi_sigma_kernel(const double *__restr
 }
 
 // perm[k] = the column holding the k-th largest value (ties by index).
+// The position of value c is the count of values ahead of it (larger, or
+// equal at a lower index); eight lanes share that count for one value, lane
+// q taking j = q, q + 8, ... (neighbouring LDS words, so no bank conflicts),
+// and three lane exchanges add their counts.
+constexpr int SORT_SPLIT = 8;
 __global__ __launch_bounds__(JNT) void jacobi_sort_kernel(const double *__restrict__ sigma, int nc,
                                                           int *__restrict__ perm) {
   extern __shared__ double sv[];
   for (int i = threadIdx.x; i < nc; i += JNT) sv[i] = sigma[i];
   __syncthreads();
-  const int c = blockIdx.x * JNT + threadIdx.x;
-  if (c >= nc) return;
-  const double me = sv[c];
-  // Position = number of values ahead of this one (larger, or equal at a
-  // lower index); LDS read in pairs, eight values per iteration.
-  auto ahead = [&](double o, int j) { return (int)((o > me) | ((o == me) & (j < c))); };
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  const d2 *s2 = reinterpret_cast<const d2 *>(sv);
-  int pos = 0, j = 0;
-  for (; j + 8 <= nc; j += 8) {
-    const d2 a = s2[j / 2], b = s2[j / 2 + 1], e = s2[j / 2 + 2], f = s2[j / 2 + 3];
-    pos += (ahead(a.x, j) + ahead(a.y, j + 1)) + (ahead(b.x, j + 2) + ahead(b.y, j + 3)) +
-           (ahead(e.x, j + 4) + ahead(e.y, j + 5)) + (ahead(f.x, j + 6) + ahead(f.y, j + 7));
+  const int c = blockIdx.x * (JNT / SORT_SPLIT) + threadIdx.x / SORT_SPLIT;
+  const int q = threadIdx.x % SORT_SPLIT;
+  const int cc = c < nc ? c : nc - 1;
+  const double me = sv[cc];
+  int pos = 0;
+#pragma unroll 4
+  for (int j = q; j < nc; j += SORT_SPLIT) {
+    const double o = sv[j];
+    pos += (int)((o > me) | ((o == me) & (j < cc)));
   }
-  for (; j < nc; ++j) pos += ahead(sv[j], j);
-  perm[pos] = c;
+  pos += __shfl_xor(pos, 1, 64);
+  pos += __shfl_xor(pos, 2, 64);
+  pos += __shfl_xor(pos, 4, 64);
+  if (c < nc && q == 0) perm[pos] = c;
 }
 
 // Rule of Eq. (eps) on the sorted values.  One workgroup of 1024 threads:
@@ -890,7 +893,8 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
   hipLaunchKernelGGL(jacobi_sigma_kernel, dim3((nc + 3) / 4), dim3(JNT), 0, s, b.W, p.L, nc, b.sigma);
   const size_t shm = (size_t)nc * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((nc + JNT - 1) / JNT), dim3(JNT), shm, s, b.sigma, nc,
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((nc + JNT / SORT_SPLIT - 1) / (JNT / SORT_SPLIT)), dim3(JNT), shm, s,
+                     b.sigma, nc,
                      b.perm);
   if (nc > 1024 * RANK_PER) return hipErrorInvalidValue;
   const double noise = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;  // as in the sweeps
@@ -929,7 +933,8 @@ hipError_t launch_column_norms(const double *W, int L, int nc, double *out, hipS
 hipError_t launch_sort_desc(const double *v, int n, int *perm, hipStream_t s) {
   const size_t shm = (size_t)n * sizeof(double);
   if (shm > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + JNT - 1) / JNT), dim3(JNT), shm, s, v, n, perm);
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + JNT / SORT_SPLIT - 1) / (JNT / SORT_SPLIT)), dim3(JNT), shm, s,
+                     v, n, perm);
   return hipGetLastError();
 }
 
