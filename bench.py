@@ -25,6 +25,9 @@ contractions): one JSON line per run.
 
 ``--adjoint`` measures the gradient of <W, A*B> with respect to the cores
 of A and B (ttm_inner_grad) on the 1024^3 chi = 128 QTTs.
+
+``--binary-sites`` runs the bench product with the field encoded as the
+paper's binary QTT (d = 2 sites) beside the d = 8 encoding.
 """
 from __future__ import annotations
 
@@ -98,6 +101,8 @@ def main():
                     help="products in flight (streams) for the batched runs, comma list")
     ap.add_argument("--batch-precisions", default="f64,f32",
                     help="contraction arithmetic of the batched runs (f64 first)")
+    ap.add_argument("--binary-sites", action="store_true",
+                    help="the bench field as a binary QTT (3 log2 n sites, d = 2) beside the d = 8 one")
     ap.add_argument("--adjoint", action="store_true",
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     args = ap.parse_args()
@@ -123,6 +128,8 @@ def main():
         return batched(args, dev)
     if args.adjoint:
         return adjoint(args, dev)
+    if args.binary_sites:
+        return binary_sites(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -523,6 +530,63 @@ def adjoint(args, dev):
         print(json.dumps(line), flush=True)
         _log("  %s: %.2f ms per gradient, %.2f TFLOP/s algorithmic, rel err vs oracle %s"
              % (prec, 1e3 * dt, flops / dt / 1e12, "%.2e" % err if err is not None else "-"))
+    return None
+
+
+def binary_sites(args, dev):
+    """The bench field (grid --grid, seed 101) squared at chi = --chi in two
+    encodings: sites of d = 8 (bits x_s, y_s, z_s together) and the paper's
+    binary sites (each split in three, d = 2).  Time per product, swap and
+    sweep counts, sampled error against the exact square of each input, and
+    for the binary one the relative error against the oracle.  One JSON
+    line per encoding."""
+    import numpy as np
+    import torch
+
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    n, chi = args.grid, args.chi
+    L = int(round(np.log2(n)))
+    _log("generating the %d^3 field as d = 8 and binary QTTs at chi %d" % (n, chi))
+    enc = {8: I.turbulence_qtt_device(n, 101, [chi], dev)[chi], 2: I.turbulence_qtt_binary_device(n, 101, chi, dev)}
+    torch.cuda.empty_cache()
+    g = torch.Generator(device="cpu")
+    g.manual_seed(7)
+    eta = torch.randint(0, 8, (4096, L), generator=g)
+    bits = torch.stack([(eta >> 2) & 1, (eta >> 1) & 1, eta & 1], dim=2).reshape(4096, 3 * L)
+    idx = {8: eta.to(dev), 2: bits.to(dev)}
+    for d in (8, 2):
+        q = enc[d]
+        A = T.pack(q, dev)
+        ws = T.Workspace(dev)
+        T.multiply(A, A, chi, args.eps, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            C, st = T.multiply(A, A, chi, args.eps, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        exact = _tt_entries(A.cores(), idx[d]) ** 2
+        got = _tt_entries(C.cores(), idx[d])
+        rel = float(torch.linalg.norm(got - exact) / torch.linalg.norm(exact))
+        oracle_err = None
+        oracle_s = None
+        if d == 2 and not args.no_cpu:
+            import oracle as O
+            t0 = time.perf_counter()
+            o = O.ttm(q, q, chi, args.eps)
+            oracle_s = time.perf_counter() - t0
+            oracle_err = float(O.rel_frob([c.detach().cpu().numpy() for c in C.cores()], o.cores))
+        line = {"binary_sites": d == 2, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=%d"
+                % (n, len(q), d), "chi": chi, "eps": args.eps, "ms_per_product": 1e3 * dt,
+                "products_per_s": 1.0 / dt, "n_swap": st["n_swap"], "n_svd": st["n_svd"],
+                "jacobi_sweeps": st["sweeps"], "max_bond": st["max_bond"], "model_flops": st["model_flops"],
+                "sampled_rel_err_vs_exact": rel, "rel_err_vs_oracle": oracle_err, "cpu_oracle_s": oracle_s}
+        print(json.dumps(line), flush=True)
+        _log("  d=%d (%d sites): %.1f ms per product, %d swaps, %d sweeps, sampled rel err %.3e%s"
+             % (d, len(q), 1e3 * dt, st["n_swap"], st["sweeps"], rel,
+                "" if oracle_err is None else ", vs oracle %.2e (oracle %.1f s)" % (oracle_err, oracle_s)))
     return None
 
 

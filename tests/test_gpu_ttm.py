@@ -210,3 +210,17 @@ def test_gpu_eps_zero_keeps_only_resolved_values():
     assert len(st["ranks"]) == len(o.ranks)
     assert all(g <= r for g, r in zip(st["ranks"], o.ranks))
     assert max(st["ranks"]) < max(o.ranks)
+
+
+def test_gpu_binary_qtt_turbulence_vs_oracle():
+    """The paper's binary encoding: a 32^3 field as 15 sites of d = 2 at
+    chi = 16 (105 swaps on 32 x 32 matrices) against the oracle."""
+    torch = _torch()
+    _say("case: binary QTT 32^3, 15 sites, chi=16")
+    q = I.turbulence_qtt_binary_device(32, 101, 16, torch.device("cuda", 0))
+    assert len(q) == 15 and all(c.shape[1] == 2 for c in q)
+    o = O.ttm(q, q, 16, 1e-14)
+    C, st = _run(q, q, 16, 1e-14)
+    assert st["ranks"] == o.ranks
+    assert O.rel_frob(C, o.cores) <= TOL
+    assert st["n_swap"] == 105

@@ -57,3 +57,16 @@ def test_advective_bond_caps():
     for (A, B, chi), c in zip(prods, chis):
         assert chi == c
         assert max(x.shape[2] for x in A) <= c and max(x.shape[2] for x in B) <= c
+
+
+def test_binary_qtt_is_the_same_field():
+    """Uncapped, the binary QTT (three d = 2 sites per d = 8 site) and the
+    d = 8 QTT of the same seed decompress to the same tensor."""
+    import oracle as O
+    q8 = I.turbulence_qtt_device(16, 5, [0], "cpu")[0]
+    q2 = I.turbulence_qtt_binary_device(16, 5, 0, "cpu")
+    assert len(q8) == 4 and len(q2) == 12
+    assert all(c.shape[1] == 2 for c in q2)
+    d8 = O.dense(q8).reshape(-1)
+    d2 = O.dense(q2).reshape(-1)
+    assert np.abs(d8 - d2).max() <= 1e-12 * np.abs(d8).max()

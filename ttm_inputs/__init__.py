@@ -28,6 +28,7 @@ __all__ = [
     "tt_svd",
     "turbulence_qtt",
     "turbulence_qtt_device",
+    "turbulence_qtt_binary_device",
     "advective_qtts_device",
     "ADVECTIVE_CHIS",
     "app_a_toy_tt",
@@ -304,23 +305,23 @@ def _interleave_device(u):
     return t.contiguous().reshape(-1)
 
 
-def _tt_compress_device(field, L, chi):
-    """Left-to-right TT-SVD (d = 8 per site) of a flattened interleaved field
-    with at most ``chi`` values per bond, via the leading eigenvectors of each
-    unfolding's Gram matrix on its smaller side."""
+def _tt_compress_device(field, L, chi, d=8):
+    """Left-to-right TT-SVD (L sites of dimension d) of a flattened
+    interleaved field with at most ``chi`` values per bond, via the leading
+    eigenvectors of each unfolding's Gram matrix on its smaller side."""
     import torch
 
     cores = []
     rest = field.reshape(1, -1)
     r_left = 1
     for i in range(L - 1):
-        mat = rest.reshape(r_left * 8, -1)
+        mat = rest.reshape(r_left * d, -1)
         m, ncol = mat.shape
         r = min(m, ncol, chi) if chi and chi > 0 else min(m, ncol)
         if m <= ncol:
             _, evec = torch.linalg.eigh(mat @ mat.T)
             U = evec[:, -r:].flip(1).contiguous()
-            cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+            cores.append(U.reshape(r_left, d, r).cpu().numpy())
             rest = U.T @ mat
         else:
             _, evec = torch.linalg.eigh(mat.T @ mat)
@@ -328,10 +329,10 @@ def _tt_compress_device(field, L, chi):
             US = mat @ V
             s = torch.linalg.norm(US, dim=0)
             U = US / torch.where(s > 0, s, torch.ones_like(s))
-            cores.append(U.reshape(r_left, 8, r).cpu().numpy())
+            cores.append(U.reshape(r_left, d, r).cpu().numpy())
             rest = s[:, None] * V.T
         r_left = r
-    cores.append(rest.reshape(r_left, 8, 1).cpu().numpy())
+    cores.append(rest.reshape(r_left, d, 1).cpu().numpy())
     return cores
 
 
@@ -359,6 +360,23 @@ def turbulence_qtt_device(n, seed, chis, device, kprime=None):
     del u
     L = int(round(np.log2(n)))
     return {chi: _tt_compress_device(field, L, chi) for chi in chis}
+
+
+def turbulence_qtt_binary_device(n, seed, chi, device, kprime=None):
+    """The field of ``turbulence_qtt_device`` (same seed, same draws) as a
+    binary QTT: each d = 8 site (bits x_s, y_s, z_s) split into three sites
+    of dimension 2, 3 log2(n) sites in all, compressed at bond cap chi.  The
+    flattened interleaved order is the same, so only the TT-SVD differs."""
+    import torch
+
+    uk, _, _ = _spectrum_device(n, seed, kprime, device)
+    u = torch.fft.irfftn(uk, s=(n, n, n))
+    del uk
+    u /= torch.sqrt(torch.mean(u * u))
+    field = _interleave_device(u)
+    del u
+    L = int(round(np.log2(n)))
+    return _tt_compress_device(field, 3 * L, chi, d=2)
 
 
 ADVECTIVE_CHIS = (512, 128, 64, 256, 32, 128, 64, 256, 32)
