@@ -194,8 +194,7 @@ hipError_t launch_frob_from_norms(const double *x, int n, double *result, hipStr
 // whose factor U_r (no x r) must have orthonormal columns: U_r holds the
 // leading right singular vectors of Y and Z = Y U_r = U_Y,r S_r.  With
 // X = Y^T (no x np):
-//   1. the columns of X are ordered by decreasing norm (block-pivoted in the
-//      QR from 2048 columns) and copied;
+//   1. the columns of X are ordered by decreasing norm and copied;
 //   2. Householder QR of the copy, X P = Q1 R1 (reflectors and T factors
 //      kept), then QR of R1^T = Q2 R2 (R2 only, k x k, k = min(np, no));
 //   3. one-sided Jacobi on W = R2^T until its columns are orthogonal: then
