@@ -78,8 +78,8 @@ def _cpu_threads():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chi", type=int, default=128)
     ap.add_argument("--eps", type=float, default=1e-14)
     ap.add_argument("--grid", type=int, default=256)
@@ -103,6 +103,8 @@ def main():
                     help="contraction arithmetic of the batched runs (f64 first)")
     ap.add_argument("--binary-sites", action="store_true",
                     help="the bench field as a binary QTT (3 log2 n sites, d = 2) beside the d = 8 one")
+    ap.add_argument("--mfma-peak", action="store_true",
+                    help="measure the FP64 matrix-core rate that the roofline quotes as its peak")
     ap.add_argument("--adjoint", action="store_true",
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     args = ap.parse_args()
@@ -130,6 +132,8 @@ def main():
         return adjoint(args, dev)
     if args.binary_sites:
         return binary_sites(args, dev)
+    if args.mfma_peak:
+        return mfma_peak(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -587,6 +591,34 @@ def binary_sites(args, dev):
         _log("  d=%d (%d sites): %.1f ms per product, %d swaps, %d sweeps, sampled rel err %.3e%s"
              % (d, len(q), 1e3 * dt, st["n_swap"], st["sweeps"], rel,
                 "" if oracle_err is None else ", vs oracle %.2e (oracle %.1f s)" % (oracle_err, oracle_s)))
+    return None
+
+
+def mfma_peak(args, dev):
+    """FP64 matrix-core rate measured on this device (eight independent
+    v_mfma_f64_16x16x4f64 chains per wave, 4096 workgroups of four waves),
+    beside the published peak that the roofline divides by."""
+    import ctypes
+
+    import torch
+
+    import paper_2410_19747_amd as T
+
+    L = T.lib()
+    blocks, iters = 4096, 10000
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    sec, fl = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    best = 0.0
+    for _ in range(3):
+        rc = L.ttm_test_mfma_f64_rate(blocks, iters, ctypes.c_void_p(out.data_ptr()), ctypes.byref(sec),
+                                      ctypes.byref(fl), None)
+        assert rc == 0, rc
+        best = max(best, fl.value / sec.value / 1e12)
+    assert bool(torch.isfinite(out).all())
+    line = {"mfma_f64_measured_tflops": best, "mfma_f64_published_tflops": FP64_MFMA_PEAK_TFLOPS,
+            "ratio": best / FP64_MFMA_PEAK_TFLOPS, "workgroups": blocks, "mfma_per_wave": 8 * iters}
+    print(json.dumps(line), flush=True)
+    _log("  FP64 MFMA measured %.1f TFLOP/s (published %.1f)" % (best, FP64_MFMA_PEAK_TFLOPS))
     return None
 
 

@@ -39,6 +39,14 @@ int ttm_test_gemm_prec(int prec, int M, int N, int K, const double *A, int64_t a
 size_t ttm_test_qr_scratch(int m, int n);
 int ttm_test_qr(const double *M, int m, int n, double *Q, double *R, double *scratch, void *stream);
 
+/* Rate of the FP64 matrix cores (v_mfma_f64_16x16x4f64) on this device:
+ * `blocks` workgroups of four waves, each wave running eight independent
+ * chains of `iters` MFMAs on register operands.  Writes the elapsed time
+ * (HIP events on the stream) and the flops done (blocks * 4 * iters * 8 *
+ * 2048) on the host; out (device, blocks * 256 doubles) receives the
+ * accumulator sums.  It measures the peak that the roofline quotes. */
+int ttm_test_mfma_f64_rate(int blocks, int iters, double *out, double *seconds, double *flops, void *stream);
+
 /* In-place Householder QR with block column pivoting of the m x n
  * column-major matrix S (device, ld m), n <= 8192: before each 16-column
  * panel the 16 remaining columns of largest norm (over the rows not yet

@@ -131,6 +131,8 @@ TESTING_PROTOTYPES = {
     "ttm_test_gemm_prec": (ctypes.c_int, [ctypes.c_int] * 4 + [_VP, _I64, _I64, _VP, _I64, _I64, _VP, _I64, _VP]),
     "ttm_test_qr_scratch": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "ttm_test_qr": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP]),
+    "ttm_test_mfma_f64_rate": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), _VP]),
     "ttm_test_qr_pivoted_scratch": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "ttm_test_qr_pivoted": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP]),
     "ttm_test_svd_ws_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),

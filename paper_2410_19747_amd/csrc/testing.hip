@@ -6,7 +6,52 @@
 #include "../../include/ttm_testing.h"
 #include "ttm_internal.h"
 
+namespace {
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+// FP64 matrix-core rate probe: every wave runs eight independent chains of
+// v_mfma_f64_16x16x4f64 (2048 flops each) on register operands, so the
+// issue rate of the matrix cores is the only limit; the accumulators are
+// written out so that nothing is optimised away.
+__global__ __launch_bounds__(256) void mfma_f64_rate_kernel(int iters, double *__restrict__ out) {
+  const double a = 1.0 + 1e-3 * (threadIdx.x & 63), b = 1.0 - 1e-3 * (threadIdx.x & 63);
+  constexpr int CH = 8;
+  dbl4_t acc[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) acc[k] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) sum += (acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3]);
+  out[blockIdx.x * 256 + threadIdx.x] = sum;
+}
+}  // namespace
+
 extern "C" {
+
+int ttm_test_mfma_f64_rate(int blocks, int iters, double *out, double *seconds, double *flops, void *stream) {
+  if (blocks < 1 || blocks > 65535 || iters < 1 || !out || !seconds || !flops) return TTM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TTM_EHIP;
+  int rc = TTM_OK;
+  float ms = 0.0f;
+  if (hipEventRecord(e0, s) != hipSuccess) rc = TTM_EHIP;
+  if (rc == TTM_OK) {
+    hipLaunchKernelGGL(mfma_f64_rate_kernel, dim3(blocks), dim3(256), 0, s, iters, out);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = TTM_EHIP;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *seconds = 1e-3 * ms;
+  *flops = (double)blocks * 4 /* waves */ * iters * 8 /* chains */ * 2048.0;
+  return rc;
+}
 
 int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs, int64_t a_cs,
                   int64_t a_bs, const double *B, int64_t b_rs, int64_t b_cs, int64_t b_bs,

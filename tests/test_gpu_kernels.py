@@ -248,3 +248,18 @@ def test_qr_block_pivoting(m, n):
     assert np.abs(R.T @ R - G).max() <= 1e-12 * np.abs(G).max()
     norms = np.linalg.norm(M, axis=0)
     assert abs(abs(R[0, 0]) - norms.max()) <= 1e-12 * norms.max()
+
+
+def test_mfma_f64_rate_probe():
+    """The FP64 matrix-core probe runs, writes finite sums, and reports a
+    rate of the order of the published peak."""
+    torch, L = _env()
+    _say("mfma f64 rate probe")
+    out = torch.empty(512 * 256, dtype=torch.float64, device="cuda")
+    sec, fl = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    assert L.ttm_test_mfma_f64_rate(512, 2000, _ptr(out), ctypes.byref(sec), ctypes.byref(fl), None) == 0
+    assert bool(torch.isfinite(out).all())
+    assert fl.value == 512 * 4 * 2000 * 8 * 2048.0
+    rate = fl.value / sec.value / 1e12
+    _say("  %.1f TFLOP/s" % rate)
+    assert 5.0 < rate < 200.0
