@@ -182,7 +182,9 @@ int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double to
  * is a chain of small dependent launches, so products overlap only on
  * distinct hardware queues; the streams are created with a CU mask of every
  * CU, which gives each a hardware queue of its own rather than one of the
- * runtime's shared default queues.  Each product's result is the one
+ * runtime's shared default queues.  The streams (and their queues) are
+ * created and destroyed within each call, so the call suits batches whose
+ * products take milliseconds or more.  Each product's result is the one
  * ttm_multiply_ex gives for the same arguments.
  * Checks: every product is validated (as ttm_query, plus the workspace and
  * output sizes and a finite tol >= 0) before any starts, and workspaces and
