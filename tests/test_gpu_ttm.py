@@ -224,3 +224,32 @@ def test_gpu_binary_qtt_turbulence_vs_oracle():
     assert st["ranks"] == o.ranks
     assert O.rel_frob(C, o.cores) <= TOL
     assert st["n_swap"] == 105
+
+
+@pytest.mark.parametrize("eps,chi_a,chi_b,chi_out,chi_mid,final_round", [
+    (1e-12, 64, 64, 64, None, True),      # the paper's largest eps
+    (1e-16, 64, 64, 64, None, True),      # and its smallest
+    (1e-14, 64, 32, 48, None, True),      # uneven inputs, chi_out between them
+    (1e-14, 48, 48, 32, 64, True),        # swaps capped above chi_out; the final sweep truncates
+    (1e-14, 48, 48, 48, None, False),     # no final rounding sweep
+])
+def test_gpu_options_turbulence_vs_oracle(eps, chi_a, chi_b, chi_out, chi_mid, final_round):
+    """The 256^3 turbulence product u_x * u_y under the option space: the
+    paper's eps values, uneven input bonds, a swap cap above chi_out, and no
+    final rounding sweep; ranks and cores against the oracle run with the
+    same options (the oracle's rank schedule forced where eps could flip a
+    rank on rounding noise, and the unforced ranks must then agree)."""
+    _say("case: 256^3 options eps=%g chiA=%d chiB=%d chi_out=%d chi_mid=%s final=%s"
+         % (eps, chi_a, chi_b, chi_out, chi_mid, final_round))
+    A = I.turbulence_qtt(256, 101, chi_a)
+    B = I.turbulence_qtt(256, 102, chi_b)
+    o = O.ttm(A, B, chi_out, eps, chi_mid=chi_mid, final_round=final_round)
+    kw = {"final_round": final_round}
+    if chi_mid is not None:
+        kw["chi_mid"] = chi_mid
+    C, st = _run(A, B, chi_out, eps, forced_ranks=o.ranks, **kw)
+    assert O.rel_frob(C, o.cores) <= TOL
+    C2, st2 = _run(A, B, chi_out, eps, **kw)
+    assert st2["ranks"] == o.ranks
+    assert O.rel_frob(C2, o.cores) <= TOL
+    assert max(c.shape[2] for c in C2) <= (chi_out if final_round else (chi_mid or chi_out))
