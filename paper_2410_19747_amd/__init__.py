@@ -8,6 +8,7 @@ The functions mirror the C entry points of ``include/ttm.h``:
     conventional(A, B, chi_out, tol, **options)   -> conventional_multiply_ex
     query(A, B, chi_out, **options)               -> ttm_query
     multiply_batch(pairs, chi_out, tol, ...)      -> ttm_multiply_batch
+    tune_batch_streams(pairs, chi_out, tol)       -> products in flight, by timing
     inner_grad(W, A, B)                           -> ttm_inner_grad
     ttm_inner_loss(W, A, B, chi_out, tol)         -> torch.autograd.Function over
                                                      ttm_multiply_ex + ttm_inner_grad
@@ -27,7 +28,8 @@ from ._abi import (  # noqa: F401
 )
 
 __all__ = [
-    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "inner_grad", "ttm_inner_loss",
+    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "tune_batch_streams", "inner_grad",
+    "ttm_inner_loss",
     "conventional", "query", "conventional_query",
     "Workspace", "lib",
 ]
@@ -404,3 +406,31 @@ def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
         _INNER_LOSS = _make_inner_loss_function()
     W, A, B = pack(W), pack(A), pack(B)
     return _INNER_LOSS.apply(A.data, B.data, A, B, W, int(chi_out), float(tol), contract_precision, opts)
+
+
+def tune_batch_streams(pairs, chi_out, tol, candidates=(2, 4, 8), repeats=1, **opts):
+    """Products in flight for ttm_multiply_batch, chosen by measurement: each
+    candidate stream count runs the whole batch `repeats` times and the
+    fastest wins.  For a batch that recurs (the nine advective products of
+    every time step) the tuning cost is paid once.  Returns (best, {streams:
+    seconds per batch}); every candidate's results are discarded."""
+    import time
+
+    import torch
+
+    packed = [(pack(a), pack(b)) for a, b in pairs]
+    wss = [Workspace(packed[0][0].data.device) for _ in packed]
+    times = {}
+    for k in candidates:
+        k = int(k)
+        if k < 1:
+            continue
+        multiply_batch(packed, chi_out, tol, streams=k, workspaces=wss, **opts)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(max(1, int(repeats))):
+            multiply_batch(packed, chi_out, tol, streams=k, workspaces=wss, **opts)
+        torch.cuda.synchronize()
+        times[k] = (time.perf_counter() - t) / max(1, int(repeats))
+    best = min(times, key=times.get)
+    return best, times

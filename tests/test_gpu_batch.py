@@ -134,3 +134,20 @@ def test_gpu_batch_mixed_shapes_and_precisions():
     # the exact one against brute force
     (A, B) = pairs[0]
     assert O.rel_frob(_host(batch[0][0]), O.brute_force(A, B)) <= TOL
+
+
+def test_gpu_batch_stream_tuner():
+    """The stream-count tuner times each candidate and returns one of them;
+    the batch run with its choice still equals the single calls."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: batch stream tuner")
+    pairs, chis = _random_pairs()
+    best, times = T.tune_batch_streams(pairs, chis, 1e-14, candidates=(1, 2, 4))
+    assert best in (1, 2, 4) and set(times) == {1, 2, 4}
+    assert all(t > 0 for t in times.values())
+    batch = T.multiply_batch(pairs, chis, 1e-14, streams=best)
+    for (A, B), c, (Cb, _) in zip(pairs, chis, batch):
+        Cs, _ = T.multiply(A, B, c, 1e-14)
+        for x, y in zip(_host(Cb), _host(Cs)):
+            assert np.array_equal(x, y)
