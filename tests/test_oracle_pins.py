@@ -263,12 +263,60 @@ def test_truncated_error_between_bounds():
         assert err >= np.sqrt(np.sum(s[8:] ** 2)) * (1 - 1e-10)
 
 
+def test_truncated_error_between_bounds_uncapped_swaps():
+    """chi_mid = 0 (reading R5): the swaps keep every value the rule of Eq.
+    (eps) keeps, and only the final sweep (reading R6) caps the bonds."""
+    A, B = _r10()
+    ref = O.brute_force(A, B)
+    res = O.ttm(A, B, 8, 1e-14, chi_mid=0)
+    assert max(O.bonds_of(res.cores)) <= 8
+    assert max(res.ranks[:45]) > 8
+    err = O.rel_frob(res.cores, ref) * np.linalg.norm(ref)
+    assert err <= res.error_bound * (1 + 1e-10) + 1e-15
+    for k in range(1, 10):
+        s = np.linalg.svd(ref.reshape(2 ** k, -1), compute_uv=False)
+        assert err >= np.sqrt(np.sum(s[8:] ** 2)) * (1 - 1e-10)
+
+
+def _regauge(T, rng, spread=1.5):
+    """The same tensor with G_k G_k^-1 inserted at every inner bond; each G_k
+    is a random rotation times a scaling over 2*spread decades, times a
+    rotation."""
+    T = [np.array(c, copy=True) for c in T]
+    for k in range(len(T) - 1):
+        r = T[k].shape[2]
+        q1, _ = np.linalg.qr(rng.standard_normal((r, r)))
+        q2, _ = np.linalg.qr(rng.standard_normal((r, r)))
+        g = q1 @ np.diag(np.logspace(-spread, spread, r)) @ q2
+        T[k] = np.tensordot(T[k], g, axes=(2, 0))
+        T[k + 1] = np.tensordot(np.linalg.inv(g), T[k + 1], axes=(1, 0))
+    return T
+
+
+def test_gauge_invariance_of_the_product():
+    """The product depends on the tensors A and B, not on the gauge of their
+    carriages: the inputs are brought to canonical form before the swaps
+    (Sec. II.B, the gauge requirement), so a far-from-orthogonal change of
+    gauge at every bond leaves the ranks and the truncated result unchanged
+    up to rounding."""
+    A, B = _r10()
+    rng = np.random.default_rng(77)
+    Ag, Bg = _regauge(A, rng), _regauge(B, rng)
+    assert O.rel_frob(Ag, O.dense(A)) <= 1e-10 and O.rel_frob(Bg, O.dense(B)) <= 1e-10
+    r1 = O.ttm(A, B, 8, 1e-14)
+    r2 = O.ttm(Ag, Bg, 8, 1e-14)
+    assert r2.ranks == r1.ranks
+    assert O.rel_frob(r2.cores, r1.cores) <= 1e-9
+
+
 def test_forced_ranks_reproduce_schedule():
     A, B = _r10()
     r1 = O.ttm(A, B, 8, 1e-10)
     r2 = O.ttm(A, B, 8, 0.5, forced_ranks=r1.ranks)
     assert r2.ranks == r1.ranks
     assert O.rel_frob(r2.cores, r1.cores) <= 1e-13
+    # the weight a forced rank discards is the tail of Eq. (eps) at that rank
+    assert np.allclose(r2.discards, r1.discards, rtol=1e-10, atol=0.0)
 
 
 def test_tt_sub_and_rel_frob_modes():
@@ -308,8 +356,8 @@ def test_variational_truncated_quality():
 
 
 def test_splitmix64_published_outputs():
-    from oracle.conventional import _splitmix64, _GAMMA, _MASK
-    outs = [_splitmix64((0 + k * _GAMMA) & _MASK) for k in (1, 2, 3)]
+    C = O.conventional
+    outs = [C._splitmix64((0 + k * C._GAMMA) & C._MASK) for k in (1, 2, 3)]
     assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     u = O.splitmix64_uniform(7, 1000)
     assert u.min() >= -1.0 and u.max() < 1.0 and abs(u.mean()) < 0.1
