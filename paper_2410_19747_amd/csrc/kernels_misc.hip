@@ -5,9 +5,19 @@ namespace ttm {
 
 // ---------------------------------------------------------------- kernel timer
 namespace {
+// One pool per host thread, reused across calls made on that thread.  A
+// batched call runs its products on worker threads that end with the call:
+// their pools destroy their events as the thread exits (every event is
+// complete by then, since each call collects its times before returning).
 struct EventPool {
   hipEvent_t ev[2 * 4096];
   int n = 0;  // events created
+  EventPool() = default;
+  EventPool(const EventPool &) = delete;
+  EventPool &operator=(const EventPool &) = delete;
+  ~EventPool() {
+    for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+  }
 };
 EventPool &pool() {
   static thread_local EventPool p;

@@ -151,3 +151,20 @@ def test_gpu_batch_stream_tuner():
         Cs, _ = T.multiply(A, B, c, 1e-14)
         for x, y in zip(_host(Cb), _host(Cs)):
             assert np.array_equal(x, y)
+
+
+def test_gpu_batch_profiled_calls_repeat():
+    """Per-kernel timing inside a batch: each worker thread's events are
+    released when the call's threads end, so profiled batches can repeat;
+    every product reports kernel times and equals the unprofiled one."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: repeated profiled batches")
+    pairs, chis = _random_pairs()
+    plain = T.multiply_batch(pairs, chis, 1e-14, streams=4)
+    for rep in range(12):
+        res = T.multiply_batch(pairs, chis, 1e-14, streams=4, profile=True)
+        for (Cp, sp), (Cq, _) in zip(res, plain):
+            assert sum(sp["kernel_ms"].values()) > 0.0, rep
+            for x, y in zip(_host(Cp), _host(Cq)):
+                assert np.array_equal(x, y), rep
