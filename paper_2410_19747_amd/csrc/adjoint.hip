@@ -62,8 +62,16 @@ GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
   const int n = W->n_sites;
   p.n = n;
   p.env_off.resize(n + 1);
+  // GEMM extents are ints and every buffer holds at most 2^36 doubles (beyond
+  // any device memory); each limit is checked before the products it bounds,
+  // so no size below can overflow.  Bonds are at most 2^20, dimensions 2^16.
+  const int64_t lim = (int64_t)1 << 30, max_entries = (int64_t)1 << 36;
   auto env = [&](int k) { return (int64_t)W->bonds[k] * A->bonds[k] * B->bonds[k]; };
   for (int k = 0; k <= n; ++k) {
+    if (env(k) > max_entries) {
+      p.fits = false;
+      return p;
+    }
     p.env_off[k] = p.env_total;
     p.env_total += (int64_t)r32(env(k));
     p.env_max = std::max(p.env_max, env(k));
@@ -71,15 +79,20 @@ GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
   for (int k = 0; k < n; ++k) {
     const int64_t d = W->phys[k], rw = W->bonds[k], rw2 = W->bonds[k + 1];
     const int64_t ra = A->bonds[k], ra2 = A->bonds[k + 1], rb = B->bonds[k], rb2 = B->bonds[k + 1];
-    p.x_max = std::max({p.x_max, d * ra * rb * rw2, d * ra2 * rw * rb2});
-    p.y_max = std::max({p.y_max, rb * d * rw2 * ra2, rw * ra * d * rb2});
-    p.v_max = std::max(p.v_max, d * rb * rw2 * ra2);
-    p.part = std::max({p.part, d * ra * ra2, d * rb * rb2, rw2 * ra2 * rb2, rw * ra * rb});
-    // GEMM extents are ints; the largest are ra*rb, rw2*ra2, d*rw2 and d*ra2*rb2.
-    const int64_t lim = (int64_t)1 << 30;
     if (ra * rb > lim || rw2 * ra2 > lim || d * rw2 > lim || ra2 * rb2 > lim || rw * ra > lim ||
-        rw * d > lim || rb * d > lim || rb * rw2 > lim || rw * rb2 > lim || d * rb2 > lim)
+        rw * d > lim || rb * d > lim || rb * rw2 > lim || rw * rb2 > lim || d * rb2 > lim) {
       p.fits = false;
+      return p;
+    }
+    // Each product below is two of the checked pairs, so at most 2^60.
+    p.x_max = std::max({p.x_max, (d * rw2) * (ra * rb), (rw * d) * (ra2 * rb2)});
+    p.y_max = std::max({p.y_max, (rb * d) * (rw2 * ra2), (rw * ra) * (d * rb2)});
+    p.v_max = std::max(p.v_max, (rb * d) * (rw2 * ra2));
+    p.part = std::max({p.part, d * ra * ra2, d * rb * rb2, (rw2 * ra2) * rb2, (rw * ra) * rb});
+    if (p.x_max > max_entries || p.y_max > max_entries || p.part > max_entries) {
+      p.fits = false;
+      return p;
+    }
   }
   p.part *= kSplitSlices;
   p.ws_doubles = (size_t)p.env_total + 2 * r32(p.env_max) + r32(p.x_max) + r32(p.y_max) + r32(p.v_max) +

@@ -53,6 +53,15 @@ struct Options {
   int contract_prec = GEMM_F64;
 };
 
+// Largest matrix a QR or SVD step takes: each side at most 2^30 (the kernels
+// hold dimensions in 32-bit integers and form offsets in 64 bits) and at most
+// 2^36 entries, beyond any device memory, so that no size sum can wrap.
+constexpr int64_t kMaxSide = (int64_t)1 << 30;
+constexpr int64_t kMaxEntries = (int64_t)1 << 36;
+bool unfolding_ok(int64_t m, int64_t n) {
+  return m >= 1 && n >= 1 && m <= kMaxSide && n <= kMaxSide && m * n <= kMaxEntries;
+}
+
 int64_t sat_mul(int64_t a, int64_t b) {
   if (a >= kSat || b >= kSat) return kSat;
   int64_t p = a * b;
@@ -203,6 +212,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
   }
   auto qr_sweep = [&](std::vector<Shape> &t) {
     for (int i = 0; i + 1 < n; ++i) {
+      if (!unfolding_ok((int64_t)t[i].rl * t[i].d, t[i].rr)) return false;
       const int m = t[i].rl * t[i].d, nn = t[i].rr;
       note_qr(pl, m, nn);
       const int k = std::min(m, nn);
@@ -211,15 +221,16 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
       note_core(pl, t[i]);
       note_core(pl, t[i + 1]);
     }
+    return true;
   };
-  qr_sweep(a);
-  qr_sweep(b);
+  if (!qr_sweep(a) || !qr_sweep(b)) return TTM_EINVAL;
   std::vector<Shape> bt(n);
   for (int i = 0; i < n; ++i) bt[i] = {b[i].rr, b[i].d, b[i].rl};
   pi[n - 1] = {a[n - 1].rl, a[n - 1].d, bt[n - 1].rr};
   note_core(pl, pi[n - 1]);
   for (int j = n - 2; j >= 0; --j) {
     for (int p = j + 1; p <= n - 2; ++p) {
+      if (!unfolding_ok((int64_t)pi[p].rl * pi[p].d, pi[p].rr)) return TTM_EINVAL;
       const int m = pi[p].rl * pi[p].d, nn = pi[p].rr;
       note_qr(pl, m, nn);
       const int k = std::min(m, nn);
@@ -230,6 +241,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     }
     Shape x = bt[j];
     for (int p = n - 1; p > j; --p) {
+      if (!unfolding_ok((int64_t)pi[p].rl * x.d, (int64_t)pi[p].d * x.rr)) return TTM_EINVAL;
       const int m = pi[p].rl * x.d, nn = pi[p].d * x.rr;
       note_svd(pl, m, nn, true);
       const int r = swap_cap(o, pl.phys, j, p, pi[p], x);
@@ -245,6 +257,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
   }
   if (o.final_round) {
     for (int i = 0; i + 1 < n; ++i) {
+      if (!unfolding_ok((int64_t)pi[i].rl * pi[i].d, pi[i].rr)) return TTM_EINVAL;
       const int m = pi[i].rl * pi[i].d, nn = pi[i].rr;
       note_svd(pl, nn, m, false);
       const int r = round_cap(chi_out, pl.phys, i, pi[i]);
@@ -699,6 +712,7 @@ int make_conv_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, ConvPlan &pl) 
   pl.rsz.assign(n + 1, 1);
   for (int i = 0; i <= n; ++i) {
     const int64_t e = (int64_t)cb[i] * A->bonds[i] * B->bonds[i];
+    if (e > kMaxEntries) return TTM_EINVAL;
     pl.lsz[i] = e;
     pl.rsz[i] = e;
   }
@@ -706,6 +720,7 @@ int make_conv_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, ConvPlan &pl) 
     const int64_t cl = cb[i], cr = cb[i + 1], al = pl.a[i].rl, ar = pl.a[i].rr, bl = pl.b[i].rl,
                   br = pl.b[i].rr, d = pl.phys[i];
     pl.tmax = std::max(pl.tmax, std::max(cl * al * d * br, cl * d * ar * br));
+    if (!unfolding_ok(cl * d, cr) || !unfolding_ok(d * cr, cl)) return TTM_EINVAL;
     pl.qr_max = std::max<int64_t>(pl.qr_max, (int64_t)qr_scratch_doubles((int)(cl * d), (int)cr));
     pl.qr_max = std::max<int64_t>(pl.qr_max, (int64_t)qr_scratch_doubles((int)(d * cr), (int)cl));
     pl.rmax = std::max(pl.rmax, std::max(cl * d, cr) * std::max(cl, cr));

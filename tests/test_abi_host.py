@@ -244,3 +244,39 @@ def test_inner_grad_rejects_before_gpu_work(L):
     assert L.ttm_inner_grad(*args, 0, ctypes.byref(v), None, None, None, 1 << 20, None) == _abi.TTM_EWORKSPACE
     assert L.ttm_inner_grad(*args, 0, ctypes.byref(v), None, None, ctypes.c_void_p(0x1000), 16,
                             None) == _abi.TTM_EWORKSPACE
+
+
+def test_oversized_shapes_rejected_by_every_query(L):
+    """Shapes whose QR or SVD unfoldings exceed 2^30 on a side, or whose
+    buffers exceed 2^36 doubles, are rejected by the size queries with
+    TTM_EINVAL; the sizes are formed in 64 bits and checked before use."""
+    ws = ctypes.c_size_t(0)
+    cap = ctypes.c_int64(0)
+    big = 1 << 16
+    # The swap of the product merges a 2^16 bond with a 2^16 dimension: 2^32 rows.
+    A = _TT([big, big], [1, big, 1])
+    B = _TT([big, big], [1, 1, 1])
+    assert _query(L, A, B, 1 << 20)[0] == _abi.TTM_EINVAL
+    # Conventional: the initial guess's unfolding d * chi is 2^32 long.
+    R1 = _TT([big, big], [1, 1, 1])
+    assert L.conventional_query(ctypes.byref(R1.view), ctypes.byref(R1.view), big, None, ctypes.byref(ws),
+                                ctypes.byref(cap)) == _abi.TTM_EINVAL
+    # Conventional: environments of chi_C * chi_A * chi_B = 2^16 * 2^20 * 2^20 doubles.
+    Wide = _TT([2] * 44, [1] + [1 << 20] * 43 + [1])
+    assert L.conventional_query(ctypes.byref(Wide.view), ctypes.byref(Wide.view), big, None, ctypes.byref(ws),
+                                ctypes.byref(cap)) == _abi.TTM_EINVAL
+    # Gradient: environments of 2^60 doubles, then GEMM extents of 2^31.
+    G = _TT([big, big], [1, 1 << 20, 1])
+    assert L.ttm_inner_grad_query(ctypes.byref(G.view), ctypes.byref(G.view), ctypes.byref(G.view),
+                                  ctypes.byref(ws)) == _abi.TTM_EINVAL
+    H = _TT([big, big], [1, 1 << 15, 1])
+    One = _TT([big, big], [1, 1, 1])
+    assert L.ttm_inner_grad_query(ctypes.byref(One.view), ctypes.byref(One.view), ctypes.byref(H.view),
+                                  ctypes.byref(ws)) == _abi.TTM_EINVAL
+    # The largest shapes the bond-dimension sweep uses still size normally.
+    b10 = [1, 8, 64, 512, 1024, 1024, 1024, 512, 64, 8, 1]
+    S = _TT([8] * 10, b10)
+    rc, need, _ = _query(L, S, S, 1024)
+    assert rc == 0 and need >= 8192 * 8192 * 8
+    assert L.ttm_inner_grad_query(ctypes.byref(S.view), ctypes.byref(S.view), ctypes.byref(S.view),
+                                  ctypes.byref(ws)) == 0
