@@ -66,9 +66,9 @@ typedef enum { TTM_F64 = 0 } ttm_dtype;
 
 /* Borrowed view of an input TT. */
 typedef struct ttm_tt {
-  int32_t n_sites;         /* N >= 1                                          */
-  const int32_t *phys;     /* host [N]: d_i >= 1                              */
-  const int32_t *bonds;    /* host [N+1]: r_0 = r_N = 1, r_i >= 1             */
+  int32_t n_sites;         /* 1 <= N <= 4096                                  */
+  const int32_t *phys;     /* host [N]: 1 <= d_i <= 65536                     */
+  const int32_t *bonds;    /* host [N+1]: r_0 = r_N = 1, 1 <= r_i <= 2^20     */
   const int64_t *offsets;  /* host [N]: element offset of core i in data      */
   const void *data;        /* device: doubles                                 */
   int32_t dtype;           /* TTM_F64                                         */
@@ -151,7 +151,10 @@ void ttm_default_options(ttm_options *opt);
  * bytes and the output capacity (doubles) needed for these inputs and
  * options: out_capacity = sum_i c_i d_i c_{i+1} with
  * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, cap), cap = chi_out when
- * final_round is set, else the swap cap.  Either output pointer may be NULL. */
+ * final_round is set, else the swap cap.  Either output pointer may be NULL.
+ * TTM_EINVAL also when a QR or SVD step of the schedule would take a matrix
+ * longer than 2^30 on a side or holding more than 2^36 entries, or a core
+ * would exceed 2^33 entries. */
 int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
               size_t *ws_bytes, int64_t *out_capacity);
 
@@ -216,13 +219,17 @@ int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, const int32_
  * storage either way).  value: host, receives L.  dA, dB: device buffers
  * laid out like A's and B's data (core k of the gradient at the same offset
  * as core k of the train), or NULL to skip; with both NULL only L is formed
- * and the right sweep is skipped.  ws: ttm_inner_grad_query's bytes.
+ * and the right sweep is skipped.  ws: ttm_inner_grad_query's bytes, which
+ * returns TTM_EINVAL when an environment or intermediate would exceed 2^36
+ * doubles or a contraction extent 2^30.
  * Blocking like the other entry points; TTM_ENONFINITE if L is not finite. */
 int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size_t *ws_bytes);
 int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                    double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream);
 
-/* Sizes for conventional_multiply (host only). */
+/* Sizes for conventional_multiply (host only).  TTM_EINVAL when an
+ * environment or a local tensor would exceed 2^36 doubles, or a QR unfolding
+ * 2^30 on a side. */
 int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
                        size_t *ws_bytes, int64_t *out_capacity);
 
