@@ -59,12 +59,24 @@ class PackedTT:
     def __init__(self, data, phys, bonds, offsets):
         import torch
 
-        assert data.dtype == torch.float64 and data.is_contiguous()
         self.data = data
         self.phys = list(int(p) for p in phys)
         self.bonds = list(int(b) for b in bonds)
         self.offsets = list(int(o) for o in offsets)
         n = len(self.phys)
+        if len(self.bonds) != n + 1 or len(self.offsets) != n:
+            raise ValueError("a PackedTT of %d sites needs %d bonds and %d offsets" % (n, n + 1, n))
+        # The library takes raw device pointers: every core must lie inside data.
+        for i in range(n):
+            size = self.bonds[i] * self.phys[i] * self.bonds[i + 1]
+            if min(self.bonds[i], self.phys[i], self.bonds[i + 1]) < 1 or self.offsets[i] < 0 \
+                    or self.offsets[i] + size > data.numel():
+                raise ValueError("core %d (offset %d, shape %d x %d x %d) lies outside the %d-element buffer"
+                                 % (i, self.offsets[i], self.bonds[i], self.phys[i], self.bonds[i + 1],
+                                    data.numel()))
+        if data.dtype != torch.float64 or not data.is_contiguous() or data.device.type != "cuda":
+            raise ValueError("a PackedTT holds a contiguous float64 GPU tensor (got %s %s on %s)"
+                             % ("contiguous" if data.is_contiguous() else "strided", data.dtype, data.device))
         self._phys = (ctypes.c_int32 * n)(*self.phys)
         self._bonds = (ctypes.c_int32 * (n + 1))(*self.bonds)
         self._offsets = (ctypes.c_int64 * n)(*self.offsets)
@@ -122,9 +134,19 @@ class Workspace:
         import torch
 
         if self.buf is None or self.buf.numel() < nbytes:
-            dev = self.device or torch.device("cuda", torch.cuda.current_device())
+            dev = torch.device(self.device) if self.device is not None else \
+                torch.device("cuda", torch.cuda.current_device())
+            if dev.type != "cuda":
+                raise ValueError("a Workspace lives in GPU memory (got %s)" % dev)
             self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
         return self.buf
+
+
+def _same_device(what, tensor, device):
+    """The library is given raw pointers: every buffer of one call must be
+    GPU memory on the inputs' device."""
+    if tensor.device != device:
+        raise ValueError("%s is on %s, the inputs on %s" % (what, tensor.device, device))
 
 
 _DEFAULT_WS = {}
@@ -193,6 +215,7 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
     import torch
 
     A, B = pack(A), pack(B)
+    _same_device("B", B.data, A.data.device)
     trace_cap = opts.pop("trace_cap", None)
     if trace_cap is None:
         trace_cap = 4 * A.n_sites * A.n_sites + 16
@@ -205,6 +228,11 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
         dev = A.data.device
         workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
     wbuf = workspace.get(ws_bytes)
+    _same_device("the workspace", wbuf, A.data.device)
+    if out is not None:
+        if out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor (got %s)" % out.dtype)
+        _same_device("out", out, A.data.device)
     if out is None or out.numel() < cap:
         out = torch.empty(max(cap, 1), dtype=torch.float64, device=A.data.device)
     n = A.n_sites
@@ -273,6 +301,9 @@ def multiply_batch(pairs, chi_out, tol, streams=4, workspaces=None, options=None
     tols = [float(tol)] * n if isinstance(tol, (int, float)) else [float(t) for t in tol]
     assert len(chis) == n and len(tols) == n
     dev = packed[0][0].data.device
+    for k, (A, B) in enumerate(packed):
+        _same_device("A of product %d" % k, A.data, dev)
+        _same_device("B of product %d" % k, B.data, dev)
     trace_cap = opts.pop("trace_cap", None)
     L = lib()
     opt_arr = (TtmOptions * n)()
@@ -291,6 +322,7 @@ def multiply_batch(pairs, chi_out, tol, streams=4, workspaces=None, options=None
         opt_arr[k] = o
         ws_bytes, cap = _query(L.ttm_query, A, B, chis[k], o)
         wbufs.append(workspaces[k].get(ws_bytes))
+        _same_device("the workspace of product %d" % k, wbufs[k], dev)
         outs.append(torch.empty(max(cap, 1), dtype=torch.float64, device=dev))
         nb = A.n_sites
         bonds.append((ctypes.c_int32 * (nb + 1))())
@@ -331,6 +363,8 @@ def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, st
     from ._abi import PRECISIONS
 
     W, A, B = pack(W), pack(A), pack(B)
+    _same_device("W", W.data, A.data.device)
+    _same_device("B", B.data, A.data.device)
     L = lib()
     need = ctypes.c_size_t(0)
     rc = L.ttm_inner_grad_query(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view),
@@ -341,6 +375,7 @@ def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, st
         dev = A.data.device
         workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
     wbuf = workspace.get(need.value)
+    _same_device("the workspace", wbuf, A.data.device)
     dA = torch.empty_like(A.data) if grads else None
     dB = torch.empty_like(B.data) if grads else None
     value = ctypes.c_double(0.0)
