@@ -253,3 +253,46 @@ def test_gpu_options_turbulence_vs_oracle(eps, chi_a, chi_b, chi_out, chi_mid, f
     assert st2["ranks"] == o.ranks
     assert O.rel_frob(C2, o.cores) <= TOL
     assert max(c.shape[2] for c in C2) <= (chi_out if final_round else (chi_mid or chi_out))
+
+
+def _cores(rng, shapes):
+    return [rng.standard_normal(s) for s in shapes]
+
+
+def test_gpu_degenerate_inputs():
+    """Degenerate cases of the method: a zero factor and a single zero core
+    (the product is zero; every SVD sees an all-zero spectrum and keeps rank
+    1), separable factors (all bonds 1), one-valued sites (d = 1 at every
+    site, inner bonds above that structural bound of 1), and bonds above the
+    structural bound (the canonicalising QR sweeps shrink them)."""
+    _say("case: degenerate inputs")
+    A, B = I.random_tt(6, 3, 4, 21), I.random_tt(6, 3, 4, 22)
+    zero = [np.zeros_like(c) for c in A]
+    one_zero = [c.copy() for c in A]
+    one_zero[3][:] = 0.0
+    for label, Z in (("zero factor", zero), ("zero core", one_zero)):
+        _say("  " + label)
+        for X, Y in ((Z, B), (B, Z)):
+            C, st = _run(X, Y, 8, 1e-14)
+            assert set(st["ranks"]) == {1}, label
+            assert O.bonds_of(C) == [1] * 7, label
+            assert np.abs(O.dense(C)).max() == 0.0, label
+    _say("  separable")
+    S1, S2 = I.random_tt(7, 4, 1, 23), I.random_tt(7, 4, 1, 24)
+    C, st = _run(S1, S2, 8, 1e-14)
+    assert set(st["ranks"]) == {1} and O.bonds_of(C) == [1] * 8
+    assert O.rel_frob(C, O.brute_force(S1, S2)) <= TOL
+    rng = np.random.default_rng(25)
+    _say("  d = 1 at every site")
+    D1 = _cores(rng, [(1, 1, 3), (3, 1, 2), (2, 1, 4), (4, 1, 1)])
+    D2 = _cores(rng, [(1, 1, 2), (2, 1, 5), (5, 1, 3), (3, 1, 1)])
+    C, st = _run(D1, D2, 8, 1e-14)
+    assert O.bonds_of(C) == [1] * 5
+    assert O.rel_frob(C, O.brute_force(D1, D2)) <= TOL
+    _say("  bonds above the structural bound")
+    W = _cores(rng, [(1, 2, 5), (5, 2, 7), (7, 2, 6), (6, 2, 1)])
+    V = _cores(rng, [(1, 2, 3), (3, 2, 9), (9, 2, 2), (2, 2, 1)])
+    C, st = _run(W, V, 16, 1e-14, chi_mid=0)
+    o = O.ttm(W, V, 16, 1e-14, chi_mid=0)
+    assert st["ranks"] == o.ranks and O.bonds_of(C) == O.bonds_of(o.cores)
+    assert O.rel_frob(C, O.brute_force(W, V)) <= TOL
