@@ -63,3 +63,16 @@ def test_gpu_conventional_turbulence_chi64_vs_oracle():
     assert st["sweeps"] == sweeps
     assert O.rel_frob(C, ref) <= 1e-10
     assert max(O.bonds_of(C)) <= 64
+
+
+def test_gpu_conventional_zero_factor():
+    """A zero factor: the fit is exactly zero, and the stop rule (a relative
+    change of the centre's norm of at most tol) holds at once on the second
+    sweep, as in the oracle."""
+    _say("case: conventional zero factor")
+    A = I.random_tt(6, 3, 4, 31)
+    Z = [np.zeros_like(c) for c in A]
+    C, st = _conv(Z, A, 8, 1e-13, max_sweeps=6)
+    assert np.abs(O.dense(C)).max() == 0.0
+    _, sweeps, _ = O.conventional_variational(Z, A, 8, 1e-13, max_sweeps=6)
+    assert st["sweeps"] == sweeps == 2
