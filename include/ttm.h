@@ -149,9 +149,13 @@ void ttm_default_options(ttm_options *opt);
 
 /* Sizes for ttm_multiply (host only, no GPU work).  Writes the workspace
  * bytes and the output capacity (doubles) needed for these inputs and
- * options: out_capacity = sum_i c_i d_i c_{i+1} with
- * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, cap), cap = chi_out when
- * final_round is set, else the swap cap.  Either output pointer may be NULL.
+ * options.  With final_round set, out_capacity = sum_i c_i d_i c_{i+1} with
+ * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, chi_out, chi_mid if > 0) (the
+ * final sweep cannot raise a bond the swaps capped).  Without it the bonds
+ * are those the swaps leave: at most the swap cap, and bounded by the cuts
+ * of the intermediate chain, where a site not yet contracted contributes its
+ * dimension twice, so a bond can exceed the product's structural bound.
+ * Either output pointer may be NULL.
  * TTM_EINVAL also when a QR or SVD step of the schedule would take a matrix
  * longer than 2^30 on a side or holding more than 2^36 entries, or a core
  * would exceed 2^33 entries. */
