@@ -231,7 +231,9 @@ int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size
 int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                    double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream);
 
-/* Sizes for conventional_multiply (host only).  TTM_EINVAL when an
+/* Sizes for conventional_multiply (host only).  The fit keeps the structural
+ * bonds capped at chi_out: out_capacity = sum_i c_i d_i c_{i+1} with
+ * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, chi_out).  TTM_EINVAL when an
  * environment or a local tensor would exceed 2^36 doubles, or a QR unfolding
  * 2^30 on a side. */
 int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,

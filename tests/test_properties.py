@@ -132,3 +132,26 @@ def test_query_capacity(data):
     Bt = [rng.standard_normal((bb[i], d[i], bb[i + 1])) for i in range(n)]
     res = O.ttm(At, Bt, chi, 0.0, chi_mid=None if chi_mid == -1 else chi_mid, final_round=final_round)
     assert sum(c.size for c in res.cores) <= cap.value
+
+
+@settings(max_examples=200, deadline=None, derandomize=True)
+@given(st.data())
+def test_conventional_query_capacity(data):
+    """The variational fit keeps the structural bonds capped at chi_out:
+    out_capacity = sum_i c_i d_i c_{i+1}, c_i = min(prod_{k<i} d_k,
+    prod_{k>=i} d_k, chi_out), whatever the input bonds."""
+    L = _lib()
+    n = data.draw(st.integers(1, 7))
+    d = [data.draw(st.integers(1, 5)) for _ in range(n)]
+    ba = [1] + [data.draw(st.integers(1, 9)) for _ in range(n - 1)] + [1]
+    bb = [1] + [data.draw(st.integers(1, 9)) for _ in range(n - 1)] + [1]
+    chi = data.draw(st.integers(1, 40))
+    ws, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+    A, B = _Train(d, ba), _Train(d, bb)
+    rc = L.conventional_query(ctypes.byref(A.view), ctypes.byref(B.view), chi, None, ctypes.byref(ws),
+                              ctypes.byref(cap))
+    assert rc == 0 and ws.value > 0
+    c = [1] * (n + 1)
+    for i in range(1, n):
+        c[i] = min(int(np.prod(d[:i])), int(np.prod(d[i:])), chi)
+    assert cap.value == sum(c[i] * d[i] * c[i + 1] for i in range(n))
