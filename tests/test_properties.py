@@ -6,7 +6,8 @@ bonds that may exceed the structural bound:
 * the product commutes (up to rounding) where nothing is truncated;
 * truncated, its error lies between the Eckart-Young bound at every cut and
   the sum of the discarded norms of Eq. (eps).
-The library's size query, on random shapes and options, gives the output
+The gradient of <W, A*B> equals the dense sum and satisfies Euler's identity
+at every core.  The library's size query, on random shapes and options, gives the output
 capacity its header states, and that capacity holds the oracle's product.
 """
 import ctypes
@@ -155,3 +156,27 @@ def test_conventional_query_capacity(data):
     for i in range(1, n):
         c[i] = min(int(np.prod(d[:i])), int(np.prod(d[i:])), chi)
     assert cap.value == sum(c[i] * d[i] * c[i + 1] for i in range(n))
+
+
+@SETTINGS
+@given(st.data())
+def test_gradient_value_and_euler_identity(data):
+    """<W, A*B> equals the dense sum, and L is linear in every core, so
+    <dL/dA_k, A_k> = <dL/dB_k, B_k> = L at every site."""
+    n = data.draw(st.integers(1, 5))
+    d = [data.draw(st.integers(1, 3)) for _ in range(n)]
+    rng = np.random.default_rng(data.draw(st.integers(0, 2 ** 31)))
+
+    def train():
+        b = [1] + [data.draw(st.integers(1, 4)) for _ in range(n - 1)] + [1]
+        return [rng.standard_normal((b[i], d[i], b[i + 1])) for i in range(n)]
+
+    W, A, B = train(), train(), train()
+    val, dA, dB = O.inner3_grad(W, A, B)
+    ref = float(np.sum(O.dense(W) * O.dense(A) * O.dense(B)))
+    scale = float(np.sum(np.abs(O.dense(W) * O.dense(A) * O.dense(B))))
+    assert abs(val - ref) <= 1e-12 * max(scale, 1e-300)
+    for k in range(n):
+        assert dA[k].shape == A[k].shape and dB[k].shape == B[k].shape
+        assert abs(float(np.sum(dA[k] * A[k])) - val) <= 1e-12 * max(scale, 1e-300)
+        assert abs(float(np.sum(dB[k] * B[k])) - val) <= 1e-12 * max(scale, 1e-300)
