@@ -1,0 +1,89 @@
+"""GPU parity over random small shapes, through the C ABI.
+
+Forty-eight seeded cases of 1-6 sites with mixed physical dimensions (1-4),
+input bonds drawn up to 6 (often above the structural bound) and random
+options.  A third of them are exact (no cap, eps = 1e-28) and compared with
+the brute-force product.  The others truncate (chi_out 1-5, swap cap
+default / uncapped / 3, with and without the final sweep).  They run with
+the oracle's rank schedule forced and are compared with the oracle's product
+at the FP64 bound, widened by the condition of the truncation where a case
+lands near a tie.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def case(k):
+    rng = np.random.default_rng(4000 + k)
+    n = int(rng.integers(1, 7))
+    d = [int(x) for x in rng.integers(1, 5, n)]
+
+    def train():
+        b = [1] + [int(x) for x in rng.integers(1, 7, n - 1)] + [1]
+        return [rng.standard_normal((b[i], d[i], b[i + 1])) for i in range(n)]
+
+    A, B = train(), train()
+    if k % 3 == 0:
+        return A, B, dict(chi_out=10 ** 4, eps=1e-28, chi_mid=0, final_round=True, exact=True)
+    chi_mid = (None, 0, 3)[int(rng.integers(0, 3))]
+    final_round = bool(k % 3 == 1 or chi_mid is not None)
+    return A, B, dict(chi_out=int(rng.integers(1, 6)), eps=1e-14, chi_mid=chi_mid, final_round=final_round,
+                      exact=False)
+
+
+@pytest.mark.parametrize("k", range(48))
+def test_gpu_random_shape(k, monkeypatch):
+    import torch
+    import paper_2410_19747_amd as T
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    A, B, c = case(k)
+    print("case %d: d=%s bonds %s x %s %s" % (k, [a.shape[1] for a in A], O.bonds_of(A), O.bonds_of(B),
+                                             {x: c[x] for x in ("chi_out", "chi_mid", "final_round")}),
+          flush=True)
+    sys.stdout.flush()
+    kw = dict(final_round=c["final_round"])
+    if c["chi_mid"] is not None:
+        kw["chi_mid"] = c["chi_mid"]
+    if c["exact"]:
+        C, _ = T.multiply(A, B, c["chi_out"], c["eps"], **kw)
+        ref = O.brute_force(A, B)
+        host = [x.detach().cpu().numpy() for x in C.cores()]
+        assert O.rel_frob(host, ref) <= TOL
+        return
+    o, gap = _oracle_with_gap(monkeypatch, A, B, c)
+    C, st = T.multiply(A, B, c["chi_out"], c["eps"], forced_ranks=o.ranks, **kw)
+    host = [x.detach().cpu().numpy() for x in C.cores()]
+    assert st["ranks"] == o.ranks
+    assert O.bonds_of(host) == O.bonds_of(o.cores)
+    # A truncation at a cut with relative gap g between the last kept and the
+    # first dropped singular value is determined to about c u / g (Wedin;
+    # backward error c u ||Theta|| with c ~ 100): the bound widens where a
+    # random case lands near a tie.
+    assert O.rel_frob(host, o.cores) <= max(TOL, 100 * np.finfo(float).eps / 2 / gap)
+
+
+def _oracle_with_gap(monkeypatch, A, B, c):
+    """The oracle's product, and the smallest relative gap at any of its
+    truncating cuts (1 when nothing is truncated)."""
+    mod = sys.modules["oracle.ttm"]
+    rule = mod.rank_rule
+    gaps = [1.0]
+
+    def recording(s, eps, cap):
+        r, disc = rule(s, eps, cap)
+        if r < len(s) and s[0] > 0:
+            gaps.append((s[r - 1] - s[r]) / s[0])
+        return r, disc
+
+    monkeypatch.setattr(mod, "rank_rule", recording)
+    o = O.ttm(A, B, c["chi_out"], c["eps"], chi_mid=c["chi_mid"], final_round=c["final_round"])
+    monkeypatch.undo()
+    return o, min(gaps)
