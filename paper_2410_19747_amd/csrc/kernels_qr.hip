@@ -34,22 +34,6 @@ int grid_for(int64_t n, int threads) {
   return (int)g;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ double block_sum(double v, double *red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  const int nw = blockDim.x >> 6;
-  for (int w = 0; w < nw; ++w) t += red[w];  // fixed order: every thread gets the same sum
-  return t;
-}
 }  // namespace
 
 // S[i + j*m] = M[i*rs + j*cs]

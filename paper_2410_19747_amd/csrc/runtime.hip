@@ -717,8 +717,8 @@ int make_conv_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, ConvPlan &pl) 
     pl.rsz[i] = e;
   }
   for (int i = 0; i < n; ++i) {
-    const int64_t cl = cb[i], cr = cb[i + 1], al = pl.a[i].rl, ar = pl.a[i].rr, bl = pl.b[i].rl,
-                  br = pl.b[i].rr, d = pl.phys[i];
+    const int64_t cl = cb[i], cr = cb[i + 1], al = pl.a[i].rl, ar = pl.a[i].rr, br = pl.b[i].rr,
+                  d = pl.phys[i];
     pl.tmax = std::max(pl.tmax, std::max(cl * al * d * br, cl * d * ar * br));
     if (!unfolding_ok(cl * d, cr) || !unfolding_ok(d * cr, cl)) return TTM_EINVAL;
     pl.qr_max = std::max<int64_t>(pl.qr_max, (int64_t)qr_scratch_doubles((int)(cl * d), (int)cr));
