@@ -7,7 +7,9 @@ bonds that may exceed the structural bound:
 * truncated, its error lies between the Eckart-Young bound at every cut and
   the sum of the discarded norms of Eq. (eps).
 The gradient of <W, A*B> equals the dense sum and satisfies Euler's identity
-at every core.  The library's size query, on random shapes and options, gives the output
+at every core.  The conventional product is exact before rounding, and its
+rounding error lies between the Eckart-Young bound and the TT-SVD bound.
+The library's size query, on random shapes and options, gives the output
 capacity its header states, and that capacity holds the oracle's product.
 """
 import ctypes
@@ -180,3 +182,28 @@ def test_gradient_value_and_euler_identity(data):
         assert dA[k].shape == A[k].shape and dB[k].shape == B[k].shape
         assert abs(float(np.sum(dA[k] * A[k])) - val) <= 1e-12 * max(scale, 1e-300)
         assert abs(float(np.sum(dB[k] * B[k])) - val) <= 1e-12 * max(scale, 1e-300)
+
+
+@SETTINGS
+@given(train_pair(), st.integers(1, 4))
+def test_conventional_products(pair, chi):
+    """Eq. (carriageXi): the Kronecker carriages give A*B exactly; rounded
+    at cap chi, the error is at least the Eckart-Young bound at every cut and
+    at most the root of the summed squared tails (one per cut, N - 1 of
+    them)."""
+    A, B = pair
+    ref = _exact(A, B)
+    nrm = np.linalg.norm(ref)
+    K = O.kron_cores(A, B)
+    assert np.linalg.norm(O.dense(K) - ref) <= 1e-12 * max(nrm, 1e-300)
+    R = O.conventional_exact(A, B, chi, 0.0)
+    assert max(O.bonds_of(R)) <= chi
+    err = np.linalg.norm(O.dense(R) - ref)
+    shape = ref.shape
+    tails = []
+    for k in range(1, len(shape)):
+        s = np.linalg.svd(ref.reshape(int(np.prod(shape[:k])), -1), compute_uv=False)
+        tail = float(np.sum(s[chi:] ** 2))
+        tails.append(tail)
+        assert err >= np.sqrt(tail) * (1 - 1e-9) - 1e-12 * nrm
+    assert err <= np.sqrt(sum(tails)) * (1 + 1e-9) + 1e-12 * nrm
