@@ -59,7 +59,7 @@ enum {
   TTM_ENONFINITE = -6,   /* NaN or Inf met in the data                        */
   TTM_EHIP = -7,         /* a HIP runtime call failed                         */
   TTM_EFORCED = -8,      /* forced rank list too short or out of range        */
-  TTM_EUNSUPPORTED = -9  /* dtype other than TTM_F64                          */
+  TTM_EUNSUPPORTED = -9  /* dtype other than TTM_F64, or an SVD beyond the kernels' size limit */
 };
 
 typedef enum { TTM_F64 = 0 } ttm_dtype;
@@ -99,8 +99,9 @@ typedef struct ttm_options {
                               report per-class totals in ttm_stats (default 0) */
   int32_t contract_precision; /* arithmetic of the contractions (Eq. (contract) and the swap
                               merges): TTM_PREC_F64 (default), TTM_PREC_F32, TTM_PREC_BF16 or
-                              TTM_PREC_BF16X3, the last three with FP32 accumulation on the
-                              matrix cores; QR, SVD and truncation stay FP64 */
+                              TTM_PREC_BF16X3, the last three on the FP32 / BF16 matrix cores,
+                              accumulated in FP32 within each 16-deep k-tile and in FP64
+                              across k-tiles; QR, SVD and truncation stay FP64 */
 } ttm_options;
 
 /* Values of ttm_options.contract_precision: operands of the contractions in
@@ -158,7 +159,13 @@ void ttm_default_options(ttm_options *opt);
  * Either output pointer may be NULL.
  * TTM_EINVAL also when a QR or SVD step of the schedule would take a matrix
  * longer than 2^30 on a side or holding more than 2^36 entries, or a core
- * would exceed 2^33 entries. */
+ * would exceed 2^33 entries.  TTM_EUNSUPPORTED when a truncated SVD of the
+ * schedule would have more than 8192 rows on the side that is kept
+ * orthonormal: a swap merging (D_l, d) x (d, D_r) with D_l d > 8192, or a
+ * final-sweep bond above 8192 (the SVD kernels hold one value per column of
+ * that side in 64 KB of LDS).  The bound is checked on the symbolic schedule
+ * with every rank at its cap, before any GPU work: with chi_mid = 0 or a
+ * chi_mid above chi_out it can reject inputs whose actual ranks would fit. */
 int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
               size_t *ws_bytes, int64_t *out_capacity);
 
@@ -181,7 +188,7 @@ int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double to
  * stats (NULL or n entries) receives each product's statistics.  Arrays are
  * host arrays of n entries.
  * Scheduling: the library creates min(n, n_streams) streams of its own
- * (1 <= n_streams <= 64), each of which first waits for the work already
+ * (1 <= n_streams <= 4), each of which first waits for the work already
  * enqueued on `stream` (the caller's hipStream_t, which produced the
  * inputs), and drives each from a host thread that takes products from a
  * queue ordered by decreasing estimated cost (swap count times the cube of
@@ -251,6 +258,15 @@ int conventional_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, 
 
 /* Static message for an error code. */
 const char *ttm_strerror(int code);
+
+/* Text describing the last failure of a compute call (ttm_multiply*,
+ * conventional_multiply*, ttm_inner_grad, ttm_multiply_batch) made on the
+ * calling thread: for TTM_EHIP the step that was being enqueued or
+ * synchronised and the HIP runtime's name and message for the error, for
+ * TTM_ENOCONV and TTM_ENONFINITE the SVD concerned.  Empty ("") after a call
+ * that succeeded or failed only in argument checks.  The string belongs to
+ * the library and stays valid until the thread's next compute call. */
+const char *ttm_last_error(void);
 
 /* Library version string. */
 const char *ttm_version(void);

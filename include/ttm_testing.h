@@ -28,7 +28,8 @@ int ttm_test_gemm(int M, int N, int K, int batch, const double *A, int64_t a_rs,
                   int64_t c_cs1, int64_t c_cs0, void *stream);
 
 /* As ttm_test_gemm, in the arithmetic `prec` (a TTM_PREC_* value of ttm.h):
- * operands rounded to FP32 / BF16 / three BF16 terms with FP32 accumulation. */
+ * operands rounded to FP32 / BF16 / three BF16 terms, accumulated in FP32
+ * within each 16-deep k-tile and in FP64 across k-tiles. */
 int ttm_test_gemm_prec(int prec, int M, int N, int K, const double *A, int64_t a_rs, int64_t a_cs,
                        const double *B, int64_t b_rs, int64_t b_cs, double *C, int64_t c_rs,
                        void *stream);
@@ -73,6 +74,18 @@ size_t ttm_test_svd_ws_bytes(int m, int n);
 int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
                  int right_pow, double *left, double *right, double *sigma, int *rank,
                  int *sweeps, void *ws, size_t ws_bytes, void *stream);
+
+/* As ttm_test_svd with the Jacobi block width chosen by the caller:
+ * block_width 16 (32-column block pairs), 32 (64-column pairs, 1024-thread
+ * solve, circle pairing, the path every matrix of 8192 rows and more than
+ * 256 columns takes) or 0 (the automatic choice).  It lets matrices small
+ * enough for a LAPACK reference run the 64-column-pair path.  Workspace:
+ * ttm_test_svd_ws_bytes_bw(m, n, block_width) bytes (0 for a bad width).
+ * TTM_EUNSUPPORTED when the orthonormal side exceeds 8192. */
+size_t ttm_test_svd_ws_bytes_bw(int m, int n, int block_width);
+int ttm_test_svd_bw(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
+                    int right_pow, double *left, double *right, double *sigma, int *rank, int *sweeps,
+                    int block_width, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

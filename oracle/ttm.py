@@ -175,11 +175,16 @@ def ttm(A, B, chi_out, eps, chi_mid=None, final_round=True, forced_ranks=None,
     # Inputs to left-orthonormal form, each in its own orientation.
     if canonicalize:
         for tt in (A, B):
+            # each QR acts on the core as the sweep has left it: its left bond
+            # is the rank k of the previous QR
+            rl = tt[0].shape[0]
             for i in range(n - 1):
-                rl, d, rr = tt[i].shape
+                _, d, rr = tt[i].shape
+                k = min(rl * d, rr)
                 res.ops.append(("qr", rl * d, rr))
-                res.ops.append(("gemm", min(rl * d, rr), rr, tt[i + 1].shape[1] * tt[i + 1].shape[2]))
+                res.ops.append(("gemm", k, rr, tt[i + 1].shape[1] * tt[i + 1].shape[2]))
                 res.n_qr += 1
+                rl = k
         A = left_orthogonalize(A)
         B = left_orthogonalize(B)
     else:

@@ -39,7 +39,8 @@ class TTMError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
         msg = lib().ttm_strerror(code).decode()
-        super().__init__("%s failed: %s (code %d)" % (where, msg, code))
+        detail = (lib().ttm_last_error() or b"").decode()
+        super().__init__("%s failed: %s (code %d)%s" % (where, msg, code, (": " + detail) if detail else ""))
 
 
 _LIB = None
@@ -221,8 +222,8 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
         trace_cap = 4 * A.n_sites * A.n_sites + 16
     o, keep = _options(trace_cap=trace_cap, **opts)
     L = lib()
-    qfn = L.ttm_query if kind == "ttm" else L.conventional_query
-    mfn = L.ttm_multiply_ex if kind == "ttm" else L.conventional_multiply_ex
+    qfn = L.conventional_query if kind == "conv" else L.ttm_query
+    mfn = L.conventional_multiply_ex if kind == "conv" else L.ttm_multiply_ex
     ws_bytes, cap = _query(qfn, A, B, chi_out, o)
     if workspace is None:
         dev = A.data.device

@@ -117,6 +117,7 @@ PROTOTYPES = {
                                                 ctypes.c_size_t, ctypes.c_void_p,
                                                 ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats)]),
     "ttm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ttm_last_error": (ctypes.c_char_p, []),
     "ttm_version": (ctypes.c_char_p, []),
 }
 
@@ -140,7 +141,13 @@ TESTING_PROTOTYPES = {
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _VP,
                                     ctypes.c_size_t, _VP]),
+    "ttm_test_svd_ws_bytes_bw": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ttm_test_svd_bw": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
 }
+
 
 
 def library_path():

@@ -168,8 +168,8 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
   };
   const int n = p.n;
   auto fail = [&](hipError_t h) {
+    note_hip_error(h, "the environment sweeps of ttm_inner_grad");
     (void)hipStreamSynchronize(st);
-    (void)h;
     return TTM_EHIP;
   };
   hipError_t h;
@@ -234,8 +234,14 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
     std::swap(Lc, Ln);
   }
   if ((h = hipMemcpyAsync(value, Lc, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return fail(h);
-  if ((h = hipStreamSynchronize(st)) != hipSuccess) return TTM_EHIP;
-  if (!isfinite(*value)) return TTM_ENONFINITE;
+  if ((h = hipStreamSynchronize(st)) != hipSuccess) {
+    note_hip_error(h, "the synchronisation at the end of ttm_inner_grad");
+    return TTM_EHIP;
+  }
+  if (!isfinite(*value)) {
+    set_last_error("the inner product <W, A*B> is not finite");
+    return TTM_ENONFINITE;
+  }
   return TTM_OK;
 }
 
@@ -247,6 +253,7 @@ extern "C" int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_
 
 extern "C" int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                               double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream) {
+  ttm::clear_last_error();
   return ttm::inner_grad(W, A, B, contract_precision, value, dA, dB, ws, ws_bytes,
                          static_cast<hipStream_t>(stream));
 }

@@ -6,16 +6,22 @@
 #include <algorithm>
 #include <atomic>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
 #include <hip/hip_runtime.h>
 
 #include "ttm.h"
+#include "ttm_internal.h"
 
 namespace {
 
-constexpr int kMaxStreams = 64;
+// Products in flight at most.  The measured optimum was 2 (a skewed batch)
+// to 4 (nine even products); more streams slowed the critical product
+// through contention for the command processor and the CUs, and every
+// stream holds a hardware queue of its own.
+constexpr int kMaxStreams = 4;
 
 // Relative cost of one product for the start order: the swap SVDs dominate,
 // N(N-1)/2 of them on matrices of side (swap cap) x (largest d).
@@ -43,6 +49,7 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
                                   const double *tol, ttm_tt_out *C, void *const *ws, const size_t *ws_bytes,
                                   const ttm_options *opt, ttm_stats *stats, int32_t n_streams, void *stream,
                                   int32_t *status) {
+  ttm::clear_last_error();
   if (n < 0 || n_streams < 1 || n_streams > kMaxStreams) return TTM_EINVAL;
   if (n == 0) return TTM_OK;
   if (!A || !B || !chi_out || !tol || !C || !ws || !ws_bytes) return TTM_EINVAL;
@@ -68,7 +75,11 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
         return TTM_EINVAL;
     }
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return TTM_EHIP;
+  hipError_t he;
+  if ((he = hipGetDevice(&dev)) != hipSuccess) {
+    ttm::note_hip_error(he, "hipGetDevice of ttm_multiply_batch");
+    return TTM_EHIP;
+  }
   const int nw = std::min<int>(n, n_streams);
   // One stream per worker, each first waiting for the work already on the
   // caller's stream, which produced the inputs.  The streams carry a CU mask
@@ -76,8 +87,10 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
   // queue of its own instead of sharing one of its few default queues, and
   // products overlap only on distinct queues.
   int n_cu = 0;
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+  if ((he = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess || n_cu < 1) {
+    ttm::note_hip_error(he, "the CU count query of ttm_multiply_batch");
     return TTM_EHIP;
+  }
   std::vector<uint32_t> mask((n_cu + 31) / 32, 0u);
   for (int c = 0; c < n_cu; ++c) mask[c / 32] |= 1u << (c % 32);
   hipStream_t caller = static_cast<hipStream_t>(stream);
@@ -91,14 +104,16 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
       }
     if (ready) (void)hipEventDestroy(ready);
   };
-  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(ready, caller) != hipSuccess) {
+  if ((he = hipEventCreateWithFlags(&ready, hipEventDisableTiming)) != hipSuccess ||
+      (he = hipEventRecord(ready, caller)) != hipSuccess) {
+    ttm::note_hip_error(he, "the start event of ttm_multiply_batch");
     release();
     return TTM_EHIP;
   }
   for (int w = 0; w < nw; ++w) {
-    if (hipExtStreamCreateWithCUMask(&own[w], (uint32_t)mask.size(), mask.data()) != hipSuccess ||
-        hipStreamWaitEvent(own[w], ready, 0) != hipSuccess) {
+    if ((he = hipExtStreamCreateWithCUMask(&own[w], (uint32_t)mask.size(), mask.data())) != hipSuccess ||
+        (he = hipStreamWaitEvent(own[w], ready, 0)) != hipSuccess) {
+      ttm::note_hip_error(he, "the stream set-up of ttm_multiply_batch");
       release();
       return TTM_EHIP;
     }
@@ -108,6 +123,7 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<int32_t> st(n, TTM_OK);
+  std::vector<std::string> why(n);
   std::atomic<int> next{0};
   // Worker w runs on own[w] and takes the next product whenever its last one
   // has finished (list scheduling, largest first).
@@ -119,10 +135,12 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
       const int i = order[q];
       if (se != hipSuccess) {
         st[i] = TTM_EHIP;
+        why[i] = std::string("hipSetDevice of a batch worker: ") + hipGetErrorName(se);
         continue;
       }
       st[i] = ttm_multiply_ex(&A[i], &B[i], chi_out[i], tol[i], &C[i], ws[i], ws_bytes[i], own[w],
                               opt ? &opt[i] : nullptr, stats ? &stats[i] : nullptr);
+      if (st[i] != TTM_OK) why[i] = ttm_last_error();
     }
   };
   if (nw == 1) {
@@ -137,7 +155,11 @@ extern "C" int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, c
   int rc = TTM_OK;
   for (int i = 0; i < n; ++i) {
     if (status) status[i] = st[i];
-    if (rc == TTM_OK && st[i] != TTM_OK) rc = st[i];
+    if (rc == TTM_OK && st[i] != TTM_OK) {
+      rc = st[i];
+      // the workers' messages are thread-local: hand the first one over
+      if (!why[i].empty()) ttm::set_last_error("product %d: %s", i, why[i].c_str());
+    }
   }
   return rc;
 }

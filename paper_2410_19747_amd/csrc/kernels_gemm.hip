@@ -2,8 +2,9 @@
 // epilogue.  FP64 (v_mfma_f64_16x16x4_f64) throughout, or, for the
 // contractions of a mixed-precision product, operands rounded to FP32
 // (v_mfma_f32_16x16x4_f32), to BF16 (v_mfma_f32_16x16x16_bf16) or split into
-// three BF16 terms (six BF16 products, about FP32 accuracy), all with FP32
-// accumulation; inputs and outputs stay FP64 in memory.
+// three BF16 terms (six BF16 products, about FP32 accuracy), all accumulated
+// in FP32 within each 16-deep k-tile and in FP64 across k-tiles; inputs and
+// outputs stay FP64 in memory.
 //
 // Used for every contraction of the TTM sweep: the COPY-tensor contraction
 // of Eq. (contract) is a batch of d products sharing the physical index; the
@@ -177,8 +178,13 @@ __device__ __forceinline__ short bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_value(short b) { return (float)__builtin_bit_cast(__bf16, b); }
 
-// The same tiling with operands rounded to FP32 or BF16 in LDS and FP32
-// accumulation.  PREC: 1 = FP32 (16x16x4 f32 MFMA, 4 k per step), 2 = BF16
+// The same tiling with operands rounded to FP32 or BF16 in LDS.  The matrix
+// cores accumulate each 16-deep k-tile in FP32, starting from zero; the
+// tile's partial sums are then added to FP64 accumulators, so that FP32
+// rounding acts on 16-term partials only, not on running sums over all of K
+// (with K up to the bond dimension, FP32 running sums lose about sqrt(K)
+// units of 2^-24, which over the N(N-1)/2 swaps of a product at bond 1024
+// added up to 3e-6).  PREC: 1 = FP32 (16x16x4 f32 MFMA, 4 k per step), 2 = BF16
 // (16x16x16 bf16 MFMA, 16 k per step), 3 = BF16 x 3: x = hi + mid + lo with
 // each term BF16, and A B ~ hi hi + hi mid + mid hi + hi lo + mid mid + lo hi
 // (the six terms above 2^-24 relative).  Operand layouts: f32 as for f64
@@ -221,8 +227,9 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
   };
 
   flt4 acc[2][2];
+  dbl4 acc64[2][2];
   for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int y = 0; y < 2; ++y) acc64[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   double ra[EA], rb[EB];
   auto fetch = [&](int k0) {
@@ -243,6 +250,10 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
   };
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
       int i, k;
@@ -294,6 +305,13 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
               acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[sa][x], b[sb][y], acc[x][y], 0, 0, 0);
         }
     }
+    // this k-tile's FP32 partial sums into the FP64 accumulators
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc64[x][y][t] += (double)acc[x][y][t];
     __syncthreads();
   }
 
@@ -308,11 +326,11 @@ __global__ __launch_bounds__(NT) void gemm_lowp_kernel(GemmArgs g) {
         const int j = tile_n + wc * 32 + y * 16 + (lane & 15);
         if (i < g.M && j < g.N) {
           if (g.ksplit > 1) {
-            g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = (double)acc[x][y][t];
+            g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = acc64[x][y][t];
             continue;
           }
           const int64_t o = out_index(g, i, j);
-          double v = g.alpha * (double)acc[x][y][t];
+          double v = g.alpha * acc64[x][y][t];
           if (g.beta != 0.0) v += g.beta * C[o];
           C[o] = v;
         }

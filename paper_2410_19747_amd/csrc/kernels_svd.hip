@@ -84,7 +84,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 }  // namespace
 
-JacobiPlan jacobi_plan(int L, int nc) {
+JacobiPlan jacobi_plan(int L, int nc, int force_bw) {
   JacobiPlan p;
   p.L = L;
   p.nc = nc;
@@ -96,7 +96,8 @@ JacobiPlan jacobi_plan(int L, int nc) {
   // than the rounds saved until W is large enough for the rounds to be HBM
   // bound.  Columns are padded with zeros to a whole even number of blocks;
   // zero columns never rotate.
-  const int bw = (L >= 8192 && nc > 256) ? 32 : 16;
+  int bw = (L >= 8192 && nc > 256) ? 32 : 16;
+  if (force_bw == 16 || force_bw == 32) bw = force_bw;  // testing hook
   int nblk = (nc + bw - 1) / bw;
   if (nblk < 2) nblk = 2;
   if (nblk & 1) ++nblk;

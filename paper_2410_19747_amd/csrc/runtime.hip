@@ -17,6 +17,7 @@
 // Every rank is read back to the host to size the next launches, so the call
 // synchronises with its stream once per SVD.
 #include <math.h>
+#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -29,6 +30,23 @@
 #include "ttm_internal.h"
 
 namespace ttm {
+
+namespace {
+thread_local char g_last_error[512];
+}  // namespace
+
+void set_last_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+void clear_last_error() { g_last_error[0] = '\0'; }
+void note_hip_error(hipError_t e, const char *what) {
+  set_last_error("%s in %s: %s", hipGetErrorName(e), what ? what : "a HIP call", hipGetErrorString(e));
+}
+const char *last_error_text() { return g_last_error; }
+
 namespace {
 
 constexpr int64_t kSat = (int64_t)1 << 40;  // saturation of structural products
@@ -186,12 +204,16 @@ void note_core(Plan &pl, const Shape &s) {
   pl.max_bond = std::max(pl.max_bond, std::max(s.rl, s.rr));
 }
 // Workspace of one truncated SVD of an np x no matrix; `own_y` adds room for
-// the matrix itself (the swap builds it there).
-void note_svd(Plan &pl, int np, int no, bool own_y) {
+// the matrix itself (the swap builds it there).  False when np (the side
+// whose singular vectors come out orthonormal, which also bounds the Jacobi
+// size) exceeds what the SVD kernels take.
+bool note_svd(Plan &pl, int np, int no, bool own_y) {
+  if (np > kSvdMaxSide) return false;
   SvdPlan sp = svd_plan(np, no);
   int64_t need = (int64_t)svd_ws_doubles(sp);
   if (own_y) need += (((int64_t)np * no + 31) & ~(int64_t)31);
   pl.max_w = std::max<int64_t>(pl.max_w, need);
+  return true;
 }
 void note_qr(Plan &pl, int m, int n) {
   pl.max_qr = std::max<int64_t>(pl.max_qr, (int64_t)qr_scratch_doubles(m, n));
@@ -243,7 +265,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     for (int p = n - 1; p > j; --p) {
       if (!unfolding_ok((int64_t)pi[p].rl * x.d, (int64_t)pi[p].d * x.rr)) return TTM_EINVAL;
       const int m = pi[p].rl * x.d, nn = pi[p].d * x.rr;
-      note_svd(pl, m, nn, true);
+      if (!note_svd(pl, m, nn, true)) return TTM_EUNSUPPORTED;
       const int r = swap_cap(o, pl.phys, j, p, pi[p], x);
       Shape xn = {pi[p].rl, x.d, r};
       Shape pn = {r, pi[p].d, x.rr};
@@ -259,7 +281,7 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     for (int i = 0; i + 1 < n; ++i) {
       if (!unfolding_ok((int64_t)pi[i].rl * pi[i].d, pi[i].rr)) return TTM_EINVAL;
       const int m = pi[i].rl * pi[i].d, nn = pi[i].rr;
-      note_svd(pl, nn, m, false);
+      if (!note_svd(pl, nn, m, false)) return TTM_EUNSUPPORTED;
       const int r = round_cap(chi_out, pl.phys, i, pi[i]);
       pl.max_r = std::max<int64_t>(pl.max_r, (int64_t)r * nn);
       pi[i].rr = r;
@@ -332,16 +354,22 @@ struct Runner {
   }
   bool hip(hipError_t e) {
     if (e != hipSuccess) {
-      if (err == TTM_OK) err = TTM_EHIP;
-      if (trace) fprintf(stderr, "[ttm] HIP error %s\n", hipGetErrorString(e));
+      if (err == TTM_OK) {
+        err = TTM_EHIP;
+        note_hip_error(e, step);
+      }
+      if (trace) fprintf(stderr, "[ttm] HIP error %s (%s) in %s\n", hipGetErrorName(e), hipGetErrorString(e), step);
       return false;
     }
     return true;
   }
+  // the step being enqueued, for error messages
+  const char *step = "the set-up of a TTM product";
   void note(const Shape &s) { max_bond = std::max(max_bond, std::max(s.rl, s.rr)); }
 
   // ---- Eq. (contract): out[a, e, b] = sum_c K[a, e, c] M[c, e, b]
   Core contract(const Core &k, const Core &m) {
+    step = "a contraction (Eq. contract)";
     Core out;
     out.p = take();
     out.s = {k.s.rl, k.s.d, m.s.rr};
@@ -365,6 +393,7 @@ struct Runner {
 
   // ---- gauge move: QR of cores[p], R into cores[p+1]
   void qr_move(std::vector<Core> &c, int p) {
+    step = "a QR gauge move";
     Core &cur = c[p];
     Core &nxt = c[p + 1];
     const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
@@ -438,6 +467,7 @@ struct Runner {
 
   // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
   void swap(Core &P, Core &X, int cap) {
+    step = "a swap";
     const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
     const int m = Dl * dx, n = dp * Dr;
     const SvdPlan sp = svd_plan(m, n);
@@ -487,6 +517,7 @@ struct Runner {
 
   // ---- final rounding step at site i: Pi_i <- U_r, Pi_{i+1} <- S_r V_r^T Pi_{i+1}
   void round_step(std::vector<Core> &c, int i, int cap) {
+    step = "a step of the final rounding sweep";
     Core &cur = c[i];
     Core &nxt = c[i + 1];
     const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
@@ -742,7 +773,10 @@ struct ConvRunner {
   double flops = 0.0;
   int n_qr = 0;
   bool hip(hipError_t e) {
-    if (e != hipSuccess && err == TTM_OK) err = TTM_EHIP;
+    if (e != hipSuccess && err == TTM_OK) {
+      err = TTM_EHIP;
+      note_hip_error(e, "the conventional variational product");
+    }
     return e == hipSuccess;
   }
   void gemm(const GemmArgs &g) {
@@ -1012,12 +1046,14 @@ const char *ttm_strerror(int code) {
     case TTM_ENONFINITE: return "NaN or Inf in the data";
     case TTM_EHIP: return "HIP runtime error";
     case TTM_EFORCED: return "forced rank list inconsistent with the schedule";
-    case TTM_EUNSUPPORTED: return "unsupported dtype";
+    case TTM_EUNSUPPORTED: return "unsupported dtype, or an SVD larger than the kernels take";
     default: return "unknown error";
   }
 }
 
-const char *ttm_version(void) { return "libttm 0.1 (gfx950, fp64)"; }
+const char *ttm_version(void) { return "libttm 0.2 (gfx950, fp64)"; }
+
+const char *ttm_last_error(void) { return ttm::last_error_text(); }
 
 int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
               size_t *ws_bytes, int64_t *out_capacity) {
@@ -1038,6 +1074,7 @@ int ttm_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_optio
 int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, ttm_tt_out *C,
                     void *ws, size_t ws_bytes, void *stream, const ttm_options *opt,
                     ttm_stats *stats) {
+  ttm::clear_last_error();
   int e = ttm::validate_pair(A, B);
   if (e) return e;
   if (chi_out < 1) return TTM_EINVAL;
@@ -1072,6 +1109,7 @@ int conventional_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const 
 int conventional_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol,
                              ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
                              const ttm_options *opt, ttm_stats *stats) {
+  ttm::clear_last_error();
   int e = ttm::validate_pair(A, B);
   if (e) return e;
   if (chi_out < 1) return TTM_EINVAL;

@@ -64,12 +64,12 @@ __global__ void sorted_sigma_kernel(const double *__restrict__ sigma, const int 
 }
 }  // namespace
 
-SvdPlan svd_plan(int np, int no) {
+SvdPlan svd_plan(int np, int no, int force_bw) {
   SvdPlan p;
   p.np = np;
   p.no = no;
   p.k = std::min(np, no);
-  p.jp = jacobi_plan(p.k, p.k);
+  p.jp = jacobi_plan(p.k, p.k, force_bw);
   return p;
 }
 
@@ -99,7 +99,10 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   auto ok = [&](hipError_t e) {
     if (e != hipSuccess) {
       out.err = TTM_EHIP;
-      if (trace) fprintf(stderr, "[ttm] HIP error %s\n", hipGetErrorString(e));
+      char what[96];
+      snprintf(what, sizeof(what), "the truncated SVD of a %d x %d matrix", p.np, p.no);
+      note_hip_error(e, what);
+      if (trace) fprintf(stderr, "[ttm] HIP error %s (%s) in %s\n", hipGetErrorName(e), hipGetErrorString(e), what);
       return false;
     }
     return true;
@@ -177,6 +180,8 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   }
   if (!conv) {
     out.err = TTM_ENOCONV;
+    set_last_error("one-sided Jacobi on the %d x %d factor of a %d x %d SVD did not converge in %d sweeps",
+                   jp.L, jp.nc, p.np, p.no, out.sweeps);
     if (trace) fprintf(stderr, "[ttm] jacobi %dx%d did not converge\n", jp.L, jp.nc);
     return out;
   }
@@ -189,6 +194,7 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   if (!sync()) return out;
   if (res[4] != 0.0) {
     out.err = TTM_ENONFINITE;
+    set_last_error("the singular values of a %d x %d SVD are not finite", p.np, p.no);
     return out;
   }
   out.rank = (int)res[0];

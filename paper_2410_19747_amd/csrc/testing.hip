@@ -107,20 +107,25 @@ int ttm_test_qr_pivoted(double *S, int m, int n, int *perm, double *scratch, voi
   return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
 }
 
-size_t ttm_test_svd_ws_bytes(int m, int n) {
+size_t ttm_test_svd_ws_bytes_bw(int m, int n, int block_width) {
   if (m < 1 || n < 1) return 0;
+  if (block_width != 0 && block_width != 16 && block_width != 32) return 0;
   // the larger of the two orientations, plus a transposed copy of M
-  const size_t a = ttm::svd_ws_doubles(ttm::svd_plan(m, n));
-  const size_t b = ttm::svd_ws_doubles(ttm::svd_plan(n, m));
+  const size_t a = ttm::svd_ws_doubles(ttm::svd_plan(m, n, block_width));
+  const size_t b = ttm::svd_ws_doubles(ttm::svd_plan(n, m, block_width));
   return (std::max(a, b) + (size_t)m * n + 64) * sizeof(double);
 }
 
-int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
-                 int right_pow, double *left, double *right, double *sigma, int *rank,
-                 int *sweeps, void *ws, size_t ws_bytes, void *stream) {
+size_t ttm_test_svd_ws_bytes(int m, int n) { return ttm_test_svd_ws_bytes_bw(m, n, 0); }
+
+int ttm_test_svd_bw(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
+                    int right_pow, double *left, double *right, double *sigma, int *rank, int *sweeps,
+                    int block_width, void *ws, size_t ws_bytes, void *stream) {
   if (m < 1 || n < 1 || !M || !left || !right || !sigma || !rank || !ws) return TTM_EINVAL;
   if (left_pow + right_pow != 1 || left_pow < 0 || right_pow < 0) return TTM_EINVAL;
-  if (ws_bytes < ttm_test_svd_ws_bytes(m, n)) return TTM_EWORKSPACE;
+  if (block_width != 0 && block_width != 16 && block_width != 32) return TTM_EINVAL;
+  if (std::min(m, n) > ttm::kSvdMaxSide || (right_pow == 0 ? m : n) > ttm::kSvdMaxSide) return TTM_EUNSUPPORTED;
+  if (ws_bytes < ttm_test_svd_ws_bytes_bw(m, n, block_width)) return TTM_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *base = static_cast<double *>(ws);
   double *Yt = base;                                           // M^T copy when needed
@@ -129,7 +134,7 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
   if (right_pow == 0) {
     // right factor orthonormal: Y = M (m x n), column-major copy of row-major M
     if (ttm::launch_transpose(Yt, M, m, n, s) != hipSuccess) return TTM_EHIP;
-    const ttm::SvdPlan sp = ttm::svd_plan(m, n);
+    const ttm::SvdPlan sp = ttm::svd_plan(m, n, block_width);
     res = ttm::svd_oside(sp, Yt, eps, cap, forced, 60, right, ttm::SVD_U_T, sigma, sws, s, nullptr, 0);
     if (res.err == TTM_OK) {
       ttm::GemmArgs g;  // left = M V_r
@@ -141,7 +146,7 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
     }
   } else {
     // left factor orthonormal: Y = M^T, whose column-major storage is M's
-    const ttm::SvdPlan sp = ttm::svd_plan(n, m);
+    const ttm::SvdPlan sp = ttm::svd_plan(n, m, block_width);
     res = ttm::svd_oside(sp, M, eps, cap, forced, 60, left, ttm::SVD_U, sigma, sws, s, nullptr, 0);
     if (res.err == TTM_OK) {
       ttm::GemmArgs g;  // right = U_r^T M
@@ -156,6 +161,13 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
   if (res.err != TTM_OK) return res.err;
   *rank = res.rank;
   return hipStreamSynchronize(s) == hipSuccess ? TTM_OK : TTM_EHIP;
+}
+
+int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced, int left_pow,
+                 int right_pow, double *left, double *right, double *sigma, int *rank,
+                 int *sweeps, void *ws, size_t ws_bytes, void *stream) {
+  return ttm_test_svd_bw(M, m, n, eps, cap, forced, left_pow, right_pow, left, right, sigma, rank, sweeps, 0,
+                         ws, ws_bytes, stream);
 }
 
 }  // extern "C"

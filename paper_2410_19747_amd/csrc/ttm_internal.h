@@ -11,6 +11,16 @@
 
 namespace ttm {
 
+// ------------------------------------------------------------------ error text
+// Description of the last failure of a library call on the calling thread,
+// returned by ttm_last_error: which HIP call or step failed and the runtime's
+// own name for the error.  Entry points clear it when they start.
+void set_last_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_last_error();
+// Records a failed HIP call: "<hipErrorName> in <what>: <hipErrorString>".
+void note_hip_error(hipError_t e, const char *what);
+const char *last_error_text();
+
 // ------------------------------------------------------------------ kernel timing
 // Optional per-launch timing with HIP events on the launching stream.  Kernel
 // classes follow ttm_stats.kernel_ms.  Events come from a process-wide pool
@@ -60,7 +70,8 @@ struct Timed {
 // The split output mapping lets a product write a permuted layout (the
 // leg exchange of a swap) directly.  beta == 0 never reads C.  prec selects
 // the arithmetic: FP64, or operands rounded to FP32, BF16 or three BF16 terms
-// with FP32 accumulation (inputs and output FP64 in memory either way).
+// accumulated in FP32 within each 16-deep k-tile and in FP64 across k-tiles
+// (inputs and output FP64 in memory either way).
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3 };
 struct GemmArgs {
   int M = 0, N = 0, K = 0, batch = 1;
@@ -145,7 +156,10 @@ struct JacobiPlan {
   int rounds = 0;        // nblk - 1
   int pairs = 0;         // nblk / 2
 };
-JacobiPlan jacobi_plan(int L, int nc);
+// force_bw (16 or 32) overrides the block width chosen from the size; 0
+// keeps the automatic choice (a testing hook: it lets small matrices take
+// the 64-column-pair path that only 8192-row matrices take otherwise).
+JacobiPlan jacobi_plan(int L, int nc, int force_bw = 0);
 // Workspace doubles of the Jacobi buffers of a plan.
 size_t jacobi_ws_doubles(const JacobiPlan &p);
 
@@ -210,7 +224,12 @@ struct SvdPlan {
   int np = 0, no = 0, k = 0;
   JacobiPlan jp;
 };
-SvdPlan svd_plan(int np, int no);
+SvdPlan svd_plan(int np, int no, int force_bw = 0);
+// Largest matrix side the SVD kernels take: the column sort and the rank
+// rule hold one value per column in LDS (64 KB) and in 1024 x 8 registers,
+// so np (the columns of X = Y^T, which bound the Jacobi size k as well)
+// must not exceed it.
+constexpr int kSvdMaxSide = 8192;
 size_t svd_ws_doubles(const SvdPlan &p);
 struct SvdResult {
   int rank = -1;

@@ -204,7 +204,7 @@ def test_batch_rejects_before_gpu_work(L):
     assert call(base, [need] * n, outs([cap] * n), count=0) == _abi.TTM_OK
     assert call(base, [need] * n, outs([cap] * n), count=-1) == _abi.TTM_EINVAL
     assert call(base, [need] * n, outs([cap] * n), n_streams=0) == _abi.TTM_EINVAL
-    assert call(base, [need] * n, outs([cap] * n), n_streams=65) == _abi.TTM_EINVAL
+    assert call(base, [need] * n, outs([cap] * n), n_streams=5) == _abi.TTM_EINVAL
     assert L.ttm_multiply_batch(n, As, As, chis, tols, None, None, None, None, None, 2, None,
                                 status) == _abi.TTM_EINVAL
     # one product's workspace too small, one product's output too small
@@ -280,3 +280,28 @@ def test_oversized_shapes_rejected_by_every_query(L):
     assert rc == 0 and need >= 8192 * 8192 * 8
     assert L.ttm_inner_grad_query(ctypes.byref(S.view), ctypes.byref(S.view), ctypes.byref(S.view),
                                   ctypes.byref(ws)) == 0
+
+
+def test_svd_size_limit_rejected_by_query(L):
+    """A schedule whose truncated SVD would keep more than 8192 rows
+    orthonormal (the SVD kernels' limit) is rejected by ttm_query with
+    TTM_EUNSUPPORTED before any GPU work, rather than failing partway."""
+    b8 = [1, 8, 64, 128, 128, 128, 64, 8, 1]
+    S = _TT([8] * 8, b8)
+    assert _query(L, S, S, 128)[0] == _abi.TTM_OK
+    uncapped = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(uncapped))
+    uncapped.chi_mid = 0
+    assert _query(L, S, S, 128, uncapped)[0] == _abi.TTM_EUNSUPPORTED
+    wide = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(wide))
+    wide.chi_mid = 2048  # swap matrices of (2048 * 8) rows
+    assert _query(L, S, S, 128, wide)[0] == _abi.TTM_EUNSUPPORTED
+    # d = 16 at bond 1024: swap matrices of 16384 rows
+    D = _TT([16] * 6, [1, 16, 256, 1024, 256, 16, 1])
+    assert _query(L, D, D, 1024)[0] == _abi.TTM_EUNSUPPORTED
+    # exactly at the limit: 1024 * 8 = 8192 rows is accepted
+    b10 = [1, 8, 64, 512, 1024, 1024, 1024, 512, 64, 8, 1]
+    T = _TT([8] * 10, b10)
+    assert _query(L, T, T, 1024)[0] == _abi.TTM_OK
+    assert b"SVD" in L.ttm_strerror(_abi.TTM_EUNSUPPORTED)

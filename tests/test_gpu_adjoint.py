@@ -86,7 +86,7 @@ def test_gpu_inner_grad_turbulence_1024_chi128():
     v32, dA32, dB32 = T.inner_grad(W, qa, qb, contract_precision="f32")
     e32 = max(_rel(_host(dA32), dAo), _rel(_host(dB32), dBo))
     _say("  FP32 contractions: rel err %.2e" % e32)
-    assert e32 <= 1e-5
+    assert e32 <= 1e-6
 
 
 def test_gpu_autograd_loss_matches_finite_differences():
@@ -162,4 +162,4 @@ def test_gpu_inner_grad_wide_w_and_fp32():
     assert abs(v - vo) <= TOL * abs(vo)
     assert _rel(_host(dA), dAo) <= TOL and _rel(_host(dB), dBo) <= TOL
     v32, dA32, dB32 = T.inner_grad(W, A, B, contract_precision="f32")
-    assert _rel(_host(dA32), dAo) <= 1e-5 and _rel(_host(dB32), dBo) <= 1e-5
+    assert _rel(_host(dA32), dAo) <= 1e-6 and _rel(_host(dB32), dBo) <= 1e-6

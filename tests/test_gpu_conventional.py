@@ -40,10 +40,14 @@ def test_gpu_conventional_truncated_r10_vs_oracle():
     ref, sweeps, hist = O.conventional_variational(A, B, 8, 1e-13, max_sweeps=10, seed=12345)
     C, st = _conv(A, B, 8, 1e-13, max_sweeps=10, seed=12345)
     assert st["sweeps"] == sweeps
-    assert O.rel_frob(C, ref) <= 1e-10
+    # Same seed, same sweeps: the fits differ by rounding only.  The sweep map
+    # does not amplify it (perturbing the oracle's input by 1e-15 moves its
+    # output by 3e-15 here, and by 5e-15 on the 256^3 case below), so the FP64
+    # bar of 1e-12 applies to these unconverged fits too.
+    assert O.rel_frob(C, ref) <= 1e-12
     # both are (near-)optimal rank-8 approximations of the same tensor
     ex = O.brute_force(A, B)
-    assert abs(O.rel_frob(C, ex) - O.rel_frob(ref, ex)) <= 1e-10
+    assert abs(O.rel_frob(C, ex) - O.rel_frob(ref, ex)) <= 1e-12
 
 
 def test_gpu_conventional_t16():
@@ -61,7 +65,7 @@ def test_gpu_conventional_turbulence_chi64_vs_oracle():
     ref, sweeps, _ = O.conventional_variational(A, A, 64, 1e-12, max_sweeps=4)
     C, st = _conv(A, A, 64, 1e-12, max_sweeps=4)
     assert st["sweeps"] == sweeps
-    assert O.rel_frob(C, ref) <= 1e-10
+    assert O.rel_frob(C, ref) <= 1e-12
     assert max(O.bonds_of(C)) <= 64
 
 

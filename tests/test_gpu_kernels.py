@@ -130,18 +130,21 @@ def test_qr(m, n):
     assert np.allclose(np.tril(R, -1), 0.0)
 
 
-def _svd(torch, L, M, eps=0.0, cap=0, forced=0, left_pow=1, right_pow=0):
+def _svd(torch, L, M, eps=0.0, cap=0, forced=0, left_pow=1, right_pow=0, block_width=0):
     m, n = M.shape
     k = min(m, n)
     dM = _dev(torch, M)
     dl = torch.zeros(m * k, dtype=torch.float64, device="cuda")
     dr = torch.zeros(k * n, dtype=torch.float64, device="cuda")
     ds = torch.zeros(k, dtype=torch.float64, device="cuda")
-    ws = torch.zeros(int(L.ttm_test_svd_ws_bytes(m, n)) // 8 + 1, dtype=torch.float64, device="cuda")
+    nbytes = int(L.ttm_test_svd_ws_bytes_bw(m, n, block_width))
+    assert nbytes > 0
+    ws = torch.zeros(nbytes // 8 + 1, dtype=torch.float64, device="cuda")
     rank = ctypes.c_int(0)
     sweeps = ctypes.c_int(0)
-    rc = L.ttm_test_svd(_ptr(dM), m, n, eps, cap, forced, left_pow, right_pow, _ptr(dl), _ptr(dr), _ptr(ds),
-                        ctypes.byref(rank), ctypes.byref(sweeps), _ptr(ws), ws.numel() * 8, None)
+    rc = L.ttm_test_svd_bw(_ptr(dM), m, n, eps, cap, forced, left_pow, right_pow, _ptr(dl), _ptr(dr), _ptr(ds),
+                           ctypes.byref(rank), ctypes.byref(sweeps), block_width, _ptr(ws), ws.numel() * 8,
+                           None)
     assert rc == 0, rc
     r = rank.value
     return (dl.cpu().numpy()[: m * r].reshape(m, r), dr.cpu().numpy()[: r * n].reshape(r, n),
@@ -191,9 +194,10 @@ def test_svd_power_law_truncated():
 
 
 def test_svd_swap_size_2048_power_law():
-    """An SVD at the largest swap size of chi = 256 (2048 x 2048, 64-column
-    Jacobi blocks) against LAPACK: singular values, the rank rule with a cap,
-    and the truncated factorisation against the best rank-r approximation."""
+    """An SVD at the largest swap size of chi = 256 (2048 x 2048; 16-column
+    blocks, so 32-column pairs with the XOR pairing) against LAPACK: singular
+    values, the rank rule with a cap, and the truncated factorisation against
+    the best rank-r approximation."""
     torch, L = _env()
     _say("svd power law 2048x2048")
     rng = np.random.default_rng(21)
@@ -208,6 +212,60 @@ def test_svd_swap_size_2048_power_law():
     assert np.allclose(sv, ref, rtol=1e-11, atol=1e-14 * ref[0])
     best = (U[:, :r] * s[:r]) @ V[:, :r].T
     assert np.linalg.norm(left @ right - best) <= 1e-11 * np.linalg.norm(M)
+    assert np.abs(right @ right.T - np.eye(r)).max() < 1e-12
+    _say("  sweeps %d" % sw)
+
+
+@pytest.mark.parametrize("n,cap", [(1024, 128), (2048, 256)])
+def test_svd_64_column_pairs_power_law(n, cap):
+    """The 64-column-pair Jacobi path (32-column blocks, 1024-thread solve
+    with the rotation in LDS, circle pairing, three launches per round),
+    which every 8192-row swap matrix of the chi = 1024 product takes, forced
+    on power-law matrices small enough for LAPACK: singular values, the rank
+    rule with a cap, the best rank-r approximation, orthonormal factors, and
+    the same results within the parity bar as the 32-column-pair path."""
+    torch, L = _env()
+    _say("svd 64-column pairs, power law %dx%d" % (n, n))
+    rng = np.random.default_rng(n + 5)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = (1.0 + np.arange(n)) ** -1.5
+    M = (U * s) @ V.T
+    ref = np.linalg.svd(M, compute_uv=False)
+    left, right, sv, r, sw = _svd(torch, L, M, eps=1e-14, cap=cap, block_width=32)
+    assert r == cap
+    assert np.allclose(sv, ref, rtol=1e-11, atol=1e-14 * ref[0])
+    best = (U[:, :r] * s[:r]) @ V[:, :r].T
+    assert np.linalg.norm(left @ right - best) <= 1e-11 * np.linalg.norm(M)
+    assert np.abs(right @ right.T - np.eye(r)).max() < 1e-12
+    _say("  sweeps %d" % sw)
+    # the other orientation (left factor orthonormal) and the rank rule alone
+    left2, right2, sv2, r2, _ = _svd(torch, L, M, eps=1e-6, cap=0, left_pow=0, right_pow=1, block_width=32)
+    import oracle as O
+    rr, _ = O.rank_rule(ref, 1e-6, 0)
+    assert r2 == rr
+    best2 = (U[:, :r2] * s[:r2]) @ V[:, :r2].T
+    assert np.linalg.norm(left2 @ right2 - best2) <= 1e-11 * np.linalg.norm(M)
+    assert np.abs(left2.T @ left2 - np.eye(r2)).max() < 1e-12
+    # the automatic choice (32-column pairs) agrees within the parity bar
+    left3, right3, _, r3, _ = _svd(torch, L, M, eps=1e-14, cap=cap)
+    assert r3 == r
+    assert np.linalg.norm(left3 @ right3 - left @ right) <= 1e-12 * np.linalg.norm(M)
+
+
+@pytest.mark.parametrize("m,n", [(1100, 1024), (1024, 1100), (700, 520)])
+def test_svd_64_column_pairs_random(m, n):
+    """Forced 64-column pairs on dense random matrices (full rank, odd block
+    counts padded with zero columns) against LAPACK."""
+    torch, L = _env()
+    _say("svd 64-column pairs, random %dx%d" % (m, n))
+    rng = np.random.default_rng(m * 7 + n)
+    M = rng.standard_normal((m, n))
+    left, right, s, r, sw = _svd(torch, L, M, block_width=32)
+    ref = np.linalg.svd(M, compute_uv=False)
+    assert r == min(m, n)
+    assert np.allclose(s, ref, rtol=1e-12, atol=1e-14 * ref[0])
+    assert np.allclose(left @ right, M, rtol=1e-12, atol=1e-12 * ref[0])
     assert np.abs(right @ right.T - np.eye(r)).max() < 1e-12
     _say("  sweeps %d" % sw)
 

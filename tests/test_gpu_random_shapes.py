@@ -7,7 +7,8 @@ the brute-force product.  The others truncate (chi_out 1-5, swap cap
 default / uncapped / 3, with and without the final sweep).  They run with
 the oracle's rank schedule forced and are compared with the oracle's product
 at the FP64 bound, widened by the condition of the truncation where a case
-lands near a tie.
+lands near a tie; where no decision is near a tie or a threshold of
+Eq. (eps), an unforced run must reach the oracle's ranks by itself.
 """
 import sys
 
@@ -58,7 +59,7 @@ def test_gpu_random_shape(k, monkeypatch):
         host = [x.detach().cpu().numpy() for x in C.cores()]
         assert O.rel_frob(host, ref) <= TOL
         return
-    o, gap = _oracle_with_gap(monkeypatch, A, B, c)
+    o, gap, clean = _oracle_with_gap(monkeypatch, A, B, c)
     C, st = T.multiply(A, B, c["chi_out"], c["eps"], forced_ranks=o.ranks, **kw)
     host = [x.detach().cpu().numpy() for x in C.cores()]
     assert st["ranks"] == o.ranks
@@ -67,23 +68,44 @@ def test_gpu_random_shape(k, monkeypatch):
     # first dropped singular value is determined to about c u / g (Wedin;
     # backward error c u ||Theta|| with c ~ 100): the bound widens where a
     # random case lands near a tie.
-    assert O.rel_frob(host, o.cores) <= max(TOL, 100 * np.finfo(float).eps / 2 / gap)
+    bound = max(TOL, 100 * np.finfo(float).eps / 2 / gap)
+    assert O.rel_frob(host, o.cores) <= bound
+    if clean and gap >= 1e-6:
+        # Every rank decision is clear of rounding (no near-tie at the cut and
+        # every tail of Eq. (eps) at least a factor 4 from its threshold): the
+        # GPU's own decisions must be the oracle's.
+        C2, st2 = T.multiply(A, B, c["chi_out"], c["eps"], **kw)
+        host2 = [x.detach().cpu().numpy() for x in C2.cores()]
+        assert st2["ranks"] == o.ranks
+        assert O.rel_frob(host2, o.cores) <= bound
 
 
 def _oracle_with_gap(monkeypatch, A, B, c):
-    """The oracle's product, and the smallest relative gap at any of its
-    truncating cuts (1 when nothing is truncated)."""
+    """The oracle's product, the smallest relative gap at any of its
+    truncating cuts (1 when nothing is truncated), and whether every
+    decision of Eq. (eps) is clear of its threshold by a factor 4 (the tail
+    that decides the rank below a quarter of eps * total, the tail of one
+    value fewer above four times it)."""
     mod = sys.modules["oracle.ttm"]
     rule = mod.rank_rule
     gaps = [1.0]
+    clean = [True]
 
     def recording(s, eps, cap):
         r, disc = rule(s, eps, cap)
         if r < len(s) and s[0] > 0:
             gaps.append((s[r - 1] - s[r]) / s[0])
+        s = np.asarray(s, dtype=float)
+        tot = float(np.sum(s * s))
+        if tot > 0 and eps > 0:
+            r0, _ = rule(s, eps, 0)
+            at = float(np.sum(s[r0:] ** 2))
+            before = float(np.sum(s[r0 - 1:] ** 2))
+            if not (at == 0.0 or at <= 0.25 * eps * tot) or not (r0 == 1 or before >= 4 * eps * tot):
+                clean[0] = False
         return r, disc
 
     monkeypatch.setattr(mod, "rank_rule", recording)
     o = O.ttm(A, B, c["chi_out"], c["eps"], chi_mid=c["chi_mid"], final_round=c["final_round"])
     monkeypatch.undo()
-    return o, min(gaps)
+    return o, min(gaps), clean[0]

@@ -144,23 +144,70 @@ def test_gpu_config2_turbulence_vs_oracle(chi):
     assert st2["max_bond"] == o.max_bond
 
 
-def test_gpu_ten_sites_1024_turbulence_vs_oracle():
+_TEN_SITE_QTTS = {}
+
+
+def _ten_site_qtts(torch):
+    """The 1024^3 turbulence field (seed 101) as 10-site d = 8 QTTs at the
+    bonds of the sweep's lower half, generated once on the device."""
+    if not _TEN_SITE_QTTS:
+        _TEN_SITE_QTTS.update(I.turbulence_qtt_device(1024, 101, [64, 128, 256], torch.device("cuda", 0)))
+        torch.cuda.empty_cache()
+    return _TEN_SITE_QTTS
+
+
+@pytest.mark.parametrize("chi", [64, 128, 256])
+def test_gpu_ten_sites_1024_turbulence_vs_oracle(chi):
     """The 10-site, d = 8 shapes of the bond-dimension sweep (a 1024^3 field,
-    generated on the device) at chi = 64 against the oracle."""
+    generated on the device) against the oracle at chi = 64, 128 and 256:
+    the GPU's own (unforced) rank decisions equal the oracle's and the
+    products agree to 1e-12.  At chi = 256 the swap SVDs are 2048 x 2048."""
     torch = _torch()
-    _say("case: 1024^3 turbulence N=10 chi=64")
-    chi = 64
-    q = I.turbulence_qtt_device(1024, 101, [chi], torch.device("cuda", 0))[chi]
-    torch.cuda.empty_cache()
+    _say("case: 1024^3 turbulence N=10 chi=%d" % chi)
+    q = _ten_site_qtts(torch)[chi]
     assert len(q) == 10 and max(c.shape[2] for c in q) == chi
     o = O.ttm(q, q, chi, 1e-14)
+    _say("  oracle done, max bond %d" % max(o.ranks))
     C, st = _run(q, q, chi, 1e-14)
     assert st["ranks"] == o.ranks
-    assert O.rel_frob(C, o.cores) <= TOL
+    err = O.rel_frob(C, o.cores)
+    _say("  relative error vs oracle %.3e" % err)
+    assert err <= TOL
     assert st["n_swap"] == 45 and st["n_contract"] == 10
+    # Mixed precision at the same point: contractions with FP32 or three-term
+    # BF16 operands, QR / SVD / truncation in FP64, within 1e-6 of the FP64
+    # oracle.
+    for prec in ("f32", "bf16x3"):
+        Cm, stm = _run(q, q, chi, 1e-14, contract_precision=prec)
+        em = O.rel_frob(Cm, o.cores)
+        _say("  %s contractions: relative error vs FP64 oracle %.3e" % (prec, em))
+        assert em <= 1e-6
 
 
-@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("bf16x3", 1e-5), ("bf16", 5e-2)])
+def test_gpu_model_flops_golden():
+    """The library's flop count of a recorded schedule (ttm_stats.model_flops)
+    against the per-operation formulas evaluated by hand for two fixed
+    three-site schedules (tests/golden/model_flops.json), one with a factor
+    whose first bond exceeds the structural bound (a wide QR)."""
+    import json
+    import os
+    from fractions import Fraction
+    _say("case: flop model of fixed three-site schedules")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "model_flops.json")))
+    for sch in g["schedules"]:
+        rng = np.random.default_rng(sch["seed"])
+
+        def train(b):
+            return [rng.standard_normal((b[i], sch["d"], b[i + 1])) for i in range(len(b) - 1)]
+
+        A, B = train(sch["A_bonds"]), train(sch["B_bonds"])
+        C, st = _run(A, B, sch["chi_out"], sch["eps"])
+        assert st["ranks"] == sch["ranks"]
+        assert np.isclose(st["model_flops"], float(Fraction(sch["total"])), rtol=1e-14, atol=0)
+        assert O.rel_frob(C, O.ttm(A, B, sch["chi_out"], sch["eps"]).cores) <= TOL
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16x3", 1e-6), ("bf16", 5e-2)])
 def test_gpu_mixed_precision_contractions_vs_fp64_oracle(prec, bound):
     """Contractions with FP32 / 3 x BF16 / BF16 operands (FP32 accumulation),
     QR, SVD and truncation in FP64, against the FP64 oracle on the 256^3

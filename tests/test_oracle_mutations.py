@@ -95,6 +95,21 @@ MUTANTS = [
     ("inputs_not_canonicalised", "ttm",
      "        A = left_orthogonalize(A)\n        B = left_orthogonalize(B)",
      "        A = [np.array(c) for c in A]\n        B = [np.array(c) for c in B]"),
+    ("flops_merge_misses_a_leg", "ttm",
+     "total += 2.0 * dl * dx * dm * dp * dr",
+     "total += 2.0 * dl * dm * dp * dr"),
+    ("flops_svd_without_back_transform", "ttm",
+     "return 4.0 * m * n * n - (4.0 / 3.0) * n ** 3 + 4.0 * (m + n) * n * r",
+     "return 4.0 * m * n * n - (4.0 / 3.0) * n ** 3"),
+    ("flops_svd_sides_not_ordered", "ttm",
+     "    if m < n:\n        m, n = n, m\n    return 4.0 * m",
+     "    return 4.0 * m"),
+    ("flops_wide_qr_as_tall", "ttm",
+     "return 2.0 * n * m * m + (2.0 / 3.0) * m ** 3",
+     "return 4.0 * m * n * n - (4.0 / 3.0) * n ** 3"),
+    ("flops_gauge_move_product_not_recorded", "ttm",
+     "    res.ops.append((\"gemm\", k, rr, nxt.shape[1] * nxt.shape[2]))\n    res.n_qr += 1",
+     "    res.n_qr += 1"),
     ("discards_not_recorded", "ttm",
      "            res.discards.append(disc)\n            res.n_swap += 1",
      "            res.discards.append(0.0)\n            res.n_swap += 1"),

@@ -408,3 +408,43 @@ def test_device_turbulence_generator_on_host():
     k = np.fft.fftfreq(n, 1.0 / n)
     kk = np.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
     assert np.abs(uk[kk > n / 2]).max() < 1e-9 * np.abs(uk).max()
+
+
+# ---------------------------------------------------------------- flop model
+def _frac(s):
+    from fractions import Fraction
+    return Fraction(s)
+
+
+def _fixture_trains(sch):
+    rng = np.random.default_rng(sch["seed"])
+    d = sch["d"]
+
+    def train(b):
+        return [rng.standard_normal((b[i], d, b[i + 1])) for i in range(len(b) - 1)]
+
+    return train(sch["A_bonds"]), train(sch["B_bonds"])
+
+
+def test_model_flops_per_operation_golden():
+    """model_flops against the per-operation formulas evaluated by hand in
+    tests/golden/model_flops.json (both sides of the QR and SVD branches)."""
+    g = json.load(open(os.path.join(GOLD, "model_flops.json")))
+    for case in g["ops"]:
+        op = tuple(case["op"])
+        assert np.isclose(O.model_flops([op]), float(_frac(case["flops"])), rtol=1e-14, atol=0), op
+
+
+def test_model_flops_schedule_golden():
+    """The operation list the oracle records for a fixed three-site schedule
+    (every bond written out in the fixture) and its flop total."""
+    g = json.load(open(os.path.join(GOLD, "model_flops.json")))
+    for sch in g["schedules"]:
+        A, B = _fixture_trains(sch)
+        res = O.ttm(A, B, sch["chi_out"], sch["eps"])
+        want = [tuple(op) for op, _ in sch["ops"]]
+        assert [tuple(int(x) if not isinstance(x, str) else x for x in op) for op in res.ops] == want
+        assert res.ranks == sch["ranks"]
+        assert sum(_frac(f) for _, f in sch["ops"]) == _frac(sch["total"])
+        assert np.isclose(res.flops, float(_frac(sch["total"])), rtol=1e-14, atol=0)
+        assert res.n_contract == 3 and res.n_swap == 3
