@@ -110,6 +110,18 @@ def main():
                     help="measure the FP64 matrix-core rate that the roofline quotes as its peak")
     ap.add_argument("--adjoint", action="store_true",
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
+    ap.add_argument("--upper-chis", default="256,1024",
+                    help="bond dimensions of the 10-site 1024^3 points added to the default line")
+    ap.add_argument("--upper-precisions", default="f32,bf16x3",
+                    help="reduced contraction precisions timed at each added point")
+    ap.add_argument("--no-upper", action="store_true", help="skip the 10-site points of the default line")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the comparison with the dense exact product and the Eckart-Young floor")
+    ap.add_argument("--chi-mid-sweep", action="store_true",
+                    help="accuracy and time of chi_mid in {chi, 2 chi, 4 chi} against the exact product")
+    ap.add_argument("--chi-mid-chis", default="64,128")
+    ap.add_argument("--variants", action="store_true",
+                    help="schedule variants: the moving factor and where a swap leaves the gauge centre")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -137,6 +149,10 @@ def main():
         return binary_sites(args, dev)
     if args.mfma_peak:
         return mfma_peak(args, dev)
+    if args.chi_mid_sweep:
+        return chi_mid_sweep(args, dev)
+    if args.variants:
+        return variants(args, dev)
 
     if args.calibrate_copy:
         # A plain copy kernel of known size: 256 MiB read, 256 MiB written.
@@ -242,23 +258,45 @@ def main():
                 "tol": 1e-12, "max_sweeps": 10, "model_flops": stc["model_flops"]}
         _log("  conventional: %.1f ms per product, %d sweeps" % (1e3 * tc, stc["sweeps"]))
 
+    cores = [c.detach().cpu().numpy() for c in C.cores()]
+    accuracy = None
+    if not args.no_exact:
+        _log("accuracy against the dense exact product (%d entries) and the Eckart-Young floor" % args.grid ** 3)
+        conv_cores = [c.detach().cpu().numpy() for c in Cc.cores()] if conv is not None else None
+        accuracy = accuracy_vs_exact(ux, ux, cores, conv_cores, args.chi)
+        _log("  rel err vs exact: TTM %.4f, conventional %s, Eckart-Young floor %.4f"
+             % (accuracy["ttm"], "-" if accuracy["conventional"] is None else "%.4f" % accuracy["conventional"],
+                accuracy["eckart_young_floor"]))
+
     rel_err = None
     cpu = None
     if not args.no_cpu:
         import oracle as O
-        _log("CPU oracle on the same product (one product as the sample)")
+        from threadpoolctl import threadpool_limits
+        _log("CPU oracle on the same product (one product as the sample), all BLAS threads")
         t0 = time.perf_counter()
         ref = O.ttm(ux, ux, args.chi, args.eps)
         dt = time.perf_counter() - t0
-        cores = [c.detach().cpu().numpy() for c in C.cores()]
         rel_err = O.rel_frob(cores, ref.cores)
         if conv is not None:
             conv["rel_diff_vs_ttm"] = O.rel_frob([c.detach().cpu().numpy() for c in Cc.cores()], cores)
-        cpu = {"value": 1.0 / dt, "unit": "TT products/s", "cores": _cpu_threads(), "kind": "oracle",
-               "sample": "one full product (%d^3 u_x*u_x, chi=%d, eps=%g), %.1f s" % (args.grid, args.chi,
-                                                                                       args.eps, dt)}
         _log("  oracle %.2f s, GPU vs oracle rel. Frobenius error %.2e, ranks equal: %s"
              % (dt, rel_err, st["ranks"] == ref.ranks))
+        _log("CPU oracle, one BLAS thread (the paper's timings are from one core)")
+        with threadpool_limits(limits=1, user_api="blas"):
+            t1 = time.perf_counter()
+            O.ttm(ux, ux, args.chi, args.eps)
+            dt1 = time.perf_counter() - t1
+        _log("  oracle on one thread %.2f s" % dt1)
+        cpu = {"value": 1.0 / dt, "unit": "TT products/s", "cores": _cpu_threads(), "kind": "oracle",
+               "sample": "one full product (%d^3 u_x*u_x, chi=%d, eps=%g), %.1f s" % (args.grid, args.chi,
+                                                                                       args.eps, dt),
+               "one_thread": {"value": 1.0 / dt1, "unit": "TT products/s", "cores": 1,
+                              "sample": "the same product on one BLAS thread, %.1f s" % dt1}}
+
+    upper = None
+    if not args.no_upper:
+        upper = upper_points(args, dev)
 
     line = {
         "metric": "TT products/s + MFMA util vs \u03c7 (64\u20131024); mixed vs FP64 TTM at rel err 1e-6",
@@ -282,12 +320,174 @@ def main():
         "jacobi_sweeps_per_step": st["sweeps"],
         "max_bond": st["max_bond"],
         "rel_err_vs_oracle": rel_err,
+        "rel_err_vs_exact": accuracy,
         "kernel_time_share": kernel_share,
         "conventional": conv,
+        "bond_dimension_points": upper,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def accuracy_vs_exact(A, B, ttm_cores, conv_cores, chi):
+    """Relative Frobenius errors against the dense exact product A(x) B(x)
+    of the TTM result and the conventional fit, and the Eckart-Young floor
+    at bond chi: any TT with every bond <= chi is at least
+    sqrt(max_k sum_{i > chi} sigma_i(k)^2) / ||A*B|| from the exact product,
+    sigma(k) the singular values of the unfolding at cut k (computed from
+    the Gram matrix of the unfolding's shorter side).  Host-side harness."""
+    import numpy as np
+
+    import oracle as O
+
+    exact = (O.dense(A) * O.dense(B)).reshape(-1)
+    nrm = float(np.linalg.norm(exact))
+    out = {"ttm": float(np.linalg.norm(O.dense(ttm_cores).reshape(-1) - exact) / nrm),
+           "conventional": (float(np.linalg.norm(O.dense(conv_cores).reshape(-1) - exact) / nrm)
+                            if conv_cores is not None else None)}
+    phys = [c.shape[1] for c in A]
+    worst = 0.0
+    m = 1
+    for k in range(len(phys) - 1):
+        m *= phys[k]
+        M = exact.reshape(m, -1)
+        G = M @ M.T if M.shape[0] <= M.shape[1] else M.T @ M
+        ev = np.linalg.eigvalsh(G)[::-1]
+        worst = max(worst, float(np.sum(np.clip(ev[chi:], 0.0, None))))
+    out["eckart_young_floor"] = float(np.sqrt(worst) / nrm)
+    out["ttm_over_floor"] = out["ttm"] / out["eckart_young_floor"] if out["eckart_young_floor"] > 0 else None
+    if out["conventional"] is not None and out["eckart_young_floor"] > 0:
+        out["conventional_over_floor"] = out["conventional"] / out["eckart_young_floor"]
+    return out
+
+
+def upper_points(args, dev):
+    """The metric's upper bond dimensions on the 10-site shapes (a 1024^3
+    field, d = 8): one measure_point per chi in --upper-chis, FP64 and the
+    reduced contraction precisions of --upper-precisions.  Returns a list."""
+    import torch
+
+    import ttm_inputs as I
+
+    chis = [int(c) for c in args.upper_chis.split(",") if c]
+    if not chis:
+        return None
+    _log("10-site points: generating 1024^3 turbulence QTTs on the device for chi %s" % chis)
+    t0 = time.time()
+    qtts = I.turbulence_qtt_device(1024, 101, chis, dev)
+    torch.cuda.empty_cache()
+    _log("  done in %.1f s" % (time.time() - t0))
+    g = torch.Generator(device="cpu")
+    g.manual_seed(7)
+    idx = torch.randint(0, 8, (4096, 10), generator=g).to(dev)
+    pts = []
+    for chi in chis:
+        pt = measure_point(qtts[chi], chi, args.eps, idx, dev,
+                           [q for q in args.upper_precisions.split(",") if q and q != "f64"])
+        pt["workload"] = "3D turbulence QTT u_x*u_x, 1024^3 grid, N=10 sites, d=8"
+        pts.append(pt)
+        torch.cuda.empty_cache()
+    return pts
+
+
+def variants(args, dev):
+    """Schedule variants on the bench grid.  (1) Where a swap leaves the
+    gauge centre: u_x * u_x at chi --chi with the default (singular values
+    into the moving carriage) and with the stated reading (into the right
+    carriage, then an LQ move).  (2) Which factor moves: u_y (bond 32) times
+    u_x (bond --chi), chi_out = --chi, moving u_x (the second factor) or the
+    smaller u_y.  Time per product, QR count, largest bond, relative
+    difference between the two variants and error against the dense exact
+    product.  One JSON line per run."""
+    import torch
+
+    import oracle as O
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    chi = args.chi
+    ux = I.turbulence_qtt(args.grid, 101, chi)
+    uy = I.turbulence_qtt(args.grid, 102, 32)
+
+    def timed(A, B, **kw):
+        ws = T.Workspace(dev)
+        T.multiply(A, B, chi, args.eps, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            C, st = T.multiply(A, B, chi, args.eps, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        return C, st, (time.perf_counter() - t) / args.steps
+
+    exact_xx = (O.dense(ux) * O.dense(ux)).reshape(-1)
+    exact_yx = (O.dense(uy) * O.dense(ux)).reshape(-1)
+    runs = [("gauge", "moving", (ux, ux), {}), ("gauge", "right", (ux, ux), {"gauge": "right"}),
+            ("move_factor", "second", (uy, ux), {}), ("move_factor", "smaller", (uy, ux), {"move_factor": "smaller"})]
+    first = {}
+    for kind, name, (a, b), kw in runs:
+        C, st, dt = timed(T.pack(a, dev), T.pack(b, dev), **kw)
+        cores = [c.detach().cpu().numpy() for c in C.cores()]
+        exact = exact_xx if kind == "gauge" else exact_yx
+        err = float(((O.dense(cores).reshape(-1) - exact) ** 2).sum() ** 0.5 / (exact ** 2).sum() ** 0.5)
+        diff = None
+        if kind in first:
+            diff = O.rel_frob(cores, first[kind])
+        else:
+            first[kind] = cores
+        line = {"variant": kind, "setting": name, "workload": "3D turbulence QTTs, %d^3 grid, N=8 sites, d=8, %s"
+                % (args.grid, "u_x*u_x at chi %d" % chi if kind == "gauge" else "u_y (chi 32) * u_x (chi %d)" % chi),
+                "chi_out": chi, "eps": args.eps, "ms_per_product": 1e3 * dt, "n_qr": st["n_qr"],
+                "n_swap": st["n_swap"], "max_bond": st["max_bond"], "jacobi_sweeps": st["sweeps"],
+                "model_flops": st["model_flops"], "rel_err_vs_exact": err, "rel_diff_vs_default": diff}
+        print(json.dumps(line), flush=True)
+        _log("  %s=%s: %.1f ms, %d QRs, max bond %d, rel err vs exact %.4f%s"
+             % (kind, name, 1e3 * dt, st["n_qr"], st["max_bond"], err,
+                "" if diff is None else ", rel diff vs default %.2e" % diff))
+    return None
+
+
+def chi_mid_sweep(args, dev):
+    """The trade-off of the swap cap (the analogue of the bond growth of
+    Sec. II.B and Fig. 3C/D): the bench field squared at each chi of
+    --chi-mid-chis with chi_mid in {chi, 2 chi, 4 chi} and the final sweep
+    capping at chi: time per product, largest bond, error against the dense
+    exact product, beside the conventional fit and the Eckart-Young floor.
+    One JSON line per (chi, chi_mid)."""
+    import torch
+
+    import ttm_inputs as I
+    import paper_2410_19747_amd as T
+
+    for chi in [int(c) for c in args.chi_mid_chis.split(",") if c]:
+        ux = I.turbulence_qtt(args.grid, 101, chi)
+        A = T.pack(ux, dev)
+        Cc, _ = T.conventional(A, A, chi, 1e-12, max_sweeps=10)
+        conv_cores = [c.detach().cpu().numpy() for c in Cc.cores()]
+        floor = None
+        for mult in (1, 2, 4):
+            cm = mult * chi
+            ws = T.Workspace(dev)
+            T.multiply(A, A, chi, args.eps, chi_mid=cm, workspace=ws)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            C, st = T.multiply(A, A, chi, args.eps, chi_mid=cm, workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            acc = accuracy_vs_exact(ux, ux, [c.detach().cpu().numpy() for c in C.cores()],
+                                    conv_cores if floor is None else None, chi)
+            if floor is None:
+                floor = acc
+            line = {"chi_mid_sweep": True, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=8 sites, d=8"
+                    % args.grid, "chi": chi, "chi_mid": cm, "eps": args.eps, "ms_per_product": 1e3 * dt,
+                    "max_bond": st["max_bond"], "jacobi_sweeps": st["sweeps"], "model_flops": st["model_flops"],
+                    "rel_err_vs_exact": acc["ttm"], "conventional_rel_err_vs_exact": floor["conventional"],
+                    "eckart_young_floor": floor["eckart_young_floor"]}
+            print(json.dumps(line), flush=True)
+            _log("  chi=%d chi_mid=%d: %.1f ms, max bond %d, rel err vs exact %.4f (conventional %.4f, floor %.4f)"
+                 % (chi, cm, 1e3 * dt, st["max_bond"], acc["ttm"], floor["conventional"],
+                    floor["eckart_young_floor"]))
+    return None
 
 
 def _tt_entries(cores, idx):
@@ -325,65 +525,84 @@ def sweep(args, dev):
     g.manual_seed(7)
     idx = torch.randint(0, 8, (4096, n_sites), generator=g).to(dev)
     for chi in chis:
-        A = T.pack(qtts[chi], dev)
-        ws = T.Workspace(dev)
-        _, cap = T.query(A, A, chi)
-        out = torch.empty(cap, dtype=torch.float64, device=dev)
-        stream = torch.cuda.current_stream()
-        steps = 2 if chi <= 256 else 1
-        if chi <= 256:
-            T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            C, st = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps
-        share = None
-        if not args.no_profile:
-            _, sp = T.multiply(A, A, chi, args.eps, workspace=ws, out=out, stream=stream, profile=True)
-            tot = sum(sp["kernel_ms"].values())
-            share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
-        a_cores = A.cores()
-        exact = _tt_entries(a_cores, idx) ** 2
-        got = _tt_entries(C.cores(), idx)
-        rel = float(torch.linalg.norm(got - exact) / torch.linalg.norm(exact))
-        # Mixed-precision contractions at the same point: time and the relative
-        # difference of the sampled entries from the FP64 product's.
-        mixed = {}
-        for prec in [q for q in args.sweep_precisions.split(",") if q and q != "f64"]:
-            torch.cuda.synchronize()
-            tm = time.perf_counter()
-            Cm, stm = T.multiply(A, A, chi, args.eps, workspace=ws, out=torch.empty_like(out), stream=stream,
-                                 contract_precision=prec)
-            torch.cuda.synchronize()
-            tm = time.perf_counter() - tm
-            gm = _tt_entries(Cm.cores(), idx)
-            mixed[prec] = {"ms_per_product": 1e3 * tm,
-                           "sampled_rel_diff_vs_f64": float(torch.linalg.norm(gm - got) / torch.linalg.norm(got)),
-                           "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"]}
-            _log("    %s contractions: %.1f ms, sampled rel diff vs FP64 %.2e"
-                 % (prec, 1e3 * tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
-            del Cm
-        line = {
-            "sweep": True, "chi": chi, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=8"
-            % (args.sweep_grid, n_sites), "eps": args.eps, "chi_out": chi, "chi_mid": chi,
-            "products_per_s": 1.0 / dt, "ms_per_product": 1e3 * dt, "steps": steps,
-            "model_flops": st["model_flops"], "svd_model_flops": st["svd_model_flops"],
-            "algorithmic_tflops": st["model_flops"] / dt / 1e12,
-            "fp64_mfma_frac": st["model_flops"] / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS,
-            "jacobi_sweeps": st["sweeps"], "jacobi_max_sweeps": st["jacobi_max_sweeps"],
-            "max_bond": st["max_bond"], "n_svd": st["n_svd"],
-            "sampled_rel_err_vs_exact": rel, "sampled_points": int(idx.shape[0]),
-            "error_bound_abs": st["error_bound"], "kernel_time_share": share,
-            "mixed_precision": mixed or None,
-            "workspace_bytes": st["peak_ws_bytes"],
-        }
+        line = measure_point(qtts[chi], chi, args.eps, idx, dev,
+                             [q for q in args.sweep_precisions.split(",") if q and q != "f64"],
+                             profile=not args.no_profile)
+        line = dict({"sweep": True, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=8"
+                     % (args.sweep_grid, n_sites)}, **line)
         print(json.dumps(line), flush=True)
-        _log("  chi=%d: %.1f ms per product, %.3f TFLOP/s algorithmic, %d sweeps, sampled rel err %.2e"
-             % (chi, 1e3 * dt, line["algorithmic_tflops"], st["sweeps"], rel))
-        del A, C, out, ws
         torch.cuda.empty_cache()
+
+
+def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=None):
+    """One point of the bond-dimension sweep: u * u for the QTT ``cores`` at
+    chi_out = chi_mid = chi.  FP64 products per second (after one warm-up
+    product below chi 512), the algorithmic flop rate and its fraction of
+    the FP64 MFMA peak, Jacobi sweeps, the relative error of the sampled
+    entries ``idx`` against the exact square A(x)^2, and for each reduced
+    contraction precision its time and the relative difference of the
+    sampled entries from the FP64 product's.  Returns a dict."""
+    import torch
+
+    import paper_2410_19747_amd as T
+
+    A = T.pack(cores, dev)
+    ws = T.Workspace(dev)
+    _, cap = T.query(A, A, chi)
+    out = torch.empty(cap, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    if steps is None:
+        steps = 2 if chi <= 256 else 1
+    if chi <= 256:
+        T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        C, st = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    share = None
+    if profile:
+        _, sp = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream, profile=True)
+        tot = sum(sp["kernel_ms"].values())
+        share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
+    exact = _tt_entries(A.cores(), idx) ** 2
+    got = _tt_entries(C.cores(), idx)
+    rel = float(torch.linalg.norm(got - exact) / torch.linalg.norm(exact))
+    # Mixed-precision contractions at the same point: time and the relative
+    # difference of the sampled entries from the FP64 product's.
+    mixed = {}
+    for prec in precisions:
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        Cm, stm = T.multiply(A, A, chi, eps, workspace=ws, out=torch.empty_like(out), stream=stream,
+                             contract_precision=prec)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - tm
+        gm = _tt_entries(Cm.cores(), idx)
+        mixed[prec] = {"ms_per_product": 1e3 * tm, "speedup_vs_f64": dt / tm,
+                       "sampled_rel_diff_vs_f64": float(torch.linalg.norm(gm - got) / torch.linalg.norm(got)),
+                       "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"]}
+        _log("    %s contractions: %.1f ms, sampled rel diff vs FP64 %.2e"
+             % (prec, 1e3 * tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
+        del Cm
+    line = {
+        "chi": chi, "eps": eps, "chi_out": chi, "chi_mid": chi,
+        "products_per_s": 1.0 / dt, "ms_per_product": 1e3 * dt, "steps": steps,
+        "model_flops": st["model_flops"], "svd_model_flops": st["svd_model_flops"],
+        "algorithmic_tflops": st["model_flops"] / dt / 1e12,
+        "fp64_mfma_frac": st["model_flops"] / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+        "jacobi_sweeps": st["sweeps"], "jacobi_max_sweeps": st["jacobi_max_sweeps"],
+        "max_bond": st["max_bond"], "n_svd": st["n_svd"],
+        "sampled_rel_err_vs_exact": rel, "sampled_points": int(idx.shape[0]),
+        "error_bound_abs": st["error_bound"], "kernel_time_share": share,
+        "mixed_precision": mixed or None,
+        "workspace_bytes": st["peak_ws_bytes"],
+    }
+    _log("  chi=%d: %.1f ms per product, %.3f TFLOP/s algorithmic, %d sweeps, sampled rel err %.2e"
+         % (chi, 1e3 * dt, line["algorithmic_tflops"], st["sweeps"], rel))
+    del A, C, out, ws
+    return line
 
 
 def batched(args, dev):

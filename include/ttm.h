@@ -102,7 +102,23 @@ typedef struct ttm_options {
                               TTM_PREC_BF16X3, the last three on the FP32 / BF16 matrix cores,
                               accumulated in FP32 within each 16-deep k-tile and in FP64
                               across k-tiles; QR, SVD and truncation stay FP64 */
+  int32_t move_factor;     /* which train is reversed and moved by the swaps: TTM_MOVE_SECOND
+                              (default: the second factor, psi of Sec. II.B) or TTM_MOVE_SMALLER
+                              (the train with the smaller largest bond; ties: the second).  The
+                              product is the same (A * B = B * A); exact intermediate bonds are
+                              bounded by chi_fixed chi_moving^2 */
+  int32_t gauge;           /* where each swap leaves the gauge centre: TTM_GAUGE_MOVING (default:
+                              the singular values go into the carriage that moves on, so the
+                              centre is inside the next pair) or TTM_GAUGE_RIGHT (as Sec. II.B
+                              states it: into the right carriage of the pair, after which an LQ
+                              factorisation of that carriage moves the centre into the moving
+                              one before the next swap; one extra QR per swap, the same result
+                              in exact arithmetic) */
 } ttm_options;
+
+/* Values of ttm_options.move_factor and ttm_options.gauge. */
+enum { TTM_MOVE_SECOND = 0, TTM_MOVE_SMALLER = 1 };
+enum { TTM_GAUGE_MOVING = 0, TTM_GAUGE_RIGHT = 1 };
 
 /* Values of ttm_options.contract_precision: operands of the contractions in
  * FP64; rounded to FP32; rounded to BF16; or each split into three BF16

@@ -36,7 +36,7 @@ from .tt import (  # noqa: F401
     is_left_orthonormal,
     is_right_orthonormal,
 )
-from .ttm import contract, swap, ttm, TTMResult, model_flops  # noqa: F401
+from .ttm import contract, swap, swap_centre_right, ttm, TTMResult, model_flops  # noqa: F401
 from .conventional import (  # noqa: F401
     kron_cores,
     conventional_exact,

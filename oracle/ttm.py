@@ -44,15 +44,12 @@ def contract(a_core, x_core):
     return out
 
 
-def swap(p_core, x_core, eps, cap, forced=None):
-    """The Swap of Fig. 1C and Eq. (eps).
-
-    The pair (p_core, x_core) = (P[a, eta, c], X[c, w, b]) is contracted over
-    its shared bond, the physical legs are exchanged, the result is unfolded
-    as rows (a, w) and columns (eta, b), and a truncated SVD splits it again:
-    X' = U_r S_r (moves left, carries the centre), P' = V_r^T.
-    Returns (X', P', r, discarded weight, singular values).
-    """
+def _merge_and_split(p_core, x_core, eps, cap, forced):
+    """The common part of a Swap (Fig. 1C, Eq. (eps)): the pair (p_core,
+    x_core) = (P[a, eta, c], X[c, w, b]) is contracted over its shared bond,
+    the physical legs are exchanged, the result is unfolded as rows (a, w)
+    and columns (eta, b), and its SVD is truncated by the rule of Eq. (eps)
+    (or at a forced rank).  Returns (u, s, vt, r, discarded weight)."""
     dl, dp, dm = p_core.shape
     dm2, dx, dr = x_core.shape
     assert dm == dm2
@@ -65,9 +62,39 @@ def swap(p_core, x_core, eps, cap, forced=None):
         r = int(forced)
         assert 1 <= r <= s.shape[0]
         disc = float(np.sum(s[r:][::-1] ** 2)) if r < s.shape[0] else 0.0
+    return u, s, vt, r, disc
+
+
+def swap(p_core, x_core, eps, cap, forced=None):
+    """The Swap of Fig. 1C and Eq. (eps), the singular values kept in the
+    carriage that moves on: X' = U_r S_r (moves left, carries the centre),
+    P' = V_r^T.  Returns (X', P', r, discarded weight, singular values)."""
+    dl, dp, _ = p_core.shape
+    _, dx, dr = x_core.shape
+    u, s, vt, r, disc = _merge_and_split(p_core, x_core, eps, cap, forced)
     x_new = (u[:, :r] * s[:r]).reshape(dl, dx, r)
     p_new = vt[:r].reshape(r, dp, dr)
     return x_new, p_new, r, disc, s
+
+
+def swap_centre_right(p_core, x_core, eps, cap, forced=None):
+    """The Swap with the gauge centre where the mixed-canonical paragraph of
+    Sec. II.B puts it: on the right carriage of the pair, the singular values
+    absorbed to the right (X' = U_r, P' = S_r V_r^T).  The next swap pairs X'
+    with the carriage to its left, so the centre is first moved into X' by
+    an LQ factorisation P' = L Q (X' <- X' L, P' <- Q).
+    Returns (X', P', r, discarded weight, singular values, R) with R the
+    triangular factor of the QR of P'^T (L = R^T)."""
+    dl, dp, _ = p_core.shape
+    _, dx, dr = x_core.shape
+    u, s, vt, r, disc = _merge_and_split(p_core, x_core, eps, cap, forced)
+    x_new = u[:, :r]                       # U_r, orthonormal columns
+    p_new = s[:r, None] * vt[:r]           # S_r V_r^T holds the centre
+    # LQ of P': the QR of its transpose, P'^T = Q R, so P' = R^T Q^T
+    q, rf = np.linalg.qr(p_new.T, mode="reduced")
+    x_new = x_new @ rf.T
+    p_new = q.T
+    return x_new.reshape(dl, dx, r), p_new.reshape(r, dp, dr), r, disc, s, rf
 
 
 def _svd_flops(m, n, r):
@@ -148,13 +175,22 @@ def _qr_move_right(cores, p, res):
 
 
 def ttm(A, B, chi_out, eps, chi_mid=None, final_round=True, forced_ranks=None,
-        canonicalize=True):
+        canonicalize=True, move_factor="second", gauge="moving"):
     """The TTM product of two TTs, C = A * B elementwise.
 
     ``chi_mid``: rank cap of every swap (None: same as chi_out; 0: uncapped).
     ``forced_ranks``: optional list of ranks that replaces the rule of Eq.
     (eps) for each truncating SVD in order (swaps, then the final sweep).
+    ``move_factor``: "second" (psi, as in Sec. II.B) or "smaller" (the
+    train with the smaller largest bond is reversed and moved; ties: the
+    second).  ``gauge``: "moving" (singular values into the carriage that
+    moves on) or "right" (into the right carriage of the pair, as Sec. II.B
+    states, followed by an LQ move of the centre, see swap_centre_right).
     """
+    assert move_factor in ("second", "smaller") and gauge in ("moving", "right")
+    if move_factor == "smaller":
+        if max(c.shape[0] for c in A) < max(c.shape[0] for c in B):
+            A, B = B, A
     n = len(A)
     assert len(B) == n and n >= 1
     for a, b in zip(A, B):
@@ -210,8 +246,15 @@ def ttm(A, B, chi_out, eps, chi_mid=None, final_round=True, forced_ranks=None,
             dl, dp, dm = Pi[p].shape
             _, dx, dr = x.shape
             res.ops.append(("merge", dl, dp, dm, dx, dr))
-            x, Pi[p], r, disc, _ = swap(Pi[p], x, eps, chi_mid, take_forced())
-            res.ops.append(("svd", dl * dx, dp * dr, r))
+            if gauge == "moving":
+                x, Pi[p], r, disc, _ = swap(Pi[p], x, eps, chi_mid, take_forced())
+                res.ops.append(("svd", dl * dx, dp * dr, r))
+            else:
+                x, Pi[p], r, disc, _, _ = swap_centre_right(Pi[p], x, eps, chi_mid, take_forced())
+                res.ops.append(("svd", dl * dx, dp * dr, r))
+                res.ops.append(("qr", dp * dr, r))
+                res.ops.append(("gemm", dl * dx, r, r))
+                res.n_qr += 1
             res.ranks.append(r)
             res.discards.append(disc)
             res.n_swap += 1

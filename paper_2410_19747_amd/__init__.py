@@ -154,10 +154,13 @@ _DEFAULT_WS = {}
 
 
 def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, seed=12345,
-             forced_ranks=None, trace_cap=0, profile=False, contract_precision="f64"):
+             forced_ranks=None, trace_cap=0, profile=False, contract_precision="f64", move_factor="second",
+             gauge="moving"):
     from ._abi import PRECISIONS
     o = TtmOptions()
     lib().ttm_default_options(ctypes.byref(o))
+    o.move_factor = {"second": 0, "smaller": 1}[move_factor] if isinstance(move_factor, str) else int(move_factor)
+    o.gauge = {"moving": 0, "right": 1}[gauge] if isinstance(gauge, str) else int(gauge)
     o.contract_precision = (PRECISIONS[contract_precision] if isinstance(contract_precision, str)
                             else int(contract_precision))
     o.chi_mid = -1 if chi_mid is None else int(chi_mid)
@@ -270,7 +273,8 @@ def multiply(A, B, chi_out, tol, **opts):
     """C = A * B elementwise by TTM.  Returns (PackedTT, stats dict).
 
     Options: chi_mid, final_round, svd_max_sweeps, forced_ranks, trace_cap,
-    profile, contract_precision ("f64", "f32", "bf16" or "bf16x3")."""
+    profile, contract_precision ("f64", "f32", "bf16" or "bf16x3"),
+    move_factor ("second" or "smaller"), gauge ("moving" or "right")."""
     return _run("ttm", A, B, chi_out, tol, **opts)
 
 
@@ -412,17 +416,31 @@ def _make_inner_loss_function():
         (ttm_multiply_ex), then <W, C> (ttm_inner_grad against the all-ones
         train).  Backward: dL/dA, dL/dB of <W, A*B> by ttm_inner_grad, the
         environments recomputed from W, A and B (nothing kept from the
-        forward pass but the inputs)."""
+        forward pass but the inputs).  That is the gradient of the loss only
+        where the product's truncations dropped nothing (TTM(A, B) = A*B);
+        reverse mode through the truncated swaps is not built, so backward
+        raises when the forward product's discarded weight exceeds rounding
+        (its error bound above 1e-12 of ||A|| ||B||)."""
 
         @staticmethod
         def forward(ctx, a_data, b_data, A, B, W, chi_out, tol, prec, opts):
-            C, _ = multiply(A, B, chi_out, tol, contract_precision=prec, **opts)
+            C, st = multiply(A, B, chi_out, tol, contract_precision=prec, **opts)
             value, _, _ = inner_grad(W, C, _ones_like_train(C), contract_precision=prec, grads=False)
+            na, _, _ = inner_grad(A, A, _ones_like_train(A), grads=False)
+            nb, _, _ = inner_grad(B, B, _ones_like_train(B), grads=False)
+            scale = max(na, 0.0) ** 0.5 * max(nb, 0.0) ** 0.5
             ctx.trains = (A, B, W, prec)
+            ctx.truncated = st["error_bound"] > 1e-12 * scale
+            ctx.error_bound = st["error_bound"]
             return torch.tensor(value, dtype=torch.float64, device=a_data.device)
 
         @staticmethod
         def backward(ctx, g):
+            if ctx.truncated:
+                raise NotImplementedError(
+                    "ttm_inner_loss: the forward product truncated (error bound %.3e), and reverse mode "
+                    "through the truncated swaps is not built; the gradient of the exact <W, A*B> is "
+                    "available from inner_grad" % ctx.error_bound)
             A, B, W, prec = ctx.trains
             _, dA, dB = inner_grad(W, A, B, contract_precision=prec)
             return g * dA.data, g * dB.data, None, None, None, None, None, None, None
@@ -436,7 +454,9 @@ _INNER_LOSS = None
 def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
     """0-d tensor <W, TTM(A, B)> whose backward gives dL/dA.data and
     dL/dB.data (PackedTT data tensors with requires_grad) through the
-    adjoint environments of ttm_inner_grad.  W is a constant train."""
+    adjoint environments of ttm_inner_grad.  W is a constant train.  The
+    backward is exact where the product's truncations drop nothing and
+    raises NotImplementedError where they drop weight."""
     global _INNER_LOSS
     if _INNER_LOSS is None:
         _INNER_LOSS = _make_inner_loss_function()
@@ -444,7 +464,7 @@ def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
     return _INNER_LOSS.apply(A.data, B.data, A, B, W, int(chi_out), float(tol), contract_precision, opts)
 
 
-def tune_batch_streams(pairs, chi_out, tol, candidates=(2, 4, 8), repeats=1, **opts):
+def tune_batch_streams(pairs, chi_out, tol, candidates=(1, 2, 4), repeats=1, **opts):
     """Products in flight for ttm_multiply_batch, chosen by measurement: each
     candidate stream count runs the whole batch `repeats` times and the
     fastest wins.  For a batch that recurs (the nine advective products of

@@ -54,6 +54,8 @@ class TtmOptions(ctypes.Structure):
         ("discard_trace", F64P),
         ("profile", ctypes.c_int32),
         ("contract_precision", ctypes.c_int32),
+        ("move_factor", ctypes.c_int32),
+        ("gauge", ctypes.c_int32),
     ]
 
 
@@ -78,6 +80,8 @@ class TtmStats(ctypes.Structure):
 
 
 TTM_PREC_F64, TTM_PREC_F32, TTM_PREC_BF16, TTM_PREC_BF16X3 = 0, 1, 2, 3
+TTM_MOVE_SECOND, TTM_MOVE_SMALLER = 0, 1
+TTM_GAUGE_MOVING, TTM_GAUGE_RIGHT = 0, 1
 PRECISIONS = {"f64": TTM_PREC_F64, "f32": TTM_PREC_F32, "bf16": TTM_PREC_BF16, "bf16x3": TTM_PREC_BF16X3}
 
 KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_solve", "jacobi_other", "other", "jacobi_apply"]

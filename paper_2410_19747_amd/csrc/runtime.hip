@@ -69,6 +69,8 @@ struct Options {
   double *discard_trace = nullptr;
   int profile = 0;
   int contract_prec = GEMM_F64;
+  int move_factor = TTM_MOVE_SECOND;
+  int gauge = TTM_GAUGE_MOVING;
 };
 
 // Largest matrix a QR or SVD step takes: each side at most 2^30 (the kernels
@@ -140,7 +142,22 @@ int resolve_options(const ttm_options *o, int chi_out, Options &r) {
   r.profile = o->profile;
   if (o->contract_precision < TTM_PREC_F64 || o->contract_precision > TTM_PREC_BF16X3) return TTM_EINVAL;
   r.contract_prec = o->contract_precision;  // TTM_PREC_* and GemmPrec share their values
+  if (o->move_factor != TTM_MOVE_SECOND && o->move_factor != TTM_MOVE_SMALLER) return TTM_EINVAL;
+  r.move_factor = o->move_factor;
+  if (o->gauge != TTM_GAUGE_MOVING && o->gauge != TTM_GAUGE_RIGHT) return TTM_EINVAL;
+  r.gauge = o->gauge;
   return TTM_OK;
+}
+
+// With move_factor = TTM_MOVE_SMALLER the train with the smaller largest
+// bond plays the moving (second) factor: returns true when A and B trade
+// places.
+bool moves_first(const ttm_tt *A, const ttm_tt *B, const Options &o) {
+  if (o.move_factor != TTM_MOVE_SMALLER) return false;
+  int ma = 1, mb = 1;
+  for (int i = 0; i <= A->n_sites; ++i) ma = std::max(ma, A->bonds[i]);
+  for (int i = 0; i <= B->n_sites; ++i) mb = std::max(mb, B->bonds[i]);
+  return ma < mb;
 }
 
 // ------------------------------------------------------------------ planning
@@ -222,6 +239,7 @@ void note_qr(Plan &pl, int m, int n) {
 }
 
 int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, Plan &pl) {
+  if (moves_first(A, B, o)) std::swap(A, B);
   const int n = A->n_sites;
   pl.n = n;
   pl.phys.assign(A->phys, A->phys + n);
@@ -265,8 +283,15 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     for (int p = n - 1; p > j; --p) {
       if (!unfolding_ok((int64_t)pi[p].rl * x.d, (int64_t)pi[p].d * x.rr)) return TTM_EINVAL;
       const int m = pi[p].rl * x.d, nn = pi[p].d * x.rr;
-      if (!note_svd(pl, m, nn, true)) return TTM_EUNSUPPORTED;
       const int r = swap_cap(o, pl.phys, j, p, pi[p], x);
+      if (o.gauge == TTM_GAUGE_RIGHT) {
+        // SVD with the orthonormal factor over the rows (a, w), then the LQ of
+        // S_r V_r^T (r x nn): a QR of its transpose and the r x r factor
+        if (!note_svd(pl, nn, m, true)) return TTM_EUNSUPPORTED;
+        note_qr(pl, nn, r);
+      } else if (!note_svd(pl, m, nn, true)) {
+        return TTM_EUNSUPPORTED;
+      }
       Shape xn = {pi[p].rl, x.d, r};
       Shape pn = {r, pi[p].d, x.rr};
       note_core(pl, xn);
@@ -293,8 +318,9 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
   pl.out_shapes = pi;
   pl.out_capacity = 0;
   for (int i = 0; i < n; ++i) pl.out_capacity += pi[i].size();
-  // Slots: A (N) + B (N) + B~/Pi (N) + X + 3 spares.
-  pl.nslots = 3 * n + 4;
+  // Slots: A (N) + B (N) + B~/Pi (N) + X + 3 spares (4 when each swap also
+  // runs an LQ move: its Q and the moved carriage are held at once).
+  pl.nslots = 3 * n + (o.gauge == TTM_GAUGE_RIGHT ? 5 : 4);
   size_t bytes = 0;
   bytes += (size_t)pl.nslots * align_up((size_t)pl.max_core * 8);
   bytes += align_up((size_t)pl.max_w * 8);
@@ -468,6 +494,10 @@ struct Runner {
   // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
   void swap(Core &P, Core &X, int cap) {
     step = "a swap";
+    if (o.gauge == TTM_GAUGE_RIGHT) {
+      swap_centre_right(P, X, cap);
+      return;
+    }
     const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
     const int m = Dl * dx, n = dp * Dr;
     const SvdPlan sp = svd_plan(m, n);
@@ -507,6 +537,86 @@ struct Runner {
     give(P.p);
     give(X.p);
     X.p = xn;
+    X.s = {Dl, dx, r};
+    P.p = pn;
+    P.s = {r, dp, Dr};
+    ++n_swap;
+    note(X.s);
+    note(P.s);
+  }
+
+  // ---- The swap with the centre put where Sec. II.B puts it: the singular
+  // values go to the right carriage, X' = U_r and P' = S_r V_r^T; then an LQ
+  // factorisation P' = L Q moves the centre into the carriage that moves on
+  // (X' <- X' L, P' <- Q), so that the next pair holds it.  In exact
+  // arithmetic L Q = S_r V_r^T with L = S_r (up to signs), and the result is
+  // the one of the default gauge.
+  void swap_centre_right(Core &P, Core &X, int cap) {
+    const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
+    const int m = Dl * dx, n = dp * Dr;
+    // Theta row-major (m x n) is the column-major n x m matrix Theta^T, whose
+    // right singular vectors are Theta's left ones.
+    const SvdPlan sp = svd_plan(n, m);
+    double *Y = wbuf;
+    double *sws = wbuf + ((((int64_t)m * n) + 31) & ~(int64_t)31);
+    GemmArgs g;
+    g.M = Dl * dp; g.N = dx * Dr; g.K = Dm;
+    g.A = P.p; g.a_rs = Dm; g.a_cs = 1;
+    g.B = X.p; g.b_rs = (int64_t)dx * Dr; g.b_cs = 1;
+    g.C = Y;
+    g.c_rdiv = dp; g.c_cdiv = Dr;
+    g.c_rs1 = (int64_t)dx * n; g.c_rs0 = Dr; g.c_cs1 = n; g.c_cs0 = 1;
+    g.prec = o.contract_prec;
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(g, st))) return;
+    }
+    flops += 2.0 * Dl * dp * (double)Dm * dx * Dr;
+    double *xn = take();
+    double *pn = take();
+    if (!xn || !pn) return;
+    // X' = U_r -> [Dl, dx, r] (orthonormal over the rows (a, w))
+    const int r = svd(sp, Y, sws, cap, xn, SVD_U);
+    if (r < 1) return;
+    // P' = U_r^T Theta = S_r V_r^T -> [r, dp, Dr]
+    GemmArgs z;
+    z.M = r; z.N = n; z.K = m;
+    z.A = xn; z.a_rs = 1; z.a_cs = r;
+    z.B = Y; z.b_rs = n; z.b_cs = 1;
+    z.C = pn; z.c_rs1 = n; z.c_cs1 = 1;
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(z, st))) return;
+    }
+    // LQ of P' through the QR of its transpose: P'^T = Q R, so P' = R^T Q^T
+    double *q = take();
+    double *xl = take();
+    if (!q || !xl) return;
+    {
+      Timed tm(&timer, KC_QR, st);
+      if (!hip(launch_qr(pn, n, r, 1, n, q, rbuf, qrbuf, st))) return;
+    }
+    {
+      Timed tm(&timer, KC_OTHER, st);
+      if (!hip(launch_transpose(pn, q, n, r, st))) return;  // P' <- Q^T (r x n)
+    }
+    GemmArgs h;  // X' <- X' R^T (m x r)
+    h.M = m; h.N = r; h.K = r;
+    h.A = xn; h.a_rs = r; h.a_cs = 1;
+    h.B = rbuf; h.b_rs = 1; h.b_cs = r;
+    h.C = xl; h.c_rs1 = r; h.c_cs1 = 1;
+    {
+      Timed tm(&timer, KC_GEMM, st);
+      if (!hip(launch_gemm(h, st))) return;
+    }
+    ++n_qr;
+    flops += 4.0 * n * (double)r * r - (4.0 / 3.0) * r * (double)r * r;
+    flops += 2.0 * m * (double)r * r;
+    give(q);
+    give(xn);
+    give(P.p);
+    give(X.p);
+    X.p = xl;
     X.s = {Dl, dx, r};
     P.p = pn;
     P.s = {r, dp, Dr};
@@ -561,6 +671,8 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
   int e = make_plan(A, B, chi_out, o, pl);
   if (e) return e;
   if (!ws || ws_bytes < pl.ws_bytes) return TTM_EWORKSPACE;
+  // the factor that moves plays B (make_plan made the same choice)
+  if (moves_first(A, B, o)) std::swap(A, B);
   if (!C || !C->bonds || !C->offsets || !C->data) return TTM_EINVAL;
   if (C->capacity < pl.out_capacity) return TTM_ECAPACITY;
   const int n = pl.n;

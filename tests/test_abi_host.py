@@ -305,3 +305,19 @@ def test_svd_size_limit_rejected_by_query(L):
     T = _TT([8] * 10, b10)
     assert _query(L, T, T, 1024)[0] == _abi.TTM_OK
     assert b"SVD" in L.ttm_strerror(_abi.TTM_EUNSUPPORTED)
+
+
+def test_last_error_is_cleared_by_each_call(L):
+    """ttm_last_error describes the last failure of a compute call on this
+    thread and is emptied when the next call starts."""
+    big = _TT([8] * 8, [1, 8, 64, 128, 128, 128, 64, 8, 1])
+    bonds = (ctypes.c_int32 * 9)()
+    offs = (ctypes.c_int64 * 8)()
+    out = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000),
+                        1 << 30)
+    assert L.ttm_multiply_ex(ctypes.byref(big.view), ctypes.byref(big.view), 128, 1e-14, ctypes.byref(out),
+                             None, 0, None, None, None) == _abi.TTM_EWORKSPACE
+    # an argument error of the next call leaves no stale text behind
+    assert L.ttm_multiply_ex(ctypes.byref(big.view), ctypes.byref(big.view), 0, 1e-14, ctypes.byref(out),
+                             None, 0, None, None, None) == _abi.TTM_EINVAL
+    assert L.ttm_last_error() == b""

@@ -130,6 +130,26 @@ def test_gpu_autograd_loss_matches_finite_differences():
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
 
 
+def test_gpu_autograd_loss_refuses_truncated_products():
+    """Where the TTM product truncates, <W, TTM(A, B)> is not <W, A*B>, and
+    the gradient of the latter is not the former's: backward raises rather
+    than return it.  The forward value is still the truncated product's."""
+    import paper_2410_19747_amd as T
+    torch = _torch()
+    _say("case: autograd loss on a truncating product")
+    W = I.random_tt(10, 2, 4, 21)
+    A, B = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2)
+    Ap, Bp = T.pack(A), T.pack(B)
+    Ap.data.requires_grad_(True)
+    Bp.data.requires_grad_(True)
+    loss = T.ttm_inner_loss(W, Ap, Bp, 8, 1e-14)
+    o = O.ttm(A, B, 8, 1e-14)
+    vo = O.inner3(W, o.cores, [np.ones((1, 2, 1))] * 10)
+    assert abs(float(loss.detach()) - vo) <= 1e-12 * max(1.0, abs(vo))
+    with pytest.raises(NotImplementedError):
+        loss.backward()
+
+
 def test_gpu_inner_grad_error_codes():
     import paper_2410_19747_amd as T
     _torch()

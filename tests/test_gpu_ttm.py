@@ -343,3 +343,52 @@ def test_gpu_degenerate_inputs():
     o = O.ttm(W, V, 16, 1e-14, chi_mid=0)
     assert st["ranks"] == o.ranks and O.bonds_of(C) == O.bonds_of(o.cores)
     assert O.rel_frob(C, O.brute_force(W, V)) <= TOL
+
+
+@pytest.mark.parametrize("case", ["r10", "turbulence256_chi64"])
+def test_gpu_gauge_centre_right_vs_oracle(case):
+    """The swap with the singular values on the right carriage and an LQ move
+    of the centre (ttm_options.gauge = TTM_GAUGE_RIGHT, the gauge as Sec. II.B
+    states it) against the oracle's same variant and against the default
+    gauge: identical ranks, 1e-12, one extra QR per swap."""
+    _say("case: gauge centre right, %s" % case)
+    if case == "r10":
+        A, B, chi = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2), 8
+    else:
+        A = I.turbulence_qtt(256, 101, 64)
+        B, chi = A, 64
+    o = O.ttm(A, B, chi, 1e-14, gauge="right")
+    C, st = _run(A, B, chi, 1e-14, gauge="right")
+    assert st["ranks"] == o.ranks
+    assert O.rel_frob(C, o.cores) <= TOL
+    Cm, stm = _run(A, B, chi, 1e-14)
+    assert stm["ranks"] == st["ranks"]
+    assert O.rel_frob(C, Cm) <= TOL
+    assert st["n_qr"] == stm["n_qr"] + st["n_swap"]
+    assert np.isclose(st["model_flops"], o.flops, rtol=1e-12)
+    if case == "r10":
+        ex, _ = _run(A, B, 64, 1e-28, chi_mid=0, gauge="right")
+        assert O.rel_frob(ex, O.brute_force(A, B)) <= TOL
+
+
+def test_gpu_move_smaller_factor_vs_oracle():
+    """ttm_options.move_factor = TTM_MOVE_SMALLER: the train with the smaller
+    bonds is reversed and moved.  Exact product of a chi-16 and a chi-2 train
+    on 16 binary sites (swap ranks within 16 * 2 * 2, unlike moving the wide
+    one) and a truncated 256^3 product with uneven bonds, against the oracle
+    with the same option."""
+    _say("case: move the smaller factor")
+    wide = I.random_tt(16, 2, 16, 61)
+    narrow = I.random_tt(16, 2, 2, 62)
+    ex, st = _run(narrow, wide, 4096, 1e-28, chi_mid=0, move_factor="smaller")
+    o = O.ttm(narrow, wide, 4096, 1e-28, chi_mid=0, move_factor="smaller")
+    assert O.rel_frob(ex, O.brute_force(narrow, wide)) <= TOL
+    assert st["ranks"] == o.ranks and max(st["ranks"][:120]) <= 64
+    _, st_wide = _run(narrow, wide, 4096, 1e-28, chi_mid=0)
+    assert max(st_wide["ranks"][:120]) > 64
+    ux = I.turbulence_qtt(256, 101, 64)
+    uy = I.turbulence_qtt(256, 102, 16)
+    o2 = O.ttm(uy, ux, 64, 1e-14, move_factor="smaller")
+    C2, st2 = _run(uy, ux, 64, 1e-14, move_factor="smaller")
+    assert st2["ranks"] == o2.ranks
+    assert O.rel_frob(C2, o2.cores) <= TOL

@@ -69,8 +69,8 @@ MUTANTS = [
      "x_new = (u[:, :r] * s[:r]).reshape(dl, dx, r)",
      "x_new = u[:, :r].reshape(dl, dx, r)"),
     ("swap_forced_discard_wrong", "ttm",
-     "disc = float(np.sum(s[r:][::-1] ** 2)) if r < s.shape[0] else 0.0\n    x_new",
-     "disc = float(np.sum(s[r:][::-1])) if r < s.shape[0] else 0.0\n    x_new"),
+     "disc = float(np.sum(s[r:][::-1] ** 2)) if r < s.shape[0] else 0.0\n    return u, s, vt, r, disc",
+     "disc = float(np.sum(s[r:][::-1])) if r < s.shape[0] else 0.0\n    return u, s, vt, r, disc"),
     ("chain_not_reversed", "ttm",
      "x = Bt[j]",
      "x = Bt[n - 1 - j]"),
@@ -110,6 +110,15 @@ MUTANTS = [
     ("flops_gauge_move_product_not_recorded", "ttm",
      "    res.ops.append((\"gemm\", k, rr, nxt.shape[1] * nxt.shape[2]))\n    res.n_qr += 1",
      "    res.n_qr += 1"),
+    ("centre_right_lq_drops_l", "ttm",
+     "    x_new = x_new @ rf.T\n",
+     "    x_new = x_new\n"),
+    ("centre_right_lq_not_transposed", "ttm",
+     "    p_new = q.T\n",
+     "    p_new = q.T[:, ::-1]\n"),
+    ("move_smaller_moves_the_larger", "ttm",
+     "if max(c.shape[0] for c in A) < max(c.shape[0] for c in B):",
+     "if max(c.shape[0] for c in A) > max(c.shape[0] for c in B):"),
     ("discards_not_recorded", "ttm",
      "            res.discards.append(disc)\n            res.n_swap += 1",
      "            res.discards.append(0.0)\n            res.n_swap += 1"),

@@ -448,3 +448,64 @@ def test_model_flops_schedule_golden():
         assert sum(_frac(f) for _, f in sch["ops"]) == _frac(sch["total"])
         assert np.isclose(res.flops, float(_frac(sch["total"])), rtol=1e-14, atol=0)
         assert res.n_contract == 3 and res.n_swap == 3
+
+
+# ---------------------------------------------------------------- schedule variants
+def test_centre_right_gauge_exact_and_within_bounds():
+    """The swap with the singular values on the right carriage and an LQ move
+    of the centre (the gauge as Sec. II.B states it) gives the exact product
+    where nothing is truncated, and in the truncated regime a result between
+    the Eckart-Young bound and its own sum of discarded norms, with the
+    ranks and the tensor of the default (mirrored) gauge: any position of the
+    centre inside the pair gives the same truncation."""
+    A, B = _r10()
+    ref = O.brute_force(A, B)
+    ex = O.ttm(A, B, 64, 1e-28, chi_mid=0, gauge="right")
+    assert O.rel_frob(ex.cores, ref) <= 1e-12
+    assert ex.n_qr == 2 * 9 + 36 + 45            # canonicalisation, gauge moves, one LQ per swap
+    res = O.ttm(A, B, 8, 1e-14, gauge="right")
+    err = O.rel_frob(res.cores, ref) * np.linalg.norm(ref)
+    assert err <= res.error_bound * (1 + 1e-10) + 1e-15
+    for k in range(1, 10):
+        s = np.linalg.svd(ref.reshape(2 ** k, -1), compute_uv=False)
+        assert err >= np.sqrt(np.sum(s[8:] ** 2)) * (1 - 1e-10)
+    mirrored = O.ttm(A, B, 8, 1e-14)
+    assert res.ranks == mirrored.ranks
+    assert O.rel_frob(res.cores, mirrored.cores) <= 1e-12
+
+
+def test_centre_right_swap_factors():
+    """One swap in the stated gauge: the moved carriage comes out with
+    orthonormal columns before the LQ move, the LQ factor L = R^T is lower
+    triangular, and after the move the right carriage has orthonormal rows
+    while the pair's product is the truncated unfolding."""
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal((3, 2, 4))
+    X = rng.standard_normal((4, 2, 5))
+    x, p, r, disc, s, rf = O.swap_centre_right(P, X, 1e-14, 0)
+    assert np.allclose(np.tril(rf.T), rf.T)
+    pm = p.reshape(r, -1)
+    assert np.abs(pm @ pm.T - np.eye(r)).max() < 1e-13
+    theta = np.tensordot(P, X, axes=(2, 0)).transpose(0, 2, 1, 3).reshape(6, 10)
+    assert np.allclose(x.reshape(6, r) @ pm, theta, atol=1e-13)
+    # the L factor holds the singular values: |diag(L)| = s_r up to ordering of the QR
+    assert np.isclose(np.linalg.norm(rf), np.linalg.norm(s[:r]), rtol=1e-13)
+
+
+def test_move_smaller_factor():
+    """Moving the train with the smaller bonds (A * B = B * A) gives the same
+    exact product.  The bond a swap creates splits the moving train at two
+    cuts and the fixed one at one, so exact intermediate bonds are at most
+    chi_fixed chi_moving^2 (reading of the moving factor): with a chi-16 and
+    a chi-2 train on 16 binary sites, moving the narrow one keeps every
+    swap rank within 16 * 2 * 2 = 64, moving the wide one exceeds it."""
+    wide = I.random_tt(16, 2, 16, 61)
+    narrow = I.random_tt(16, 2, 2, 62)
+    ref = O.brute_force(narrow, wide)
+    moves_wide = O.ttm(narrow, wide, 4096, 1e-28, chi_mid=0)
+    moves_narrow = O.ttm(narrow, wide, 4096, 1e-28, chi_mid=0, move_factor="smaller")
+    assert O.rel_frob(moves_wide.cores, ref) <= 1e-12 and O.rel_frob(moves_narrow.cores, ref) <= 1e-12
+    assert max(moves_narrow.ranks[:120]) <= 16 * 2 * 2
+    assert max(moves_wide.ranks[:120]) > 16 * 2 * 2
+    same = O.ttm(wide, narrow, 4096, 1e-28, chi_mid=0, move_factor="smaller")  # already in place
+    assert same.ranks == moves_narrow.ranks
