@@ -196,6 +196,29 @@ int ttm_multiply_ex(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double to
                     ttm_tt_out *C, void *ws, size_t ws_bytes, void *stream,
                     const ttm_options *opt, ttm_stats *stats);
 
+/* Size in bytes of the static device workspace of ttm_multiply_static. */
+#define TTM_STATIC_WS_BYTES ((size_t)32 << 20)
+
+/* ttm_multiply_ex without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The workspace is a static device array of
+ * TTM_STATIC_WS_BYTES (32 MiB) that the library holds on every device it
+ * runs on until the process ends; the call allocates nothing and creates no
+ * HIP object.  Inputs, output, options, statistics, blocking and return codes
+ * are those of ttm_multiply_ex, and the result is bitwise the one
+ * ttm_multiply_ex gives for the same arguments.  Limits:
+ *   - a product whose ttm_query workspace exceeds TTM_STATIC_WS_BYTES returns
+ *     TTM_EWORKSPACE before any GPU work (ttm_last_error gives both sizes):
+ *     32 MiB holds, e.g., 8 sites of d = 8 at bond 64, not at bond 128;
+ *   - opt->profile must be 0 (event timing creates HIP events): TTM_EINVAL.
+ * The array of a device is shared by every call on that device (the HIP
+ * device current in the calling thread) and keeps the last call's contents;
+ * each call clears what it reads before writing.  Calls that overlap in time
+ * on one device, from several threads or streams, race on the array and give
+ * wrong results: serialise them. */
+int ttm_multiply_static(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, ttm_tt_out *C,
+                        void *stream, const ttm_options *opt, ttm_stats *stats);
+
 /* n independent products C[i] = A[i] * B[i] by TTM (Sec. II.B) in one call,
  * for workloads of many products at uneven bonds, such as the nine terms
  * u_j d_j u_i of the advection term that motivates the method (Sec. I).

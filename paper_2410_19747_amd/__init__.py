@@ -5,6 +5,7 @@ kernels of ``libttm.so``; PyTorch provides device memory and the stream.
 The functions mirror the C entry points of ``include/ttm.h``:
 
     multiply(A, B, chi_out, tol, **options)       -> ttm_multiply_ex
+    multiply_static(A, B, chi_out, tol, ...)      -> ttm_multiply_static (no workspace)
     conventional(A, B, chi_out, tol, **options)   -> conventional_multiply_ex
     query(A, B, chi_out, **options)               -> ttm_query
     multiply_batch(pairs, chi_out, tol, ...)      -> ttm_multiply_batch
@@ -28,7 +29,7 @@ from ._abi import (  # noqa: F401
 )
 
 __all__ = [
-    "TTMError", "PackedTT", "pack", "multiply", "multiply_batch", "tune_batch_streams", "inner_grad",
+    "TTMError", "PackedTT", "pack", "multiply", "multiply_static", "multiply_batch", "tune_batch_streams", "inner_grad",
     "ttm_inner_loss",
     "conventional", "query", "conventional_query",
     "Workspace", "lib",
@@ -226,13 +227,15 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
     o, keep = _options(trace_cap=trace_cap, **opts)
     L = lib()
     qfn = L.conventional_query if kind == "conv" else L.ttm_query
-    mfn = L.conventional_multiply_ex if kind == "conv" else L.ttm_multiply_ex
+    mfn = {"ttm": L.ttm_multiply_ex, "conv": L.conventional_multiply_ex, "static": L.ttm_multiply_static}[kind]
     ws_bytes, cap = _query(qfn, A, B, chi_out, o)
-    if workspace is None:
-        dev = A.data.device
-        workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
-    wbuf = workspace.get(ws_bytes)
-    _same_device("the workspace", wbuf, A.data.device)
+    wbuf = None
+    if kind != "static":
+        if workspace is None:
+            dev = A.data.device
+            workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
+        wbuf = workspace.get(ws_bytes)
+        _same_device("the workspace", wbuf, A.data.device)
     if out is not None:
         if out.dtype != torch.float64 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 tensor (got %s)" % out.dtype)
@@ -246,9 +249,13 @@ def _run(kind, A, B, chi_out, tol, workspace=None, out=None, stream=None, **opts
                     ctypes.cast(offs, ctypes.POINTER(ctypes.c_int64)),
                     ctypes.c_void_p(out.data_ptr()), out.numel())
     st = TtmStats()
-    rc = mfn(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), float(tol), ctypes.byref(cout),
-             ctypes.c_void_p(wbuf.data_ptr()), ctypes.c_size_t(wbuf.numel()), _stream_handle(stream),
-             ctypes.byref(o), ctypes.byref(st))
+    if kind == "static":
+        rc = mfn(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), float(tol), ctypes.byref(cout),
+                 _stream_handle(stream), ctypes.byref(o), ctypes.byref(st))
+    else:
+        rc = mfn(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), float(tol), ctypes.byref(cout),
+                 ctypes.c_void_p(wbuf.data_ptr()), ctypes.c_size_t(wbuf.numel()), _stream_handle(stream),
+                 ctypes.byref(o), ctypes.byref(st))
     if rc != TTM_OK:
         raise TTMError(rc, mfn.__name__)
     res = PackedTT(out, [A.phys[i] for i in range(n)], list(bonds), list(offs))
@@ -276,6 +283,16 @@ def multiply(A, B, chi_out, tol, **opts):
     profile, contract_precision ("f64", "f32", "bf16" or "bf16x3"),
     move_factor ("second" or "smaller"), gauge ("moving" or "right")."""
     return _run("ttm", A, B, chi_out, tol, **opts)
+
+
+def multiply_static(A, B, chi_out, tol, **opts):
+    """As multiply, through ttm_multiply_static: the library's static device
+    workspace (TTM_STATIC_WS_BYTES per device) instead of a caller buffer,
+    for code that must not allocate device memory.  Calls overlapping on one
+    device race on that workspace."""
+    if "workspace" in opts:
+        raise ValueError("multiply_static takes no workspace")
+    return _run("static", A, B, chi_out, tol, **opts)
 
 
 def conventional(A, B, chi_out, tol, **opts):

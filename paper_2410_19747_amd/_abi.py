@@ -120,6 +120,9 @@ PROTOTYPES = {
                                                 ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
                                                 ctypes.c_size_t, ctypes.c_void_p,
                                                 ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats)]),
+    "ttm_multiply_static": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                           ctypes.c_double, ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
+                                           ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats)]),
     "ttm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ttm_last_error": (ctypes.c_char_p, []),
     "ttm_version": (ctypes.c_char_p, []),
@@ -152,6 +155,7 @@ TESTING_PROTOTYPES = {
                                        ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
 }
 
+TTM_STATIC_WS_BYTES = 32 << 20
 
 
 def library_path():

@@ -93,6 +93,7 @@ int main() {
     EXPECT(ttm_multiply_ex(&A.view, &B.view, 0, 1e-12, &C, nullptr, 0, nullptr, &o, nullptr) == TTM_EINVAL);
     if (rc == TTM_OK) {
       EXPECT(ttm_multiply_ex(&A.view, &B.view, chi, 1e-12, &C, nullptr, 0, nullptr, &o, nullptr) == TTM_EWORKSPACE);
+      EXPECT(ttm_multiply_static(&A.view, &B.view, chi, 1e-12, &C, nullptr, &o, nullptr) == TTM_ECAPACITY);
       EXPECT(strlen(ttm_last_error()) == 0);
     }
     EXPECT(conventional_multiply_ex(&A.view, &B.view, chi, NAN, &C, nullptr, 0, nullptr, &o, nullptr) ==

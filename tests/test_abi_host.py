@@ -307,6 +307,42 @@ def test_svd_size_limit_rejected_by_query(L):
     assert b"SVD" in L.ttm_strerror(_abi.TTM_EUNSUPPORTED)
 
 
+def test_static_workspace_entry_rejects_before_gpu_work(L):
+    """ttm_multiply_static checks its arguments, the profile option and the
+    product's workspace against the static array's size before any HIP
+    call, and says why in ttm_last_error."""
+    bonds = (ctypes.c_int32 * 9)()
+    offs = (ctypes.c_int64 * 8)()
+    out = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000),
+                        1 << 30)
+    big = _TT([8] * 8, [1, 8, 64, 128, 128, 128, 64, 8, 1])
+    rc, need, _ = _query(L, big, big, 128)
+    assert rc == 0 and need > _abi.TTM_STATIC_WS_BYTES
+    assert L.ttm_multiply_static(ctypes.byref(big.view), ctypes.byref(big.view), 128, 1e-14, ctypes.byref(out),
+                                 None, None, None) == _abi.TTM_EWORKSPACE
+    msg = L.ttm_last_error().decode()
+    assert str(need) in msg and str(_abi.TTM_STATIC_WS_BYTES) in msg
+    small = _TT([8] * 8, [1, 8, 64, 64, 64, 64, 64, 8, 1])
+    rc, need, _ = _query(L, small, small, 64)
+    assert rc == 0 and need <= _abi.TTM_STATIC_WS_BYTES
+    o = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(o))
+    o.profile = 1
+    assert L.ttm_multiply_static(ctypes.byref(small.view), ctypes.byref(small.view), 64, 1e-14,
+                                 ctypes.byref(out), None, ctypes.byref(o), None) == _abi.TTM_EINVAL
+    assert L.ttm_multiply_static(ctypes.byref(small.view), ctypes.byref(small.view), 64, float("nan"),
+                                 ctypes.byref(out), None, None, None) == _abi.TTM_EINVAL
+    assert L.ttm_multiply_static(ctypes.byref(small.view), ctypes.byref(small.view), 0, 1e-14,
+                                 ctypes.byref(out), None, None, None) == _abi.TTM_EINVAL
+    assert L.ttm_multiply_static(None, ctypes.byref(small.view), 64, 1e-14, ctypes.byref(out), None, None,
+                                 None) == _abi.TTM_EINVAL
+    assert L.ttm_multiply_static(ctypes.byref(small.view), ctypes.byref(small.view), 64, 1e-14, None, None, None,
+                                 None) == _abi.TTM_EINVAL
+    tight = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000), 8)
+    assert L.ttm_multiply_static(ctypes.byref(small.view), ctypes.byref(small.view), 64, 1e-14, ctypes.byref(tight),
+                                 None, None, None) == _abi.TTM_ECAPACITY
+
+
 def test_last_error_is_cleared_by_each_call(L):
     """ttm_last_error describes the last failure of a compute call on this
     thread and is emptied when the next call starts."""
@@ -315,8 +351,9 @@ def test_last_error_is_cleared_by_each_call(L):
     offs = (ctypes.c_int64 * 8)()
     out = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000),
                         1 << 30)
-    assert L.ttm_multiply_ex(ctypes.byref(big.view), ctypes.byref(big.view), 128, 1e-14, ctypes.byref(out),
-                             None, 0, None, None, None) == _abi.TTM_EWORKSPACE
+    assert L.ttm_multiply_static(ctypes.byref(big.view), ctypes.byref(big.view), 128, 1e-14, ctypes.byref(out),
+                                 None, None, None) == _abi.TTM_EWORKSPACE
+    assert L.ttm_last_error() != b""
     # an argument error of the next call leaves no stale text behind
     assert L.ttm_multiply_ex(ctypes.byref(big.view), ctypes.byref(big.view), 0, 1e-14, ctypes.byref(out),
                              None, 0, None, None, None) == _abi.TTM_EINVAL
