@@ -45,3 +45,4 @@ from .conventional import (  # noqa: F401
     initial_guess,
 )
 from .adjoint import inner3_grad, left_envs, right_envs  # noqa: F401,E402
+from .ttm_grad import ttm_vjp, qr_vjp, trunc_svd_vjp  # noqa: F401,E402

@@ -18,9 +18,10 @@ import pytest
 import oracle as _real
 import test_oracle_adjoint as _pins_adjoint
 import test_oracle_pins as _pins
+import test_oracle_ttm_grad as _pins_grad
 
 _ROOT = os.path.dirname(os.path.abspath(_real.__file__))
-_MODULES = ("tt", "ttm", "conventional", "adjoint")   # dependency order
+_MODULES = ("tt", "ttm", "conventional", "adjoint", "ttm_grad")   # dependency order
 
 # (case id, oracle module, fragment as written in the oracle, planted mistake)
 MUTANTS = [
@@ -145,6 +146,25 @@ MUTANTS = [
     ("grad_a_contracts_wrong_bond", "adjoint",
      "ga[:, s, :] = np.tensordot(ua, Fr, axes=([1, 2], [0, 2]))",
      "ga[:, s, :] = np.tensordot(ua, Fr, axes=([1, 2], [0, 1]))"),
+    # --- reverse mode through the TTM product
+    ("vjp_qr_mirrors_wrong_triangle", "ttm_grad",
+     "X = np.tril(X) + np.tril(X, -1).T",
+     "X = np.triu(X) + np.triu(X, 1).T"),
+    ("vjp_svd_drops_direct_term", "ttm_grad",
+     "    matbar = Zbar @ Vr.T\n",
+     "    matbar = 0.0 * Zbar @ Vr.T\n"),
+    ("vjp_svd_wrong_gap_sign", "ttm_grad",
+     "F = 1.0 / (lam[None, :r] - lam[r:, None])",
+     "F = 1.0 / (lam[r:, None] - lam[None, :r])"),
+    ("vjp_svd_drops_null_space", "ttm_grad",
+     "        Gbar = Gbar + (Nbar / lam[None, :r]) @ Vr.T",
+     "        Gbar = Gbar"),
+    ("vjp_merge_legs_not_exchanged", "ttm_grad",
+     "tb = matbar.reshape(dl, dx, dp, dr).transpose(0, 2, 1, 3)",
+     "tb = matbar.reshape(dl, dp, dx, dr)"),
+    ("vjp_round_next_core_transposed", "ttm_grad",
+     "            Pib[i + 1] = np.tensordot(Zt, nb, axes=(0, 0))",
+     "            Pib[i + 1] = np.tensordot(Zt[::-1], nb, axes=(0, 0))"),
     ("grad_b_uses_wrong_factor", "adjoint",
      "ub = np.tensordot(t, a[:, s, :], axes=(0, 0))",
      "ub = np.tensordot(t, 2.0 * a[:, s, :], axes=(0, 0))"),
@@ -190,7 +210,7 @@ def _drop(name):
 def _pin_calls():
     """Every pin of the oracle as (label, zero-argument call)."""
     calls = []
-    for mod in (_pins, _pins_adjoint):
+    for mod in (_pins, _pins_adjoint, _pins_grad):
         for attr in sorted(vars(mod)):
             fn = getattr(mod, attr)
             if not (attr.startswith("test_") and callable(fn)):
@@ -198,8 +218,10 @@ def _pin_calls():
             params = [m for m in getattr(fn, "pytestmark", []) if m.name == "parametrize"]
             if params:
                 argname, values = params[0].args[0], params[0].args[1]
+                names = [a.strip() for a in argname.split(",")]
                 for v in values:
-                    calls.append(("%s[%s]" % (attr, v), lambda f=fn, a=argname, v=v: f(**{a: v})))
+                    kw = dict(zip(names, v)) if len(names) > 1 else {names[0]: v}
+                    calls.append(("%s[%s]" % (attr, v), lambda f=fn, kw=kw: f(**kw)))
             else:
                 calls.append((attr, fn))
     return calls
@@ -208,8 +230,8 @@ def _pin_calls():
 def _run_pins(pkg, stop_at_first):
     """Run the pins with ``O`` bound to ``pkg``; return the labels that fail."""
     failed = []
-    saved = (_pins.O, _pins_adjoint.O)
-    _pins.O = _pins_adjoint.O = pkg
+    saved = (_pins.O, _pins_adjoint.O, _pins_grad.O)
+    _pins.O = _pins_adjoint.O = _pins_grad.O = pkg
     try:
         for label, call in _pin_calls():
             try:
@@ -221,7 +243,7 @@ def _run_pins(pkg, stop_at_first):
                 if stop_at_first:
                     break
     finally:
-        _pins.O, _pins_adjoint.O = saved
+        _pins.O, _pins_adjoint.O, _pins_grad.O = saved
     return failed
 
 
