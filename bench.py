@@ -24,7 +24,8 @@ after another and in single ttm_multiply_batch calls (FP64 and FP32
 contractions): one JSON line per run.
 
 ``--adjoint`` measures the gradient of <W, A*B> with respect to the cores
-of A and B (ttm_inner_grad) on the 1024^3 chi = 128 QTTs.
+of A and B (ttm_inner_grad) on the 1024^3 chi = 128 QTTs, then the reverse
+mode through the truncated product (ttm_multiply_vjp) against the product.
 
 ``--binary-sites`` runs the bench product with the field encoded as the
 paper's binary QTT (d = 2 sites) beside the d = 8 encoding.
@@ -758,7 +759,45 @@ def adjoint(args, dev):
         print(json.dumps(line), flush=True)
         _log("  %s: %.2f ms per gradient, %.2f TFLOP/s algorithmic, rel err vs oracle %s"
              % (prec, 1e3 * dt, flops / dt / 1e12, "%.2e" % err if err is not None else "-"))
+    _reverse_mode(args, dev, A, B, Wp)
     return None
+
+
+def _reverse_mode(args, dev, A, B, Wp):
+    """Reverse mode through the truncated product: the gradient of
+    <W, TTM(A, B)> at chi = 128, eps = 1e-14 (dL/dC by ttm_inner_grad, then
+    ttm_multiply_vjp, which re-runs the product with every step recorded),
+    timed against the product alone.  One JSON line."""
+    import torch
+
+    import paper_2410_19747_amd as T
+
+    chi, tol = 128, 1e-14
+    ws, wsv = T.Workspace(dev), T.Workspace(dev)
+    C, st = T.multiply(A, B, chi, tol, workspace=ws)
+    _, dC, _ = T.inner_grad(Wp, C, T._ones_like_train(C), workspace=ws)
+    for _ in range(max(args.warmup, 1)):
+        T.multiply(A, B, chi, tol, workspace=ws)
+        T.multiply_vjp(A, B, chi, tol, dC, workspace=wsv)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    t = time.perf_counter()
+    for _ in range(steps):
+        T.multiply(A, B, chi, tol, workspace=ws)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t) / steps
+    t = time.perf_counter()
+    for _ in range(steps):
+        _, dA, dB, stv = T.multiply_vjp(A, B, chi, tol, dC, workspace=wsv)
+    torch.cuda.synchronize()
+    t_vjp = (time.perf_counter() - t) / steps
+    line = {"reverse_mode": True, "workload": "grad of <W, TTM(A, B)>: 1024^3 turbulence QTTs u_x, u_y at chi 128 "
+            "(N=10, d=8), product at chi 128, eps 1e-14, W random at chi 32",
+            "ms_product": 1e3 * t_fwd, "ms_vjp": 1e3 * t_vjp, "vjp_over_product": t_vjp / t_fwd,
+            "workspace_gib": wsv.get(0).numel() / 2 ** 30, "ranks_equal": stv["ranks"] == st["ranks"],
+            "grad_norm": float(torch.sqrt((dA.data ** 2).sum() + (dB.data ** 2).sum()))}
+    print(json.dumps(line), flush=True)
+    _log("  reverse mode: product %.1f ms, product + reverse pass %.1f ms" % (1e3 * t_fwd, 1e3 * t_vjp))
 
 
 def binary_sites(args, dev):

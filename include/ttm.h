@@ -277,6 +277,33 @@ int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size
 int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                    double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream);
 
+/* Reverse mode of the TTM product (the paper has no gradients): given the
+ * cotangent Cbar of the output cores (for a loss L(C), Cbar = dL/dC, laid out
+ * like C), the cotangents dA = dL/dA and dB = dL/dB of the input cores,
+ * through every step of Sec. II.B as computed: the canonicalising QR sweeps,
+ * the reversal of the second train (Eq. tensor), the contractions
+ * (Eq. contract), the QR gauge moves, the swaps' merges and truncated SVDs
+ * (Fig. 1C, Eq. (eps)) and the final rounding sweep.  The ranks chosen by the
+ * truncations are piecewise constant and held at the forward pass's.
+ * The call runs the product again with every step's operands recorded in
+ * ws, writes it to C like ttm_multiply_ex, checks that Cbar has its bonds
+ * (TTM_ESHAPE otherwise), then undoes the steps in reverse order on the
+ * device.  A truncated SVD's adjoint weights each pair of a kept and a dropped
+ * singular value by 1/(sigma_i^2 - sigma_j^2) and the unresolved and null
+ * directions by 1/sigma_i^2: it is defined where the kept values are
+ * separated from the dropped ones, and its error grows as 1/gap.  A QR
+ * adjoint solves with R^T: the unfoldings must have full rank (input bonds
+ * within the structural bounds).  Default gauge only (TTM_EUNSUPPORTED for
+ * TTM_GAUGE_RIGHT); move_factor is honoured.  dA, dB: device buffers laid out
+ * like A's and B's data.  ws: ttm_vjp_query's bytes (the product's own
+ * workspace, the record of its steps, the cotangents and scratch).  opt->profile
+ * must be 0.  Blocking like the other entry points. */
+int ttm_vjp_query(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, const ttm_options *opt,
+                  size_t *ws_bytes, int64_t *out_capacity);
+int ttm_multiply_vjp(const ttm_tt *A, const ttm_tt *B, int32_t chi_out, double tol, const ttm_options *opt,
+                     const ttm_tt *Cbar, ttm_tt_out *C, double *dA, double *dB, void *ws, size_t ws_bytes,
+                     void *stream, ttm_stats *stats);
+
 /* Sizes for conventional_multiply (host only).  The fit keeps the structural
  * bonds capped at chi_out: out_capacity = sum_i c_i d_i c_{i+1} with
  * c_i = min(prod_{k<i} d_k, prod_{k>=i} d_k, chi_out).  TTM_EINVAL when an

@@ -11,6 +11,7 @@ The functions mirror the C entry points of ``include/ttm.h``:
     multiply_batch(pairs, chi_out, tol, ...)      -> ttm_multiply_batch
     tune_batch_streams(pairs, chi_out, tol)       -> products in flight, by timing
     inner_grad(W, A, B)                           -> ttm_inner_grad
+    multiply_vjp(A, B, chi_out, tol, Cbar)        -> ttm_multiply_vjp (reverse mode)
     ttm_inner_loss(W, A, B, chi_out, tol)         -> torch.autograd.Function over
                                                      ttm_multiply_ex + ttm_inner_grad
 
@@ -29,7 +30,7 @@ from ._abi import (  # noqa: F401
 )
 
 __all__ = [
-    "TTMError", "PackedTT", "pack", "multiply", "multiply_static", "multiply_batch", "tune_batch_streams", "inner_grad",
+    "TTMError", "PackedTT", "pack", "multiply", "multiply_static", "multiply_vjp", "multiply_batch", "tune_batch_streams", "inner_grad",
     "ttm_inner_loss",
     "conventional", "query", "conventional_query",
     "Workspace", "lib",
@@ -413,6 +414,55 @@ def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, st
     return (value.value, PackedTT(dA, A.phys, A.bonds, A.offsets), PackedTT(dB, B.phys, B.bonds, B.offsets))
 
 
+def multiply_vjp(A, B, chi_out, tol, Cbar, workspace=None, stream=None, **opts):
+    """Reverse mode of the TTM product through ttm_multiply_vjp: for the
+    cotangent ``Cbar`` of the output cores (a PackedTT with C's bonds, e.g.
+    dL/dC), returns (C, dA, dB, stats) with dA, dB the cotangents of A's and
+    B's cores (PackedTTs laid out like A and B).  The product C is recomputed
+    with every step recorded; ranks are those of that product."""
+    import torch
+
+    A, B, Cbar = pack(A), pack(B), pack(Cbar)
+    _same_device("B", B.data, A.data.device)
+    _same_device("Cbar", Cbar.data, A.data.device)
+    trace_cap = opts.pop("trace_cap", None)
+    if trace_cap is None:
+        trace_cap = 4 * A.n_sites * A.n_sites + 16
+    o, keep = _options(trace_cap=trace_cap, **opts)
+    L = lib()
+    need = ctypes.c_size_t(0)
+    cap = ctypes.c_int64(0)
+    rc = L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), ctypes.byref(o),
+                         ctypes.byref(need), ctypes.byref(cap))
+    if rc != TTM_OK:
+        raise TTMError(rc, "ttm_vjp_query")
+    if workspace is None:
+        dev = A.data.device
+        workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
+    wbuf = workspace.get(need.value)
+    _same_device("the workspace", wbuf, A.data.device)
+    out = torch.empty(max(cap.value, 1), dtype=torch.float64, device=A.data.device)
+    n = A.n_sites
+    bonds = (ctypes.c_int32 * (n + 1))()
+    offs = (ctypes.c_int64 * n)()
+    cout = TtmTTOut(ctypes.cast(bonds, ctypes.POINTER(ctypes.c_int32)),
+                    ctypes.cast(offs, ctypes.POINTER(ctypes.c_int64)),
+                    ctypes.c_void_p(out.data_ptr()), out.numel())
+    dA = torch.zeros_like(A.data)
+    dB = torch.zeros_like(B.data)
+    st = TtmStats()
+    rc = L.ttm_multiply_vjp(ctypes.byref(A.view), ctypes.byref(B.view), int(chi_out), float(tol), ctypes.byref(o),
+                            ctypes.byref(Cbar.view), ctypes.byref(cout), ctypes.c_void_p(dA.data_ptr()),
+                            ctypes.c_void_p(dB.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
+                            ctypes.c_size_t(wbuf.numel()), _stream_handle(stream), ctypes.byref(st))
+    if rc != TTM_OK:
+        raise TTMError(rc, "ttm_multiply_vjp")
+    C = PackedTT(out, list(A.phys), list(bonds), list(offs))
+    stats = _stats_dict(st, o)
+    del keep
+    return (C, PackedTT(dA, A.phys, A.bonds, A.offsets), PackedTT(dB, B.phys, B.bonds, B.offsets), stats)
+
+
 def _ones_like_train(T):
     """The all-ones train (every bond 1) with T's physical dimensions."""
     import torch
@@ -431,35 +481,24 @@ def _make_inner_loss_function():
     class TTMInnerLoss(torch.autograd.Function):
         """loss = <W, TTM(A, B)> with W fixed.  Forward: the TTM product
         (ttm_multiply_ex), then <W, C> (ttm_inner_grad against the all-ones
-        train).  Backward: dL/dA, dL/dB of <W, A*B> by ttm_inner_grad, the
-        environments recomputed from W, A and B (nothing kept from the
-        forward pass but the inputs).  That is the gradient of the loss only
-        where the product's truncations dropped nothing (TTM(A, B) = A*B);
-        reverse mode through the truncated swaps is not built, so backward
-        raises when the forward product's discarded weight exceeds rounding
-        (its error bound above 1e-12 of ||A|| ||B||)."""
+        train).  Backward: dL/dC = the gradient of <W, C> with respect to C's
+        cores (ttm_inner_grad, environments recomputed from W and C), then
+        the reverse mode of the product (ttm_multiply_vjp), which recomputes
+        the product with every step recorded and undoes the steps, truncated
+        SVDs included.  Only the inputs and C are kept from the forward pass."""
 
         @staticmethod
         def forward(ctx, a_data, b_data, A, B, W, chi_out, tol, prec, opts):
             C, st = multiply(A, B, chi_out, tol, contract_precision=prec, **opts)
             value, _, _ = inner_grad(W, C, _ones_like_train(C), contract_precision=prec, grads=False)
-            na, _, _ = inner_grad(A, A, _ones_like_train(A), grads=False)
-            nb, _, _ = inner_grad(B, B, _ones_like_train(B), grads=False)
-            scale = max(na, 0.0) ** 0.5 * max(nb, 0.0) ** 0.5
-            ctx.trains = (A, B, W, prec)
-            ctx.truncated = st["error_bound"] > 1e-12 * scale
-            ctx.error_bound = st["error_bound"]
+            ctx.trains = (A, B, W, C, chi_out, tol, prec, opts)
             return torch.tensor(value, dtype=torch.float64, device=a_data.device)
 
         @staticmethod
         def backward(ctx, g):
-            if ctx.truncated:
-                raise NotImplementedError(
-                    "ttm_inner_loss: the forward product truncated (error bound %.3e), and reverse mode "
-                    "through the truncated swaps is not built; the gradient of the exact <W, A*B> is "
-                    "available from inner_grad" % ctx.error_bound)
-            A, B, W, prec = ctx.trains
-            _, dA, dB = inner_grad(W, A, B, contract_precision=prec)
+            A, B, W, C, chi_out, tol, prec, opts = ctx.trains
+            _, dC, _ = inner_grad(W, C, _ones_like_train(C))
+            _, dA, dB, _ = multiply_vjp(A, B, chi_out, tol, dC, contract_precision=prec, **opts)
             return g * dA.data, g * dB.data, None, None, None, None, None, None, None
 
     return TTMInnerLoss
@@ -470,10 +509,9 @@ _INNER_LOSS = None
 
 def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
     """0-d tensor <W, TTM(A, B)> whose backward gives dL/dA.data and
-    dL/dB.data (PackedTT data tensors with requires_grad) through the
-    adjoint environments of ttm_inner_grad.  W is a constant train.  The
-    backward is exact where the product's truncations drop nothing and
-    raises NotImplementedError where they drop weight."""
+    dL/dB.data (PackedTT data tensors with requires_grad): the environments
+    of ttm_inner_grad for dL/dC, then the reverse mode of the truncated
+    product (ttm_multiply_vjp).  W is a constant train."""
     global _INNER_LOSS
     if _INNER_LOSS is None:
         _INNER_LOSS = _make_inner_loss_function()

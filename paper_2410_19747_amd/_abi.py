@@ -123,6 +123,14 @@ PROTOTYPES = {
     "ttm_multiply_static": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
                                            ctypes.c_double, ctypes.POINTER(TtmTTOut), ctypes.c_void_p,
                                            ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmStats)]),
+    "ttm_vjp_query": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                     ctypes.POINTER(TtmOptions), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "ttm_multiply_vjp": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
+                                        ctypes.c_double, ctypes.POINTER(TtmOptions), ctypes.POINTER(TtmTT),
+                                        ctypes.POINTER(TtmTTOut), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(TtmStats)]),
     "ttm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ttm_last_error": (ctypes.c_char_p, []),
     "ttm_version": (ctypes.c_char_p, []),

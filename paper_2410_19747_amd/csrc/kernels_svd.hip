@@ -885,6 +885,7 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
     result[0] = (double)r;
     result[2] = total;
     result[4] = isfinite(total) ? 0.0 : 1.0;
+    result[6] = (double)nsig;  // values above the noise level (resolved vectors)
   }
 }
 

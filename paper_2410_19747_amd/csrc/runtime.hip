@@ -176,7 +176,12 @@ struct Plan {
   std::vector<Shape> out_shapes;
   size_t ws_bytes = 0;
   int nslots = 0;
+  // reverse mode: doubles of the record of every step (upper bound), and
+  // the largest SVD matrix (m n doubles)
+  int64_t tape = 0;
+  int64_t max_mn = 1;
 };
+int64_t tape_round(int64_t n) { return (n + 31) & ~(int64_t)31; }
 
 // Structural bound of a bond of the product: min(prod_{k<i} d_k, prod_{k>=i} d_k).
 int64_t product_bound(const std::vector<int> &phys, int i) {
@@ -250,11 +255,16 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
     note_core(pl, a[i]);
     note_core(pl, b[i]);
   }
+  auto tape_qr = [&](int64_t m, int64_t nn, int64_t ncol) {
+    const int64_t k = std::min(m, nn);
+    pl.tape += tape_round(m * nn) + tape_round(m * k) + tape_round(k * nn) + tape_round(nn * ncol);
+  };
   auto qr_sweep = [&](std::vector<Shape> &t) {
     for (int i = 0; i + 1 < n; ++i) {
       if (!unfolding_ok((int64_t)t[i].rl * t[i].d, t[i].rr)) return false;
       const int m = t[i].rl * t[i].d, nn = t[i].rr;
       note_qr(pl, m, nn);
+      tape_qr(m, nn, (int64_t)t[i + 1].d * t[i + 1].rr);
       const int k = std::min(m, nn);
       t[i].rr = k;
       t[i + 1].rl = k;
@@ -268,11 +278,13 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
   for (int i = 0; i < n; ++i) bt[i] = {b[i].rr, b[i].d, b[i].rl};
   pi[n - 1] = {a[n - 1].rl, a[n - 1].d, bt[n - 1].rr};
   note_core(pl, pi[n - 1]);
+  pl.tape += tape_round(a[n - 1].size()) + tape_round(bt[n - 1].size());
   for (int j = n - 2; j >= 0; --j) {
     for (int p = j + 1; p <= n - 2; ++p) {
       if (!unfolding_ok((int64_t)pi[p].rl * pi[p].d, pi[p].rr)) return TTM_EINVAL;
       const int m = pi[p].rl * pi[p].d, nn = pi[p].rr;
       note_qr(pl, m, nn);
+      tape_qr(m, nn, (int64_t)pi[p + 1].d * pi[p + 1].rr);
       const int k = std::min(m, nn);
       pi[p].rr = k;
       pi[p + 1].rl = k;
@@ -296,11 +308,18 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
       Shape pn = {r, pi[p].d, x.rr};
       note_core(pl, xn);
       note_core(pl, pn);
+      {
+        const int64_t mm = m, nnn = nn, kk = std::min(mm, nnn);
+        pl.max_mn = std::max(pl.max_mn, mm * nnn);
+        pl.tape += tape_round(pi[p].size()) + tape_round(x.size()) + tape_round(mm * nnn) +
+                   tape_round(nnn * kk) + tape_round(kk) + tape_round(mm * r);
+      }
       x = xn;
       pi[p] = pn;
     }
     pi[j] = {a[j].rl, a[j].d, x.rr};
     note_core(pl, pi[j]);
+    pl.tape += tape_round(a[j].size()) + tape_round(x.size());
   }
   if (o.final_round) {
     for (int i = 0; i + 1 < n; ++i) {
@@ -309,6 +328,12 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
       if (!note_svd(pl, nn, m, false)) return TTM_EUNSUPPORTED;
       const int r = round_cap(chi_out, pl.phys, i, pi[i]);
       pl.max_r = std::max<int64_t>(pl.max_r, (int64_t)r * nn);
+      {
+        const int64_t mm = m, nnn = nn, kk = std::min(mm, nnn);
+        pl.max_mn = std::max(pl.max_mn, mm * nnn);
+        pl.tape += tape_round(mm * nnn) + tape_round(mm * kk) + tape_round(kk) + tape_round((int64_t)r * nnn) +
+                   tape_round(nnn * (int64_t)pi[i + 1].d * pi[i + 1].rr);
+      }
       pi[i].rr = r;
       pi[i + 1].rl = r;
       note_core(pl, pi[i]);
@@ -353,6 +378,24 @@ struct Runner {
   int forced_pos = 0;
   int err = TTM_OK;
   KernelTimer timer;
+  Tape *tape = nullptr;  // reverse mode: record every step's operands
+
+  void tape_full() {
+    if (err == TTM_OK) {
+      err = TTM_EWORKSPACE;
+      set_last_error("the reverse-mode record outgrew its workspace region");
+    }
+  }
+  // A device copy of n doubles in the tape region.
+  double *keep(const double *src, int64_t n) {
+    double *dst = tape->alloc((size_t)n);
+    if (!dst) {
+      tape_full();
+      return nullptr;
+    }
+    hip(launch_copy(dst, src, n, st));
+    return dst;
+  }
 
   Runner(hipStream_t s, const Options &opt) : st(s), o(opt) {
     const char *tv = getenv("TTM_TRACE");
@@ -394,8 +437,17 @@ struct Runner {
   void note(const Shape &s) { max_bond = std::max(max_bond, std::max(s.rl, s.rr)); }
 
   // ---- Eq. (contract): out[a, e, b] = sum_c K[a, e, c] M[c, e, b]
-  Core contract(const Core &k, const Core &m) {
+  Core contract(const Core &k, const Core &m, int site = 0) {
     step = "a contraction (Eq. contract)";
+    if (tape) {
+      TapeEntry e;
+      e.kind = TapeEntry::CONTRACT;
+      e.p = site;
+      e.dl = k.s.rl; e.d = k.s.d; e.dm = k.s.rr; e.dr = m.s.rr;
+      e.K = keep(k.p, k.s.size());
+      e.X = keep(m.p, m.s.size());
+      tape->e.push_back(e);
+    }
     Core out;
     out.p = take();
     out.s = {k.s.rl, k.s.d, m.s.rr};
@@ -418,17 +470,32 @@ struct Runner {
   }
 
   // ---- gauge move: QR of cores[p], R into cores[p+1]
-  void qr_move(std::vector<Core> &c, int p) {
+  void qr_move(std::vector<Core> &c, int p, int arr = 2) {
     step = "a QR gauge move";
     Core &cur = c[p];
     Core &nxt = c[p + 1];
     const int m = cur.s.rl * cur.s.d, n = cur.s.rr;
     const int k = std::min(m, n);
+    TapeEntry e;
+    if (tape) {
+      e.kind = TapeEntry::QR;
+      e.arr = arr;
+      e.p = p;
+      e.m = m; e.n = n; e.k = k; e.ncol = nxt.s.d * nxt.s.rr;
+      e.rl = cur.s.rl; e.d = cur.s.d;
+      e.M = keep(cur.p, (int64_t)m * n);
+      e.nxt = keep(nxt.p, (int64_t)n * e.ncol);
+    }
     double *q = take();
     if (!q) return;
     {
       Timed tm(&timer, KC_QR, st);
       hip(launch_qr(cur.p, m, n, n, 1, q, rbuf, qrbuf, st));
+    }
+    if (tape) {
+      e.Q = keep(q, (int64_t)m * k);
+      e.R = keep(rbuf, (int64_t)k * n);
+      tape->e.push_back(e);
     }
     double *nn = take();
     if (!nn) return;
@@ -454,7 +521,7 @@ struct Runner {
   // ---- one truncated SVD (svd_oside) with the bookkeeping of the rule of
   // Eq. (eps): forced ranks, traces, discarded weight and the flop model.
   // Returns the rank, or -1 after setting err.
-  int svd(const SvdPlan &sp, const double *Y, double *ws, int cap, double *u, int u_layout) {
+  int svd(const SvdPlan &sp, const double *Y, double *ws, int cap, double *u, int u_layout, SvdAll *all = nullptr) {
     int forced = 0;
     if (o.forced) {
       if (forced_pos >= o.n_forced) {
@@ -469,7 +536,7 @@ struct Runner {
       }
     }
     SvdResult so = svd_oside(sp, Y, eps_, cap, forced, o.svd_max_sweeps, u, u_layout, nullptr, ws, st, &timer,
-                             trace);
+                             trace, all);
     jac_sweeps += so.sweeps;
     jac_max = std::max(jac_max, so.sweeps);
     if (so.err != TTM_OK) {
@@ -492,7 +559,7 @@ struct Runner {
   }
 
   // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
-  void swap(Core &P, Core &X, int cap) {
+  void swap(Core &P, Core &X, int cap, int pos = 0, int site = 0) {
     step = "a swap";
     if (o.gauge == TTM_GAUGE_RIGHT) {
       swap_centre_right(P, X, cap);
@@ -501,6 +568,25 @@ struct Runner {
     const int Dl = P.s.rl, dp = P.s.d, Dm = P.s.rr, dx = X.s.d, Dr = X.s.rr;
     const int m = Dl * dx, n = dp * Dr;
     const SvdPlan sp = svd_plan(m, n);
+    TapeEntry e;
+    SvdAll all;
+    if (tape) {
+      e.kind = TapeEntry::SWAP;
+      e.p = pos;
+      e.j = site;
+      e.dl = Dl; e.dp = dp; e.dm = Dm; e.dx = dx; e.dr = Dr;
+      e.m = m; e.n = n; e.k = sp.k;
+      e.P = keep(P.p, P.s.size());
+      e.X = keep(X.p, X.s.size());
+      e.V = tape->alloc((size_t)n * sp.k);
+      e.sigma = tape->alloc((size_t)sp.k);
+      if (!e.V || !e.sigma) {
+        tape_full();
+        return;
+      }
+      all.u = e.V;
+      all.sigma = e.sigma;
+    }
     double *Y = wbuf;
     double *sws = wbuf + ((((int64_t)m * n) + 31) & ~(int64_t)31);
     // merge: theta[(a,e),(w,b)] = sum_c P[a,e,c] X[c,w,b], stored as the
@@ -521,8 +607,9 @@ struct Runner {
     double *xn = take();
     double *pn = take();
     if (!xn || !pn) return;
+    if (tape) e.theta = keep(Y, (int64_t)m * n);
     // P' = V_r^T -> [r, dp, Dr] (the orthonormal factor, over Theta's columns)
-    const int r = svd(sp, Y, sws, cap, pn, SVD_U_T);
+    const int r = svd(sp, Y, sws, cap, pn, SVD_U_T, tape ? &all : nullptr);
     if (r < 1) return;
     // X' = Theta V_r = U_r S_r -> [Dl, dx, r]
     GemmArgs z;
@@ -533,6 +620,12 @@ struct Runner {
     {
       Timed tm(&timer, KC_GEMM, st);
       if (!hip(launch_gemm(z, st))) return;
+    }
+    if (tape) {
+      e.r = r;
+      e.kg = all.kg;
+      e.Z = keep(xn, (int64_t)m * r);
+      tape->e.push_back(e);
     }
     give(P.p);
     give(X.p);
@@ -634,10 +727,28 @@ struct Runner {
     // The row-major m x n core is the column-major n x m matrix Y = Pi_i^T,
     // whose right singular vectors are Pi_i's left ones.
     const SvdPlan sp = svd_plan(n, m);
+    TapeEntry e;
+    SvdAll all;
+    if (tape) {
+      e.kind = TapeEntry::ROUND;
+      e.p = i;
+      e.m = m; e.n = n; e.k = sp.k; e.ncol = nxt.s.d * nxt.s.rr;
+      e.rl = cur.s.rl; e.d = cur.s.d;
+      e.M = keep(cur.p, (int64_t)m * n);
+      e.nxt = keep(nxt.p, (int64_t)n * e.ncol);
+      e.V = tape->alloc((size_t)m * sp.k);
+      e.sigma = tape->alloc((size_t)sp.k);
+      if (!e.V || !e.sigma) {
+        tape_full();
+        return;
+      }
+      all.u = e.V;
+      all.sigma = e.sigma;
+    }
     double *un = take();
     double *nn = take();
     if (!un || !nn) return;
-    const int r = svd(sp, cur.p, wbuf, cap, un, SVD_U);
+    const int r = svd(sp, cur.p, wbuf, cap, un, SVD_U, tape ? &all : nullptr);
     if (r < 1) return;
     // S_r V_r^T = U_r^T Pi_i  (r x n), then into the next core
     GemmArgs h;
@@ -650,6 +761,12 @@ struct Runner {
       Timed tm(&timer, KC_GEMM, st);
       if (!hip(launch_gemm(h, st))) return;
       if (!hip(launch_gemm(gemm_rowmajor(r, ncol, n, rbuf, n, nxt.p, ncol, nn, ncol), st))) return;
+    }
+    if (tape) {
+      e.r = r;
+      e.kg = all.kg;
+      e.Zt = keep(rbuf, (int64_t)r * n);
+      tape->e.push_back(e);
     }
     flops += 2.0 * r * (double)n * ncol;
     give(cur.p);
@@ -666,7 +783,8 @@ struct Runner {
 };
 
 int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C, void *ws,
-                 size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats, bool &enqueued) {
+                 size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats, bool &enqueued,
+                 Tape *tape = nullptr) {
   Plan pl;
   int e = make_plan(A, B, chi_out, o, pl);
   if (e) return e;
@@ -679,6 +797,7 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
 
   Runner R(st, o);
   R.eps_ = tol;
+  R.tape = tape;
   enqueued = true;
   char *base = static_cast<char *>(ws);
   size_t off = 0;
@@ -723,8 +842,8 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     if (hflag[0]) return TTM_ENONFINITE;
   }
   // 1. canonical form of both inputs
-  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(a, i);
-  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(b, i);
+  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(a, i, 0);
+  for (int i = 0; i + 1 < n && !R.err; ++i) R.qr_move(b, i, 1);
   // 2. reversal of B
   std::vector<Core> bt(n);
   for (int i = 0; i < n && !R.err; ++i) {
@@ -737,8 +856,13 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     b[i].p = nullptr;
   }
   if (R.err) return R.err;
+  if (tape) {
+    TapeEntry e;
+    e.kind = TapeEntry::REVERSE;
+    tape->e.push_back(e);
+  }
   // 3. contract site N-1
-  pi[n - 1] = R.contract(a[n - 1], bt[n - 1]);
+  pi[n - 1] = R.contract(a[n - 1], bt[n - 1], n - 1);
   R.give(a[n - 1].p);
   R.give(bt[n - 1].p);
   // 4. swaps and contractions
@@ -747,10 +871,10 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     Core x = bt[j];
     for (int p = n - 1; p > j && !R.err; --p) {
       const int cap = swap_cap(o, pl.phys, j, p, pi[p].s, x.s);
-      R.swap(pi[p], x, cap);
+      R.swap(pi[p], x, cap, p, j);
     }
     if (R.err) break;
-    pi[j] = R.contract(a[j], x);
+    pi[j] = R.contract(a[j], x, j);
     R.give(a[j].p);
     R.give(x.p);
   }
@@ -804,6 +928,49 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
   }
   return TTM_OK;
 }
+
+}  // namespace
+
+// The product with its reverse-mode record (used by ttm_multiply_vjp): the
+// schedule of run_ttm with every step's operands copied into `tape`.
+int run_ttm_taped(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, const ttm_options *opt,
+                  ttm_tt_out *C, void *ws, size_t ws_bytes, hipStream_t st, ttm_stats *stats, Tape *tape,
+                  bool *swapped) {
+  Options o;
+  int e = resolve_options(opt, chi_out, o);
+  if (e) return e;
+  if (o.gauge != TTM_GAUGE_MOVING) return TTM_EUNSUPPORTED;
+  *swapped = moves_first(A, B, o);
+  bool enqueued = false;
+  e = run_ttm_impl(A, B, chi_out, tol, C, ws, ws_bytes, st, o, stats, enqueued, tape);
+  if (e == TTM_OK && tape->overflow) e = TTM_EWORKSPACE;
+  if (e != TTM_OK && enqueued) (void)hipStreamSynchronize(st);
+  return e;
+}
+
+// Sizes of the reverse mode: the product's workspace, its record, the
+// largest core and SVD matrix (doubles), and the output capacity.
+int vjp_sizes(const ttm_tt *A, const ttm_tt *B, int chi_out, const ttm_options *opt, size_t *fwd_ws,
+              int64_t *tape_doubles, int64_t *max_core, int64_t *max_mn, int64_t *out_capacity) {
+  int e = validate_pair(A, B);
+  if (e) return e;
+  if (chi_out < 1) return TTM_EINVAL;
+  Options o;
+  e = resolve_options(opt, chi_out, o);
+  if (e) return e;
+  if (o.gauge != TTM_GAUGE_MOVING) return TTM_EUNSUPPORTED;
+  Plan pl;
+  e = make_plan(A, B, chi_out, o, pl);
+  if (e) return e;
+  *fwd_ws = pl.ws_bytes;
+  *tape_doubles = pl.tape + 64 * (int64_t)(8 * pl.n * pl.n + 16);  // per-entry alignment slack
+  *max_core = pl.max_core;
+  *max_mn = pl.max_mn;
+  *out_capacity = pl.out_capacity;
+  return TTM_OK;
+}
+
+namespace {
 
 int run_ttm(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_tt_out *C, void *ws,
             size_t ws_bytes, hipStream_t st, const Options &o, ttm_stats *stats) {

@@ -92,7 +92,7 @@ size_t svd_ws_doubles(const SvdPlan &p) {
 
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, int trace) {
+                    KernelTimer *timer, int trace, SvdAll *all) {
   SvdResult out;
   SvdBufs b = carve(p, ws);
   const JacobiPlan &jp = p.jp;
@@ -204,14 +204,36 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   // U_r^T row-major is that column-major matrix, so SVD_U_T is formed in u.
   const int r = out.rank;
   double *ucm = (u_layout == SVD_U_T) ? u : b.Xt;
-  {
-    Timed tm(timer, KC_JAC_OTHER, s);
-    if (p.k < p.no && !ok(launch_fill(ucm, 0.0, (int64_t)p.no * r, s))) return out;
-    if (!ok(launch_jacobi_write_u(jp, b.jb, nullptr, r, ucm, 1, p.no, s))) return out;
-  }
-  {
-    Timed tm(timer, KC_QR, s);
-    if (!ok(launch_apply_q(b.S, p.no, p.k, b.Tall, ucm, r, b.qr, s))) return out;
+  if (all) {
+    // every resolved vector; U_r is their leading r columns
+    const int kg = std::max(r, std::min(p.k, (int)res[6]));
+    all->kg = kg;
+    {
+      Timed tm(timer, KC_JAC_OTHER, s);
+      if (p.k < p.no && !ok(launch_fill(all->u, 0.0, (int64_t)p.no * kg, s))) return out;
+      if (!ok(launch_jacobi_write_u(jp, b.jb, nullptr, kg, all->u, 1, p.no, s))) return out;
+    }
+    {
+      Timed tm(timer, KC_QR, s);
+      if (!ok(launch_apply_q(b.S, p.no, p.k, b.Tall, all->u, kg, b.qr, s))) return out;
+    }
+    {
+      Timed tm(timer, KC_JAC_OTHER, s);
+      if (!ok(launch_copy(ucm, all->u, (int64_t)p.no * r, s))) return out;
+      hipLaunchKernelGGL(sorted_sigma_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s, b.jb.sigma, b.jb.perm,
+                         p.k, all->sigma);
+      if (!ok(hipGetLastError())) return out;
+    }
+  } else {
+    {
+      Timed tm(timer, KC_JAC_OTHER, s);
+      if (p.k < p.no && !ok(launch_fill(ucm, 0.0, (int64_t)p.no * r, s))) return out;
+      if (!ok(launch_jacobi_write_u(jp, b.jb, nullptr, r, ucm, 1, p.no, s))) return out;
+    }
+    {
+      Timed tm(timer, KC_QR, s);
+      if (!ok(launch_apply_q(b.S, p.no, p.k, b.Tall, ucm, r, b.qr, s))) return out;
+    }
   }
   {
     Timed tm(timer, KC_JAC_OTHER, s);

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/ttm.h"
 
 namespace ttm {
@@ -174,7 +176,7 @@ struct JacobiBufs {
   double *qbuf = nullptr;   // pairs * (2bw)^2: rotations of the current round
   int *flag = nullptr;      // pairs: rotation is not the identity
   double *result = nullptr; // 8 doubles: [0]=rank,[1]=discarded,[2]=total,[3]=max off,[4]=nonfinite,
-                            // [5]=squared Frobenius norm of W
+                            // [5]=squared Frobenius norm of W, [6]=count of values above the noise level
 };
 
 // One sweep of rounds; after it b.result[3] holds the sweep's largest scaled
@@ -245,9 +247,73 @@ struct SvdResult {
 // stream once per Jacobi sweep (convergence test) and at the end.  trace > 0
 // prints one line per SVD to stderr, trace > 1 also one per sweep.
 enum { SVD_U_T = 0, SVD_U = 1 };
+// With `all` set, the SVD also hands out every resolved singular vector for
+// the reverse mode: the kg values above the rounding-noise level (kg >= r;
+// the others' vectors are not resolved, see jacobi_rank_kernel) with their
+// orthonormal vectors U_kg as the columns of all->u (no x kg, column-major),
+// and the k singular values in decreasing order in all->sigma.  u then
+// receives the first r of those columns in its layout.
+struct SvdAll {
+  double *u = nullptr;      // no x k capacity (column-major), written no x kg
+  double *sigma = nullptr;  // k doubles, decreasing
+  int kg = 0;               // out
+};
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, int trace);
+                    KernelTimer *timer, int trace, SvdAll *all = nullptr);
+
+// ------------------------------------------------------------------ reverse mode
+// The record a TTM product keeps for its reverse mode: one entry per step,
+// with device copies (in a caller workspace region) of what the step's
+// adjoint reads.  Shapes are host integers.
+struct TapeEntry {
+  enum Kind { QR = 0, CONTRACT = 1, SWAP = 2, ROUND = 3, REVERSE = 4 };
+  int kind = QR;
+  int arr = 0;  // QR: the train moved (0 = A, 1 = B, 2 = the product block)
+  int p = 0;    // QR: core index; CONTRACT: site; SWAP: position of P; ROUND: site
+  int j = 0;    // SWAP: the site whose carriage moves
+  // QR: M (m x n, row-major) = Q R with Q (m x k), R (k x n); the old next
+  // core nxt (n x ncol) became R nxt; rl, d: the core's left bond and
+  // physical dimension (m = rl d).
+  // CONTRACT: K [dl, d, dm], X [dm, d, dr].
+  // SWAP: P [dl, dp, dm], X [dm, dx, dr]; theta (m = dl dx by n = dp dr,
+  // column-major); V (n x kg, column-major) the resolved right singular
+  // vectors, sigma (min(m, n), decreasing); Z = theta V_r (m x r, row-major).
+  // ROUND: M = Pi_i (m = rl d by n = rr, row-major); V (m x kg, column-major)
+  // its resolved left singular vectors; sigma; Zt = S_r V_r^T (r x n); nxt
+  // (n x ncol) the old next core.
+  int m = 0, n = 0, k = 0, ncol = 0, r = 0, kg = 0;
+  int rl = 0, d = 0, dl = 0, dp = 0, dm = 0, dx = 0, dr = 0;
+  double *M = nullptr, *Q = nullptr, *R = nullptr, *nxt = nullptr;
+  double *K = nullptr, *X = nullptr, *P = nullptr, *theta = nullptr, *V = nullptr, *sigma = nullptr,
+         *Z = nullptr, *Zt = nullptr;
+};
+struct Tape {
+  std::vector<TapeEntry> e;
+  double *base = nullptr;
+  size_t cap = 0, used = 0;  // doubles
+  bool overflow = false;
+  double *alloc(size_t n) {
+    n = (n + 31) & ~(size_t)31;
+    if (used + n > cap) {
+      overflow = true;
+      return nullptr;
+    }
+    double *p = base + used;
+    used += n;
+    return p;
+  }
+};
+
+// The TTM product with every step recorded in `tape` (default gauge only:
+// TTM_EUNSUPPORTED otherwise); *swapped reports whether the two trains
+// traded places (move_factor = TTM_MOVE_SMALLER).
+int run_ttm_taped(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, const ttm_options *opt,
+                  ttm_tt_out *C, void *ws, size_t ws_bytes, hipStream_t st, ttm_stats *stats, Tape *tape,
+                  bool *swapped);
+// Sizes for the reverse mode (host only).
+int vjp_sizes(const ttm_tt *A, const ttm_tt *B, int chi_out, const ttm_options *opt, size_t *fwd_ws,
+              int64_t *tape_doubles, int64_t *max_core, int64_t *max_mn, int64_t *out_capacity);
 
 // ------------------------------------------------------------------ conventional
 // Dense transposed copy used by the variational driver:

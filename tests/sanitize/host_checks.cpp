@@ -100,6 +100,23 @@ int main() {
            TTM_EINVAL);
     double v = 0.0;
     EXPECT(ttm_inner_grad(&A.view, &A.view, &B.view, 9, &v, nullptr, nullptr, nullptr, 0, nullptr) == TTM_EINVAL);
+    // the reverse mode: its sizes cover the product's, and its argument
+    // checks come before any HIP call as well
+    size_t vws = 0;
+    int64_t vcap = 0;
+    const int vrc = ttm_vjp_query(&A.view, &B.view, chi, &o, &vws, &vcap);
+    EXPECT(vrc == (o.gauge == TTM_GAUGE_RIGHT && rc == TTM_OK ? TTM_EUNSUPPORTED : rc));
+    if (vrc == TTM_OK) {
+      size_t fws = 0;
+      int64_t fcap = 0;
+      EXPECT(ttm_query(&A.view, &B.view, chi, &o, &fws, &fcap) == TTM_OK);
+      EXPECT(vws > fws && vcap == fcap);
+      double *fake = reinterpret_cast<double *>(0x4000);
+      EXPECT(ttm_multiply_vjp(&A.view, &B.view, chi, 1e-12, &o, &A.view, &C, fake, fake, nullptr, 0, nullptr,
+                              nullptr) == TTM_EWORKSPACE);
+      EXPECT(ttm_multiply_vjp(&A.view, &B.view, chi, NAN, &o, &A.view, &C, fake, fake, nullptr, 0, nullptr,
+                              nullptr) == TTM_EINVAL);
+    }
   }
   // 2. malformed descriptors and options
   {

@@ -358,3 +358,53 @@ def test_last_error_is_cleared_by_each_call(L):
     assert L.ttm_multiply_ex(ctypes.byref(big.view), ctypes.byref(big.view), 0, 1e-14, ctypes.byref(out),
                              None, 0, None, None, None) == _abi.TTM_EINVAL
     assert L.ttm_last_error() == b""
+
+
+def test_vjp_rejects_before_gpu_work(L):
+    """ttm_vjp_query sizes the reverse mode from shapes (more than the
+    product's own workspace: the record of the steps comes on top), refuses
+    the centre-right gauge, and ttm_multiply_vjp rejects bad arguments before
+    any HIP call."""
+    A = _TT([2] * 4, [1, 2, 4, 2, 1])
+    o = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(o))
+    need, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(A.view), 4, ctypes.byref(o), ctypes.byref(need),
+                           ctypes.byref(cap)) == 0
+    rc, fwd, fcap = _query(L, A, A, 4, o)
+    assert rc == 0 and cap.value == fcap
+    assert need.value > fwd
+    right = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(right))
+    right.gauge = _abi.TTM_GAUGE_RIGHT
+    assert L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(A.view), 4, ctypes.byref(right),
+                           ctypes.byref(need), ctypes.byref(cap)) == _abi.TTM_EUNSUPPORTED
+    assert L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(A.view), 0, ctypes.byref(o), ctypes.byref(need),
+                           ctypes.byref(cap)) == _abi.TTM_EINVAL
+    bonds = (ctypes.c_int32 * 5)()
+    offs = (ctypes.c_int64 * 4)()
+    out = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000),
+                        1 << 20)
+    dA, dB, ws = ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000), ctypes.c_void_p(0x3000)
+    pre = (ctypes.byref(A.view), ctypes.byref(A.view), 4)
+
+    def call(tol=1e-12, opt=o, cbar=A, C=out, ws=ws, nbytes=1 << 30, da=dA):
+        return L.ttm_multiply_vjp(*pre, tol, ctypes.byref(opt), ctypes.byref(cbar.view) if cbar else None,
+                                  ctypes.byref(C) if C else None, da, dB, ws, nbytes, None, None)
+
+    assert call(tol=float("nan")) == _abi.TTM_EINVAL
+    assert call(tol=-1.0) == _abi.TTM_EINVAL
+    prof = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(prof))
+    prof.profile = 1
+    assert call(opt=prof) == _abi.TTM_EINVAL
+    assert call(opt=right) == _abi.TTM_EUNSUPPORTED
+    assert call(ws=None) == _abi.TTM_EWORKSPACE
+    assert call(nbytes=need.value - 8) == _abi.TTM_EWORKSPACE
+    assert call(C=None) == _abi.TTM_EINVAL
+    small = _abi.TtmTTOut(ctypes.cast(bonds, _abi.I32P), ctypes.cast(offs, _abi.I64P), ctypes.c_void_p(0x2000), 3)
+    assert call(C=small) == _abi.TTM_ECAPACITY
+    assert call(cbar=None) == _abi.TTM_EINVAL
+    assert call(da=None) == _abi.TTM_EINVAL
+    three = _TT([2] * 3, [1, 2, 2, 1])
+    assert call(cbar=three) == _abi.TTM_ESHAPE
