@@ -219,6 +219,7 @@ def main():
         # its dominant kernel (one launch = one round of one Jacobi sweep of
         # one SVD: every block pair's Gram diagonalised, V rotated).
         flops_per_launch = sum(s["svd_model_flops"] for s in pstats) / rot_n
+        own_per_launch = sum(s["jacobi_solve_flops"] for s in pstats) / rot_n
         avg_launch_s = rot_ms / rot_n / 1e3
         achieved = flops_per_launch / avg_launch_s / 1e12
         # The solve kernel's arithmetic is FP64 vector ALU work (plane
@@ -235,6 +236,15 @@ def main():
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_flops_per_launch": flops_per_launch,
             "profiled_ms_per_step": 1e3 * tp / args.steps,
+            # Context for the accounting above, which credits the product's
+            # SVD model flops to the solve launches: the solve kernel's own
+            # arithmetic (it diagonalises small pair Grams in LDS: latency
+            # bound), and the whole product's model flops against the FP64
+            # matrix-core peak.
+            "kernel_own_flops_per_launch": own_per_launch,
+            "kernel_own_frac": own_per_launch / avg_launch_s / 1e12 / FP64_VALU_PEAK_TFLOPS,
+            "product_algorithmic_tflops": model_flops / (ms_per_step / 1e3) / 1e12,
+            "product_mfma_frac": model_flops / (ms_per_step / 1e3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
         }
         if roofline["traffic"] is not None:
             roofline["traffic_gbs"] = roofline["traffic"] / avg_launch_s / 1e9
@@ -318,6 +328,7 @@ def main():
         "model_flops_per_step": model_flops,
         "svd_model_flops_per_step": svd_flops,
         "algorithmic_tflops": model_flops / (ms_per_step / 1e3) / 1e12,
+        "fp64_mfma_frac": model_flops / (ms_per_step / 1e3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
         "jacobi_sweeps_per_step": st["sweeps"],
         "max_bond": st["max_bond"],
         "rel_err_vs_oracle": rel_err,

@@ -152,6 +152,10 @@ typedef struct ttm_stats {
   double error_bound;      /* sum over SVDs of sqrt(discarded weight): bounds ||C - A*B|| */
   double model_flops;      /* algorithmic flops of the recorded schedule       */
   double svd_model_flops;  /* the part of model_flops spent in SVDs            */
+  double jacobi_solve_flops; /* arithmetic of the Jacobi pair solves themselves (Gram
+                              partial sums, the in-LDS rotation sweep, the
+                              re-orthogonalisation), counted for every pair
+                              launched: the solve kernel's own work       */
   size_t peak_ws_bytes;    /* workspace bytes the call used                    */
   double kernel_ms[TTM_KC_COUNT];        /* with opt.profile: summed event time per class */
   int64_t kernel_launches[TTM_KC_COUNT]; /* with opt.profile: timed regions per class: one launch

@@ -73,6 +73,7 @@ class TtmStats(ctypes.Structure):
         ("error_bound", ctypes.c_double),
         ("model_flops", ctypes.c_double),
         ("svd_model_flops", ctypes.c_double),
+        ("jacobi_solve_flops", ctypes.c_double),
         ("peak_ws_bytes", ctypes.c_size_t),
         ("kernel_ms", ctypes.c_double * 7),
         ("kernel_launches", ctypes.c_int64 * 7),

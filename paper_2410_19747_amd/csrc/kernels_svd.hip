@@ -113,6 +113,14 @@ JacobiPlan jacobi_plan(int L, int nc, int force_bw) {
   p.sw = (L + p.rows_per_wg - 1) / p.rows_per_wg;
   p.rounds = nblk - 1;
   p.pairs = nblk / 2;
+  // With circle pairing a Gram workgroup sums gsub consecutive row chunks
+  // in its matrix-core accumulators, so that the solve reduces gsw partials
+  // instead of sw: each partial is a full 2bw x 2bw Gram, and at 8192 rows
+  // the partials of one round would otherwise be 268 MB written and read
+  // back.  gsub is chosen to keep about 1024 Gram workgroups.  (The XOR
+  // kernel forms its Grams per chunk in the rotation pass: gsub = 1.)
+  p.gsub = p.xs ? 1 : std::max(1, std::min(p.sw, p.pairs * p.sw / 1024));
+  p.gsw = (p.sw + p.gsub - 1) / p.gsub;
   return p;
 }
 
@@ -120,7 +128,7 @@ size_t jacobi_ws_doubles(const JacobiPlan &p) {
   const size_t b2 = 2 * (size_t)p.bw;
   size_t n = 0;
   n += 2 * (size_t)p.L * p.ncp;               // W and its reordering buffer
-  n += (size_t)p.pairs * p.sw * b2 * b2;      // partial Grams
+  n += (size_t)p.pairs * p.gsw * b2 * b2;     // partial Grams
   n += (size_t)p.rounds * p.pairs;            // conv
   n += (size_t)p.pairs * b2 * b2;             // rotations of the current round
   n += (size_t)p.pairs;                       // rotation flags (ints)
@@ -138,12 +146,16 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // and B(k+l/16, l%16); accumulator register t of lane l holds
 // D(4t + l/16, l%16).  a(i,k) / b(k,j) are LDS accessors.
 template <typename FA, typename FB>
-__device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+__device__ __forceinline__ dbl4 mfma_tile_acc(FA a, FB b, int K, int lane, dbl4 acc) {
   const int r = lane & 15, kq = lane >> 4;
   for (int k = 0; k < K; k += 4)
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(r, k + kq), b(k + kq, r), acc, 0, 0, 0);
   return acc;
+}
+template <typename FA, typename FB>
+__device__ __forceinline__ dbl4 mfma_tile(FA a, FB b, int K, int lane) {
+  const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
+  return mfma_tile_acc(a, b, K, lane, zero);
 }
 
 // ------------------------------------------------------------------ pair pieces
@@ -182,43 +194,6 @@ __device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, in
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * JNT;
     P[e % RC][e / RC] = v[q];
-  }
-}
-
-// out (B2 x B2, row-major) = P^T P over the tile; the four waves take the
-// 16 x 16 output tiles in turn.
-template <int BW, int RC>
-__device__ __forceinline__ void gram_of_tile(const typename Pair<BW>::template Tile<RC> &P, double *__restrict__ out) {
-  constexpr int B2 = Pair<BW>::B2, NT = B2 / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int t = wave; t < NT * NT; t += JNT / 64) {
-    const int ti = t / NT, tj = t % NT;
-    dbl4 acc = mfma_tile([&](int i, int k) { return P[k][ti * 16 + i]; },
-                         [&](int k, int j) { return P[k][tj * 16 + j]; }, RC, lane);
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti * 16 + 4 * q + (lane >> 4), j = tj * 16 + (lane & 15);
-      out[i * B2 + j] = acc[q];
-    }
-  }
-}
-
-// W rows of the tile <- P Q (P, Q in LDS); the four waves take the 16 x 16
-// output tiles in turn.
-template <int BW, int RC>
-__device__ __forceinline__ void apply_tile(const typename Pair<BW>::template Tile<RC> &P,
-                                           const typename Pair<BW>::Square &Q, double *__restrict__ W, int L, int bi,
-                                           int bj, int chunk) {
-  constexpr int B2 = Pair<BW>::B2, NC = B2 / 16, NR = RC / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = chunk * RC, nr = min(RC, L - r0);
-  for (int t = wave; t < NR * NC; t += JNT / 64) {
-    const int rt = t / NC, y = t % NC;
-    dbl4 acc = mfma_tile([&](int i, int k) { return P[rt * 16 + i][k]; },
-                         [&](int k, int j) { return Q[k][y * 16 + j]; }, B2, lane);
-    for (int q = 0; q < 4; ++q) {
-      const int i = rt * 16 + 4 * q + (lane >> 4), c = y * 16 + (lane & 15);
-      if (i < nr) W[(int64_t)pair_col<BW>(bi, bj, c) * L + r0 + i] = acc[q];
-    }
   }
 }
 
@@ -465,18 +440,42 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 }
 
 // ------------------------------------------------------------------ kernels of a round
-// grid (pairs, sw).  Partial Gram of every block pair over one row chunk.
+// grid (pairs, gsw).  Partial Gram of every block pair over gsub
+// consecutive row chunks, accumulated on the matrix cores (each wave owns
+// the same 16 x 16 output tiles throughout) and stored once.
 template <int BW, int RC>
 __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk, int xs,
-                                                          int round, double *__restrict__ part, int sw) {
+                                                          int round, double *__restrict__ part, int gsw,
+                                                          int gsub) {
   __shared__ typename Pair<BW>::template Tile<RC> P;
-  constexpr int B2 = Pair<BW>::B2;
+  constexpr int B2 = Pair<BW>::B2, NT = B2 / 16, TPW = NT * NT / (JNT / 64);
+  static_assert(TPW * (JNT / 64) == NT * NT, "whole tiles per wave");
   const int pair = blockIdx.x, s = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bi, bj;
   pair_blocks(xs, nblk, round, pair, bi, bj);
-  load_pair_chunk<BW, RC>(W, L, bi, bj, s, P);
-  __syncthreads();
-  gram_of_tile<BW, RC>(P, part + ((int64_t)pair * sw + s) * B2 * B2);
+  dbl4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  for (int sub = 0; sub < gsub; ++sub) {
+    const int chunk = s * gsub + sub;
+    if (chunk * RC >= L) break;  // uniform over the workgroup
+    if (sub > 0) __syncthreads();  // the previous chunk's tile has been read
+    load_pair_chunk<BW, RC>(W, L, bi, bj, chunk, P);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wave + i * (JNT / 64), ti = t / NT, tj = t % NT;
+      acc[i] = mfma_tile_acc([&](int r, int k) { return P[k][ti * 16 + r]; },
+                             [&](int k, int j) { return P[k][tj * 16 + j]; }, RC, lane, acc[i]);
+    }
+  }
+  double *out = part + ((int64_t)pair * gsw + s) * B2 * B2;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = wave + i * (JNT / 64), ti = t / NT, tj = t % NT;
+    for (int q = 0; q < 4; ++q) out[(ti * 16 + 4 * q + (lane >> 4)) * B2 + tj * 16 + (lane & 15)] = acc[i][q];
+  }
 }
 
 // grid (pairs).  One workgroup per block pair: the solve, the rotation into
@@ -502,33 +501,54 @@ __global__ __launch_bounds__(Pair<BW>::THREADS) void jacobi_solve_kernel(int L, 
   }
 }
 
-// grid (pairs, sw).  Apply the stored rotation of each pair to one row chunk
-// of W.  The flag, the rotation and the chunk are loaded together; a pair
-// that did not rotate stores nothing.
+// grid (pairs, sw).  Apply the stored rotation Q of each pair to one row
+// chunk of W: W_rows <- W_rows Q.  Only Q is staged in LDS.  Each wave takes
+// 16-row tiles and forms the transposed product Q^T W_rows^T on the matrix
+// cores: the operand W_rows^T is then read straight from W with sixteen
+// consecutive rows of one column per sixteen lanes, and the accumulator
+// layout (lane l, register t: output column 4t + l/16 of the 16-column tile,
+// row l%16) stores sixteen consecutive rows of a column per sixteen lanes.
+// A wave reads all of its rows before it writes them.  A pair that did not
+// rotate stores nothing.
 template <int BW, int RC>
 __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ W, int L, int nblk, int xs,
                                                            int round, const double *__restrict__ qbuf,
                                                            const int *__restrict__ flag) {
-  __shared__ typename Pair<BW>::Square Qn;
-  __shared__ typename Pair<BW>::template Tile<RC> P;
-  constexpr int B2 = Pair<BW>::B2, QPER = B2 * B2 / JNT;
+  constexpr int B2 = Pair<BW>::B2, QPER = B2 * B2 / JNT, KS = B2 / 4, NC = B2 / 16;
+  __shared__ double Qs[B2][B2 + 1];
   const int pair = blockIdx.x, chunk = blockIdx.y;
-  const int rot = flag[pair];
+  if (flag[pair] == 0) return;  // uniform over the workgroup
   int bi, bj;
   pair_blocks(xs, nblk, round, pair, bi, bj);
   const double *qsrc = qbuf + (int64_t)pair * B2 * B2;
   double qv[QPER];
 #pragma unroll
   for (int q = 0; q < QPER; ++q) qv[q] = qsrc[threadIdx.x + q * JNT];
-  load_pair_chunk<BW, RC>(W, L, bi, bj, chunk, P);
 #pragma unroll
   for (int q = 0; q < QPER; ++q) {
     const int e = threadIdx.x + q * JNT;
-    Qn[e / B2][e % B2] = qv[q];
+    Qs[e / B2][e % B2] = qv[q];
   }
-  if (rot == 0) return;  // uniform over the workgroup
   __syncthreads();
-  apply_tile<BW, RC>(P, Qn, W, L, bi, bj, chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, kq = lane >> 4;
+  for (int rt = wave; rt < RC / 16; rt += JNT / 64) {
+    const int row = chunk * RC + rt * 16 + r;
+    const bool in = row < L;
+    double bv[KS];  // operand: W(row, 4k + kq)
+#pragma unroll
+    for (int k = 0; k < KS; ++k) bv[k] = in ? W[(int64_t)pair_col<BW>(bi, bj, 4 * k + kq) * L + row] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < NC; ++ct) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[4 * k + kq][ct * 16 + r], bv[k], acc, 0, 0, 0);
+      if (in) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) W[(int64_t)pair_col<BW>(bi, bj, ct * 16 + 4 * t + kq) * L + row] = acc[t];
+      }
+    }
+  }
 }
 
 // grid (nblk / 4, sw), XOR pairing, 32-column pairs, in place.  Round
@@ -717,13 +737,13 @@ void launch_round(const JacobiPlan &p, const JacobiBufs &b, int round, double to
                   KernelTimer *timer, bool gram, bool apply) {
   if (gram) {
     Timed tm(timer, KC_JAC_GRAM, s);
-    hipLaunchKernelGGL((jacobi_gram_kernel<BW, RC>), dim3(p.pairs, p.sw), dim3(JNT), 0, s, b.W, p.L, p.nblk, p.xs,
-                       round, b.part, p.sw);
+    hipLaunchKernelGGL((jacobi_gram_kernel<BW, RC>), dim3(p.pairs, p.gsw), dim3(JNT), 0, s, b.W, p.L, p.nblk,
+                       p.xs, round, b.part, p.gsw, p.gsub);
   }
   {
     Timed tm(timer, KC_JAC_SOLVE, s);
     hipLaunchKernelGGL(jacobi_solve_kernel<BW>, dim3(p.pairs), dim3(Pair<BW>::THREADS), 0, s, p.L, p.nblk, round,
-                       b.part, p.sw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
+                       b.part, p.gsw, b.conv, tol, b.result, noise2, b.qbuf, b.flag);
   }
   if (apply) {
     Timed tm(timer, KC_JAC_APPLY, s);

@@ -374,7 +374,7 @@ struct Runner {
   // stats
   int n_contract = 0, n_swap = 0, n_qr = 0, n_svd = 0, n_trace = 0, max_bond = 1;
   int jac_sweeps = 0, jac_max = 0;
-  double disc_sum = 0.0, err_bound = 0.0, flops = 0.0, svd_flops = 0.0;
+  double disc_sum = 0.0, err_bound = 0.0, flops = 0.0, svd_flops = 0.0, solve_flops = 0.0;
   int forced_pos = 0;
   int err = TTM_OK;
   KernelTimer timer;
@@ -555,6 +555,15 @@ struct Runner {
     const double f = 4.0 * m * (double)n * n - (4.0 / 3.0) * n * (double)n * n + 4.0 * (m + n) * (double)n * so.rank;
     flops += f;
     svd_flops += f;
+    // the solve kernel's own arithmetic per pair and launch: the sum of gsw
+    // partial Grams, B2 - 1 rotation steps (6 flops per entry of G and Q),
+    // and two B2^3 products of the re-orthogonalisation
+    {
+      const JacobiPlan &jp = sp.jp;
+      const double b2 = 2.0 * jp.bw;
+      const double per_pair = jp.gsw * b2 * b2 + 6.0 * b2 * b2 * (b2 - 1.0) + 4.0 * b2 * b2 * b2;
+      solve_flops += (double)so.sweeps * jp.rounds * jp.pairs * per_pair;
+    }
     return so.rank;
   }
 
@@ -920,6 +929,7 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     stats->error_bound = R.err_bound;
     stats->model_flops = R.flops;
     stats->svd_model_flops = R.svd_flops;
+    stats->jacobi_solve_flops = R.solve_flops;
     stats->peak_ws_bytes = pl.ws_bytes;
     for (int c = 0; c < KC_COUNT; ++c) {
       stats->kernel_ms[c] = R.timer.ms[c];

@@ -47,7 +47,7 @@ SvdBufs carve(const SvdPlan &p, double *base) {
   b.perm1 = reinterpret_cast<int *>(adv((size_t)p.np));
   b.jb.W = adv((size_t)jp.L * jp.ncp);
   b.jb.Wt = adv((size_t)jp.L * jp.ncp);
-  b.jb.part = adv((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
+  b.jb.part = adv((size_t)jp.pairs * jp.gsw * 4 * jp.bw * jp.bw);
   b.jb.conv = adv((size_t)jp.rounds * jp.pairs);
   b.jb.qbuf = adv((size_t)jp.pairs * 4 * jp.bw * jp.bw);
   b.jb.flag = reinterpret_cast<int *>(adv((size_t)jp.pairs));
@@ -81,7 +81,7 @@ size_t svd_ws_doubles(const SvdPlan &p) {
   n += r32((size_t)((p.k + kPanel - 1) / kPanel) * kPanel * kPanel);
   n += 2 * r32((size_t)p.np);
   n += 2 * r32((size_t)jp.L * jp.ncp);
-  n += r32((size_t)jp.pairs * jp.sw * 4 * jp.bw * jp.bw);
+  n += r32((size_t)jp.pairs * jp.gsw * 4 * jp.bw * jp.bw);
   n += r32((size_t)jp.rounds * jp.pairs);
   n += r32((size_t)jp.pairs * 4 * jp.bw * jp.bw);
   n += r32((size_t)jp.pairs);

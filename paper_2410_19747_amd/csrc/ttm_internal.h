@@ -155,6 +155,8 @@ struct JacobiPlan {
   int xs = 0;            // 1: XOR pairing (round r pairs blocks i and i ^ (r + 1)), else circle method
   int rows_per_wg = 0;   // row chunk per workgroup for Gram and update
   int sw = 0;            // row chunks of W
+  int gsub = 1;          // row chunks summed by one Gram workgroup (circle pairing)
+  int gsw = 0;           // partial Grams per pair: ceil(sw / gsub)
   int rounds = 0;        // nblk - 1
   int pairs = 0;         // nblk / 2
 };

@@ -216,14 +216,16 @@ def test_svd_swap_size_2048_power_law():
     _say("  sweeps %d" % sw)
 
 
-@pytest.mark.parametrize("n,cap", [(1024, 128), (2048, 256)])
+@pytest.mark.parametrize("n,cap", [(1024, 128), (2048, 256), (4096, 512)])
 def test_svd_64_column_pairs_power_law(n, cap):
     """The 64-column-pair Jacobi path (32-column blocks, 1024-thread solve
     with the rotation in LDS, circle pairing, three launches per round),
     which every 8192-row swap matrix of the chi = 1024 product takes, forced
     on power-law matrices small enough for LAPACK: singular values, the rank
     rule with a cap, the best rank-r approximation, orthonormal factors, and
-    the same results within the parity bar as the 32-column-pair path."""
+    the same results within the parity bar as the 32-column-pair path.  At
+    4096 each Gram workgroup sums two row chunks (as at 8192, where it sums
+    eight)."""
     torch, L = _env()
     _say("svd 64-column pairs, power law %dx%d" % (n, n))
     rng = np.random.default_rng(n + 5)
@@ -251,6 +253,28 @@ def test_svd_64_column_pairs_power_law(n, cap):
     left3, right3, _, r3, _ = _svd(torch, L, M, eps=1e-14, cap=cap)
     assert r3 == r
     assert np.linalg.norm(left3 @ right3 - left @ right) <= 1e-12 * np.linalg.norm(M)
+
+
+def test_svd_gram_over_several_row_chunks():
+    """32-column pairs with circle pairing at 2900 columns (not a power of
+    two): 23 row chunks of 128, summed two at a time by the Gram workgroups,
+    the last one alone.  Against LAPACK."""
+    torch, L = _env()
+    n, cap = 2900, 300
+    _say("svd 32-column pairs, circle pairing, power law %dx%d" % (n, n))
+    rng = np.random.default_rng(29)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = (1.0 + np.arange(n)) ** -1.5
+    M = (U * s) @ V.T
+    ref = np.linalg.svd(M, compute_uv=False)
+    left, right, sv, r, sw = _svd(torch, L, M, eps=1e-14, cap=cap)
+    assert r == cap
+    assert np.allclose(sv, ref, rtol=1e-11, atol=1e-14 * ref[0])
+    best = (U[:, :r] * s[:r]) @ V[:, :r].T
+    assert np.linalg.norm(left @ right - best) <= 1e-11 * np.linalg.norm(M)
+    assert np.abs(right @ right.T - np.eye(r)).max() < 1e-12
+    _say("  sweeps %d" % sw)
 
 
 @pytest.mark.parametrize("m,n", [(1100, 1024), (1024, 1100), (700, 520)])
