@@ -95,6 +95,12 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="bond-dimension sweep on the 10-site shapes")
     ap.add_argument("--sweep-chis", default="64,128,256,512,1024")
     ap.add_argument("--sweep-grid", type=int, default=1024)
+    ap.add_argument("--qtt-cache", default="",
+                    help="directory for the sweep's QTTs: loaded when present, else generated and saved there")
+    ap.add_argument("--generate-only", action="store_true",
+                    help="with --sweep and --qtt-cache: generate and save the QTTs, then stop")
+    ap.add_argument("--svd-size", type=int, default=0,
+                    help="time one N x N truncated SVD (cap N/8, columns scaled by 1/j) through the test hook")
     ap.add_argument("--sweep-precisions", default="f64",
                     help="contraction arithmetic per sweep point, e.g. f64,f32,bf16x3,bf16 (f64 first)")
     ap.add_argument("--batched", action="store_true",
@@ -140,6 +146,8 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.svd_size:
+        return svd_size(args, dev)
     if args.sweep:
         return sweep(args, dev)
     if args.batched:
@@ -519,6 +527,72 @@ def _tt_entries(cores, idx):
     return v[:, 0]
 
 
+def _sweep_qtts(args, chis, dev):
+    """The sweep's QTTs (seed 101) for each chi: from --qtt-cache when saved
+    there, else generated on the device (and saved when a cache is given).
+    Loading them lets a counter run profile the product without the input
+    generator's own GPU libraries in the process."""
+    import numpy as np
+
+    import ttm_inputs as I
+
+    out, missing = {}, []
+    for chi in chis:
+        path = os.path.join(args.qtt_cache, "turbulence%d_s101_chi%d.npz" % (args.sweep_grid, chi))
+        if args.qtt_cache and os.path.exists(path):
+            z = np.load(path)
+            out[chi] = [z["arr_%d" % i] for i in range(len(z.files))]
+        else:
+            missing.append(chi)
+    if missing:
+        out.update(I.turbulence_qtt_device(args.sweep_grid, 101, missing, dev))
+        if args.qtt_cache:
+            os.makedirs(args.qtt_cache, exist_ok=True)
+            for chi in missing:
+                np.savez(os.path.join(args.qtt_cache, "turbulence%d_s101_chi%d.npz" % (args.sweep_grid, chi)),
+                         *out[chi])
+    return out
+
+
+def svd_size(args, dev):
+    """One N x N truncated SVD, the size of a swap matrix at chi = N / 8 and
+    d = 8 (Gaussian columns scaled by 1/j, cap N / 8, eps 1e-14), through the
+    library's SVD test hook: time and Jacobi sweeps.  One JSON line."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2410_19747_amd import _abi
+
+    L = _abi.load_library()
+    n = args.svd_size
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((n, n)) * (np.arange(1, n + 1) ** -1.0)[None, :]
+    dM = torch.tensor(M.T.copy().ravel(), device=dev)
+    del M
+    dl = torch.zeros(n * n, dtype=torch.float64, device=dev)
+    dr = torch.zeros(n * n, dtype=torch.float64, device=dev)
+    ds = torch.zeros(n, dtype=torch.float64, device=dev)
+    nb = L.ttm_test_svd_ws_bytes_bw(n, n, 0)
+    ws = torch.zeros(nb // 8 + 1, dtype=torch.float64, device=dev)
+    rank, sw = ctypes.c_int(0), ctypes.c_int(0)
+    _log("svd %d x %d, workspace %.1f GiB" % (n, n, nb / 2 ** 30))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc = L.ttm_test_svd_bw(ctypes.c_void_p(dM.data_ptr()), n, n, 1e-14, n // 8, 0, 1, 0,
+                           ctypes.c_void_p(dl.data_ptr()), ctypes.c_void_p(dr.data_ptr()),
+                           ctypes.c_void_p(ds.data_ptr()), ctypes.byref(rank), ctypes.byref(sw), 0,
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8, None)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    if rc != 0:
+        raise RuntimeError("ttm_test_svd returned %d" % rc)
+    print(json.dumps({"svd_size": n, "cap": n // 8, "rank": rank.value, "jacobi_sweeps": sw.value,
+                      "seconds": dt}), flush=True)
+    return None
+
+
 def sweep(args, dev):
     import numpy as np
     import torch
@@ -529,7 +603,9 @@ def sweep(args, dev):
     chis = [int(c) for c in args.sweep_chis.split(",") if c]
     _log("generating %d^3 turbulence QTTs on the device for chi %s" % (args.sweep_grid, chis))
     t0 = time.time()
-    qtts = I.turbulence_qtt_device(args.sweep_grid, 101, chis, dev)
+    qtts = _sweep_qtts(args, chis, dev)
+    if args.generate_only:
+        return None
     torch.cuda.empty_cache()
     _log("  done in %.1f s" % (time.time() - t0))
     n_sites = len(next(iter(qtts.values())))
