@@ -819,14 +819,14 @@ def adjoint(args, dev):
         t = time.perf_counter()
         ref = O.inner3_grad(W, qa, qb)
         cpu = time.perf_counter() - t
-    ws = T.Workspace(dev)
-    for prec in ("f64", "f32"):
+    for prec, stride in (("f64", 1), ("f32", 1), ("f64", 0)):
+        ws = T.Workspace(dev)
         for _ in range(max(args.warmup, 1)):
-            T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws)
+            T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws, env_stride=stride)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
-            v, dA, dB = T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws)
+            v, dA, dB = T.inner_grad(Wp, A, B, contract_precision=prec, workspace=ws, env_stride=stride)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
         err = None
@@ -842,10 +842,11 @@ def adjoint(args, dev):
                 "algorithmic_tflops": flops / dt / 1e12,
                 "fp64_mfma_frac": flops / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS,
                 "rel_err_vs_oracle_gradient": err, "value": v,
+                "env_stride": stride, "workspace_mib": ws.get(0).numel() / 2 ** 20,
                 "cpu_oracle_s": cpu, "cpu_cores": _cpu_threads() if cpu is not None else None}
         print(json.dumps(line), flush=True)
-        _log("  %s: %.2f ms per gradient, %.2f TFLOP/s algorithmic, rel err vs oracle %s"
-             % (prec, 1e3 * dt, flops / dt / 1e12, "%.2e" % err if err is not None else "-"))
+        _log("  %s, env stride %d: %.2f ms per gradient, %.2f TFLOP/s algorithmic, rel err vs oracle %s"
+             % (prec, stride, 1e3 * dt, flops / dt / 1e12, "%.2e" % err if err is not None else "-"))
     _reverse_mode(args, dev, A, B, Wp)
     return None
 

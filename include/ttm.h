@@ -263,8 +263,8 @@ int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, const int32_
  * environment of the sites after k (three-train environments).  Wherever the
  * truncations of TTM (Sec. II.B) drop nothing, TTM(A, B) is A*B and this is
  * the gradient of <W, TTM(A, B)>; where they do drop weight it is the
- * gradient of the exact product that TTM approximates, with the truncation
- * held fixed.
+ * gradient of the exact product that TTM approximates, not that of the
+ * truncated product (ttm_multiply_vjp differentiates that).
  * The environments are recomputed on every call: a right-to-left sweep
  * keeps the right ones in ws, then one left-to-right sweep forms both
  * gradients at each site and the next left environment.
@@ -280,6 +280,23 @@ int ttm_multiply_batch(int32_t n, const ttm_tt *A, const ttm_tt *B, const int32_
 int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size_t *ws_bytes);
 int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                    double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream);
+
+/* As ttm_inner_grad_query / ttm_inner_grad, with the right environments
+ * kept at checkpoints and recomputed between them instead of all stored.
+ * env_stride = 1: all N stored (the plain entry points).  env_stride = s >= 2:
+ * F_N, F_{N-s}, F_{N-2s}, ... are kept; when the left sweep reaches a site
+ * whose F_{k+1} lies between two checkpoints, the environments of that
+ * segment are recomputed from the checkpoint above it into s - 1 further
+ * buffers.  Memory: ceil(N / s) + s - 1 environments of the largest size
+ * instead of N + 1; work: at most twice the right sweep.  env_stride = 0:
+ * s = ceil(sqrt(N)) (at least 2).  Values and gradients are bitwise those of
+ * the stored form (the same products on the same inputs).  A negative
+ * env_stride is TTM_EINVAL. */
+int ttm_inner_grad_query_ex(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t env_stride,
+                            size_t *ws_bytes);
+int ttm_inner_grad_ex(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
+                      double *value, double *dA, double *dB, int32_t env_stride, void *ws, size_t ws_bytes,
+                      void *stream);
 
 /* Reverse mode of the TTM product (the paper has no gradients): given the
  * cotangent Cbar of the output cores (for a loss L(C), Cbar = dL/dC, laid out

@@ -378,10 +378,12 @@ def multiply_batch(pairs, chi_out, tol, streams=4, workspaces=None, options=None
     return res if raise_errors else (res, codes)
 
 
-def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, stream=None):
+def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, stream=None, env_stride=1):
     """L = <W, A*B> and, with ``grads``, dL/dA and dL/dB as PackedTTs laid
-    out like A and B, by one call of ttm_inner_grad.  Returns (L, dA, dB)
-    (dA, dB None without ``grads``)."""
+    out like A and B, by one call of ttm_inner_grad_ex.  ``env_stride``: 1
+    keeps every right environment, s >= 2 keeps every s-th and recomputes
+    the others one segment at a time, 0 picks s = ceil(sqrt(N)).  Returns
+    (L, dA, dB) (dA, dB None without ``grads``)."""
     import torch
     from ._abi import PRECISIONS
 
@@ -390,10 +392,10 @@ def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, st
     _same_device("B", B.data, A.data.device)
     L = lib()
     need = ctypes.c_size_t(0)
-    rc = L.ttm_inner_grad_query(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view),
-                                ctypes.byref(need))
+    rc = L.ttm_inner_grad_query_ex(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view),
+                                   int(env_stride), ctypes.byref(need))
     if rc != TTM_OK:
-        raise TTMError(rc, "ttm_inner_grad_query")
+        raise TTMError(rc, "ttm_inner_grad_query_ex")
     if workspace is None:
         dev = A.data.device
         workspace = _DEFAULT_WS.setdefault(str(dev), Workspace(dev))
@@ -403,12 +405,13 @@ def inner_grad(W, A, B, contract_precision="f64", grads=True, workspace=None, st
     dB = torch.empty_like(B.data) if grads else None
     value = ctypes.c_double(0.0)
     prec = PRECISIONS[contract_precision] if isinstance(contract_precision, str) else int(contract_precision)
-    rc = L.ttm_inner_grad(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view), prec,
-                          ctypes.byref(value), ctypes.c_void_p(dA.data_ptr() if grads else None),
-                          ctypes.c_void_p(dB.data_ptr() if grads else None), ctypes.c_void_p(wbuf.data_ptr()),
-                          ctypes.c_size_t(wbuf.numel()), _stream_handle(stream))
+    rc = L.ttm_inner_grad_ex(ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(B.view), prec,
+                             ctypes.byref(value), ctypes.c_void_p(dA.data_ptr() if grads else None),
+                             ctypes.c_void_p(dB.data_ptr() if grads else None), int(env_stride),
+                             ctypes.c_void_p(wbuf.data_ptr()), ctypes.c_size_t(wbuf.numel()),
+                             _stream_handle(stream))
     if rc != TTM_OK:
-        raise TTMError(rc, "ttm_inner_grad")
+        raise TTMError(rc, "ttm_inner_grad_ex")
     if not grads:
         return value.value, None, None
     return (value.value, PackedTT(dA, A.phys, A.bonds, A.offsets), PackedTT(dB, B.phys, B.bonds, B.offsets))
@@ -482,7 +485,9 @@ def _make_inner_loss_function():
         """loss = <W, TTM(A, B)> with W fixed.  Forward: the TTM product
         (ttm_multiply_ex), then <W, C> (ttm_inner_grad against the all-ones
         train).  Backward: dL/dC = the gradient of <W, C> with respect to C's
-        cores (ttm_inner_grad, environments recomputed from W and C), then
+        cores (ttm_inner_grad_ex, environments recomputed from W and C, with
+        checkpoints every ceil(sqrt(N)) sites and the others rebuilt one
+        segment at a time), then
         the reverse mode of the product (ttm_multiply_vjp), which recomputes
         the product with every step recorded and undoes the steps, truncated
         SVDs included.  Only the inputs and C are kept from the forward pass."""
@@ -497,7 +502,7 @@ def _make_inner_loss_function():
         @staticmethod
         def backward(ctx, g):
             A, B, W, C, chi_out, tol, prec, opts = ctx.trains
-            _, dC, _ = inner_grad(W, C, _ones_like_train(C))
+            _, dC, _ = inner_grad(W, C, _ones_like_train(C), env_stride=0)
             _, dA, dB, _ = multiply_vjp(A, B, chi_out, tol, dC, contract_precision=prec, **opts)
             return g * dA.data, g * dB.data, None, None, None, None, None, None, None
 

@@ -110,6 +110,12 @@ PROTOTYPES = {
     "ttm_inner_grad": (ctypes.c_int, [ctypes.POINTER(TtmTT)] * 3 + [ctypes.c_int32, F64P, ctypes.c_void_p,
                                                                     ctypes.c_void_p, ctypes.c_void_p,
                                                                     ctypes.c_size_t, ctypes.c_void_p]),
+    "ttm_inner_grad_query_ex": (ctypes.c_int, [ctypes.POINTER(TtmTT)] * 3 + [ctypes.c_int32,
+                                                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "ttm_inner_grad_ex": (ctypes.c_int, [ctypes.POINTER(TtmTT)] * 3 + [ctypes.c_int32, F64P, ctypes.c_void_p,
+                                                                       ctypes.c_void_p, ctypes.c_int32,
+                                                                       ctypes.c_void_p, ctypes.c_size_t,
+                                                                       ctypes.c_void_p]),
     "conventional_query": (ctypes.c_int, [ctypes.POINTER(TtmTT), ctypes.POINTER(TtmTT), ctypes.c_int32,
                                           ctypes.POINTER(TtmOptions), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_int64)]),

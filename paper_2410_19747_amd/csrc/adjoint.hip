@@ -47,7 +47,12 @@ int check_triple(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
 
 struct GradPlan {
   int n = 0;
-  std::vector<int64_t> env_off;  // right environment k at env_off[k] (doubles)
+  // Right environments.  stride 1: F_k at env_off[k] (doubles), all kept.
+  // stride s >= 2: the checkpoints F_k with (N - k) % s == 0 in slots
+  // (N - k) / s, every other F_k in slot nck + (c - k - 1) of the segment
+  // buffer, c the checkpoint above k; slots of env_max doubles.
+  int stride = 1, nck = 0;
+  std::vector<int64_t> env_off;
   int64_t env_total = 0, env_max = 0;
   int64_t x_max = 0;  // T1 (left sweep) / U1 (right sweep)
   int64_t y_max = 0;  // T2 / U2
@@ -57,10 +62,12 @@ struct GradPlan {
   bool fits = true;
 };
 
-GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
+GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int stride) {
   GradPlan p;
   const int n = W->n_sites;
   p.n = n;
+  if (stride == 0) stride = std::max(2, (int)std::ceil(std::sqrt((double)n)));
+  p.stride = std::max(1, std::min(stride, std::max(n, 1)));
   p.env_off.resize(n + 1);
   // GEMM extents are ints and every buffer holds at most 2^36 doubles (beyond
   // any device memory); each limit is checked before the products it bounds,
@@ -95,6 +102,10 @@ GradPlan make_grad_plan(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B) {
     }
   }
   p.part *= kSplitSlices;
+  if (p.stride > 1) {
+    p.nck = (n - 1) / p.stride + 1;  // F_N, F_{N-s}, ... down to F_1 or above
+    p.env_total = (int64_t)(p.nck + p.stride - 1) * r32(p.env_max);
+  }
   p.ws_doubles = (size_t)p.env_total + 2 * r32(p.env_max) + r32(p.x_max) + r32(p.y_max) + r32(p.v_max) +
                  r32(p.part) + 32;
   return p;
@@ -132,22 +143,23 @@ GemmArgs strided(int M, int N, int K, int batch, const double *Am, int64_t a_rs,
 
 }  // namespace
 
-int inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size_t *ws_bytes) {
+int inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int stride, size_t *ws_bytes) {
   const int e = check_triple(W, A, B);
   if (e) return e;
-  const GradPlan p = make_grad_plan(W, A, B);
+  if (stride < 0) return TTM_EINVAL;
+  const GradPlan p = make_grad_plan(W, A, B, stride);
   if (!p.fits) return TTM_EINVAL;
   if (ws_bytes) *ws_bytes = p.ws_doubles * sizeof(double);
   return TTM_OK;
 }
 
 int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, double *value, double *dA,
-               double *dB, void *ws, size_t ws_bytes, hipStream_t st) {
+               double *dB, int stride, void *ws, size_t ws_bytes, hipStream_t st) {
   int e = check_triple(W, A, B);
   if (e) return e;
-  if (!value) return TTM_EINVAL;
+  if (!value || stride < 0) return TTM_EINVAL;
   if (prec < TTM_PREC_F64 || prec > TTM_PREC_BF16X3) return TTM_EINVAL;
-  const GradPlan p = make_grad_plan(W, A, B);
+  const GradPlan p = make_grad_plan(W, A, B, stride);
   if (!p.fits) return TTM_EINVAL;
   if (!ws || ws_bytes < p.ws_doubles * sizeof(double)) return TTM_EWORKSPACE;
   const int gp = prec == TTM_PREC_F32 ? GEMM_F32 : prec == TTM_PREC_BF16 ? GEMM_BF16
@@ -174,30 +186,58 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
   };
   hipError_t h;
   // Right environments F_N .. F_1 (F_0 is not needed), only for gradients.
+  const int s = p.stride;
+  const int64_t slot = r32(p.env_max);
+  auto is_ck = [&](int k) { return (n - k) % s == 0; };
+  auto env_at = [&](int k) -> double * {
+    if (s == 1) return R + p.env_off[k];
+    if (is_ck(k)) return R + (int64_t)((n - k) / s) * slot;
+    const int c = n - ((n - k) / s) * s;  // the checkpoint above k
+    return R + (int64_t)(p.nck + (c - k - 1)) * slot;
+  };
+  // F_k from F_{k+1} (three products)
+  auto right_step = [&](int k) -> hipError_t {
+    const int d = W->phys[k], rw = W->bonds[k], rw2 = W->bonds[k + 1];
+    const int ra = A->bonds[k], ra2 = A->bonds[k + 1], rb = B->bonds[k], rb2 = B->bonds[k + 1];
+    const double *Rn = env_at(k + 1);
+    // U1[s][a'][w][b'] = sum_w' W[w,s,w'] F_{k+1}[w',a',b']  (rows w*d+s, columns a'*rb2+b')
+    GemmArgs g1 = strided(rw * d, ra2 * rb2, rw2, 1, core(W, k), rw2, 1, 0, Rn, (int64_t)ra2 * rb2, 1, 0, X, 0,
+                          d, rb2, (int64_t)ra2 * rw * rb2, rb2, (int64_t)rw * rb2, 1, gp);
+    // U2[w][a][s][b'] = sum_a' A[a,s,a'] U1[s][a'][w][b']  (batch s; rows a, columns w*rb2+b')
+    GemmArgs g2 = strided(ra, rw * rb2, ra2, d, core(A, k), (int64_t)d * ra2, 1, ra2, X, (int64_t)rw * rb2, 1,
+                          (int64_t)ra2 * rw * rb2, Y, rb2, 1, (int64_t)d * rb2, 0, rb2,
+                          (int64_t)ra * d * rb2, 1, gp);
+    // F_k[w][a][b] = sum_{s,b'} U2[w][a][s][b'] B[b,s,b']  (rows w*ra+a, K = s*rb2+b')
+    GemmArgs g3 = strided(rw * ra, rb, d * rb2, 1, Y, (int64_t)d * rb2, 1, 0, core(B, k), 1, (int64_t)d * rb2, 0,
+                          env_at(k), 0, 1, rb, 0, 1, 1, 0, gp);
+    hipError_t h1;
+    if ((h1 = gemm(g1)) != hipSuccess || (h1 = gemm(g2)) != hipSuccess) return h1;
+    return gemm(g3);
+  };
+  // With checkpoints the sweep leaves the lowest segment (F_1 upwards) in the
+  // segment buffer; the left sweep recomputes each higher segment from its
+  // checkpoint when it reaches it (same products on the same inputs, so the
+  // same values).
+  int seg_loaded = -1;  // checkpoint above the segment the buffer holds
   if (grads) {
-    if ((h = launch_fill(R + p.env_off[n], 1.0, 1, st)) != hipSuccess) return fail(h);
-    for (int k = n - 1; k >= 1; --k) {
-      const int d = W->phys[k], rw = W->bonds[k], rw2 = W->bonds[k + 1];
-      const int ra = A->bonds[k], ra2 = A->bonds[k + 1], rb = B->bonds[k], rb2 = B->bonds[k + 1];
-      const double *Rn = R + p.env_off[k + 1];
-      // U1[s][a'][w][b'] = sum_w' W[w,s,w'] F_{k+1}[w',a',b']  (rows w*d+s, columns a'*rb2+b')
-      GemmArgs g1 = strided(rw * d, ra2 * rb2, rw2, 1, core(W, k), rw2, 1, 0, Rn, (int64_t)ra2 * rb2, 1, 0, X, 0,
-                            d, rb2, (int64_t)ra2 * rw * rb2, rb2, (int64_t)rw * rb2, 1, gp);
-      // U2[w][a][s][b'] = sum_a' A[a,s,a'] U1[s][a'][w][b']  (batch s; rows a, columns w*rb2+b')
-      GemmArgs g2 = strided(ra, rw * rb2, ra2, d, core(A, k), (int64_t)d * ra2, 1, ra2, X, (int64_t)rw * rb2, 1,
-                            (int64_t)ra2 * rw * rb2, Y, rb2, 1, (int64_t)d * rb2, 0, rb2,
-                            (int64_t)ra * d * rb2, 1, gp);
-      // F_k[w][a][b] = sum_{s,b'} U2[w][a][s][b'] B[b,s,b']  (rows w*ra+a, K = s*rb2+b')
-      GemmArgs g3 = strided(rw * ra, rb, d * rb2, 1, Y, (int64_t)d * rb2, 1, 0, core(B, k), 1, (int64_t)d * rb2, 0,
-                            R + p.env_off[k], 0, 1, rb, 0, 1, 1, 0, gp);
-      if ((h = gemm(g1)) != hipSuccess || (h = gemm(g2)) != hipSuccess ||
-          (h = gemm(g3)) != hipSuccess)
-        return fail(h);
-    }
+    if ((h = launch_fill(env_at(n), 1.0, 1, st)) != hipSuccess) return fail(h);
+    for (int k = n - 1; k >= 1; --k)
+      if ((h = right_step(k)) != hipSuccess) return fail(h);
+    if (s > 1 && n > 1 && !is_ck(1)) seg_loaded = n - ((n - 1) / s) * s;
   }
   // Left sweep: E_0 = 1; at each site the gradients, then E_{k+1}.
   if ((h = launch_fill(Lc, 1.0, 1, st)) != hipSuccess) return fail(h);
   for (int k = 0; k < n; ++k) {
+    // F_{k+1} in a segment the buffer does not hold: F_{c-1} .. F_{k+1} from
+    // the checkpoint F_c above (before T1 and T2, whose buffers it uses)
+    if (grads && s > 1 && !is_ck(k + 1)) {
+      const int c = n - ((n - k - 1) / s) * s;
+      if (c != seg_loaded) {
+        for (int j = c - 1; j >= k + 1; --j)
+          if ((h = right_step(j)) != hipSuccess) return fail(h);
+        seg_loaded = c;
+      }
+    }
     const int d = W->phys[k], rw = W->bonds[k], rw2 = W->bonds[k + 1];
     const int ra = A->bonds[k], ra2 = A->bonds[k + 1], rb = B->bonds[k], rb2 = B->bonds[k + 1];
     // T1[s][a][b][w'] = sum_w E_k[w,a,b] W[w,s,w']  (rows a*rb+b, columns s*rw2+w')
@@ -209,7 +249,7 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
                           0, gp);
     if ((h = gemm(t1)) != hipSuccess || (h = gemm(t2)) != hipSuccess) return fail(h);
     if (grads) {
-      const double *Rn = R + p.env_off[k + 1];
+      const double *Rn = env_at(k + 1);
       if (dB) {
         // dB_k[b,s,b'] = sum_{w',a'} T2[b][s][w'][a'] F_{k+1}[w'][a'][b']  (rows b*d+s)
         GemmArgs gb = strided(rb * d, rb2, rw2 * ra2, 1, Y, (int64_t)rw2 * ra2, 1, 0, Rn, rb2, 1, 0,
@@ -248,12 +288,25 @@ int inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int prec, doub
 }  // namespace ttm
 
 extern "C" int ttm_inner_grad_query(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, size_t *ws_bytes) {
-  return ttm::inner_grad_query(W, A, B, ws_bytes);
+  return ttm::inner_grad_query(W, A, B, 1, ws_bytes);
 }
 
 extern "C" int ttm_inner_grad(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
                               double *value, double *dA, double *dB, void *ws, size_t ws_bytes, void *stream) {
   ttm::clear_last_error();
-  return ttm::inner_grad(W, A, B, contract_precision, value, dA, dB, ws, ws_bytes,
+  return ttm::inner_grad(W, A, B, contract_precision, value, dA, dB, 1, ws, ws_bytes,
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" int ttm_inner_grad_query_ex(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t env_stride,
+                                       size_t *ws_bytes) {
+  return ttm::inner_grad_query(W, A, B, env_stride, ws_bytes);
+}
+
+extern "C" int ttm_inner_grad_ex(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t contract_precision,
+                                 double *value, double *dA, double *dB, int32_t env_stride, void *ws,
+                                 size_t ws_bytes, void *stream) {
+  ttm::clear_last_error();
+  return ttm::inner_grad(W, A, B, contract_precision, value, dA, dB, env_stride, ws, ws_bytes,
                          static_cast<hipStream_t>(stream));
 }

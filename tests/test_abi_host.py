@@ -408,3 +408,26 @@ def test_vjp_rejects_before_gpu_work(L):
     assert call(da=None) == _abi.TTM_EINVAL
     three = _TT([2] * 3, [1, 2, 2, 1])
     assert call(cbar=three) == _abi.TTM_ESHAPE
+
+
+def test_inner_grad_checkpoint_sizes(L):
+    """ttm_inner_grad_query_ex: stride 1 is the plain query; checkpoints need
+    less workspace as N grows; a negative stride is rejected."""
+    n = 16
+    W = _TT([2] * n, [1] + [4] * (n - 1) + [1])
+    A = _TT([2] * n, [1] + [8] * (n - 1) + [1])
+    plain, s1, s0, s4 = (ctypes.c_size_t(0) for _ in range(4))
+    args = (ctypes.byref(W.view), ctypes.byref(A.view), ctypes.byref(A.view))
+    assert L.ttm_inner_grad_query(*args, ctypes.byref(plain)) == 0
+    assert L.ttm_inner_grad_query_ex(*args, 1, ctypes.byref(s1)) == 0
+    assert L.ttm_inner_grad_query_ex(*args, 0, ctypes.byref(s0)) == 0
+    assert L.ttm_inner_grad_query_ex(*args, 4, ctypes.byref(s4)) == 0
+    assert s1.value == plain.value
+    env = 4 * 8 * 8 * 8  # one environment slot, in bytes
+    # 17 environments stored against 4 checkpoints + 3 segment buffers (stride 4 = ceil(sqrt(16)))
+    assert plain.value - s0.value >= (17 - 7) * env - 64 * 8 * 17
+    assert s4.value == s0.value
+    assert L.ttm_inner_grad_query_ex(*args, -1, ctypes.byref(s0)) == _abi.TTM_EINVAL
+    v = ctypes.c_double(0.0)
+    assert L.ttm_inner_grad_ex(*args, 0, ctypes.byref(v), None, None, -2, ctypes.c_void_p(0x1000), 1 << 20,
+                               None) == _abi.TTM_EINVAL

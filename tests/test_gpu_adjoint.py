@@ -198,3 +198,26 @@ def test_gpu_inner_grad_wide_w_and_fp32():
     assert _rel(_host(dA), dAo) <= TOL and _rel(_host(dB), dBo) <= TOL
     v32, dA32, dB32 = T.inner_grad(W, A, B, contract_precision="f32")
     assert _rel(_host(dA32), dAo) <= 1e-6 and _rel(_host(dB32), dBo) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 10])
+def test_gpu_inner_grad_checkpointed_environments_bitwise(n):
+    """Right environments kept only at checkpoints and recomputed segment by
+    segment give bitwise the value and gradients of the stored form, for
+    every stride (including strides that do not divide N)."""
+    import paper_2410_19747_amd as T
+    torch = _torch()
+    _say("case: checkpointed environments, N=%d" % n)
+    d = [2, 3, 2, 4, 2, 3, 2, 2, 3, 2][:n]
+
+    def train(chi, seed):
+        r = np.random.default_rng(seed)
+        b = [1] + [int(min(chi, x)) for x in r.integers(2, chi + 1, n - 1)] + [1]
+        return [r.standard_normal((b[i], d[i], b[i + 1])) for i in range(n)]
+
+    W, A, B = train(4, 1 + n), train(7, 2 + n), train(6, 3 + n)
+    v1, a1, b1 = T.inner_grad(W, A, B, env_stride=1)
+    for stride in (0, 2, 3, 4, n + 5):
+        v, a, b = T.inner_grad(W, A, B, env_stride=stride)
+        assert v == v1, stride
+        assert torch.equal(a.data, a1.data) and torch.equal(b.data, b1.data), stride
