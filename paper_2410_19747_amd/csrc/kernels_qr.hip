@@ -16,6 +16,8 @@
 // reaches every lane at its own rows by a DPP row broadcast (the 16 lanes
 // of a row group hold the 16 columns at the same rows); T is assembled
 // after the last column.
+#include <hip/hip_cooperative_groups.h>
+
 #include "ttm_internal.h"
 
 namespace ttm {
@@ -490,6 +492,115 @@ __global__ __launch_bounds__(PNT) void qr_panel_ext_kernel(double *__restrict__ 
   store_rows(0);
 }
 
+// Panels taller than 2048 rows on G = ceil(mv / 1024) workgroups launched
+// together (cooperative launch: all resident at once), each holding 1024
+// rows in registers as qr_panel_reg_kernel<16> does.  Per column every
+// workgroup reduces d_c over its rows, publishes its 16 sums (and workgroup
+// 0 row CC) in gbuf, and after a grid-wide barrier every workgroup adds the
+// G sums in the same order, so all of them take bitwise the same reflector
+// and update their own rows.  One grid barrier per column; workgroup 0
+// writes T.  gbuf: coop_panel_doubles(m) doubles.
+constexpr int COOP_ROWS = 64 * MAX_REG_SLOTS;
+__host__ __device__ constexpr int coop_groups(int mv) { return (mv + COOP_ROWS - 1) / COOP_ROWS; }
+
+template <int CC>
+__device__ __forceinline__ void coop_column(double (&x)[MAX_REG_SLOTS], PanelSmem &sm, double *__restrict__ gbuf,
+                                            int G, int wg, int w, int g, int c, int ig0, double &myscale,
+                                            double &mybeta) {
+  constexpr int SL = MAX_REG_SLOTS, B = CC & 1;
+  double *xr = gbuf + (int64_t)QB * QB * G;  // row CC of every column, per column CC
+  double b[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) b[s] = row_bcast<CC>(x[s]);
+  double dp[4] = {(ig0 > CC) ? b[0] * x[0] : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 1; s < SL; ++s) dp[s & 3] = fma(b[s], x[s], dp[s & 3]);
+  if (CC >= 2 && w == 0 && g == 0) t_column(sm, CC - 2, c);
+  double d = rowgroup_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
+  if (g == 0) sm.red[B][w][c] = d;
+  __syncthreads();
+  const double dloc = rowgroup_sum((sm.red[B][g][c] + sm.red[B][4 + g][c]) + (sm.red[B][8 + g][c] + sm.red[B][12 + g][c]));
+  if (w == 0 && g == 0) gbuf[((int64_t)CC * G + wg) * QB + c] = dloc;
+  if (ig0 == CC) xr[CC * QB + c] = x[0];  // only in workgroup 0
+  cooperative_groups::this_grid().sync();
+  double dc = 0.0;
+  for (int q = 0; q < G; ++q) dc += gbuf[((int64_t)CC * G + q) * QB + c];
+  const double xnorm2 = row_bcast<CC>(dc);
+  const double alpha = xr[CC * QB + CC], xc = xr[CC * QB + c];
+  double tau = 0.0, scale = 0.0, beta = alpha;
+  if (xnorm2 > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+    tau = (beta - alpha) * recip(beta);
+    scale = recip(alpha - beta);
+  }
+  const double tot = fma(scale, dc, xc);
+  const double f = (c > CC) ? tau * tot : 0.0, fs = f * scale;
+  x[0] = (ig0 > CC) ? fma(-fs, b[0], x[0]) : (ig0 == CC ? x[0] - f : x[0]);
+#pragma unroll
+  for (int s = 1; s < SL; ++s) x[s] = fma(-fs, b[s], x[s]);
+  if (c == CC) {
+    myscale = scale;
+    mybeta = beta;
+  }
+  if (w == 0 && g == 0) {
+    if (c < CC) sm.zs[CC][c] = myscale * tot;
+    if (c == CC) sm.taus[CC] = tau;
+  }
+}
+
+template <int CC = 0>
+__device__ __forceinline__ void coop_columns(double (&x)[MAX_REG_SLOTS], PanelSmem &sm, double *gbuf, int G,
+                                             int wg, int jb, int w, int g, int c, int ig0, double &myscale,
+                                             double &mybeta) {
+  if constexpr (CC < QB) {
+    if (CC < jb) {  // uniform over the grid
+      coop_column<CC>(x, sm, gbuf, G, wg, w, g, c, ig0, myscale, mybeta);
+      coop_columns<CC + 1>(x, sm, gbuf, G, wg, jb, w, g, c, ig0, myscale, mybeta);
+    }
+  }
+}
+
+__global__ __launch_bounds__(PNT) void qr_panel_coop_kernel(double *__restrict__ S, int m, int j0, int jb,
+                                                            double *__restrict__ T, double *__restrict__ gbuf) {
+  __shared__ PanelSmem sm;
+  __shared__ double tile[QB][COOP_ROWS + 1];
+  constexpr int SL = MAX_REG_SLOTS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int wg = blockIdx.x, G = gridDim.x;
+  const int mv = m - j0, r0 = wg * COOP_ROWS;  // this workgroup's first panel row
+  const int i0 = 4 * w + g, ig0 = r0 + i0;
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    const int e = tid + PNT * q, cc = e / COOP_ROWS, i = e % COOP_ROWS;
+    tile[cc][i] = (r0 + i < mv && cc < jb) ? S[(int64_t)(j0 + cc) * m + j0 + r0 + i] : 0.0;
+  }
+  if (w == 0 && g == 0)
+    for (int b = 0; b < QB; ++b) sm.Tl[c][b] = 0.0;
+  __syncthreads();
+  double x[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) x[s] = tile[c][i0 + 64 * s];
+  double myscale = 0.0, mybeta = 0.0;
+  coop_columns(x, sm, gbuf, G, wg, jb, w, g, c, ig0, myscale, mybeta);
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int i = i0 + 64 * s, ig = r0 + i;
+    tile[c][i] = (ig > c) ? x[s] * myscale : (ig == c ? mybeta : x[s]);
+  }
+  __syncthreads();
+  if (wg == 0 && w == 0 && g == 0) {
+    if (jb >= 2) t_column(sm, jb - 2, c);
+    t_column(sm, jb - 1, c);
+    for (int b = 0; b < QB; ++b) T[c * QB + b] = (c < jb && b < jb) ? sm.Tl[c][b] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < SL; ++q) {
+    const int e = tid + PNT * q, cc = e / COOP_ROWS, i = e % COOP_ROWS;
+    if (r0 + i < mv && cc < jb) S[(int64_t)(j0 + cc) * m + j0 + r0 + i] = tile[cc][i];
+  }
+}
+
 // Sum over the 64 lanes of a wave of each of 16 values: after the call lane
 // l holds (bitwise the same in the four lanes of its quad) the wave total of
 // value col(l) = 8 [l & 32] + 4 [l & 16] + 2 [l & 8] + [l & 4]: at each
@@ -862,7 +973,7 @@ struct Pivot {
   double *scratch = nullptr;
 };
 
-hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *T, const Pivot &pv,
+hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *T, const Pivot &pv, double *coop,
                         hipStream_t s) {
   const int sl = (m - j0 + 63) / 64;
   const dim3 g(1), b(PNT);
@@ -873,7 +984,16 @@ hipError_t launch_panel(double *S, int m, int n, int j0, int jb, double *T, cons
   else if (sl <= 8) hipLaunchKernelGGL(qr_panel_reg_kernel<8>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_reg_kernel<16>, g, b, 0, s, TTM_PANEL_ARGS);
   else if (sl <= 2 * MAX_REG_SLOTS) hipLaunchKernelGGL(qr_panel_ext_kernel, g, b, 0, s, TTM_PANEL_ARGS);
-  else hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, TTM_PANEL_ARGS);
+  else {
+    if (coop && !pv.cnorm) {
+      void *args[] = {&S, &m, &j0, &jb, &T, &coop};
+      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(qr_panel_coop_kernel),
+                                                      dim3(coop_groups(m - j0)), b, args, 0, s);
+      if (e == hipSuccess) return hipSuccess;
+      (void)hipGetLastError();  // not launched: the one-workgroup panel below
+    }
+    hipLaunchKernelGGL(qr_panel_mem_kernel, g, b, 0, s, TTM_PANEL_ARGS);
+  }
 #undef TTM_PANEL_ARGS
   return hipGetLastError();
 }
@@ -902,8 +1022,12 @@ static size_t update_part_doubles(int m, int nc) {
   return (size_t)((nc + QB - 1) / QB) * update_chunks(m) * QB * QB;
 }
 
+// Exchange buffer of the cooperative panel: per column the G workgroup sums
+// of 16 columns, and row CC.
+static size_t coop_panel_doubles(int m) { return (size_t)QB * QB * (coop_groups(m) + 1); }
+
 size_t qr_inplace_scratch_doubles(int m, int n) {
-  return QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + 4 * 32;
+  return QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + coop_panel_doubles(m) + 5 * 32;
 }
 
 hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s) {
@@ -914,6 +1038,7 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   auto adv = [&](size_t nd) { double *x = p; p += (nd + 31) & ~(size_t)31; return x; };
   double *T1 = adv(QB * QB);
   double *part = adv(update_part_doubles(m, n));
+  double *coop = adv(coop_panel_doubles(m));
   Pivot pv;
   if (perm) {
     double *cnorm = adv((size_t)n);
@@ -926,7 +1051,7 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   for (int j0 = 0; j0 < k; j0 += QB) {
     const int jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall ? Tall + (size_t)(j0 / QB) * QB * QB : T1;
-    hipError_t e = launch_panel(S, m, n, j0, jb, T, pv, s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, T, pv, coop, s);
     if (e != hipSuccess) return e;
     e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), S, jb, T, 1, const_cast<double *>(pv.cnorm), jb, part, s);
     if (e != hipSuccess) return e;
@@ -957,7 +1082,8 @@ size_t qr_scratch_doubles(int m, int n) {
   t += (size_t)np * QB * QB;   // T per panel
   t += (size_t)m * k;          // Qs
   t += update_part_doubles(m, n);  // split-update partials
-  return t + 4 * 32;
+  t += coop_panel_doubles(m);      // cooperative panel exchange
+  return t + 5 * 32;
 }
 
 hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, double *q, double *r,
@@ -971,12 +1097,13 @@ hipError_t launch_qr(const double *M, int m, int n, int64_t rs, int64_t cs, doub
   double *Tall = adv((size_t)np * QB * QB);
   double *Qs = adv((size_t)m * k);
   double *part = adv(update_part_doubles(m, n));
+  double *coop = adv(coop_panel_doubles(m));
   const int64_t tot = (int64_t)m * n;
   hipLaunchKernelGGL(strided_to_colmajor_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, S, M, m, n, rs, cs);
   for (int pi = 0; pi < np; ++pi) {
     const int j0 = pi * QB, jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall + (size_t)pi * QB * QB;
-    hipError_t e = launch_panel(S, m, n, j0, jb, T, Pivot(), s);
+    hipError_t e = launch_panel(S, m, n, j0, jb, T, Pivot(), coop, s);
     if (e != hipSuccess) return e;
     e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), S, jb, T, 1, nullptr, 0, part, s);
     if (e != hipSuccess) return e;

@@ -85,6 +85,13 @@ int main() {
     if (rc == TTM_OK) EXPECT(ws > 0 && cap >= n);
     EXPECT(conventional_query(&A.view, &B.view, chi, &o, &ws, &cap) == TTM_OK);
     EXPECT(ttm_inner_grad_query(&A.view, &A.view, &B.view, &ws) == TTM_OK);
+    {
+      size_t plain = 0, ck = 0;
+      EXPECT(ttm_inner_grad_query(&A.view, &A.view, &B.view, &plain) == TTM_OK);
+      EXPECT(ttm_inner_grad_query_ex(&A.view, &A.view, &B.view, uniform(seed, 0, 12), &ck) == TTM_OK);
+      EXPECT(ck > 0 && plain > 0);
+      EXPECT(ttm_inner_grad_query_ex(&A.view, &A.view, &B.view, -3, &ck) == TTM_EINVAL);
+    }
     // argument checks of the compute calls: all fail before any HIP call
     std::vector<int32_t> cb(n + 1);
     std::vector<int64_t> co(n);
