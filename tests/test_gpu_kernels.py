@@ -111,8 +111,12 @@ def test_gemm_strided_operands_and_split_output():
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (3, 3), (37, 11), (11, 37), (300, 64), (1024, 128), (1100, 100),
-                                 (1500, 40), (2048, 48), (2500, 40)])
+                                 (1500, 40), (2048, 48), (2500, 40), (5000, 33), (8192, 40)])
 def test_qr(m, n):
+    """Householder QR with explicit Q.  Panels of more than 2048 rows run on
+    ceil(rows / 1024) workgroups with a grid barrier per column (2500: three,
+    the last one partly filled; 5000: five, with a one-column last panel;
+    8192: eight)."""
     torch, L = _env()
     _say("qr %d %d" % (m, n))
     rng = np.random.default_rng(m * 7 + n)
