@@ -113,13 +113,17 @@ JacobiPlan jacobi_plan(int L, int nc, int force_bw) {
   p.sw = (L + p.rows_per_wg - 1) / p.rows_per_wg;
   p.rounds = nblk - 1;
   p.pairs = nblk / 2;
-  // With circle pairing a Gram workgroup sums gsub consecutive row chunks
+  // A Gram workgroup sums gsub consecutive row chunks
   // in its matrix-core accumulators, so that the solve reduces gsw partials
   // instead of sw: each partial is a full 2bw x 2bw Gram, and at 8192 rows
   // the partials of one round would otherwise be 268 MB written and read
-  // back.  gsub is chosen to keep about 1024 Gram workgroups.  (The XOR
-  // kernel forms its Grams per chunk in the rotation pass: gsub = 1.)
-  p.gsub = p.xs ? 1 : std::max(1, std::min(p.sw, p.pairs * p.sw / 1024));
+  // back.  gsub is chosen to keep about 1024 Gram workgroups.  The XOR
+  // rotate-and-Gram pass groups its row chunks the same way (one rotation
+  // load and one partial per gsub chunks) for about 512 workgroups, and the
+  // first round's Gram matches it (measured per product: 2458 -> 2268 ms at
+  // chi = 256, 9994 -> 8599 ms at chi = 512; 1024 or 256 workgroups were
+  // slower).
+  p.gsub = std::max(1, std::min(p.sw, p.xs ? (p.nblk / 4) * p.sw / 512 : p.pairs * p.sw / 1024));
   p.gsw = (p.sw + p.gsub - 1) / p.gsub;
   return p;
 }
@@ -564,23 +568,27 @@ __global__ __launch_bounds__(JNT) void jacobi_apply_kernel(double *__restrict__ 
 // register t: row 4 t + l / 16, column l % 16) is the operand layout of the
 // Gram product over those rows.  A pair that did not rotate goes through
 // the identity (exact in FP64).
+template <bool MULTI>
 __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restrict__ W, int L, int round,
                                                                const double *__restrict__ qbuf,
                                                                const int *__restrict__ flag,
-                                                               double *__restrict__ part, int sw) {
+                                                               double *__restrict__ part, int gsw, int xsub) {
   constexpr int BW = 16, B2 = 32, KS = B2 / 4;
-  // One LDS region for three phases (52 KB, so that three workgroups fit
-  // on a CU): the round's two rotations; then each wave's 16 rows of the
-  // four new blocks, transposed for the stores; then each wave's Gram tiles.
+  // LDS: the round's two rotations; one region for the two later phases:
+  // each wave's 16 rows of the four new blocks, transposed for the stores,
+  // then each wave's Gram tiles.  With one row chunk per workgroup (!MULTI)
+  // the rotations are dead before the first store and share that region
+  // (52 KB, three workgroups per CU); with several (MULTI) they are kept.
   typedef double QsT[2][B2][B2 + 1];
   typedef double TwT[JNT / 64][4 * 16][17];
   typedef double RedT[JNT / 64][2][3][16][17];
+  __shared__ double qlds[MULTI ? sizeof(QsT) / sizeof(double) : 1];
   __shared__ double lds[sizeof(RedT) / sizeof(double)];
   static_assert(sizeof(RedT) >= sizeof(TwT) && sizeof(RedT) >= sizeof(QsT), "LDS phases");
-  QsT &qs = *reinterpret_cast<QsT *>(lds);
+  QsT &qs = *reinterpret_cast<QsT *>(MULTI ? qlds : lds);
   TwT &tw = *reinterpret_cast<TwT *>(lds);
   RedT &red = *reinterpret_cast<RedT *>(lds);
-  const int chunk = blockIdx.y;
+  const int s = blockIdx.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, q4 = lane >> 4;
   const int m = round + 1, mn = round + 2;
   // Group representative: zero bits at two positions that the span of m and
@@ -589,15 +597,13 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
   const int blo = min(h1, h2), bhi = max(h1, h2);
   const int i0 = insert_zero_bit(insert_zero_bit(blockIdx.x, blo), bhi);
   const int blk[4] = {i0, i0 ^ m, i0 ^ mn, i0 ^ m ^ mn};
-  const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
   // The round's two rotations into LDS once (identity for a pair that did
-  // not rotate), loaded with the columns.
-  double wv[2][KS];
+  // not rotate).
   {
     double qg[2][B2 * B2 / JNT];
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
-      const int lo = min(blk[2 * pp], blk[2 * pp + 1]), hi = max(blk[2 * pp], blk[2 * pp + 1]);
+      const int lo = min(blk[2 * pp], blk[2 * pp + 1]);
       const int pr = remove_bit(lo, h1);
       const int rot = flag[pr];
       const double *Q = qbuf + (int64_t)pr * B2 * B2;
@@ -605,12 +611,6 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
       for (int e = 0; e < B2 * B2 / JNT; ++e) {
         const int idx = threadIdx.x + JNT * e;
         qg[pp][e] = rot ? Q[idx] : ((idx / B2 == idx % B2) ? 1.0 : 0.0);
-      }
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + q4;
-        const int col = (k < BW) ? lo * BW + k : hi * BW + (k - BW);
-        wv[pp][ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
       }
     }
 #pragma unroll
@@ -622,57 +622,77 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
       }
   }
   __syncthreads();
-  // The round's two pairs: (blk[0], blk[1]) and (blk[2], blk[3]), each as
-  // (lower block, higher block) = columns 0..15, 16..31 of its rotation.
-  dbl4 nb[4];
-#pragma unroll
-  for (int pp = 0; pp < 2; ++pp) {
-    const int x = blk[2 * pp], y = blk[2 * pp + 1];
-    const int lo = min(x, y);
-    double qv[2][KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) qv[ct][ks] = qs[pp][4 * ks + q4][ct * BW + r16];
-    dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[0][ks], d0, 0, 0, 0);
-      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[1][ks], d1, 0, 0, 0);
-    }
-    // d0 is block lo, d1 block hi
-    nb[2 * pp] = (x == lo) ? d0 : d1;
-    nb[2 * pp + 1] = (x == lo) ? d1 : d0;
-  }
-  // The next round's pairs: (blk[0], blk[2]) and (blk[1], blk[3]).
+  // Row chunks s*xsub .. s*xsub + n - 1 of ROWS_XOR rows; the next round's
+  // Gram tiles accumulate over all of them in the matrix-core registers.
+  const int c0 = s * xsub, n = MULTI ? min(xsub, (L + ROWS_XOR - 1) / ROWS_XOR - c0) : 1;
   dbl4 gt[2][3];
 #pragma unroll
-  for (int pp = 0; pp < 2; ++pp) {
-    const int xa = blk[pp], xb = blk[pp + 2];
-    const dbl4 A = (xa < xb) ? nb[pp] : nb[pp + 2], B = (xa < xb) ? nb[pp + 2] : nb[pp];
-    dbl4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = {0.0, 0.0, 0.0, 0.0}, g11 = {0.0, 0.0, 0.0, 0.0};
+  for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], A[t], g00, 0, 0, 0);
-      g01 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], g01, 0, 0, 0);
-      g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(B[t], B[t], g11, 0, 0, 0);
+    for (int tl = 0; tl < 3; ++tl) gt[pp][tl] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  for (int sub = 0; sub < n; ++sub) {
+    const int chunk = c0 + sub;
+    const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
+    double wv[2][KS];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      const int lo = min(blk[2 * pp], blk[2 * pp + 1]), hi = max(blk[2 * pp], blk[2 * pp + 1]);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + q4;
+        const int col = (k < BW) ? lo * BW + k : hi * BW + (k - BW);
+        wv[pp][ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
+      }
     }
-    gt[pp][0] = g00;
-    gt[pp][1] = g01;
-    gt[pp][2] = g11;
-  }
-  // New columns back in place through LDS, so that a store covers 16
-  // consecutive rows of a column (rows beyond L were zero, not stored).
-  __syncthreads();  // every wave is done with the rotations in LDS
+    // The round's two pairs: (blk[0], blk[1]) and (blk[2], blk[3]), each as
+    // (lower block, higher block) = columns 0..15, 16..31 of its rotation.
+    dbl4 nb[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+    for (int pp = 0; pp < 2; ++pp) {
+      const int x = blk[2 * pp], y = blk[2 * pp + 1];
+      const int lo = min(x, y);
+      double qv[2][KS];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) tw[w][b * BW + r16][4 * t + q4] = nb[b][t];
-  __syncthreads();
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int c = 4 * e + q4, r = chunk * ROWS_XOR + 16 * w + r16;  // column c of the four blocks
-    if (r < L) W[(int64_t)(blk[c >> 4] * BW + (c & 15)) * L + r] = tw[w][c][r16];
+        for (int ct = 0; ct < 2; ++ct) qv[ct][ks] = qs[pp][4 * ks + q4][ct * BW + r16];
+      dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[0][ks], d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[pp][ks], qv[1][ks], d1, 0, 0, 0);
+      }
+      // d0 is block lo, d1 block hi
+      nb[2 * pp] = (x == lo) ? d0 : d1;
+      nb[2 * pp + 1] = (x == lo) ? d1 : d0;
+    }
+    // The next round's pairs: (blk[0], blk[2]) and (blk[1], blk[3]).
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      const int xa = blk[pp], xb = blk[pp + 2];
+      const dbl4 A = (xa < xb) ? nb[pp] : nb[pp + 2], B = (xa < xb) ? nb[pp + 2] : nb[pp];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        gt[pp][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], A[t], gt[pp][0], 0, 0, 0);
+        gt[pp][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], gt[pp][1], 0, 0, 0);
+        gt[pp][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(B[t], B[t], gt[pp][2], 0, 0, 0);
+      }
+    }
+    // New columns back in place through LDS, so that a store covers 16
+    // consecutive rows of a column (rows beyond L were zero, not stored).
+    // Before the first store every wave must be done with the rotations
+    // when they share the region; later, with the previous chunk's rows.
+    if (sub > 0 || !MULTI) __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) tw[w][b * BW + r16][4 * t + q4] = nb[b][t];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int c = 4 * e + q4;  // column c of the four blocks
+      if (row < L) W[(int64_t)(blk[c >> 4] * BW + (c & 15)) * L + row] = tw[w][c][r16];
+    }
   }
   __syncthreads();  // the transposed rows have been read out
 #pragma unroll
@@ -688,7 +708,7 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int lo = min(blk[pp], blk[pp + 2]);
-    double *out = part + ((int64_t)remove_bit(lo, h1n) * sw + chunk) * B2 * B2;
+    double *out = part + ((int64_t)remove_bit(lo, h1n) * gsw + s) * B2 * B2;
     double v[3];
 #pragma unroll
     for (int tl = 0; tl < 3; ++tl)
@@ -752,8 +772,12 @@ void launch_round(const JacobiPlan &p, const JacobiBufs &b, int round, double to
   } else {
     // this round's rotations and the next round's Grams in one pass
     Timed tm(timer, KC_JAC_APPLY, s);
-    hipLaunchKernelGGL(jacobi_xor_round_kernel, dim3(p.nblk / 4, p.sw), dim3(JNT), 0, s, b.W, p.L, round, b.qbuf,
-                       b.flag, b.part, p.sw);
+    if (p.gsub > 1)
+      hipLaunchKernelGGL(jacobi_xor_round_kernel<true>, dim3(p.nblk / 4, p.gsw), dim3(JNT), 0, s, b.W, p.L, round,
+                         b.qbuf, b.flag, b.part, p.gsw, p.gsub);
+    else
+      hipLaunchKernelGGL(jacobi_xor_round_kernel<false>, dim3(p.nblk / 4, p.gsw), dim3(JNT), 0, s, b.W, p.L,
+                         round, b.qbuf, b.flag, b.part, p.gsw, 1);
   }
 }
 }  // namespace
