@@ -949,6 +949,198 @@ __global__ __launch_bounds__(UNT) void qr_update_apply_kernel(double *S, int m, 
   }
 }
 
+// For tall trailing updates (many row chunks) the chunk partials are summed
+// once per column block instead of once per (column block, chunk):
+//   qr_update_reduce_kernel<K>: grid (column blocks); W1 = sum over chunks of
+//     part[cb][ch] (K x 16, fixed order), W2 = op(T) W1 -> w2[cb];
+//   qr_update_apply_w2_kernel<K>: grid (column blocks, chunks); A_ch -= V_ch W2.
+// K = 16 (one panel, op(T) = T^T when trans) or AGG (aggregated panels, T^T).
+constexpr int UPD_REDUCE_MIN_CHUNKS = 17;
+
+template <int K>
+__global__ __launch_bounds__(UNT) void qr_update_reduce_kernel(const double *__restrict__ part, int nch,
+                                                               const double *__restrict__ T, int trans,
+                                                               double *__restrict__ w2) {
+  __shared__ double W1[K][QB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < K * QB; e += UNT) {
+    const double *pp = part + (int64_t)blockIdx.x * nch * K * QB + e;
+    double sum = 0.0;
+    for (int c = 0; c < nch; ++c) sum += pp[(int64_t)c * K * QB];
+    W1[e / QB][e % QB] = sum;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * QB; e += UNT) {
+    const int i = e / QB, j = e % QB;
+    double t2 = 0.0;
+    if (trans)
+      for (int b = 0; b <= i; ++b) t2 = fma(T[b * K + i], W1[b][j], t2);  // T upper triangular
+    else
+      for (int b = i; b < K; ++b) t2 = fma(T[i * K + b], W1[b][j], t2);
+    w2[(int64_t)blockIdx.x * K * QB + e] = t2;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(UNT) void qr_update_apply_w2_kernel(double *S, int m, int j0, int c0, int nc,
+                                                                 const double *Vs, int nbw,
+                                                                 const double *__restrict__ w2) {
+  __shared__ double W2[K][QB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mv = m - j0;
+  const int cb = c0 + QB * blockIdx.x, ch = blockIdx.y;
+  const int ncol = min(QB, c0 + nc - cb);
+  double *A = S + (int64_t)cb * m + j0;
+  for (int e = tid; e < K * QB; e += UNT) W2[e / QB][e % QB] = w2[(int64_t)blockIdx.x * K * QB + e];
+  __syncthreads();
+  // two 16-row tiles per wave: A^T -= W2^T V^T on the matrix cores
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = ch * URC + 16 * w + 64 * h + r16;
+    const bool ok = r < mv;
+    dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < K / 4; ++u) {
+      const int col = 4 * u + q4;
+      const double vv = ok ? vload(Vs, m, nbw, col, r) : 0.0;
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(W2[col][r16], vv, d, 0, 0, 0);
+    }
+    if (ok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 4 * t + q4;
+        if (col < ncol) A[(int64_t)col * m + r] -= d[t];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ aggregated reflectors
+// Up to four consecutive panels (NB <= 64 columns) whose reflectors are
+// applied to the trailing columns as one block reflector
+// H_0 H_1 H_2 H_3 = I - V T V^T, V the NB columns in place (the panels' V
+// read by vload over NB columns), T (NB x NB, upper triangular) built from
+// the panels' T_p and the cross Grams V_p^T V_q:
+//   T = [[T_{0:q}, -T_{0:q} (V_{0:q}^T V_q) T_q], [0, T_q]], q = 1 .. nsub-1.
+// The trailing columns are then read twice and written once per 64 columns
+// instead of per 16.
+constexpr int AGG = 4 * QB;      // columns of an aggregated block reflector
+// Aggregation pays only where the trailing matrix is large: per product
+// 41.5 against 42.2 s at chi = 1024 (8192 rows), but 8.70 against 8.55 s at
+// chi = 512 (4096 rows) with a 2048-row threshold.
+constexpr int AGG_MIN_ROWS = 4096;
+
+// grid (chunks).  gpart[ch][t] (t < 6: the cross blocks (p, q), p < q, in
+// the order (0,1) (0,2) (0,3) (1,2) (1,3) (2,3); 16 x 16 row-major) =
+// V_p^T V_q over the chunk's rows; wave w takes tiles w and w + 4.
+__global__ __launch_bounds__(UNT) void qr_vgram_part_kernel(const double *Vs, int m, int mv, int nbw,
+                                                            double *__restrict__ gpart) {
+  constexpr int PQ[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int ch = blockIdx.x;
+  for (int t = w; t < 6; t += UNT / 64) {
+    const int bp = PQ[t][0], bq = PQ[t][1];
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < URC / 4; ++u) {
+      const int kk = ch * URC + 4 * u + q4;
+      const bool ok = kk < mv;
+      const double a = ok ? vload(Vs, m, nbw, QB * bp + r16, kk) : 0.0;
+      const double b = ok ? vload(Vs, m, nbw, QB * bq + r16, kk) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    double *out = gpart + ((int64_t)ch * 6 + t) * QB * QB;
+    for (int i = 0; i < 4; ++i) out[(4 * i + q4) * QB + r16] = acc[i];
+  }
+}
+
+// One workgroup: the cross Grams summed over the chunks (fixed order), then
+// T (AGG x AGG, row-major, zero outside nbw x nbw) from Tp (nsub panels'
+// 16 x 16 T factors, consecutive).
+__global__ __launch_bounds__(UNT) void qr_tagg_kernel(const double *__restrict__ gpart, int nch, int nsub,
+                                                      int nbw, const double *__restrict__ Tp,
+                                                      double *__restrict__ Tout) {
+  __shared__ double G[6][QB][QB + 1];
+  __shared__ double T[AGG][AGG + 1];
+  __shared__ double Y[AGG][QB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 6 * QB * QB; e += UNT) {
+    const int t = e / (QB * QB), r = e % (QB * QB);
+    double sum = 0.0;
+    for (int c = 0; c < nch; ++c) sum += gpart[((int64_t)c * 6 + t) * QB * QB + r];
+    G[t][r / QB][r % QB] = sum;
+  }
+  for (int e = tid; e < AGG * AGG; e += UNT) {
+    const int i = e / AGG, j = e % AGG, pb = i / QB, qb = j / QB;
+    T[i][j] = (pb == qb && pb < nsub) ? Tp[(int64_t)pb * QB * QB + (i % QB) * QB + (j % QB)] : 0.0;
+  }
+  __syncthreads();
+  auto gidx = [](int bp, int bq) { return bp == 0 ? bq - 1 : (bp == 1 ? bq + 1 : 5); };
+  for (int q = 1; q < nsub; ++q) {
+    const int rows = QB * q;
+    // Y = T[0:rows, 0:rows] X, X = the stacked G blocks (p, q), p < q
+    for (int e = tid; e < rows * QB; e += UNT) {
+      const int i = e / QB, j = e % QB;
+      double acc = 0.0;
+      for (int l = i; l < rows; ++l) acc = fma(T[i][l], G[gidx(l / QB, q)][l % QB][j], acc);
+      Y[i][j] = acc;
+    }
+    __syncthreads();
+    // T[0:rows, q block] = -Y T_q
+    for (int e = tid; e < rows * QB; e += UNT) {
+      const int i = e / QB, j = e % QB;
+      double acc = 0.0;
+      for (int l = 0; l <= j; ++l) acc = fma(Y[i][l], T[QB * q + l][QB * q + j], acc);
+      T[i][QB * q + j] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < AGG * AGG; e += UNT) {
+    const int i = e / AGG, j = e % AGG;
+    Tout[e] = (i < nbw && j < nbw) ? T[i][j] : 0.0;
+  }
+}
+
+// As qr_update_part_kernel with V of AGG columns: part[cb][ch] = V_ch^T A_ch
+// (AGG x 16, row-major).  Wave w reduces URC / 4 rows for all four 16-row
+// tiles of V^T.
+__global__ __launch_bounds__(UNT) void qr_update64_part_kernel(const double *S, int m, int j0, int c0, int nc,
+                                                               const double *Vs, int nbw,
+                                                               double *__restrict__ part) {
+  __shared__ double Wp[4][AGG][QB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int mv = m - j0;
+  const int cb = c0 + QB * blockIdx.x, ch = blockIdx.y;
+  const int ncol = min(QB, c0 + nc - cb);
+  const double *A = S + (int64_t)cb * m + j0;
+  constexpr int KS = URC / 16;
+  const int kb = ch * URC + w * (URC / 4);
+  double ab[KS];
+#pragma unroll
+  for (int u = 0; u < KS; ++u) {
+    const int kk = kb + 4 * u + q4;
+    ab[u] = (kk < mv && r16 < ncol) ? A[(int64_t)r16 * m + kk] : 0.0;
+  }
+#pragma unroll
+  for (int ti = 0; ti < AGG / QB; ++ti) {
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int kk = kb + 4 * u + q4;
+      const double va = (kk < mv) ? vload(Vs, m, nbw, QB * ti + r16, kk) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ab[u], acc, 0, 0, 0);
+    }
+    for (int t = 0; t < 4; ++t) Wp[w][QB * ti + 4 * t + q4][r16] = acc[t];
+  }
+  __syncthreads();
+  for (int e = tid; e < AGG * QB; e += UNT) {
+    const int i = e / QB, j = e % QB;
+    part[((int64_t)blockIdx.x * gridDim.y + ch) * AGG * QB + e] = (Wp[0][i][j] + Wp[1][i][j]) + (Wp[2][i][j] + Wp[3][i][j]);
+  }
+}
+
 // R (k x n, row-major) = upper triangle of S[0:k, :]; Qs = first k columns of I.
 __global__ void qr_r_and_identity_kernel(const double *__restrict__ S, int m, int n, int k,
                                          double *__restrict__ r, double *__restrict__ Qs) {
@@ -1006,9 +1198,17 @@ hipError_t launch_update(double *A, int m, int j0, int c0, int nc, const double 
   const double *Vs = Sf + (int64_t)j0 * m + j0;
   const int ncb = (nc + QB - 1) / QB;
   if (cnorm == nullptr && part != nullptr) {
-    const dim3 grid(ncb, update_chunks(m - j0));
+    const int nch = update_chunks(m - j0);
+    const dim3 grid(ncb, nch);
     hipLaunchKernelGGL(qr_update_part_kernel, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, part);
-    hipLaunchKernelGGL(qr_update_apply_kernel, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, T, trans, part);
+    if (nch >= UPD_REDUCE_MIN_CHUNKS) {
+      // W2 per column block after the partials (they occupy ncb * nch tiles)
+      double *w2 = part + (size_t)ncb * nch * QB * QB;
+      hipLaunchKernelGGL(qr_update_reduce_kernel<QB>, dim3(ncb), dim3(UNT), 0, s, part, nch, T, trans, w2);
+      hipLaunchKernelGGL(qr_update_apply_w2_kernel<QB>, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, w2);
+    } else {
+      hipLaunchKernelGGL(qr_update_apply_kernel, grid, dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, T, trans, part);
+    }
   } else {
     hipLaunchKernelGGL(qr_update_kernel, dim3(ncb), dim3(UNT), 0, s, A, m, j0, c0, nc, Vs, jb, T, trans, cnorm,
                        next);
@@ -1019,15 +1219,25 @@ hipError_t launch_update(double *A, int m, int j0, int c0, int nc, const double 
 
 // Partial products of the split update over nc columns of an m-row block.
 static size_t update_part_doubles(int m, int nc) {
-  return (size_t)((nc + QB - 1) / QB) * update_chunks(m) * QB * QB;
+  // the partials, and W2 per column block when they are reduced separately
+  return (size_t)((nc + QB - 1) / QB) * (update_chunks(m) + 1) * QB * QB;
 }
 
 // Exchange buffer of the cooperative panel: per column the G workgroup sums
 // of 16 columns, and row CC.
 static size_t coop_panel_doubles(int m) { return (size_t)QB * QB * (coop_groups(m) + 1); }
 
+// Scratch of the aggregated updates: the 64 x 16 partials per column block
+// and chunk, the cross-Gram partials, the panels' T and the aggregated T.
+static size_t agg_doubles(int m, int n) {
+  if (m <= AGG_MIN_ROWS) return 0;
+  return (size_t)((n + QB - 1) / QB) * update_chunks(m) * AGG * QB + (size_t)update_chunks(m) * 6 * QB * QB +
+         4 * QB * QB + AGG * AGG + (size_t)((n + QB - 1) / QB) * AGG * QB;
+}
+
 size_t qr_inplace_scratch_doubles(int m, int n) {
-  return QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + coop_panel_doubles(m) + 5 * 32;
+  return QB * QB + (size_t)n + 2 * (size_t)QB * m + update_part_doubles(m, n) + coop_panel_doubles(m) +
+         agg_doubles(m, n) + 10 * 32;
 }
 
 hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm, double *Tall, hipStream_t s) {
@@ -1039,6 +1249,14 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
   double *T1 = adv(QB * QB);
   double *part = adv(update_part_doubles(m, n));
   double *coop = adv(coop_panel_doubles(m));
+  double *apart = nullptr, *gpart = nullptr, *Tp = nullptr, *Tagg = nullptr, *w2buf = nullptr;
+  if (m > AGG_MIN_ROWS) {
+    apart = adv((size_t)((n + QB - 1) / QB) * update_chunks(m) * AGG * QB);
+    gpart = adv((size_t)update_chunks(m) * 6 * QB * QB);
+    Tp = adv(4 * QB * QB);
+    Tagg = adv(AGG * AGG);
+    w2buf = adv((size_t)((n + QB - 1) / QB) * AGG * QB);
+  }
   Pivot pv;
   if (perm) {
     double *cnorm = adv((size_t)n);
@@ -1048,13 +1266,45 @@ hipError_t launch_qr_inplace(double *S, int m, int n, double *scratch, int *perm
     hipError_t e = launch_column_norms(S, m, n, cnorm, s);
     if (e != hipSuccess) return e;
   }
-  for (int j0 = 0; j0 < k; j0 += QB) {
+  for (int j0 = 0; j0 < k;) {
+    const int nsub = std::min(4, (k - j0 + QB - 1) / QB);
+    if (!perm && apart && m - j0 > AGG_MIN_ROWS && nsub >= 2 && n - j0 > AGG) {
+      // Up to four panels; each updates only the rest of the group, then the
+      // group's aggregated reflector updates the trailing columns.
+      const int nbw = std::min(AGG, k - j0);
+      for (int p = 0; p < nsub; ++p) {
+        const int jp = j0 + QB * p, jb = std::min(QB, k - jp);
+        double *T = Tp + (size_t)p * QB * QB;
+        hipError_t e = launch_panel(S, m, n, jp, jb, T, pv, coop, s);
+        if (e != hipSuccess) return e;
+        if (Tall) {
+          e = launch_copy(Tall + (size_t)(jp / QB) * QB * QB, T, QB * QB, s);
+          if (e != hipSuccess) return e;
+        }
+        e = launch_update(S, m, jp, jp + jb, j0 + nbw - (jp + jb), S, jb, T, 1, nullptr, 0, part, s);
+        if (e != hipSuccess) return e;
+      }
+      const int mv = m - j0, nch = update_chunks(mv);
+      const double *Vs = S + (int64_t)j0 * m + j0;
+      hipLaunchKernelGGL(qr_vgram_part_kernel, dim3(nch), dim3(UNT), 0, s, Vs, m, mv, nbw, gpart);
+      hipLaunchKernelGGL(qr_tagg_kernel, dim3(1), dim3(UNT), 0, s, gpart, nch, nsub, nbw, Tp, Tagg);
+      const int c0 = j0 + nbw, nc = n - c0;
+      const dim3 grid((nc + QB - 1) / QB, nch);
+      hipLaunchKernelGGL(qr_update64_part_kernel, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vs, nbw, apart);
+      hipLaunchKernelGGL(qr_update_reduce_kernel<AGG>, dim3(grid.x), dim3(UNT), 0, s, apart, nch, Tagg, 1, w2buf);
+      hipLaunchKernelGGL(qr_update_apply_w2_kernel<AGG>, grid, dim3(UNT), 0, s, S, m, j0, c0, nc, Vs, nbw, w2buf);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      j0 += nbw;
+      continue;
+    }
     const int jb = (k - j0) < QB ? (k - j0) : QB;
     double *T = Tall ? Tall + (size_t)(j0 / QB) * QB * QB : T1;
     hipError_t e = launch_panel(S, m, n, j0, jb, T, pv, coop, s);
     if (e != hipSuccess) return e;
     e = launch_update(S, m, j0, j0 + jb, n - (j0 + jb), S, jb, T, 1, const_cast<double *>(pv.cnorm), jb, part, s);
     if (e != hipSuccess) return e;
+    j0 += jb;
   }
   return hipSuccess;
 }
