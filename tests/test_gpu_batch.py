@@ -219,3 +219,24 @@ def test_gpu_batch_profiled_calls_repeat():
             assert sum(sp["kernel_ms"].values()) > 0.0, rep
             for x, y in zip(_host(Cp), _host(Cq)):
                 assert np.array_equal(x, y), rep
+
+
+def test_gpu_batch_tall_panels_concurrently():
+    """Two chi = 512 products of the 1024^3 field side by side (4096-row
+    swap matrices: their QR panels run as cooperative multi-workgroup
+    launches, their trailing updates through the per-column-block
+    reduction), in one batch on two streams: bit for bit the single calls."""
+    import paper_2410_19747_amd as T
+    torch = _torch()
+    _say("case: batch of two chi=512 products on two streams")
+    q = I.turbulence_qtt_device(1024, 101, [512], torch.device("cuda", 0))[512]
+    torch.cuda.empty_cache()
+    A = T.pack(q)
+    pairs = [(A, A), (A, A)]
+    single = T.multiply(A, A, 512, 1e-14)
+    batch = T.multiply_batch(pairs, [512, 512], 1e-14, streams=2)
+    for Cb, sb in batch:
+        assert sb["ranks"] == single[1]["ranks"]
+        assert Cb.bonds == single[0].bonds
+        for x, y in zip(Cb.cores(), single[0].cores()):
+            assert torch.equal(x, y)
