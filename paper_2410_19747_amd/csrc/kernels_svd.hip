@@ -182,6 +182,45 @@ __device__ __forceinline__ int pair_col(int bi, int bj, int c) {
   return (c < BW) ? bi * BW + c : bj * BW + (c - BW);
 }
 
+// One row chunk of a pair in two halves: the thread's loads into
+// registers, then their LDS stores, so that the loads of the next chunk can
+// be in flight while the current one is consumed.
+// Thread t loads row r0 + t % RC of the pair's columns t / RC + q JNT / RC,
+// as 32-bit element offsets (BW L < 2^32) from one 64-bit base per block,
+// which keeps the addresses of the in-flight loads out of the registers.
+template <int BW, int RC>
+__device__ __forceinline__ void fetch_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
+                                                 double (&v)[RC * Pair<BW>::B2 / JNT]) {
+  constexpr int B2 = Pair<BW>::B2, PER = RC * B2 / JNT, CS = JNT / RC;
+  static_assert(JNT % RC == 0 && BW % CS == 0, "whole columns per load round, rounds within a block");
+  const int r0 = chunk * RC, nr = min(RC, L - r0), i = threadIdx.x % RC, c0 = threadIdx.x / RC;
+  const double *wi = W + (int64_t)bi * BW * L, *wj = W + (int64_t)bj * BW * L;
+  const unsigned o = (unsigned)(c0 * L + r0 + i);
+  if (nr == RC) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int c = q * CS;  // column of the pair at load round q, relative to c0
+      v[q] = (c < BW) ? wi[o + (unsigned)(c * L)] : wj[o + (unsigned)((c - BW) * L)];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int c = q * CS;
+      v[q] = (i < nr) ? ((c < BW) ? wi[o + (unsigned)(c * L)] : wj[o + (unsigned)((c - BW) * L)]) : 0.0;
+    }
+  }
+}
+template <int BW, int RC>
+__device__ __forceinline__ void stash_pair_chunk(const double (&v)[RC * Pair<BW>::B2 / JNT],
+                                                 typename Pair<BW>::template Tile<RC> &P) {
+  constexpr int B2 = Pair<BW>::B2, PER = RC * B2 / JNT;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * JNT;
+    P[e % RC][e / RC] = v[q];
+  }
+}
+
 // Every load of the thread is issued before the first LDS store.
 template <int BW, int RC>
 __device__ __forceinline__ void load_pair_chunk(const double *__restrict__ W, int L, int bi, int bj, int chunk,
@@ -446,7 +485,12 @@ __device__ int solve_pair(const double *__restrict__ part, int sw, double tol, d
 // ------------------------------------------------------------------ kernels of a round
 // grid (pairs, gsw).  Partial Gram of every block pair over gsub
 // consecutive row chunks, accumulated on the matrix cores (each wave owns
-// the same 16 x 16 output tiles throughout) and stored once.
+// the same 16 x 16 output tiles throughout) and stored once.  For 64-column
+// pairs only the ten tiles on and above the diagonal are formed (62.5% of
+// the products; the lower tiles are stored as their transposes): each wave
+// takes a quarter of the chunk's rows and forms all ten tiles over them,
+// with the four 16-column operand blocks of a k-step loaded once for ten
+// products, and the four waves' tiles are summed through LDS at the end.
 template <int BW, int RC>
 __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restrict__ W, int L, int nblk, int xs,
                                                           int round, double *__restrict__ part, int gsw,
@@ -458,6 +502,58 @@ __global__ __launch_bounds__(JNT) void jacobi_gram_kernel(const double *__restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bi, bj;
   pair_blocks(xs, nblk, round, pair, bi, bj);
+  if constexpr (BW == 32) {
+    static_assert(JNT == 256 && RC % 16 == 0, "four waves, whole MFMA k-steps per wave");
+    static_assert(sizeof(P) >= 3 * 10 * 256 * sizeof(double), "the tile exchange fits in the chunk tile");
+    constexpr int RW = RC / 4;  // rows of a chunk per wave
+    // upper tiles (ti, tj), ti <= tj, in the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3)
+    constexpr int TI[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3}, TJ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+    dbl4 acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    const int r = lane & 15, kq = lane >> 4;
+    // The chunks of this workgroup; the next one is fetched into registers
+    // while the matrix cores work on the current one.
+    const int c0 = s * gsub, nsub = max(0, min(gsub, (L + RC - 1) / RC - c0));
+    double v[RC * B2 / JNT];
+    if (nsub > 0) fetch_pair_chunk<BW, RC>(W, L, bi, bj, c0, v);
+    for (int sub = 0; sub < nsub; ++sub) {
+      if (sub > 0) __syncthreads();  // the previous chunk's tile has been read
+      stash_pair_chunk<BW, RC>(v, P);
+      __syncthreads();
+      if (sub + 1 < nsub) fetch_pair_chunk<BW, RC>(W, L, bi, bj, c0 + sub + 1, v);
+#pragma unroll
+      for (int k = 0; k < RW; k += 4) {
+        const int row = wave * RW + k + kq;
+        double x[4];  // operand of 16-column block c at this k-step: P(row, 16 c + r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = P[row][16 * c + r];
+#pragma unroll
+        for (int t = 0; t < 10; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[TI[t]], x[TJ[t]], acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave is done with the chunk tile
+    double *xch = &P[0][0];
+    if (wave > 0)
+#pragma unroll
+      for (int t = 0; t < 10; ++t)
+        for (int q = 0; q < 4; ++q) xch[((wave - 1) * 10 + t) * 256 + q * 64 + lane] = acc[t][q];
+    __syncthreads();
+    if (wave == 0) {
+      double *out = part + ((int64_t)pair * gsw + s) * B2 * B2;
+#pragma unroll
+      for (int t = 0; t < 10; ++t) {
+        for (int q = 0; q < 4; ++q) {
+          double v = acc[t][q];
+          for (int w = 0; w < 3; ++w) v += xch[(w * 10 + t) * 256 + q * 64 + lane];
+          const int i = TI[t] * 16 + 4 * q + kq, j = TJ[t] * 16 + r;
+          out[i * B2 + j] = v;
+          if (TI[t] != TJ[t]) out[j * B2 + i] = v;
+        }
+      }
+    }
+    return;
+  }
   dbl4 acc[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = (dbl4){0.0, 0.0, 0.0, 0.0};
