@@ -693,43 +693,15 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
   const int blo = min(h1, h2), bhi = max(h1, h2);
   const int i0 = insert_zero_bit(insert_zero_bit(blockIdx.x, blo), bhi);
   const int blk[4] = {i0, i0 ^ m, i0 ^ mn, i0 ^ m ^ mn};
-  // The round's two rotations into LDS once (identity for a pair that did
-  // not rotate).
-  {
-    double qg[2][B2 * B2 / JNT];
-#pragma unroll
-    for (int pp = 0; pp < 2; ++pp) {
-      const int lo = min(blk[2 * pp], blk[2 * pp + 1]);
-      const int pr = remove_bit(lo, h1);
-      const int rot = flag[pr];
-      const double *Q = qbuf + (int64_t)pr * B2 * B2;
-#pragma unroll
-      for (int e = 0; e < B2 * B2 / JNT; ++e) {
-        const int idx = threadIdx.x + JNT * e;
-        qg[pp][e] = rot ? Q[idx] : ((idx / B2 == idx % B2) ? 1.0 : 0.0);
-      }
-    }
-#pragma unroll
-    for (int pp = 0; pp < 2; ++pp)
-#pragma unroll
-      for (int e = 0; e < B2 * B2 / JNT; ++e) {
-        const int idx = threadIdx.x + JNT * e;
-        qs[pp][idx / B2][idx % B2] = qg[pp][e];
-      }
-  }
-  __syncthreads();
-  // Row chunks s*xsub .. s*xsub + n - 1 of ROWS_XOR rows; the next round's
-  // Gram tiles accumulate over all of them in the matrix-core registers.
+  // Row chunks s*xsub .. s*xsub + n - 1 of ROWS_XOR rows.  This lane's
+  // operand values of a chunk: W(row, column 4 ks + q4 of pair pp) for the
+  // row of the wave's 16-row tile.  The first chunk's loads are issued
+  // before the rotations', and each later chunk's while the previous one is
+  // still being rotated and stored.
   const int c0 = s * xsub, n = MULTI ? min(xsub, (L + ROWS_XOR - 1) / ROWS_XOR - c0) : 1;
-  dbl4 gt[2][3];
-#pragma unroll
-  for (int pp = 0; pp < 2; ++pp)
-#pragma unroll
-    for (int tl = 0; tl < 3; ++tl) gt[pp][tl] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  for (int sub = 0; sub < n; ++sub) {
-    const int chunk = c0 + sub;
-    const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
-    double wv[2][KS];
+  double wv[2][KS];
+  auto fetch = [&](int chunk) {
+    const int row = chunk * ROWS_XOR + 16 * w + r16;
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
       const int lo = min(blk[2 * pp], blk[2 * pp + 1]), hi = max(blk[2 * pp], blk[2 * pp + 1]);
@@ -740,6 +712,50 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
         wv[pp][ks] = (row < L) ? W[(int64_t)col * L + row] : 0.0;
       }
     }
+  };
+  if (n > 0) fetch(c0);
+  // The round's two rotations into LDS once (identity for a pair that did
+  // not rotate).
+  {
+    // Both flags and both rotations are loaded unconditionally (qbuf holds a
+    // matrix for every pair) and the identity is selected afterwards, so that
+    // the loads are in flight together.
+    double qg[2][B2 * B2 / JNT];
+    int rot[2];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) rot[pp] = flag[remove_bit(min(blk[2 * pp], blk[2 * pp + 1]), h1)];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      const double *Q = qbuf + (int64_t)remove_bit(min(blk[2 * pp], blk[2 * pp + 1]), h1) * B2 * B2;
+#pragma unroll
+      for (int e = 0; e < B2 * B2 / JNT; ++e) qg[pp][e] = Q[threadIdx.x + JNT * e];
+    }
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int e = 0; e < B2 * B2 / JNT; ++e) {
+        const int idx = threadIdx.x + JNT * e;
+        qg[pp][e] = rot[pp] ? qg[pp][e] : ((idx / B2 == idx % B2) ? 1.0 : 0.0);
+      }
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int e = 0; e < B2 * B2 / JNT; ++e) {
+        const int idx = threadIdx.x + JNT * e;
+        qs[pp][idx / B2][idx % B2] = qg[pp][e];
+      }
+  }
+  __syncthreads();
+  // The next round's Gram tiles accumulate over the chunks in the
+  // matrix-core registers.
+  dbl4 gt[2][3];
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+    for (int tl = 0; tl < 3; ++tl) gt[pp][tl] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  for (int sub = 0; sub < n; ++sub) {
+    const int chunk = c0 + sub;
+    const int row = chunk * ROWS_XOR + 16 * w + r16;  // this lane's row of the operand tile
     // The round's two pairs: (blk[0], blk[1]) and (blk[2], blk[3]), each as
     // (lower block, higher block) = columns 0..15, 16..31 of its rotation.
     dbl4 nb[4];
@@ -762,6 +778,7 @@ __global__ __launch_bounds__(JNT) void jacobi_xor_round_kernel(double *__restric
       nb[2 * pp] = (x == lo) ? d0 : d1;
       nb[2 * pp + 1] = (x == lo) ? d1 : d0;
     }
+    if (MULTI && sub + 1 < n) fetch(chunk + 1);
     // The next round's pairs: (blk[0], blk[2]) and (blk[1], blk[3]).
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
