@@ -119,9 +119,12 @@ def main():
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     ap.add_argument("--upper-chis", default="256,1024",
                     help="bond dimensions of the 10-site 1024^3 points added to the default line")
-    ap.add_argument("--upper-precisions", default="f32,bf16x3",
-                    help="reduced contraction precisions timed at each added point")
+    ap.add_argument("--upper-precisions", default="f32,bf16x3,rsvd,rsvd+f32",
+                    help="reduced-accuracy modes timed at each added point: contraction precisions, "
+                         "rsvd (randomized swap SVDs) and rsvd+<precision>")
     ap.add_argument("--no-upper", action="store_true", help="skip the 10-site points of the default line")
+    ap.add_argument("--no-rsvd", action="store_true",
+                    help="skip the randomized-swap-SVD products of the default line")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the comparison with the dense exact product and the Eckart-Young floor")
     ap.add_argument("--chi-mid-sweep", action="store_true",
@@ -278,6 +281,29 @@ def main():
         _log("  conventional: %.1f ms per product, %d sweeps" % (1e3 * tc, stc["sweeps"]))
 
     cores = [c.detach().cpu().numpy() for c in C.cores()]
+    # The reduced-accuracy mode on the same workload: the swap SVDs by the
+    # randomized range finder (svd_mode="randomized"), with FP64 and with
+    # FP32 contractions, K products each after one warm-up.
+    rsvd = {}
+    rsvd_cores = {}
+    if not args.no_rsvd:
+        for mode in ("rsvd", "rsvd+f32"):
+            kw = _mode_options(mode)
+            rout = torch.empty(cap, dtype=torch.float64, device=dev)
+            T.multiply(A, B, args.chi, args.eps, workspace=ws, out=rout, stream=stream, **kw)
+            torch.cuda.synchronize()
+            tr = time.perf_counter()
+            for _ in range(args.steps):
+                Cr, sr = T.multiply(A, B, args.chi, args.eps, workspace=ws, out=rout, stream=stream, **kw)
+            torch.cuda.synchronize()
+            tr = (time.perf_counter() - tr) / args.steps
+            rsvd_cores[mode] = [c.detach().cpu().numpy() for c in Cr.cores()]
+            rsvd[mode] = {"ms_per_product": 1e3 * tr, "products_per_s": 1.0 / tr,
+                          "speedup_vs_f64": (ms_per_step / 1e3) / tr, "randomized_svds": sr["n_rsvd"],
+                          "randomized_fallbacks": sr["n_rsvd_fallback"], "jacobi_sweeps": sr["sweeps"],
+                          "ranks_equal_f64": sr["ranks"] == st["ranks"]}
+            _log("  %s: %.1f ms per product (%.2fx over FP64), %d randomized SVDs"
+                 % (mode, 1e3 * tr, rsvd[mode]["speedup_vs_f64"], sr["n_rsvd"]))
     accuracy = None
     if not args.no_exact:
         _log("accuracy against the dense exact product (%d entries) and the Eckart-Young floor" % args.grid ** 3)
@@ -299,6 +325,9 @@ def main():
         rel_err = O.rel_frob(cores, ref.cores)
         if conv is not None:
             conv["rel_diff_vs_ttm"] = O.rel_frob([c.detach().cpu().numpy() for c in Cc.cores()], cores)
+        for mode, rc_ in rsvd_cores.items():
+            rsvd[mode]["rel_err_vs_oracle"] = O.rel_frob(rc_, ref.cores)
+            _log("  %s: rel. Frobenius error vs the FP64 oracle %.2e" % (mode, rsvd[mode]["rel_err_vs_oracle"]))
         _log("  oracle %.2f s, GPU vs oracle rel. Frobenius error %.2e, ranks equal: %s"
              % (dt, rel_err, st["ranks"] == ref.ranks))
         _log("CPU oracle, one BLAS thread (the paper's timings are from one core)")
@@ -343,6 +372,7 @@ def main():
         "rel_err_vs_exact": accuracy,
         "kernel_time_share": kernel_share,
         "conventional": conv,
+        "randomized_svd": rsvd or None,
         "bond_dimension_points": upper,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -622,6 +652,18 @@ def sweep(args, dev):
         torch.cuda.empty_cache()
 
 
+def _mode_options(mode):
+    """Options of a reduced-accuracy mode name: a contraction precision
+    ("f32", "bf16", "bf16x3"), "rsvd" (the randomized swap SVD, FP64
+    contractions) or "rsvd+<precision>"."""
+    if mode.startswith("rsvd"):
+        kw = {"svd_mode": "randomized"}
+        if "+" in mode:
+            kw["contract_precision"] = mode.split("+", 1)[1]
+        return kw
+    return {"contract_precision": mode}
+
+
 def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=None):
     """One point of the bond-dimension sweep: u * u for the QTT ``cores`` at
     chi_out = chi_mid = chi.  FP64 products per second (after one warm-up
@@ -661,18 +703,22 @@ def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=No
     # difference of the sampled entries from the FP64 product's.
     mixed = {}
     for prec in precisions:
+        kw = _mode_options(prec)
+        if kw.get("svd_mode") == "randomized" and chi <= 256:
+            # one warm-up, as for the FP64 timing
+            T.multiply(A, A, chi, eps, workspace=ws, out=torch.empty_like(out), stream=stream, **kw)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        Cm, stm = T.multiply(A, A, chi, eps, workspace=ws, out=torch.empty_like(out), stream=stream,
-                             contract_precision=prec)
+        Cm, stm = T.multiply(A, A, chi, eps, workspace=ws, out=torch.empty_like(out), stream=stream, **kw)
         torch.cuda.synchronize()
         tm = time.perf_counter() - tm
         gm = _tt_entries(Cm.cores(), idx)
         mixed[prec] = {"ms_per_product": 1e3 * tm, "speedup_vs_f64": dt / tm,
                        "sampled_rel_diff_vs_f64": float(torch.linalg.norm(gm - got) / torch.linalg.norm(got)),
-                       "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"]}
-        _log("    %s contractions: %.1f ms, sampled rel diff vs FP64 %.2e"
-             % (prec, 1e3 * tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
+                       "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"],
+                       "randomized_svds": stm["n_rsvd"], "randomized_fallbacks": stm["n_rsvd_fallback"]}
+        _log("    %s: %.1f ms (%.2fx), sampled rel diff vs FP64 %.2e"
+             % (prec, 1e3 * tm, dt / tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
         del Cm
     line = {
         "chi": chi, "eps": eps, "chi_out": chi, "chi_mid": chi,

@@ -114,7 +114,25 @@ typedef struct ttm_options {
                               factorisation of that carriage moves the centre into the moving
                               one before the next swap; one extra QR per swap, the same result
                               in exact arithmetic) */
+  int32_t svd_mode;        /* the truncated SVD of each capped swap: TTM_SVD_JACOBI (default: the
+                              full SVD, results within 1e-12 of an exact truncation) or
+                              TTM_SVD_RANDOMIZED, a reduced-accuracy mode: a subspace-iteration
+                              range finder with 2 cap columns (Halko, Martinsson and Tropp 2011,
+                              Alg. 4.4), its products on FP32 operands, CholeskyQR2 in FP64, then
+                              the FP64 Jacobi SVD of the 2 cap projected columns and the rule of
+                              Eq. (eps) with the uncaptured weight counted as tail.  Used where
+                              4 cap <= min(m, n) of the swap matrix and no forced ranks are given;
+                              other SVDs take the full SVD, and so does any swap whose CholeskyQR
+                              breaks down or whose estimated subspace error, (s_2cap / s_r)^(2q+1)
+                              s_r / ||Theta||_F from the projected values, exceeds 2e-8.  About
+                              2e-7 of the FP64 product on the turbulence workloads, not 1e-12.
+                              Not with ttm_multiply_vjp (TTM_EUNSUPPORTED) */
+  int32_t rsvd_power;      /* TTM_SVD_RANDOMIZED: subspace iterations q, 0 <= q <= 64 (default 10);
+                              the subspace error decays like (sigma_{2 cap + 1} / sigma_r)^(2q+1) */
 } ttm_options;
+
+/* Values of ttm_options.svd_mode. */
+enum { TTM_SVD_JACOBI = 0, TTM_SVD_RANDOMIZED = 1 };
 
 /* Values of ttm_options.move_factor and ttm_options.gauge. */
 enum { TTM_MOVE_SECOND = 0, TTM_MOVE_SMALLER = 1 };
@@ -161,6 +179,9 @@ typedef struct ttm_stats {
   int64_t kernel_launches[TTM_KC_COUNT]; /* with opt.profile: timed regions per class: one launch
                                             each, except a whole QR or a column reordering,
                                             which are timed as one region */
+  int32_t n_rsvd;          /* svd_mode TTM_SVD_RANDOMIZED: swaps truncated by the randomized SVD */
+  int32_t n_rsvd_fallback; /* ... and eligible swaps that fell back to the full SVD (CholeskyQR
+                              breakdown or an estimate above the acceptance bound) */
 } ttm_stats;
 
 /* Defaults: chi_mid = -1 (same as chi_out), final_round = 1, max_sweeps = 10,

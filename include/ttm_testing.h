@@ -87,6 +87,16 @@ int ttm_test_svd_bw(const double *M, int m, int n, double eps, int cap, int forc
                     int right_pow, double *left, double *right, double *sigma, int *rank, int *sweeps,
                     int block_width, void *ws, size_t ws_bytes, void *stream);
 
+/* CholeskyQR2 of the p x l column-major Y (ld p, l <= p) in place: two
+ * passes of Y^T Y = R^T R, Y <- Y R^-1, as the randomized swap SVD
+ * (TTM_SVD_RANDOMIZED) orthonormalises its sketches.  *breakdown = 1 when a
+ * Cholesky pivot fell to the rounding level of its column (Y numerically
+ * rank deficient, or cond(Y) beyond about 1e7); Y is then not orthonormal.
+ * ws: device, ttm_test_cholqr2_ws_bytes(p, l) bytes (0 for bad sizes).
+ * Synchronises the stream. */
+size_t ttm_test_cholqr2_ws_bytes(int p, int l);
+int ttm_test_cholqr2(double *Y, int p, int l, int *breakdown, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

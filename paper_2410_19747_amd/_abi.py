@@ -56,6 +56,8 @@ class TtmOptions(ctypes.Structure):
         ("contract_precision", ctypes.c_int32),
         ("move_factor", ctypes.c_int32),
         ("gauge", ctypes.c_int32),
+        ("svd_mode", ctypes.c_int32),
+        ("rsvd_power", ctypes.c_int32),
     ]
 
 
@@ -77,12 +79,16 @@ class TtmStats(ctypes.Structure):
         ("peak_ws_bytes", ctypes.c_size_t),
         ("kernel_ms", ctypes.c_double * 7),
         ("kernel_launches", ctypes.c_int64 * 7),
+        ("n_rsvd", ctypes.c_int32),
+        ("n_rsvd_fallback", ctypes.c_int32),
     ]
 
 
 TTM_PREC_F64, TTM_PREC_F32, TTM_PREC_BF16, TTM_PREC_BF16X3 = 0, 1, 2, 3
 TTM_MOVE_SECOND, TTM_MOVE_SMALLER = 0, 1
 TTM_GAUGE_MOVING, TTM_GAUGE_RIGHT = 0, 1
+TTM_SVD_JACOBI, TTM_SVD_RANDOMIZED = 0, 1
+SVD_MODES = {"jacobi": TTM_SVD_JACOBI, "randomized": TTM_SVD_RANDOMIZED}
 PRECISIONS = {"f64": TTM_PREC_F64, "f32": TTM_PREC_F32, "bf16": TTM_PREC_BF16, "bf16x3": TTM_PREC_BF16X3}
 
 KERNEL_CLASSES = ["gemm", "qr", "jacobi_gram", "jacobi_solve", "jacobi_other", "other", "jacobi_apply"]
@@ -168,6 +174,9 @@ TESTING_PROTOTYPES = {
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP,
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
+    "ttm_test_cholqr2_ws_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "ttm_test_cholqr2": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _VP,
+                                        ctypes.c_size_t, _VP]),
 }
 
 TTM_STATIC_WS_BYTES = 32 << 20

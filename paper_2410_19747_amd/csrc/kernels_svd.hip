@@ -972,6 +972,7 @@ constexpr int RANK_PER = 8;  // n <= 8192
 __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restrict__ sigma,
                                                            const int *__restrict__ perm, int n,
                                                            double eps, double noise, int cap, int forced,
+                                                           const double *__restrict__ full_total,
                                                            double *__restrict__ result) {
   __shared__ double csum[2][1024];
   __shared__ int best, nsig;
@@ -1002,8 +1003,12 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
     src ^= 1;
     __syncthreads();
   }
-  const double after = (t + 1 < nt) ? csum[src][t + 1] : 0.0;  // sum over i >= hi
-  const double total = csum[src][0];
+  // With full_total, the weight outside the resolved values joins every
+  // tail (and the total).
+  const double wsum = csum[src][0];
+  const double extra = full_total ? fmax(full_total[0] - wsum, 0.0) : 0.0;
+  const double after = ((t + 1 < nt) ? csum[src][t + 1] : 0.0) + extra;  // sum over i >= hi
+  const double total = wsum + extra;
   // The smallest kept count r < n whose tail (sum over i >= r) is zero or
   // below eps * total; the tail of kept = k + 1 is suf[k + 1 - lo] + after
   // inside the chunk and `after` at its end.
@@ -1018,7 +1023,7 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
   }
   if (mine < n) atomicMin(&best, mine);
   // values above the noise level (sorted, so they are the leading ones)
-  const double nz2 = noise * noise * total;
+  const double nz2 = noise * noise * wsum;
   int above = 0;
 #pragma unroll
   for (int j = 0; j < RANK_PER; ++j)
@@ -1038,7 +1043,7 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
   for (int j = 0; j < RANK_PER; ++j)
     if (lo + j < hi && lo + j == r) result[1] = suf[j] + after;
   if (t == 0) {
-    if (r == n) result[1] = 0.0;
+    if (r == n) result[1] = extra;
     result[0] = (double)r;
     result[2] = total;
     result[4] = isfinite(total) ? 0.0 : 1.0;
@@ -1047,7 +1052,7 @@ __global__ __launch_bounds__(1024) void jacobi_rank_kernel(const double *__restr
 }
 
 hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double eps, int cap,
-                                int forced, hipStream_t s) {
+                                int forced, hipStream_t s, const double *full_total) {
   const int nc = p.nc;
   hipLaunchKernelGGL(jacobi_sigma_kernel, dim3((nc + 3) / 4), dim3(JNT), 0, s, b.W, p.L, nc, b.sigma);
   const size_t shm = (size_t)nc * sizeof(double);
@@ -1058,7 +1063,7 @@ hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double
   if (nc > 1024 * RANK_PER) return hipErrorInvalidValue;
   const double noise = 8.0 * sqrt((double)p.L) * 2.220446049250313e-16;  // as in the sweeps
   hipLaunchKernelGGL(jacobi_rank_kernel, dim3(1), dim3(1024), 0, s, b.sigma, b.perm, nc, eps, noise, cap,
-                     forced, b.result);
+                     forced, full_total, b.result);
   return hipGetLastError();
 }
 

@@ -71,6 +71,8 @@ struct Options {
   int contract_prec = GEMM_F64;
   int move_factor = TTM_MOVE_SECOND;
   int gauge = TTM_GAUGE_MOVING;
+  int svd_mode = TTM_SVD_JACOBI;
+  int rsvd_power = 10;
 };
 
 // Largest matrix a QR or SVD step takes: each side at most 2^30 (the kernels
@@ -144,6 +146,10 @@ int resolve_options(const ttm_options *o, int chi_out, Options &r) {
   r.contract_prec = o->contract_precision;  // TTM_PREC_* and GemmPrec share their values
   if (o->move_factor != TTM_MOVE_SECOND && o->move_factor != TTM_MOVE_SMALLER) return TTM_EINVAL;
   r.move_factor = o->move_factor;
+  if (o->svd_mode != TTM_SVD_JACOBI && o->svd_mode != TTM_SVD_RANDOMIZED) return TTM_EINVAL;
+  r.svd_mode = o->svd_mode;
+  if (o->rsvd_power < 0 || o->rsvd_power > 64) return TTM_EINVAL;
+  r.rsvd_power = o->rsvd_power;
   if (o->gauge != TTM_GAUGE_MOVING && o->gauge != TTM_GAUGE_RIGHT) return TTM_EINVAL;
   r.gauge = o->gauge;
   return TTM_OK;
@@ -304,6 +310,9 @@ int make_plan(const ttm_tt *A, const ttm_tt *B, int chi_out, const Options &o, P
       } else if (!note_svd(pl, m, nn, true)) {
         return TTM_EUNSUPPORTED;
       }
+      if (o.gauge != TTM_GAUGE_RIGHT && o.svd_mode == TTM_SVD_RANDOMIZED && !o.forced && rsvd_eligible(m, nn, r))
+        pl.max_w = std::max<int64_t>(pl.max_w, (int64_t)rsvd_ws_doubles(m, nn, r) +
+                                                   ((((int64_t)m * nn) + 31) & ~(int64_t)31));
       Shape xn = {pi[p].rl, x.d, r};
       Shape pn = {r, pi[p].d, x.rr};
       note_core(pl, xn);
@@ -373,6 +382,8 @@ struct Runner {
   int trace = 0;  // TTM_TRACE: 1 = one line per step, 2 = also one per Jacobi sweep
   // stats
   int n_contract = 0, n_swap = 0, n_qr = 0, n_svd = 0, n_trace = 0, max_bond = 1;
+  int64_t n_rsvd = 0;  // randomized SVDs started (each takes its own stretch of the random stream)
+  int n_rsvd_done = 0, n_rsvd_fallback = 0;
   int jac_sweeps = 0, jac_max = 0;
   double disc_sum = 0.0, err_bound = 0.0, flops = 0.0, svd_flops = 0.0, solve_flops = 0.0;
   int forced_pos = 0;
@@ -567,6 +578,39 @@ struct Runner {
     return so.rank;
   }
 
+  // ---- the randomized truncated SVD of a swap matrix (svd_mode
+  // TTM_SVD_RANDOMIZED) with the same bookkeeping as svd(); *done = false
+  // when it fell back (CholeskyQR breakdown) and the full SVD must run.
+  int rsvd(const double *Y, int m, int n, int cap, double *pt, double *ws, bool *done) {
+    *done = false;
+    RsvdResult rs = rsvd_oside(Y, m, n, cap, o.rsvd_power, o.svd_max_sweeps, eps_, o.contract_prec, o.seed,
+                               (int64_t)n_rsvd << 40, pt, ws, st, &timer, trace);
+    ++n_rsvd;
+    jac_sweeps += rs.sweeps;
+    jac_max = std::max(jac_max, rs.sweeps);
+    if (rs.err != TTM_OK) {
+      if (err == TTM_OK) err = rs.err;
+      return -1;
+    }
+    if (rs.fallback) {
+      ++n_rsvd_fallback;
+      return 0;
+    }
+    *done = true;
+    ++n_rsvd_done;
+    ++n_svd;
+    disc_sum += rs.disc;
+    err_bound += sqrt(std::max(rs.disc, 0.0));
+    if (n_trace < o.trace_cap) {
+      o.rank_trace[n_trace] = rs.rank;
+      o.discard_trace[n_trace] = rs.disc;
+    }
+    ++n_trace;
+    flops += rs.flops;
+    svd_flops += rs.flops;
+    return rs.rank;
+  }
+
   // ---- Swap of Fig. 1C: (P, X) -> (X', P') with X' = U_r S_r, P' = V_r^T.
   void swap(Core &P, Core &X, int cap, int pos = 0, int site = 0) {
     step = "a swap";
@@ -618,7 +662,13 @@ struct Runner {
     if (!xn || !pn) return;
     if (tape) e.theta = keep(Y, (int64_t)m * n);
     // P' = V_r^T -> [r, dp, Dr] (the orthonormal factor, over Theta's columns)
-    const int r = svd(sp, Y, sws, cap, pn, SVD_U_T, tape ? &all : nullptr);
+    int r = 0;
+    bool done = false;
+    if (o.svd_mode == TTM_SVD_RANDOMIZED && !o.forced && !tape && rsvd_eligible(m, n, cap)) {
+      r = rsvd(Y, m, n, cap, pn, sws, &done);
+      if (r < 0) return;
+    }
+    if (!done) r = svd(sp, Y, sws, cap, pn, SVD_U_T, tape ? &all : nullptr);
     if (r < 1) return;
     // X' = Theta V_r = U_r S_r -> [Dl, dx, r]
     GemmArgs z;
@@ -931,6 +981,8 @@ int run_ttm_impl(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, ttm_
     stats->svd_model_flops = R.svd_flops;
     stats->jacobi_solve_flops = R.solve_flops;
     stats->peak_ws_bytes = pl.ws_bytes;
+    stats->n_rsvd = R.n_rsvd_done;
+    stats->n_rsvd_fallback = R.n_rsvd_fallback;
     for (int c = 0; c < KC_COUNT; ++c) {
       stats->kernel_ms[c] = R.timer.ms[c];
       stats->kernel_launches[c] = R.timer.launches[c];
@@ -949,7 +1001,8 @@ int run_ttm_taped(const ttm_tt *A, const ttm_tt *B, int chi_out, double tol, con
   Options o;
   int e = resolve_options(opt, chi_out, o);
   if (e) return e;
-  if (o.gauge != TTM_GAUGE_MOVING) return TTM_EUNSUPPORTED;
+  // the reverse mode differentiates the full SVD's truncation only
+  if (o.gauge != TTM_GAUGE_MOVING || o.svd_mode != TTM_SVD_JACOBI) return TTM_EUNSUPPORTED;
   *swapped = moves_first(A, B, o);
   bool enqueued = false;
   e = run_ttm_impl(A, B, chi_out, tol, C, ws, ws_bytes, st, o, stats, enqueued, tape);
@@ -968,7 +1021,7 @@ int vjp_sizes(const ttm_tt *A, const ttm_tt *B, int chi_out, const ttm_options *
   Options o;
   e = resolve_options(opt, chi_out, o);
   if (e) return e;
-  if (o.gauge != TTM_GAUGE_MOVING) return TTM_EUNSUPPORTED;
+  if (o.gauge != TTM_GAUGE_MOVING || o.svd_mode != TTM_SVD_JACOBI) return TTM_EUNSUPPORTED;
   Plan pl;
   e = make_plan(A, B, chi_out, o, pl);
   if (e) return e;
@@ -1322,6 +1375,8 @@ void ttm_default_options(ttm_options *opt) {
   opt->max_sweeps = 10;
   opt->svd_max_sweeps = 40;
   opt->seed = 12345;
+  opt->svd_mode = TTM_SVD_JACOBI;
+  opt->rsvd_power = 10;
 }
 
 const char *ttm_strerror(int code) {

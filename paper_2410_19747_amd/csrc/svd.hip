@@ -92,7 +92,7 @@ size_t svd_ws_doubles(const SvdPlan &p) {
 
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, int trace, SvdAll *all) {
+                    KernelTimer *timer, int trace, SvdAll *all, const double *full_total) {
   SvdResult out;
   SvdBufs b = carve(p, ws);
   const JacobiPlan &jp = p.jp;
@@ -188,7 +188,7 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
   // 4. singular values and the rank rule
   {
     Timed tm(timer, KC_JAC_OTHER, s);
-    if (!ok(launch_jacobi_finish(jp, b.jb, eps, cap, forced, s))) return out;
+    if (!ok(launch_jacobi_finish(jp, b.jb, eps, cap, forced, s, full_total))) return out;
   }
   if (!ok(hipMemcpyAsync(res, b.jb.result, sizeof(res), hipMemcpyDeviceToHost, s))) return out;
   if (!sync()) return out;

@@ -170,4 +170,16 @@ int ttm_test_svd(const double *M, int m, int n, double eps, int cap, int forced,
                          ws, ws_bytes, stream);
 }
 
+size_t ttm_test_cholqr2_ws_bytes(int p, int l) {
+  if (p < 1 || l < 1 || l > p) return 0;
+  return ttm::cholqr2_ws_doubles(p, l) * sizeof(double);
+}
+
+int ttm_test_cholqr2(double *Y, int p, int l, int *breakdown, void *ws, size_t ws_bytes, void *stream) {
+  if (p < 1 || l < 1 || l > p || !Y || !breakdown || !ws) return TTM_EINVAL;
+  if (ws_bytes < ttm::cholqr2_ws_doubles(p, l) * sizeof(double)) return TTM_EWORKSPACE;
+  const hipError_t e = ttm::cholqr2(Y, p, l, static_cast<double *>(ws), breakdown, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TTM_OK : TTM_EHIP;
+}
+
 }  // extern "C"

@@ -192,8 +192,10 @@ hipError_t launch_jacobi_sort_columns(const JacobiPlan &p, JacobiBufs &b, hipStr
 // Column norms, descending order, and the rank rule of Eq. (eps):
 // r = min{k>=1 : tail_k < eps*total or tail_k == 0}, then min(r, cap) when
 // cap > 0; forced > 0 replaces the rule.  Writes result[0..2].
+// With full_total set (device), the rule counts full_total - (the sum of
+// squares of W's values) as extra weight in every tail and in the total.
 hipError_t launch_jacobi_finish(const JacobiPlan &p, const JacobiBufs &b, double eps, int cap,
-                                int forced, hipStream_t s);
+                                int forced, hipStream_t s, const double *full_total = nullptr);
 // u[rowperm[j]*u_os + t*u_ts] = j-th entry of the t-th largest column of W
 // divided by its norm (j < L, t < r).
 hipError_t launch_jacobi_write_u(const JacobiPlan &p, const JacobiBufs &b, const int *rowperm, int r,
@@ -260,9 +262,40 @@ struct SvdAll {
   double *sigma = nullptr;  // k doubles, decreasing
   int kg = 0;               // out
 };
+// full_total (device, optional): the squared Frobenius norm of a larger
+// matrix of which Y is a projection; the rank rule then counts the weight
+// outside Y, full_total - ||Y||_F^2, as part of every tail (randomized SVD).
 SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int forced, int max_sweeps,
                     double *u, int u_layout, double *sigma_out, double *ws, hipStream_t s,
-                    KernelTimer *timer, int trace, SvdAll *all = nullptr);
+                    KernelTimer *timer, int trace, SvdAll *all = nullptr, const double *full_total = nullptr);
+
+// Randomized truncated SVD of a swap matrix (rsvd.hip): Theta (m x n,
+// column-major, ld m) ~ X' P' with P' = V_r^T (r x n, row-major, written to
+// pt, orthonormal rows) from a subspace-iteration range finder with
+// rsvd_sketch_cols(cap) columns and `power` iterations (products in the
+// GemmPrec sketch_prec), then the Jacobi SVD
+// of the projection.  Theta is left intact.  fallback = true (no error)
+// when a CholeskyQR broke down or the estimated subspace error exceeded the
+// acceptance bound: the caller runs the full SVD instead.  The
+// test matrix is the SplitMix64 stream of `seed` from counter stream_pos.
+struct RsvdResult {
+  int rank = -1;
+  double disc = 0.0, total = 0.0, flops = 0.0;
+  double estimate = 0.0;  // the subspace-error estimate of the acceptance test
+  int sweeps = 0;
+  bool fallback = false;
+  int err = 0;
+};
+int rsvd_sketch_cols(int cap);
+// CholeskyQR2 of the p x l column-major Y in place (a testing hook):
+// *fail_host = 1 when a Cholesky pivot broke down.  Synchronises s.
+size_t cholqr2_ws_doubles(int p, int l);
+hipError_t cholqr2(double *Y, int p, int l, double *ws, int *fail_host, hipStream_t s);
+bool rsvd_eligible(int m, int n, int cap);
+size_t rsvd_ws_doubles(int m, int n, int cap);
+RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int max_sweeps, double eps,
+                      int sketch_prec, uint64_t seed, int64_t stream_pos, double *pt, double *ws, hipStream_t s,
+                      KernelTimer *timer, int trace);
 
 // ------------------------------------------------------------------ reverse mode
 // The record a TTM product keeps for its reverse mode: one entry per step,

@@ -77,6 +77,8 @@ int main() {
     o.move_factor = uniform(seed, 0, 1);
     o.gauge = uniform(seed, 0, 1);
     o.contract_precision = uniform(seed, 0, 3);
+    o.svd_mode = uniform(seed, 0, 1);
+    o.rsvd_power = uniform(seed, 0, 12);
     const int chi = uniform(seed, 1, 80);
     size_t ws = 0;
     int64_t cap = 0;
@@ -112,7 +114,8 @@ int main() {
     size_t vws = 0;
     int64_t vcap = 0;
     const int vrc = ttm_vjp_query(&A.view, &B.view, chi, &o, &vws, &vcap);
-    EXPECT(vrc == (o.gauge == TTM_GAUGE_RIGHT && rc == TTM_OK ? TTM_EUNSUPPORTED : rc));
+    EXPECT(vrc == ((o.gauge == TTM_GAUGE_RIGHT || o.svd_mode == TTM_SVD_RANDOMIZED) && rc == TTM_OK
+                       ? TTM_EUNSUPPORTED : rc));
     if (vrc == TTM_OK) {
       size_t fws = 0;
       int64_t fcap = 0;
@@ -141,6 +144,12 @@ int main() {
     EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
     ttm_default_options(&o);
     o.move_factor = -1;
+    EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
+    ttm_default_options(&o);
+    o.svd_mode = 2;
+    EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
+    ttm_default_options(&o);
+    o.rsvd_power = 65;
     EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
     ttm_default_options(&o);
     o.n_forced = 2;

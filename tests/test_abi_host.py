@@ -431,3 +431,27 @@ def test_inner_grad_checkpoint_sizes(L):
     v = ctypes.c_double(0.0)
     assert L.ttm_inner_grad_ex(*args, 0, ctypes.byref(v), None, None, -2, ctypes.c_void_p(0x1000), 1 << 20,
                                None) == _abi.TTM_EINVAL
+
+
+def test_randomized_svd_options(L):
+    """svd_mode and rsvd_power are checked on the host; the randomized mode
+    asks for at least the full SVD's workspace (the full SVD stays its
+    fallback) and is refused by the reverse mode, which differentiates the
+    full SVD's truncation only."""
+    A = _TT([8] * 8, [1, 8, 64, 128, 128, 128, 64, 8, 1])
+    o = _abi.TtmOptions()
+    L.ttm_default_options(ctypes.byref(o))
+    assert o.svd_mode == _abi.TTM_SVD_JACOBI and o.rsvd_power == 10
+    rc, ws_full, cap_full = _query(L, A, A, 128, o)
+    assert rc == 0
+    o.svd_mode = _abi.TTM_SVD_RANDOMIZED
+    rc, ws_r, cap_r = _query(L, A, A, 128, o)
+    assert rc == 0 and ws_r >= ws_full and cap_r == cap_full
+    for mode, power in ((2, 10), (-1, 10), (1, -1), (1, 65)):
+        o.svd_mode, o.rsvd_power = mode, power
+        assert _query(L, A, A, 128, o)[0] == _abi.TTM_EINVAL
+    o.svd_mode, o.rsvd_power = _abi.TTM_SVD_RANDOMIZED, 0
+    assert _query(L, A, A, 128, o)[0] == 0
+    need, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(A.view), 128, ctypes.byref(o), ctypes.byref(need),
+                           ctypes.byref(cap)) == _abi.TTM_EUNSUPPORTED

@@ -349,3 +349,42 @@ def test_mfma_f64_rate_probe():
     rate = fl.value / sec.value / 1e12
     _say("  %.1f TFLOP/s" % rate)
     assert 5.0 < rate < 200.0
+
+
+@pytest.mark.parametrize("p,l,cond", [(1024, 256, 1e3), (700, 130, 1e6), (2048, 512, 1e4), (64, 64, 10.0)])
+def test_cholqr2_orthonormalises(p, l, cond):
+    """CholeskyQR2 (the orthonormalisation of the randomized swap SVD):
+    blocked Cholesky of Y^T Y on 64 x 64 diagonal blocks, blocked triangular
+    solve; ragged last block (l = 130), square case.  Q^T Q = I to rounding,
+    span(Q) = span(Y), and no breakdown up to cond(Y) = 1e6."""
+    torch, L = _env()
+    _say("cholqr2 %dx%d cond %.0e" % (p, l, cond))
+    rng = np.random.default_rng(p + l)
+    U, _ = np.linalg.qr(rng.standard_normal((p, l)))
+    V, _ = np.linalg.qr(rng.standard_normal((l, l)))
+    Y = (U * np.geomspace(1.0, 1.0 / cond, l)) @ V.T
+    dY = _dev(torch, Y.T)  # column-major p x l
+    ws = torch.empty(L.ttm_test_cholqr2_ws_bytes(p, l) // 8 + 1, dtype=torch.float64, device="cuda")
+    bd = ctypes.c_int(-1)
+    rc = L.ttm_test_cholqr2(_ptr(dY), p, l, ctypes.byref(bd), _ptr(ws), ws.numel() * 8, None)
+    assert rc == 0 and bd.value == 0
+    Q = dY.cpu().numpy().T
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-13
+    # Y lies in span(Q): the residual of its projection is at rounding level
+    assert np.linalg.norm(Y - Q @ (Q.T @ Y)) <= 1e-13 * np.linalg.norm(Y)
+
+
+def test_cholqr2_reports_breakdown():
+    """A rank-deficient Y (two equal columns) raises the breakdown flag
+    instead of returning a non-orthonormal Q."""
+    torch, L = _env()
+    _say("cholqr2 rank deficient")
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((512, 128))
+    Y[:, 77] = Y[:, 5]
+    dY = _dev(torch, Y.T)
+    ws = torch.empty(L.ttm_test_cholqr2_ws_bytes(512, 128) // 8 + 1, dtype=torch.float64, device="cuda")
+    bd = ctypes.c_int(-1)
+    rc = L.ttm_test_cholqr2(_ptr(dY), 512, 128, ctypes.byref(bd), _ptr(ws), ws.numel() * 8, None)
+    assert rc == 0 and bd.value == 1
+    assert np.isfinite(dY.cpu().numpy()).all()

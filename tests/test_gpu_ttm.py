@@ -142,6 +142,17 @@ def test_gpu_config2_turbulence_vs_oracle(chi):
     assert st2["ranks"] == o.ranks
     assert O.rel_frob(C2, o.cores) <= TOL
     assert st2["max_bond"] == o.max_bond
+    # The reduced-accuracy mode: the eligible swaps (4 chi <= the smaller
+    # side) truncated by the randomized range finder (a few with flat spectra
+    # at the cut take the full SVD), within 1e-6 of the FP64 oracle with the
+    # oracle's ranks.
+    Cr, sr = _run(A, B, chi, 1e-14, svd_mode="randomized")
+    er = O.rel_frob(Cr, o.cores)
+    _say("  randomized swap SVDs (%d, %d fell back): relative error vs oracle %.3e"
+         % (sr["n_rsvd"], sr["n_rsvd_fallback"], er))
+    assert sr["n_rsvd"] >= 10 and sr["n_rsvd"] >= 3 * sr["n_rsvd_fallback"]
+    assert sr["ranks"] == o.ranks
+    assert er <= 1e-6
 
 
 _TEN_SITE_QTTS = {}
@@ -182,6 +193,14 @@ def test_gpu_ten_sites_1024_turbulence_vs_oracle(chi):
         em = O.rel_frob(Cm, o.cores)
         _say("  %s contractions: relative error vs FP64 oracle %.3e" % (prec, em))
         assert em <= 1e-6
+    # The randomized swap SVDs, alone and with FP32 contractions.
+    for prec in ("f64", "f32"):
+        Cr, sr = _run(q, q, chi, 1e-14, svd_mode="randomized", contract_precision=prec)
+        er = O.rel_frob(Cr, o.cores)
+        _say("  randomized swap SVDs (%d), %s contractions: relative error vs FP64 oracle %.3e"
+             % (sr["n_rsvd"], prec, er))
+        assert sr["n_rsvd"] >= 10 and sr["n_rsvd"] >= 3 * sr["n_rsvd_fallback"]
+        assert er <= 1e-6
 
 
 def test_gpu_model_flops_golden():
@@ -392,3 +411,35 @@ def test_gpu_move_smaller_factor_vs_oracle():
     C2, st2 = _run(uy, ux, 64, 1e-14, move_factor="smaller")
     assert st2["ranks"] == o2.ranks
     assert O.rel_frob(C2, o2.cores) <= TOL
+
+
+def test_gpu_randomized_svd_eligibility_and_fallback():
+    """svd_mode="randomized" leaves swaps too small for the range finder
+    (4 cap > the smaller side: every swap of the config-1 QTTs) on the full
+    SVD, bit for bit; forced ranks keep the full SVD too; and a swap whose
+    sketch is rank deficient (a swap matrix of rank below 2 cap) falls back
+    to the full SVD instead of returning a wrong product."""
+    _say("case: randomized SVD eligibility and fallback")
+    A, B = I.random_tt(10, 2, 8, 1), I.random_tt(10, 2, 8, 2)
+    C0, s0 = _run(A, B, 8, 1e-14)
+    C1, s1 = _run(A, B, 8, 1e-14, svd_mode="randomized")
+    assert s1["n_rsvd"] == 0 and s1["n_rsvd_fallback"] == 0
+    assert all(np.array_equal(x, y) for x, y in zip(C0, C1))
+    U = I.turbulence_qtt(256, 101, 64)
+    o = O.ttm(U, U, 64, 1e-14)
+    Cf, sf = _run(U, U, 64, 1e-14, svd_mode="randomized", forced_ranks=o.ranks)
+    assert sf["n_rsvd"] == 0 and O.rel_frob(Cf, o.cores) <= TOL
+    # A factor whose cores do not depend on the physical index is a constant
+    # tensor (rank 1) carried on bonds of 32: the swap matrices keep their
+    # sizes, but their rank is below the 2 cap sketch columns.
+    rng = np.random.default_rng(31)
+    bonds = [1, 8, 32, 32, 32, 8, 1]
+    R = [rng.standard_normal((bonds[i], 8, bonds[i + 1])) for i in range(6)]
+    K = [np.repeat(rng.standard_normal((bonds[i], 1, bonds[i + 1])), 8, axis=1) for i in range(6)]
+    ok = O.ttm(R, K, 8, 1e-14)
+    Ck, sk = _run(R, K, 8, 1e-14, svd_mode="randomized")
+    ek = O.rel_frob(Ck, ok.cores)
+    _say("  rank-deficient swaps: %d randomized, %d fell back, relative error vs oracle %.3e"
+         % (sk["n_rsvd"], sk["n_rsvd_fallback"], ek))
+    assert sk["n_rsvd_fallback"] >= 1
+    assert ek <= 1e-6
