@@ -82,6 +82,14 @@ __global__ void diag_kernel(const double *__restrict__ G, int ld, int n, double 
   if (i < n) dst[i] = G[(int64_t)i * ld + i];
 }
 
+// 1 / sqrt(d) for d > 0: the hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
 // Cholesky of the w x w diagonal block at G (row-major, ld), upper:
 // G_kk = R^T R, one workgroup, padded to CNB with the identity.  Writes
 // R^-1 (upper triangular, CNB x CNB row-major, zero below the diagonal) to
@@ -89,20 +97,21 @@ __global__ void diag_kernel(const double *__restrict__ G, int ld, int n, double 
 // (the squared column norms); a pivot at or below 64 u gd_j, or not
 // positive, sets *fail and is replaced by gd_j (or 1) so that everything
 // stays finite.
-// Factorisation: thread t holds row i = t / 4 of the block at the columns
-// k = t % 4 + 4 m (m < 16) in registers.  Step j: the four threads of row j
-// publish it in LDS (double-buffered), one barrier, and every thread with
-// i > j applies the rank-one update a_ik -= g_ji g_jk / g_jj to its entries
-// with k > j; row j of R is g_jk / sqrt(g_jj).  Inverse: thread t takes
-// column c = t / 4 of R^-1 at rows r = t % 4 + 4 m, starting from e_c, by
-// back substitution over R (in LDS); each x_i reaches the four threads of
+// Factorisation, four rows per step: thread t holds row i = t / 4 at the
+// columns k = t % 4 + 4 m (m < 16) in registers.  Step s: the sixteen
+// threads of rows 4s .. 4s+3 publish them in LDS (double-buffered), one
+// barrier; every thread factors the 4 x 4 diagonal block U^T U itself, forms
+// the four rows of R at its columns by U^-T, and, for i > 4s+3, applies the
+// rank-four update; rows 4s .. 4s+3 become rows of R.  Inverse: thread t
+// takes column c = t / 4 of R^-1 at rows r = t % 4 + 4 m, starting from e_c,
+// by back substitution over R (in LDS); each x_i reaches the four threads of
 // its column by a lane shuffle, so the unrolled steps need no barrier.
 __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict__ G, int ld, int w,
                                                         const double *__restrict__ gd, double *__restrict__ rinv,
                                                         int *__restrict__ fail) {
   static_assert(CNB == 64 && CNT == 256, "four threads per row of the block");
   __shared__ double R[CNB][CNB + 1];
-  __shared__ double rowb[2][CNB];
+  __shared__ double rowb[2][4][CNB];
   __shared__ double piv[CNB];
   const int t = threadIdx.x, i = t >> 2, q = t & 3;
   double a[16];
@@ -113,32 +122,57 @@ __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict
   }
   if (t < CNB) piv[t] = (t < w) ? gd[t] : 1.0;
   bool bad = false;
-  for (int j = 0; j < CNB; ++j) {
-    double *rb = rowb[j & 1];
-    if (i == j) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) rb[q + 4 * m] = a[m];
-    }
-    __syncthreads();
-    const double ref = piv[j];
-    double d = rb[j];
+  auto pivot = [&](double d, double ref, double &r, double &ri) {
     const bool ok = d > 64.0 * kU * ref;  // false for NaN as well
     bad |= !ok;
     d = ok ? d : (ref > 0.0 ? ref : 1.0);
-    const double rinvd = 1.0 / d, rs = 1.0 / sqrt(d);
-    // Branch-free: rows i < j take f = 0 and keep their values (row i of R
-    // since step i); row j becomes row j of R; columns k <= j of the rows
-    // below keep their (dead) values.
-    const double f = (i > j) ? rb[i] * rinvd : 0.0;
-    double v[16];
+    ri = rsqrt_nr(d);
+    r = d * ri;
+  };
+  for (int st = 0; st < CNB / 4; ++st) {
+    const int j0 = 4 * st;
+    double (*rb)[CNB] = rowb[st & 1];
+    if (i >= j0 && i < j0 + 4) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = rb[q + 4 * m];
+      for (int m = 0; m < 16; ++m) rb[i - j0][q + 4 * m] = a[m];
+    }
+    __syncthreads();
+    // U^T U = the 4 x 4 diagonal block (upper entries of the published rows)
+    double u00, u11, u22, u33, i00, i11, i22, i33;
+    pivot(rb[0][j0], piv[j0], u00, i00);
+    const double u01 = rb[0][j0 + 1] * i00, u02 = rb[0][j0 + 2] * i00, u03 = rb[0][j0 + 3] * i00;
+    pivot(rb[1][j0 + 1] - u01 * u01, piv[j0 + 1], u11, i11);
+    const double u12 = (rb[1][j0 + 2] - u01 * u02) * i11, u13 = (rb[1][j0 + 3] - u01 * u03) * i11;
+    pivot(rb[2][j0 + 2] - u02 * u02 - u12 * u12, piv[j0 + 2], u22, i22);
+    const double u23 = (rb[2][j0 + 3] - u02 * u03 - u12 * u13) * i22;
+    pivot(rb[3][j0 + 3] - u03 * u03 - u13 * u13 - u23 * u23, piv[j0 + 3], u33, i33);
+    // rows j0 .. j0+3 of R at column k (k > j0 + 3): x = U^-T g_k
+    auto rows = [&](int k, double &x0, double &x1, double &x2, double &x3) {
+      const double g0 = rb[0][k], g1 = rb[1][k], g2 = rb[2][k], g3 = rb[3][k];
+      x0 = g0 * i00;
+      x1 = (g1 - u01 * x0) * i11;
+      x2 = (g2 - u02 * x0 - u12 * x1) * i22;
+      x3 = (g3 - u03 * x0 - u13 * x1 - u23 * x2) * i33;
+    };
+    double y0, y1, y2, y3;  // rows j0.. of R at column i (the update's left factor)
+    rows(i, y0, y1, y2, y3);
+    const bool below = i > j0 + 3, in = (i >= j0) && !below;
+    const int r0 = i - j0;
+    // this thread's row of U when it holds one of the block's rows
+    const double ub0 = (r0 == 0) ? u00 : 0.0;
+    const double ub1 = (r0 == 0) ? u01 : (r0 == 1 ? u11 : 0.0);
+    const double ub2 = (r0 == 0) ? u02 : (r0 == 1 ? u12 : (r0 == 2 ? u22 : 0.0));
+    const double ub3 = (r0 == 0) ? u03 : (r0 == 1 ? u13 : (r0 == 2 ? u23 : u33));
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int k = q + 4 * m;
-      const double nv = (k > j) ? fma(-f, v[m], a[m]) : a[m];
-      const double rr = (k > j) ? v[m] * rs : (k == j ? d * rs : 0.0);
-      a[m] = (i == j) ? rr : nv;
+      double x0, x1, x2, x3;
+      rows(k, x0, x1, x2, x3);
+      const double upd = fma(-y3, x3, fma(-y2, x2, fma(-y1, x1, fma(-y0, x0, a[m]))));
+      const double mine = (r0 == 0) ? x0 : (r0 == 1 ? x1 : (r0 == 2 ? x2 : x3));
+      const double rin = (k > j0 + 3) ? mine
+                         : (k == j0 ? ub0 : (k == j0 + 1 ? ub1 : (k == j0 + 2 ? ub2 : (k == j0 + 3 ? ub3 : 0.0))));
+      a[m] = in ? rin : ((below && k > j0 + 3) ? upd : a[m]);
     }
   }
 #pragma unroll
