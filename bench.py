@@ -119,12 +119,15 @@ def main():
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     ap.add_argument("--upper-chis", default="256,1024",
                     help="bond dimensions of the 10-site 1024^3 points added to the default line")
-    ap.add_argument("--upper-precisions", default="f32,bf16x3,rsvd,rsvd+f32",
+    ap.add_argument("--upper-precisions", default="f32,rsvd,rsvd+f32",
                     help="reduced-accuracy modes timed at each added point: contraction precisions, "
                          "rsvd (randomized swap SVDs) and rsvd+<precision>")
     ap.add_argument("--no-upper", action="store_true", help="skip the 10-site points of the default line")
     ap.add_argument("--no-rsvd", action="store_true",
                     help="skip the randomized-swap-SVD products of the default line")
+    ap.add_argument("--svd-mode", default="jacobi", choices=["jacobi", "randomized"],
+                    help="swap SVD of the timed products (randomized: the reduced-accuracy mode; the line's "
+                         "value is then that mode's, for profiling runs)")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the comparison with the dense exact product and the Eckart-Young floor")
     ap.add_argument("--chi-mid-sweep", action="store_true",
@@ -186,8 +189,9 @@ def main():
     stream = torch.cuda.current_stream()
     prof = not args.no_profile
 
+    mode = {"svd_mode": args.svd_mode}
     for _ in range(args.warmup):
-        T.multiply(A, B, args.chi, args.eps, workspace=ws, out=out, stream=stream, profile=prof)
+        T.multiply(A, B, args.chi, args.eps, workspace=ws, out=out, stream=stream, profile=prof, **mode)
     torch.cuda.synchronize()
 
     # Timed region: K whole products, no instrumentation.
@@ -195,7 +199,7 @@ def main():
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        C, st = T.multiply(A, B, args.chi, args.eps, workspace=ws, out=out, stream=stream)
+        C, st = T.multiply(A, B, args.chi, args.eps, workspace=ws, out=out, stream=stream, **mode)
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -219,7 +223,7 @@ def main():
         tp = time.perf_counter()
         for _ in range(args.steps):
             _, s_ = T.multiply(A, B, args.chi, args.eps, workspace=ws, out=out, stream=stream,
-                               profile=True)
+                               profile=True, **mode)
             pstats.append(s_)
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp
@@ -286,7 +290,7 @@ def main():
     # FP32 contractions, K products each after one warm-up.
     rsvd = {}
     rsvd_cores = {}
-    if not args.no_rsvd:
+    if not args.no_rsvd and args.svd_mode == "jacobi":
         for mode in ("rsvd", "rsvd+f32"):
             kw = _mode_options(mode)
             rout = torch.empty(cap, dtype=torch.float64, device=dev)
@@ -361,7 +365,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=8 sites, d=8" % args.grid,
                    "chi": args.chi, "chi_out": args.chi, "chi_mid": args.chi, "eps": args.eps,
-                   "parallelism": "single GPU"},
+                   "svd_mode": args.svd_mode, "parallelism": "single GPU"},
         "model_flops_per_step": model_flops,
         "svd_model_flops_per_step": svd_flops,
         "algorithmic_tflops": model_flops / (ms_per_step / 1e3) / 1e12,
