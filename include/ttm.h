@@ -121,7 +121,8 @@ typedef struct ttm_options {
                               Alg. 4.4), its products on FP32 operands, CholeskyQR2 in FP64, then
                               the FP64 Jacobi SVD of the 2 cap projected columns and the rule of
                               Eq. (eps) with the uncaptured weight counted as tail.  Used where
-                              4 cap <= min(m, n) of the swap matrix and no forced ranks are given;
+                              4 cap <= min(m, n) of the swap matrix, with the default gauge and
+                              no forced ranks;
                               other SVDs take the full SVD, and so does any swap whose CholeskyQR
                               breaks down or whose estimated subspace error, (s_2cap / s_r)^(2q+1)
                               s_r / ||Theta||_F from the projected values, exceeds 2e-8.  About

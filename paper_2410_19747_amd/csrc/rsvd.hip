@@ -108,7 +108,7 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // its column by a lane shuffle, so the unrolled steps need no barrier.
 __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict__ G, int ld, int w,
                                                         const double *__restrict__ gd, double *__restrict__ rinv,
-                                                        int *__restrict__ fail) {
+                                                        double *__restrict__ rout, int *__restrict__ fail) {
   static_assert(CNB == 64 && CNT == 256, "four threads per row of the block");
   __shared__ double R[CNB][CNB + 1];
   __shared__ double rowb[2][4][CNB];
@@ -177,6 +177,11 @@ __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict
   }
 #pragma unroll
   for (int m = 0; m < 16; ++m) R[i][q + 4 * m] = a[m];
+  if (rout && i < w) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (q + 4 * m < w) rout[(int64_t)i * ld + q + 4 * m] = a[m];
+  }
   if (bad && t == 0) atomicOr(fail, 1);
   __syncthreads();
   if (t < CNB) piv[t] = 1.0 / R[t][t];
@@ -203,9 +208,9 @@ __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict
   for (int m = 0; m < 16; ++m) rinv[(g + 4 * m) * CNB + c] = x[m];
 }
 
-hipError_t launch_chol_diag(const double *G, int ld, int w, const double *gd, double *rinv, int *fail,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(CNT), 0, s, G, ld, w, gd, rinv, fail);
+hipError_t launch_chol_diag(const double *G, int ld, int w, const double *gd, double *rinv, double *rout,
+                            int *fail, hipStream_t s) {
+  hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(CNT), 0, s, G, ld, w, gd, rinv, rout, fail);
   return hipGetLastError();
 }
 
@@ -242,10 +247,13 @@ CqrBufs cqr_carve(int l, double *base) {
 
 // One CholeskyQR pass: Q = Y R^-1 with Y^T Y = R^T R, Y and Q column-major
 // p x l (ld p).  Y is overwritten (the block solve updates it in place).
+// With want_r, b.Rf holds all of R afterwards (row-major, zero below the
+// diagonal); otherwise only its blocks right of the diagonal blocks.
 hipError_t cholqr(double *Y, int p, int l, double *Q, const CqrBufs &b, int *fail, hipStream_t s,
-                  KernelTimer *timer) {
+                  KernelTimer *timer, bool want_r = false) {
   Timed tm(timer, KC_QR, s);
   hipError_t e;
+  if (want_r && (e = launch_fill(b.Rf, 0.0, (int64_t)l * l, s)) != hipSuccess) return e;
   {
     // G = Y^T Y (row-major, ld l), K split when the output is small
     GemmArgs g;
@@ -264,7 +272,9 @@ hipError_t cholqr(double *Y, int p, int l, double *Q, const CqrBufs &b, int *fai
   for (int kb = 0; kb < nb; ++kb) {
     const int b0 = kb * CNB, w = std::min(CNB, l - b0), rest = l - b0 - w;
     double *rk = b.rinv + (int64_t)kb * CNB * CNB;
-    if ((e = launch_chol_diag(b.G + (int64_t)b0 * l + b0, l, w, b.gd + b0, rk, fail, s)) != hipSuccess) return e;
+    double *rout = want_r ? b.Rf + (int64_t)b0 * l + b0 : nullptr;
+    if ((e = launch_chol_diag(b.G + (int64_t)b0 * l + b0, l, w, b.gd + b0, rk, rout, fail, s)) != hipSuccess)
+      return e;
     if (rest == 0) break;
     GemmArgs g;
     g.M = w; g.N = rest; g.K = w;
@@ -310,7 +320,10 @@ struct RsvdBufs {
   double *vbt = nullptr;   // l x l: V_B,r^T
   double *sig = nullptr;   // l: the singular values of B, decreasing
   double *full = nullptr;  // [0] = ||Theta||_F^2; [8, 8 + SQB): its block partials
-  int *fail = nullptr;     // 1
+  int *fail = nullptr;     // 1: a CholeskyQR of the range finder broke down
+  int *fail2 = nullptr;    // 1: the CholeskyQR2 of B broke down
+  double *R1 = nullptr;    // l x l: R of the first pass on B (row-major)
+  double *RB = nullptr;    // l x l: R_B = R2 R1 (column-major)
   CqrBufs cq;
   double *svd = nullptr;   // the Jacobi SVD of B
 };
@@ -343,7 +356,7 @@ size_t rsvd_ws_doubles(int m, int n, int cap) {
   const size_t mx = std::max(m, n);
   size_t t = 0;
   t += 3 * r32(mx * l) + r32((size_t)m * l) + r32((size_t)l * l);
-  t += r32((size_t)l) + r32(8 + SQB) + r32(8);
+  t += r32((size_t)l) + r32(8 + SQB) + r32(8) + r32(8) + 2 * r32((size_t)l * l);
   t += cqr_doubles(l);
   t += svd_ws_doubles(svd_plan(m, l));
   return t;
@@ -368,6 +381,9 @@ RsvdBufs rsvd_carve(int m, int n, int cap, double *base) {
   b.sig = adv((size_t)l);
   b.full = adv(8 + SQB);
   b.fail = reinterpret_cast<int *>(adv(8));
+  b.fail2 = reinterpret_cast<int *>(adv(8));
+  b.R1 = adv((size_t)l * l);
+  b.RB = adv((size_t)l * l);
   b.cq = cqr_carve(l, q);
   q += cqr_doubles(l);
   b.svd = q;
@@ -445,21 +461,51 @@ RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int
     Timed tm(timer, KC_GEMM, s);
     if (!ok(launch_gemm(g, s))) return out;
   }
-  // A breakdown of any CholeskyQR makes the result meaningless: read the
-  // flag before the Jacobi SVD of B.
-  int fail = 0;
-  if (!ok(hipMemcpyAsync(&fail, b.fail, sizeof(int), hipMemcpyDeviceToHost, s))) return out;
+  // B = Q_B R_B by CholeskyQR2 with R_B = R2 R1 kept (Q_B is not needed):
+  // B's right singular vectors and values are R_B's, and the Jacobi SVD then
+  // runs on the l x l R_B instead of the m x l B.
+  if (!ok(launch_zero_int(b.fail2, 1, s))) return out;
+  if (!ok(cholqr(b.B, m, l, spare, b.cq, b.fail2, s, timer, true))) return out;
+  if (!ok(launch_copy(b.R1, b.cq.Rf, (int64_t)l * l, s))) return out;
+  if (!ok(cholqr(spare, m, l, zcur, b.cq, b.fail2, s, timer, true))) return out;
+  {
+    GemmArgs g;
+    g.M = l; g.N = l; g.K = l;
+    g.A = b.cq.Rf; g.a_rs = l; g.a_cs = 1;
+    g.B = b.R1; g.b_rs = l; g.b_cs = 1;
+    g.C = b.RB; g.c_rs1 = 1; g.c_cs1 = l;
+    Timed tm(timer, KC_GEMM, s);
+    if (!ok(launch_gemm(g, s))) return out;
+  }
+  // A breakdown of the range finder's CholeskyQR makes its result
+  // meaningless: read both flags before the SVD.
+  int fail[2] = {0, 0};
+  if (!ok(hipMemcpyAsync(&fail[0], b.fail, sizeof(int), hipMemcpyDeviceToHost, s))) return out;
+  if (!ok(hipMemcpyAsync(&fail[1], b.fail2, sizeof(int), hipMemcpyDeviceToHost, s))) return out;
   if (!ok(hipStreamSynchronize(s))) return out;
   if (timer && timer->on) timer->collect();
-  if (fail) {
+  if (fail[0]) {
     out.fallback = true;
     if (trace) fprintf(stderr, "[ttm] rsvd %dx%d cap %d: CholeskyQR breakdown, full SVD instead\n", m, n, cap);
     return out;
   }
-  // SVD of B: its right singular vectors (over the l side) come out
+  // The SVD of R_B (or of B itself when its CholeskyQR2 broke down, B
+  // formed again): the right singular vectors (over the l side) come out
   // orthonormal; the rank rule adds the weight outside span(Y).
-  const SvdPlan sp = svd_plan(m, l);
-  SvdResult so = svd_oside(sp, b.B, eps, cap, 0, max_sweeps, b.vbt, SVD_U_T, b.sig, b.svd, s, timer, trace, nullptr,
+  const double *Ysvd = b.RB;
+  SvdPlan sp = svd_plan(l, l);
+  if (fail[1]) {
+    GemmArgs g;
+    g.M = m; g.N = l; g.K = n;
+    g.A = Theta; g.a_rs = 1; g.a_cs = m;
+    g.B = ycur; g.b_rs = 1; g.b_cs = n;
+    g.C = b.B; g.c_rs1 = 1; g.c_cs1 = m;
+    Timed tm(timer, KC_GEMM, s);
+    if (!ok(launch_gemm(g, s))) return out;
+    Ysvd = b.B;
+    sp = svd_plan(m, l);
+  }
+  SvdResult so = svd_oside(sp, Ysvd, eps, cap, 0, max_sweeps, b.vbt, SVD_U_T, b.sig, b.svd, s, timer, trace, nullptr,
                            b.full);
   out.sweeps = so.sweeps;
   if (so.err != TTM_OK) {

@@ -240,3 +240,30 @@ def test_gpu_batch_tall_panels_concurrently():
         assert Cb.bonds == single[0].bonds
         for x, y in zip(Cb.cores(), single[0].cores()):
             assert torch.equal(x, y)
+
+
+def test_gpu_batch_randomized_svd_equals_single():
+    """Products in the reduced-accuracy mode (svd_mode="randomized") in one
+    batch beside a full-SVD product: each equals its single call bit for bit
+    (the test matrices come from the product's own counter stream), and the
+    randomized ones are within 1e-6 of the oracle."""
+    import paper_2410_19747_amd as T
+    _torch()
+    _say("case: batch with randomized swap SVDs")
+    ux = I.turbulence_qtt(256, 101, 64)
+    uy = I.turbulence_qtt(256, 102, 64)
+    pairs = [(ux, uy), (uy, uy), (ux, ux)]
+    chis = [64, 64, 64]
+    options = [{"svd_mode": "randomized"}, {}, {"svd_mode": "randomized", "contract_precision": "f32"}]
+    single = [T.multiply(A, B, c, 1e-14, **o) for (A, B), c, o in zip(pairs, chis, options)]
+    batch = T.multiply_batch(pairs, chis, 1e-14, streams=2, options=options)
+    for k, ((Cb, sb), (Cs, ss)) in enumerate(zip(batch, single)):
+        assert Cb.bonds == Cs.bonds and sb["ranks"] == ss["ranks"], k
+        assert sb["n_rsvd"] == ss["n_rsvd"], k
+        for x, y in zip(_host(Cb), _host(Cs)):
+            assert np.array_equal(x, y), k
+    assert batch[0][1]["n_rsvd"] > 0 and batch[1][1]["n_rsvd"] == 0
+    o = O.ttm(ux, uy, 64, 1e-14)
+    e = O.rel_frob(_host(batch[0][0]), o.cores)
+    _say("  randomized product in the batch: relative error vs oracle %.3e" % e)
+    assert e <= 1e-6
