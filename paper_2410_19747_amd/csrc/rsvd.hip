@@ -93,33 +93,51 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // Cholesky of the w x w diagonal block at G (row-major, ld), upper:
 // G_kk = R^T R, one workgroup, padded to CNB with the identity.  Writes
 // R^-1 (upper triangular, CNB x CNB row-major, zero below the diagonal) to
-// rinv.  gd holds the block's diagonal as it was before any elimination
-// (the squared column norms); a pivot at or below 64 u gd_j, or not
-// positive, sets *fail and is replaced by gd_j (or 1) so that everything
-// stays finite.
-// Factorisation, four rows per step: thread t holds row i = t / 4 at the
-// columns k = t % 4 + 4 m (m < 16) in registers.  Step s: the sixteen
-// threads of rows 4s .. 4s+3 publish them in LDS (double-buffered), one
-// barrier; every thread factors the 4 x 4 diagonal block U^T U itself, forms
-// the four rows of R at its columns by U^-T, and, for i > 4s+3, applies the
-// rank-four update; rows 4s .. 4s+3 become rows of R.  Inverse: thread t
-// takes column c = t / 4 of R^-1 at rows r = t % 4 + 4 m, starting from e_c,
-// by back substitution over R (in LDS); each x_i reaches the four threads of
-// its column by a lane shuffle, so the unrolled steps need no barrier.
+// rinv, and R itself to rout (row-major, ld, w x w) when rout is set.  gd
+// holds the block's diagonal as it was before any elimination (the squared
+// column norms); a pivot at or below 64 u gd_j, or not positive, sets *fail
+// and is replaced by gd_j (or 1) so that everything stays finite.
+// Thread t owns the 4 x 4 tile (t / 16, t % 16) of the block in registers.
+// Factorisation, four rows per step: the sixteen threads of tile row s
+// publish rows 4s .. 4s+3 in LDS (double-buffered), one barrier; every
+// thread factors the 4 x 4 diagonal block U^T U itself, forms the block's
+// rows of R at its tile's four columns and four rows by U^-T, and tiles
+// below and right of the block take the rank-four update; tile row s
+// becomes its rows of R.  Inverse, by block rows from the bottom: the
+// threads of tile row b form X_b = U_bb^-1 (their accumulated right-hand
+// side) and publish it; after one barrier every tile row above subtracts
+// R_a,b X_b from its accumulator.
+__device__ __forceinline__ void inv4_upper(const double (&u)[4][4], double (&x)[4][4]) {
+  const double d0 = 1.0 / u[0][0], d1 = 1.0 / u[1][1], d2 = 1.0 / u[2][2], d3 = 1.0 / u[3][3];
+  x[0][0] = d0; x[1][1] = d1; x[2][2] = d2; x[3][3] = d3;
+  x[1][0] = x[2][0] = x[2][1] = x[3][0] = x[3][1] = x[3][2] = 0.0;
+  x[0][1] = -u[0][1] * d1 * d0;
+  x[1][2] = -u[1][2] * d2 * d1;
+  x[2][3] = -u[2][3] * d3 * d2;
+  x[0][2] = -(u[0][1] * x[1][2] + u[0][2] * d2) * d0;
+  x[1][3] = -(u[1][2] * x[2][3] + u[1][3] * d3) * d1;
+  x[0][3] = -(u[0][1] * x[1][3] + u[0][2] * x[2][3] + u[0][3] * d3) * d0;
+}
+
 __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict__ G, int ld, int w,
                                                         const double *__restrict__ gd, double *__restrict__ rinv,
                                                         double *__restrict__ rout, int *__restrict__ fail) {
-  static_assert(CNB == 64 && CNT == 256, "four threads per row of the block");
-  __shared__ double R[CNB][CNB + 1];
-  __shared__ double rowb[2][4][CNB];
+  static_assert(CNB == 64 && CNT == 256, "one 4 x 4 tile per thread");
+  constexpr int LD = CNB + 2;  // 16-byte aligned rows
+  __shared__ __align__(16) double R[CNB][LD];
+  __shared__ __align__(16) double Xs[CNB][LD];
+  __shared__ __align__(16) double rb[2][4][CNB];
   __shared__ double piv[CNB];
-  const int t = threadIdx.x, i = t >> 2, q = t & 3;
-  double a[16];
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int t = threadIdx.x, ti = t >> 4, tk = t & 15, i0 = 4 * ti, k0 = 4 * tk;
+  double a[4][4];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int k = q + 4 * m;
-    a[m] = (i < w && k < w) ? G[(int64_t)i * ld + k] : (i == k ? 1.0 : 0.0);
-  }
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, k = k0 + c;
+      a[r][c] = (i < w && k < w) ? G[(int64_t)i * ld + k] : (i == k ? 1.0 : 0.0);
+    }
   if (t < CNB) piv[t] = (t < w) ? gd[t] : 1.0;
   bool bad = false;
   auto pivot = [&](double d, double ref, double &r, double &ri) {
@@ -131,81 +149,120 @@ __global__ __launch_bounds__(CNT) void chol_diag_kernel(const double *__restrict
   };
   for (int st = 0; st < CNB / 4; ++st) {
     const int j0 = 4 * st;
-    double (*rb)[CNB] = rowb[st & 1];
-    if (i >= j0 && i < j0 + 4) {
+    double (*buf)[CNB] = rb[st & 1];
+    if (ti == st) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) rb[i - j0][q + 4 * m] = a[m];
+      for (int r = 0; r < 4; ++r) {
+        *(d2 *)&buf[r][k0] = d2{a[r][0], a[r][1]};
+        *(d2 *)&buf[r][k0 + 2] = d2{a[r][2], a[r][3]};
+      }
     }
     __syncthreads();
     // U^T U = the 4 x 4 diagonal block (upper entries of the published rows)
-    double u00, u11, u22, u33, i00, i11, i22, i33;
-    pivot(rb[0][j0], piv[j0], u00, i00);
-    const double u01 = rb[0][j0 + 1] * i00, u02 = rb[0][j0 + 2] * i00, u03 = rb[0][j0 + 3] * i00;
-    pivot(rb[1][j0 + 1] - u01 * u01, piv[j0 + 1], u11, i11);
-    const double u12 = (rb[1][j0 + 2] - u01 * u02) * i11, u13 = (rb[1][j0 + 3] - u01 * u03) * i11;
-    pivot(rb[2][j0 + 2] - u02 * u02 - u12 * u12, piv[j0 + 2], u22, i22);
-    const double u23 = (rb[2][j0 + 3] - u02 * u03 - u12 * u13) * i22;
-    pivot(rb[3][j0 + 3] - u03 * u03 - u13 * u13 - u23 * u23, piv[j0 + 3], u33, i33);
-    // rows j0 .. j0+3 of R at column k (k > j0 + 3): x = U^-T g_k
-    auto rows = [&](int k, double &x0, double &x1, double &x2, double &x3) {
-      const double g0 = rb[0][k], g1 = rb[1][k], g2 = rb[2][k], g3 = rb[3][k];
-      x0 = g0 * i00;
-      x1 = (g1 - u01 * x0) * i11;
-      x2 = (g2 - u02 * x0 - u12 * x1) * i22;
-      x3 = (g3 - u03 * x0 - u13 * x1 - u23 * x2) * i33;
+    double u[4][4], iv[4];
+    pivot(buf[0][j0], piv[j0], u[0][0], iv[0]);
+    u[0][1] = buf[0][j0 + 1] * iv[0];
+    u[0][2] = buf[0][j0 + 2] * iv[0];
+    u[0][3] = buf[0][j0 + 3] * iv[0];
+    pivot(buf[1][j0 + 1] - u[0][1] * u[0][1], piv[j0 + 1], u[1][1], iv[1]);
+    u[1][2] = (buf[1][j0 + 2] - u[0][1] * u[0][2]) * iv[1];
+    u[1][3] = (buf[1][j0 + 3] - u[0][1] * u[0][3]) * iv[1];
+    pivot(buf[2][j0 + 2] - u[0][2] * u[0][2] - u[1][2] * u[1][2], piv[j0 + 2], u[2][2], iv[2]);
+    u[2][3] = (buf[2][j0 + 3] - u[0][2] * u[0][3] - u[1][2] * u[1][3]) * iv[2];
+    pivot(buf[3][j0 + 3] - u[0][3] * u[0][3] - u[1][3] * u[1][3] - u[2][3] * u[2][3], piv[j0 + 3], u[3][3], iv[3]);
+    u[1][0] = u[2][0] = u[2][1] = u[3][0] = u[3][1] = u[3][2] = 0.0;
+    // rows j0 .. j0+3 of R at a column k: x = U^-T g_k (forward substitution)
+    auto solve = [&](int k, double &x0, double &x1, double &x2, double &x3) {
+      const double g0 = buf[0][k], g1 = buf[1][k], g2 = buf[2][k], g3 = buf[3][k];
+      x0 = g0 * iv[0];
+      x1 = (g1 - u[0][1] * x0) * iv[1];
+      x2 = (g2 - u[0][2] * x0 - u[1][2] * x1) * iv[2];
+      x3 = (g3 - u[0][3] * x0 - u[1][3] * x1 - u[2][3] * x2) * iv[3];
     };
-    double y0, y1, y2, y3;  // rows j0.. of R at column i (the update's left factor)
-    rows(i, y0, y1, y2, y3);
-    const bool below = i > j0 + 3, in = (i >= j0) && !below;
-    const int r0 = i - j0;
-    // this thread's row of U when it holds one of the block's rows
-    const double ub0 = (r0 == 0) ? u00 : 0.0;
-    const double ub1 = (r0 == 0) ? u01 : (r0 == 1 ? u11 : 0.0);
-    const double ub2 = (r0 == 0) ? u02 : (r0 == 1 ? u12 : (r0 == 2 ? u22 : 0.0));
-    const double ub3 = (r0 == 0) ? u03 : (r0 == 1 ? u13 : (r0 == 2 ? u23 : u33));
+    double xk[4][4], xi[4][4];  // [block row][own column / own row]
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int k = q + 4 * m;
-      double x0, x1, x2, x3;
-      rows(k, x0, x1, x2, x3);
-      const double upd = fma(-y3, x3, fma(-y2, x2, fma(-y1, x1, fma(-y0, x0, a[m]))));
-      const double mine = (r0 == 0) ? x0 : (r0 == 1 ? x1 : (r0 == 2 ? x2 : x3));
-      const double rin = (k > j0 + 3) ? mine
-                         : (k == j0 ? ub0 : (k == j0 + 1 ? ub1 : (k == j0 + 2 ? ub2 : (k == j0 + 3 ? ub3 : 0.0))));
-      a[m] = in ? rin : ((below && k > j0 + 3) ? upd : a[m]);
+    for (int c = 0; c < 4; ++c) {
+      solve(k0 + c, xk[0][c], xk[1][c], xk[2][c], xk[3][c]);
+      solve(i0 + c, xi[0][c], xi[1][c], xi[2][c], xi[3][c]);
+    }
+    const bool upd = (ti > st) && (tk > st);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double nv = fma(-xi[3][r], xk[3][c], fma(-xi[2][r], xk[2][c],
+                              fma(-xi[1][r], xk[1][c], fma(-xi[0][r], xk[0][c], a[r][c]))));
+        const double rrow = (tk > st) ? xk[r][c] : (tk == st ? u[r][c] : 0.0);
+        a[r][c] = (ti == st) ? rrow : (upd ? nv : a[r][c]);
+      }
+  }
+  if (bad && t == 0) atomicOr(fail, 1);
+  // R (zero below the diagonal tiles) into LDS, and out when asked for
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double z = (ti > tk) ? 0.0 : 1.0;
+    *(d2 *)&R[i0 + r][k0] = d2{a[r][0] * z, a[r][1] * z};
+    *(d2 *)&R[i0 + r][k0 + 2] = d2{a[r][2] * z, a[r][3] * z};
+    if (rout && i0 + r < w) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (k0 + c < w) rout[(int64_t)(i0 + r) * ld + k0 + c] = a[r][c] * z;
+    }
+  }
+  __syncthreads();
+  // R^-1 by block rows from the bottom; acc is this tile's right-hand side.
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = (ti == tk && r == c) ? 1.0 : 0.0;
+  for (int bb = CNB / 4 - 1; bb >= 0; --bb) {
+    if (ti == bb) {
+      double ub[4][4], ui[4][4], xo[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ub[r][c] = R[4 * bb + r][4 * bb + c];
+      inv4_upper(ub, ui);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v = fma(ui[r][q], acc[q][c], v);
+          xo[r][c] = (tk >= bb) ? v : 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        *(d2 *)&Xs[i0 + r][k0] = d2{xo[r][0], xo[r][1]};
+        *(d2 *)&Xs[i0 + r][k0 + 2] = d2{xo[r][2], xo[r][3]};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = xo[r][c];
+      }
+    }
+    __syncthreads();
+    if (ti < bb) {
+      double rt[4][4], xt[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const d2 r01 = *(const d2 *)&R[i0 + r][4 * bb], r23 = *(const d2 *)&R[i0 + r][4 * bb + 2];
+        rt[r][0] = r01.x; rt[r][1] = r01.y; rt[r][2] = r23.x; rt[r][3] = r23.y;
+        const d2 x01 = *(const d2 *)&Xs[4 * bb + r][k0], x23 = *(const d2 *)&Xs[4 * bb + r][k0 + 2];
+        xt[r][0] = x01.x; xt[r][1] = x01.y; xt[r][2] = x23.x; xt[r][3] = x23.y;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[r][c] = fma(-rt[r][3], xt[3][c], fma(-rt[r][2], xt[2][c],
+                          fma(-rt[r][1], xt[1][c], fma(-rt[r][0], xt[0][c], acc[r][c]))));
     }
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m) R[i][q + 4 * m] = a[m];
-  if (rout && i < w) {
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-      if (q + 4 * m < w) rout[(int64_t)i * ld + q + 4 * m] = a[m];
-  }
-  if (bad && t == 0) atomicOr(fail, 1);
-  __syncthreads();
-  if (t < CNB) piv[t] = 1.0 / R[t][t];
-  __syncthreads();
-  // R^-1: thread (c, g) holds rows g + 4 m of column c, b = e_c at first.
-  // Step ii: x_ii = b_ii / R_ii (held by the lane with g = ii % 4 at slot
-  // ii / 4), then b_r -= x_ii R_r,ii for every row; rows below ii meet the
-  // zeros under R's diagonal, and row ii's slot is set to x_ii afterwards.
-  const int c = t >> 2, g = t & 3;
-  double x[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) x[m] = (g + 4 * m == c) ? 1.0 : 0.0;
-#pragma unroll
-  for (int ii = CNB - 1; ii >= 0; --ii) {
-    const double v = __shfl(x[ii >> 2], (t & 63 & ~3) | (ii & 3), 64) * piv[ii];
-    double rc[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) rc[m] = R[g + 4 * m][ii];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = fma(-v, rc[m], x[m]);
-    x[ii >> 2] = (g == (ii & 3)) ? v : x[ii >> 2];
-  }
-#pragma unroll
-  for (int m = 0; m < 16; ++m) rinv[(g + 4 * m) * CNB + c] = x[m];
+    for (int c = 0; c < 4; ++c) rinv[(i0 + r) * CNB + k0 + c] = (tk >= ti) ? acc[r][c] : 0.0;
 }
 
 hipError_t launch_chol_diag(const double *G, int ld, int w, const double *gd, double *rinv, double *rout,
