@@ -443,3 +443,22 @@ def test_gpu_randomized_svd_eligibility_and_fallback():
          % (sk["n_rsvd"], sk["n_rsvd_fallback"], ek))
     assert sk["n_rsvd_fallback"] >= 1
     assert ek <= 1e-6
+
+
+def test_gpu_randomized_svd_eps_cut_inside_sketch():
+    """The randomized rank rule when Eq. (eps) cuts below the cap: at
+    eps = 1e-6 the oracle keeps 4 ... 62 values in several swaps of the 256^3
+    chi = 64 product.  The rule on the 2 cap computed values, with the weight
+    outside the sketch counted as tail, must find the same ranks, and the
+    product stays within 1e-6 of the oracle's."""
+    _say("case: randomized SVD, eps = 1e-6 cuts below the cap")
+    ux = I.turbulence_qtt(256, 101, 64)
+    o = O.ttm(ux, ux, 64, 1e-6)
+    assert min(o.ranks) < 64
+    C, st = _run(ux, ux, 64, 1e-6, svd_mode="randomized")
+    e = O.rel_frob(C, o.cores)
+    _say("  %d randomized, %d fell back; ranks equal %s; relative error vs oracle %.3e"
+         % (st["n_rsvd"], st["n_rsvd_fallback"], st["ranks"] == o.ranks, e))
+    assert st["n_rsvd"] >= 10
+    assert st["ranks"] == o.ranks
+    assert e <= 1e-6
