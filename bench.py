@@ -649,7 +649,8 @@ def sweep(args, dev):
     for chi in chis:
         line = measure_point(qtts[chi], chi, args.eps, idx, dev,
                              [q for q in args.sweep_precisions.split(",") if q and q != "f64"],
-                             profile=not args.no_profile)
+                             profile=not args.no_profile, base={"svd_mode": args.svd_mode})
+        line["svd_mode"] = args.svd_mode
         line = dict({"sweep": True, "workload": "3D turbulence QTT u_x*u_x, %d^3 grid, N=%d sites, d=8"
                      % (args.sweep_grid, n_sites)}, **line)
         print(json.dumps(line), flush=True)
@@ -668,7 +669,7 @@ def _mode_options(mode):
     return {"contract_precision": mode}
 
 
-def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=None):
+def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=None, base=None):
     """One point of the bond-dimension sweep: u * u for the QTT ``cores`` at
     chi_out = chi_mid = chi.  FP64 products per second (after one warm-up
     product below chi 512), the algorithmic flop rate and its fraction of
@@ -687,17 +688,18 @@ def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=No
     stream = torch.cuda.current_stream()
     if steps is None:
         steps = 2 if chi <= 256 else 1
+    base = base or {}
     if chi <= 256:
-        T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream)
+        T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream, **base)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(steps):
-        C, st = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream)
+        C, st = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream, **base)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / steps
     share = None
     if profile:
-        _, sp = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream, profile=True)
+        _, sp = T.multiply(A, A, chi, eps, workspace=ws, out=out, stream=stream, profile=True, **base)
         tot = sum(sp["kernel_ms"].values())
         share = {k: v / tot for k, v in sp["kernel_ms"].items()} if tot > 0 else None
     exact = _tt_entries(A.cores(), idx) ** 2
