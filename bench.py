@@ -119,7 +119,7 @@ def main():
                     help="gradient of <W, A*B> (1024^3 turbulence QTTs at chi 128, W random at chi 32)")
     ap.add_argument("--upper-chis", default="256,1024",
                     help="bond dimensions of the 10-site 1024^3 points added to the default line")
-    ap.add_argument("--upper-precisions", default="f32,rsvd,rsvd+f32",
+    ap.add_argument("--upper-precisions", default="f32,rsvd,rsvd+f32,rsvd-fp64",
                     help="reduced-accuracy modes timed at each added point: contraction precisions, "
                          "rsvd (randomized swap SVDs) and rsvd+<precision>")
     ap.add_argument("--no-upper", action="store_true", help="skip the 10-site points of the default line")
@@ -291,7 +291,7 @@ def main():
     rsvd = {}
     rsvd_cores = {}
     if not args.no_rsvd and args.svd_mode == "jacobi":
-        for mode in ("rsvd", "rsvd+f32"):
+        for mode in ("rsvd", "rsvd+f32", "rsvd-fp64"):
             kw = _mode_options(mode)
             rout = torch.empty(cap, dtype=torch.float64, device=dev)
             T.multiply(A, B, args.chi, args.eps, workspace=ws, out=rout, stream=stream, **kw)
@@ -660,7 +660,11 @@ def sweep(args, dev):
 def _mode_options(mode):
     """Options of a reduced-accuracy mode name: a contraction precision
     ("f32", "bf16", "bf16x3"), "rsvd" (the randomized swap SVD, FP64
-    contractions) or "rsvd+<precision>"."""
+    contractions), "rsvd+<precision>", or "rsvd-fp64" (the randomized swap
+    SVD with 20 iterations and an acceptance bound of 1e-14)."""
+    if mode == "rsvd-fp64":
+        # the randomized swap SVD tuned to FP64 parity: 20 iterations, acceptance bound 1e-14
+        return {"svd_mode": "randomized", "rsvd_power": 20, "rsvd_tol": 1e-14}
     if mode.startswith("rsvd"):
         kw = {"svd_mode": "randomized"}
         if "+" in mode:

@@ -125,11 +125,16 @@ typedef struct ttm_options {
                               no forced ranks;
                               other SVDs take the full SVD, and so does any swap whose CholeskyQR
                               breaks down or whose estimated subspace error, (s_2cap / s_r)^(2q+1)
-                              s_r / ||Theta||_F from the projected values, exceeds 2e-8.  About
-                              2e-7 of the FP64 product on the turbulence workloads, not 1e-12.
+                              s_r / ||Theta||_F from the projected values, exceeds rsvd_tol.  With
+                              the defaults about 3e-8 of the FP64 product on the turbulence
+                              workloads, not 1e-12.
                               Not with ttm_multiply_vjp (TTM_EUNSUPPORTED) */
   int32_t rsvd_power;      /* TTM_SVD_RANDOMIZED: subspace iterations q, 0 <= q <= 64 (default 10);
                               the subspace error decays like (sigma_{2 cap + 1} / sigma_r)^(2q+1) */
+  double rsvd_tol;         /* TTM_SVD_RANDOMIZED: the acceptance bound on the estimated subspace error,
+                              0 < rsvd_tol <= 1 (default 2e-8); swaps above it take the full SVD.  With
+                              rsvd_power = 20 and rsvd_tol = 1e-14 the products of the turbulence
+                              workloads agree with the full SVD's to FP64 parity (1e-12) */
 } ttm_options;
 
 /* Values of ttm_options.svd_mode. */

@@ -157,13 +157,15 @@ _DEFAULT_WS = {}
 
 def _options(chi_mid=None, final_round=True, max_sweeps=10, svd_max_sweeps=40, seed=12345,
              forced_ranks=None, trace_cap=0, profile=False, contract_precision="f64", move_factor="second",
-             gauge="moving", svd_mode="jacobi", rsvd_power=None):
+             gauge="moving", svd_mode="jacobi", rsvd_power=None, rsvd_tol=None):
     from ._abi import PRECISIONS, SVD_MODES
     o = TtmOptions()
     lib().ttm_default_options(ctypes.byref(o))
     o.svd_mode = SVD_MODES[svd_mode] if isinstance(svd_mode, str) else int(svd_mode)
     if rsvd_power is not None:
         o.rsvd_power = int(rsvd_power)
+    if rsvd_tol is not None:
+        o.rsvd_tol = float(rsvd_tol)
     o.move_factor = {"second": 0, "smaller": 1}[move_factor] if isinstance(move_factor, str) else int(move_factor)
     o.gauge = {"moving": 0, "right": 1}[gauge] if isinstance(gauge, str) else int(gauge)
     o.contract_precision = (PRECISIONS[contract_precision] if isinstance(contract_precision, str)
@@ -287,7 +289,8 @@ def multiply(A, B, chi_out, tol, **opts):
     profile, contract_precision ("f64", "f32", "bf16" or "bf16x3"),
     move_factor ("second" or "smaller"), gauge ("moving" or "right"),
     svd_mode ("jacobi" or "randomized": the reduced-accuracy range-finder SVD
-    of the capped swaps) and rsvd_power (its subspace iterations, default 10)."""
+    of the capped swaps), rsvd_power (its subspace iterations, default 10) and
+    rsvd_tol (its acceptance bound, default 2e-8)."""
     return _run("ttm", A, B, chi_out, tol, **opts)
 
 

@@ -58,6 +58,7 @@ class TtmOptions(ctypes.Structure):
         ("gauge", ctypes.c_int32),
         ("svd_mode", ctypes.c_int32),
         ("rsvd_power", ctypes.c_int32),
+        ("rsvd_tol", ctypes.c_double),
     ]
 
 

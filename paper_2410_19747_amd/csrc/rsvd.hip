@@ -33,7 +33,8 @@
 // After the SVD of B that is estimated from B's own values, rho =
 // sigma_l / sigma_r, as rho^(2q+1) sigma_r / ||Theta||_F (the move of the
 // kept part relative to the chain's norm); a swap whose estimate exceeds
-// 2e-8 (a spectrum too flat at the cut) also takes the full SVD.  At q = 10
+// the acceptance bound (default 2e-8; a spectrum too flat at the cut) also
+// takes the full SVD.  At q = 10
 // the products of the turbulence workloads stay within about 2e-7 of the
 // FP64 product (the mixed-precision bar is 1e-6); the FP32 sketch products
 // set a floor of about 1e-8 per swap.  The full SVD meets 1e-12.
@@ -50,7 +51,6 @@ namespace {
 constexpr int CNB = 64;   // Cholesky block
 constexpr int CNT = 256;  // threads of the diagonal-block kernel
 constexpr double kU = 2.220446049250313e-16;
-constexpr double kRsvdAccept = 2e-8;  // largest accepted subspace-error estimate per swap
 
 size_t r32(size_t n) { return (n + 31) & ~(size_t)31; }
 
@@ -448,9 +448,9 @@ RsvdBufs rsvd_carve(int m, int n, int cap, double *base) {
 }
 }  // namespace
 
-RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int max_sweeps, double eps,
-                      int sketch_prec, uint64_t seed, int64_t stream_pos, double *pt, double *ws, hipStream_t s,
-                      KernelTimer *timer, int trace) {
+RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, double accept, int max_sweeps,
+                      double eps, int sketch_prec, uint64_t seed, int64_t stream_pos, double *pt, double *ws,
+                      hipStream_t s, KernelTimer *timer, int trace) {
   RsvdResult out;
   const int l = rsvd_sketch_cols(cap);
   RsvdBufs b = rsvd_carve(m, n, cap, ws);
@@ -574,8 +574,8 @@ RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int
   // about rho^(2q+1) with rho = sigma_{l+1} / sigma_r, bounded here by the
   // computed sigma_l / sigma_r; relative to the chain's norm the kept part
   // moves by about rho^(2q+1) sigma_r / ||Theta||_F.  Swaps whose estimate
-  // exceeds kRsvdAccept (a spectrum too flat at the cut for q iterations)
-  // take the full SVD.
+  // exceeds `accept` (a spectrum too flat at the cut for q iterations) take
+  // the full SVD.
   {
     double sv[2] = {0.0, 0.0};
     if (!ok(hipMemcpyAsync(&sv[0], b.sig + (r - 1), sizeof(double), hipMemcpyDeviceToHost, s))) return out;
@@ -585,10 +585,10 @@ RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int
     const double rho = sv[0] > 0.0 ? sv[1] / sv[0] : 1.0;
     const double est = pow(rho, 2.0 * power + 1.0) * (so.total > 0.0 ? sv[0] / sqrt(so.total) : 1.0);
     out.estimate = est;
-    if (!(est <= kRsvdAccept)) {
+    if (!(est <= accept)) {
       out.fallback = true;
       if (trace) fprintf(stderr, "[ttm] rsvd %dx%d cap %d: estimate %.2e above %.0e, full SVD instead\n", m, n, cap,
-                         est, kRsvdAccept);
+                         est, accept);
       return out;
     }
   }

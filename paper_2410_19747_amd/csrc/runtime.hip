@@ -73,6 +73,7 @@ struct Options {
   int gauge = TTM_GAUGE_MOVING;
   int svd_mode = TTM_SVD_JACOBI;
   int rsvd_power = 10;
+  double rsvd_tol = 2e-8;
 };
 
 // Largest matrix a QR or SVD step takes: each side at most 2^30 (the kernels
@@ -150,6 +151,8 @@ int resolve_options(const ttm_options *o, int chi_out, Options &r) {
   r.svd_mode = o->svd_mode;
   if (o->rsvd_power < 0 || o->rsvd_power > 64) return TTM_EINVAL;
   r.rsvd_power = o->rsvd_power;
+  if (!(o->rsvd_tol > 0.0 && o->rsvd_tol <= 1.0)) return TTM_EINVAL;  // also rejects NaN
+  r.rsvd_tol = o->rsvd_tol;
   if (o->gauge != TTM_GAUGE_MOVING && o->gauge != TTM_GAUGE_RIGHT) return TTM_EINVAL;
   r.gauge = o->gauge;
   return TTM_OK;
@@ -583,8 +586,8 @@ struct Runner {
   // when it fell back (CholeskyQR breakdown) and the full SVD must run.
   int rsvd(const double *Y, int m, int n, int cap, double *pt, double *ws, bool *done) {
     *done = false;
-    RsvdResult rs = rsvd_oside(Y, m, n, cap, o.rsvd_power, o.svd_max_sweeps, eps_, o.contract_prec, o.seed,
-                               (int64_t)n_rsvd << 40, pt, ws, st, &timer, trace);
+    RsvdResult rs = rsvd_oside(Y, m, n, cap, o.rsvd_power, o.rsvd_tol, o.svd_max_sweeps, eps_, o.contract_prec,
+                               o.seed, (int64_t)n_rsvd << 40, pt, ws, st, &timer, trace);
     ++n_rsvd;
     jac_sweeps += rs.sweeps;
     jac_max = std::max(jac_max, rs.sweeps);
@@ -1377,6 +1380,7 @@ void ttm_default_options(ttm_options *opt) {
   opt->seed = 12345;
   opt->svd_mode = TTM_SVD_JACOBI;
   opt->rsvd_power = 10;
+  opt->rsvd_tol = 2e-8;
 }
 
 const char *ttm_strerror(int code) {

@@ -276,7 +276,7 @@ SvdResult svd_oside(const SvdPlan &p, const double *Y, double eps, int cap, int 
 // GemmPrec sketch_prec), then the Jacobi SVD
 // of the projection.  Theta is left intact.  fallback = true (no error)
 // when a CholeskyQR broke down or the estimated subspace error exceeded the
-// acceptance bound: the caller runs the full SVD instead.  The
+// acceptance bound `accept`: the caller runs the full SVD instead.  The
 // test matrix is the SplitMix64 stream of `seed` from counter stream_pos.
 struct RsvdResult {
   int rank = -1;
@@ -293,9 +293,9 @@ size_t cholqr2_ws_doubles(int p, int l);
 hipError_t cholqr2(double *Y, int p, int l, double *ws, int *fail_host, hipStream_t s);
 bool rsvd_eligible(int m, int n, int cap);
 size_t rsvd_ws_doubles(int m, int n, int cap);
-RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, int max_sweeps, double eps,
-                      int sketch_prec, uint64_t seed, int64_t stream_pos, double *pt, double *ws, hipStream_t s,
-                      KernelTimer *timer, int trace);
+RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, double accept, int max_sweeps,
+                      double eps, int sketch_prec, uint64_t seed, int64_t stream_pos, double *pt, double *ws,
+                      hipStream_t s, KernelTimer *timer, int trace);
 
 // ------------------------------------------------------------------ reverse mode
 // The record a TTM product keeps for its reverse mode: one entry per step,

@@ -79,6 +79,7 @@ int main() {
     o.contract_precision = uniform(seed, 0, 3);
     o.svd_mode = uniform(seed, 0, 1);
     o.rsvd_power = uniform(seed, 0, 12);
+    o.rsvd_tol = uniform(seed, 0, 1) ? 1e-14 : 2e-8;
     const int chi = uniform(seed, 1, 80);
     size_t ws = 0;
     int64_t cap = 0;
@@ -151,6 +152,11 @@ int main() {
     ttm_default_options(&o);
     o.rsvd_power = 65;
     EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
+    for (double bad_tol : {0.0, -1.0, 2.0, (double)NAN}) {
+      ttm_default_options(&o);
+      o.rsvd_tol = bad_tol;
+      EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);
+    }
     ttm_default_options(&o);
     o.n_forced = 2;
     EXPECT(ttm_query(&A.view, &B.view, 4, &o, &ws, &cap) == TTM_EINVAL);

@@ -441,7 +441,7 @@ def test_randomized_svd_options(L):
     A = _TT([8] * 8, [1, 8, 64, 128, 128, 128, 64, 8, 1])
     o = _abi.TtmOptions()
     L.ttm_default_options(ctypes.byref(o))
-    assert o.svd_mode == _abi.TTM_SVD_JACOBI and o.rsvd_power == 10
+    assert o.svd_mode == _abi.TTM_SVD_JACOBI and o.rsvd_power == 10 and o.rsvd_tol == 2e-8
     rc, ws_full, cap_full = _query(L, A, A, 128, o)
     assert rc == 0
     o.svd_mode = _abi.TTM_SVD_RANDOMIZED
@@ -451,6 +451,11 @@ def test_randomized_svd_options(L):
         o.svd_mode, o.rsvd_power = mode, power
         assert _query(L, A, A, 128, o)[0] == _abi.TTM_EINVAL
     o.svd_mode, o.rsvd_power = _abi.TTM_SVD_RANDOMIZED, 0
+    assert _query(L, A, A, 128, o)[0] == 0
+    for tol in (0.0, -1e-8, 1.5, float("nan")):
+        o.rsvd_tol = tol
+        assert _query(L, A, A, 128, o)[0] == _abi.TTM_EINVAL
+    o.rsvd_tol = 1e-14
     assert _query(L, A, A, 128, o)[0] == 0
     need, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
     assert L.ttm_vjp_query(ctypes.byref(A.view), ctypes.byref(A.view), 128, ctypes.byref(o), ctypes.byref(need),

@@ -153,6 +153,14 @@ def test_gpu_config2_turbulence_vs_oracle(chi):
     assert sr["n_rsvd"] >= 10 and sr["n_rsvd"] >= 3 * sr["n_rsvd_fallback"]
     assert sr["ranks"] == o.ranks
     assert er <= 1e-6
+    # With 20 subspace iterations and an acceptance bound of 1e-14 the
+    # randomized swaps reach FP64 parity.
+    Cq, sq = _run(A, B, chi, 1e-14, svd_mode="randomized", rsvd_power=20, rsvd_tol=1e-14)
+    eq = O.rel_frob(Cq, o.cores)
+    _say("  randomized, q = 20, bound 1e-14 (%d, %d fell back): relative error vs oracle %.3e"
+         % (sq["n_rsvd"], sq["n_rsvd_fallback"], eq))
+    assert sq["n_rsvd"] >= 1 and sq["ranks"] == o.ranks
+    assert eq <= TOL
 
 
 _TEN_SITE_QTTS = {}
@@ -201,6 +209,12 @@ def test_gpu_ten_sites_1024_turbulence_vs_oracle(chi):
              % (sr["n_rsvd"], prec, er))
         assert sr["n_rsvd"] >= 10 and sr["n_rsvd"] >= 3 * sr["n_rsvd_fallback"]
         assert er <= 1e-6
+    Cq, sq = _run(q, q, chi, 1e-14, svd_mode="randomized", rsvd_power=20, rsvd_tol=1e-14)
+    eq = O.rel_frob(Cq, o.cores)
+    _say("  randomized, q = 20, bound 1e-14 (%d, %d fell back): relative error vs FP64 oracle %.3e"
+         % (sq["n_rsvd"], sq["n_rsvd_fallback"], eq))
+    assert sq["n_rsvd"] >= 1 and sq["ranks"] == o.ranks
+    assert eq <= TOL
 
 
 def test_gpu_model_flops_golden():
