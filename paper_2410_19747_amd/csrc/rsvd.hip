@@ -1,7 +1,7 @@
-// Randomized truncated SVD of a swap matrix (the reduced-accuracy mode
-// TTM_SVD_RANDOMIZED): a range finder by subspace iteration (Halko,
-// Martinsson and Tropp, SIAM Review 53 (2011), Algorithms 4.3 and 4.4),
-// followed by the one-sided Jacobi SVD of the projected matrix.
+// Randomized truncated SVD of a swap matrix (TTM_SVD_RANDOMIZED): a range
+// finder by subspace iteration (Halko, Martinsson and Tropp, SIAM Review 53
+// (2011), Algorithms 4.3 and 4.4), followed by the one-sided Jacobi SVD of
+// the projected matrix.
 //
 // The Swap of Sec. II.B keeps r = min(r_eps, cap) singular triplets of an
 // m x n matrix Theta whose sides are d times the bond, so a cap of chi keeps
@@ -10,10 +10,12 @@
 //      counter-based SplitMix64 stream; Y <- orth(Y);
 //   2. q times: Z = orth(Theta Y), Y = orth(Theta^T Z); then a second
 //      orthonormalisation pass on Y;
-//   3. B = Theta Y (m x l, FP64), its SVD B = U S V_B^T by the one-sided
-//      Jacobi driver (svd_oside, l columns);
-//   4. the rule of Eq. (eps) on S with the weight that the l directions do
-//      not capture, ||Theta||_F^2 - ||B||_F^2, added to every tail;
+//   3. B = Theta Y (m x l, FP64) = Q_B R_B by CholeskyQR2, and the SVD of
+//      the l x l factor R_B (B's values and right vectors V_B) by the
+//      one-sided Jacobi driver (svd_oside);
+//   4. the rule of Eq. (eps) on those values with the weight that the l
+//      directions do not capture, ||Theta||_F^2 - ||B||_F^2, added to every
+//      tail;
 //   5. V_r = Y V_B,r: P' = V_r^T (orthonormal rows), and the caller forms
 //      X' = Theta V_r.
 // The products of steps 1-2 take the operand precision of the contractions
@@ -21,23 +23,23 @@
 // within each 16-deep k-tile and FP64 across tiles): they only steer the
 // subspace.  orth() is one CholeskyQR pass (G = Y^T Y = R^T R, Y <- Y R^-1)
 // on the intermediate bases and two (CholeskyQR2; Yamamoto et al., ETNA 44
-// (2015)) on the final one, all in FP64: a blocked
-// Cholesky (one workgroup per 64 x 64 diagonal block, matrix-core products
-// for the panels and trailing updates) and a blocked triangular solve.
-// CholeskyQR needs kappa(Y) well below u^(-1/2); a pivot that falls to the
-// rounding level of its column's norm (rank-deficient Theta, or
-// kappa(Y) beyond ~1e7) raises a flag, and the caller then runs the full
-// SVD on the same matrix instead.
+// (2015)) on the final one, all in FP64: a blocked Cholesky (one workgroup
+// per 64 x 64 diagonal block, matrix-core products for the panels and
+// trailing updates) and a blocked triangular solve.  CholeskyQR needs
+// kappa(Y) well below u^(-1/2); a pivot that falls to the rounding level of
+// its column's norm (rank-deficient Theta, or kappa(Y) beyond ~1e7) raises
+// a flag, and the caller then runs the full SVD on the same matrix instead.
 //
 // Accuracy: the subspace error decays like (sigma_{l+1} / sigma_r)^(2q+1).
-// After the SVD of B that is estimated from B's own values, rho =
+// After the SVD it is estimated from the computed values, rho =
 // sigma_l / sigma_r, as rho^(2q+1) sigma_r / ||Theta||_F (the move of the
 // kept part relative to the chain's norm); a swap whose estimate exceeds
 // the acceptance bound (default 2e-8; a spectrum too flat at the cut) also
-// takes the full SVD.  At q = 10
-// the products of the turbulence workloads stay within about 2e-7 of the
-// FP64 product (the mixed-precision bar is 1e-6); the FP32 sketch products
-// set a floor of about 1e-8 per swap.  The full SVD meets 1e-12.
+// takes the full SVD.  With the defaults (q = 10) the products of the
+// turbulence workloads stay within about 3e-8 of the FP64 product (the
+// mixed-precision bar is 1e-6); FP32 sketch products add about 5e-7.  With
+// q = 20 and a bound of 1e-14 they agree with the full SVD's to FP64
+// parity (below 1e-13).
 #include <math.h>
 #include <stdio.h>
 
