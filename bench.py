@@ -305,7 +305,8 @@ def main():
             rsvd[mode] = {"ms_per_product": 1e3 * tr, "products_per_s": 1.0 / tr,
                           "speedup_vs_f64": (ms_per_step / 1e3) / tr, "randomized_svds": sr["n_rsvd"],
                           "randomized_fallbacks": sr["n_rsvd_fallback"], "jacobi_sweeps": sr["sweeps"],
-                          "ranks_equal_f64": sr["ranks"] == st["ranks"]}
+                          "ranks_equal_f64": sr["ranks"] == st["ranks"],
+                          "effective_fp64_mfma_frac": model_flops / tr / 1e12 / FP64_MFMA_PEAK_TFLOPS}
             _log("  %s: %.1f ms per product (%.2fx over FP64), %d randomized SVDs"
                  % (mode, 1e3 * tr, rsvd[mode]["speedup_vs_f64"], sr["n_rsvd"]))
     accuracy = None
@@ -726,7 +727,10 @@ def measure_point(cores, chi, eps, idx, dev, precisions, profile=False, steps=No
         mixed[prec] = {"ms_per_product": 1e3 * tm, "speedup_vs_f64": dt / tm,
                        "sampled_rel_diff_vs_f64": float(torch.linalg.norm(gm - got) / torch.linalg.norm(got)),
                        "jacobi_sweeps": stm["sweeps"], "max_bond": stm["max_bond"],
-                       "randomized_svds": stm["n_rsvd"], "randomized_fallbacks": stm["n_rsvd_fallback"]}
+                       "randomized_svds": stm["n_rsvd"], "randomized_fallbacks": stm["n_rsvd_fallback"],
+                       # the FP64 schedule's algorithmic flops over this mode's time: the rate at
+                       # which it delivers the same product, against the FP64 matrix peak
+                       "effective_fp64_mfma_frac": st["model_flops"] / tm / 1e12 / FP64_MFMA_PEAK_TFLOPS}
         _log("    %s: %.1f ms (%.2fx), sampled rel diff vs FP64 %.2e"
              % (prec, 1e3 * tm, dt / tm, mixed[prec]["sampled_rel_diff_vs_f64"]))
         del Cm
