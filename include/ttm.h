@@ -116,19 +116,19 @@ typedef struct ttm_options {
                               in exact arithmetic) */
   int32_t svd_mode;        /* the truncated SVD of each capped swap: TTM_SVD_JACOBI (default: the
                               full SVD, results within 1e-12 of an exact truncation) or
-                              TTM_SVD_RANDOMIZED, a reduced-accuracy mode: a subspace-iteration
-                              range finder with 2 cap columns (Halko, Martinsson and Tropp 2011,
-                              Alg. 4.4), its products on FP32 operands, CholeskyQR2 in FP64, then
-                              the FP64 Jacobi SVD of the 2 cap projected columns and the rule of
-                              Eq. (eps) with the uncaptured weight counted as tail.  Used where
-                              4 cap <= min(m, n) of the swap matrix, with the default gauge and
-                              no forced ranks;
-                              other SVDs take the full SVD, and so does any swap whose CholeskyQR
-                              breaks down or whose estimated subspace error, (s_2cap / s_r)^(2q+1)
-                              s_r / ||Theta||_F from the projected values, exceeds rsvd_tol.  With
-                              the defaults about 3e-8 of the FP64 product on the turbulence
-                              workloads, not 1e-12.
-                              Not with ttm_multiply_vjp (TTM_EUNSUPPORTED) */
+                              TTM_SVD_RANDOMIZED: a subspace-iteration range finder with 2 cap
+                              columns (Halko, Martinsson and Tropp 2011, Alg. 4.4) whose products
+                              take the contraction precision, CholeskyQR orthonormalisation in
+                              FP64, then the FP64 Jacobi SVD of the 2 cap x 2 cap factor of the
+                              projected matrix and the rule of Eq. (eps) with the uncaptured
+                              weight counted as tail.  Used where 4 cap <= min(m, n) of the swap
+                              matrix, with the default gauge and no forced ranks; other SVDs take
+                              the full SVD, and so does any swap whose CholeskyQR breaks down or
+                              whose estimated subspace error, (s_2cap / s_r)^(2q+1) s_r /
+                              ||Theta||_F from the projected values, exceeds rsvd_tol.  With the
+                              defaults about 3e-8 of the FP64 product on the turbulence workloads;
+                              see rsvd_tol for FP64 parity.  Not with ttm_multiply_vjp
+                              (TTM_EUNSUPPORTED) */
   int32_t rsvd_power;      /* TTM_SVD_RANDOMIZED: subspace iterations q, 0 <= q <= 64 (default 10);
                               the subspace error decays like (sigma_{2 cap + 1} / sigma_r)^(2q+1) */
   double rsvd_tol;         /* TTM_SVD_RANDOMIZED: the acceptance bound on the estimated subspace error,
