@@ -59,7 +59,9 @@ enum {
   TTM_ENONFINITE = -6,   /* NaN or Inf met in the data                        */
   TTM_EHIP = -7,         /* a HIP runtime call failed                         */
   TTM_EFORCED = -8,      /* forced rank list too short or out of range        */
-  TTM_EUNSUPPORTED = -9  /* dtype other than TTM_F64, or an SVD beyond the kernels' size limit */
+  TTM_EUNSUPPORTED = -9  /* dtype other than TTM_F64, an option that the     */
+                         /* entry point does not take, or an SVD beyond the   */
+                         /* kernels' size limit                               */
 };
 
 typedef enum { TTM_F64 = 0 } ttm_dtype;

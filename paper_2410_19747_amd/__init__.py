@@ -25,8 +25,8 @@ import os
 
 from ._abi import (  # noqa: F401
     TTM_OK, TTM_EINVAL, TTM_ESHAPE, TTM_EWORKSPACE, TTM_ECAPACITY, TTM_ENOCONV, TTM_ENONFINITE,
-    TTM_EHIP, TTM_EFORCED, TTM_EUNSUPPORTED, TtmTT, TtmTTOut, TtmOptions, TtmStats, load_library,
-    library_path,
+    TTM_EHIP, TTM_EFORCED, TTM_EUNSUPPORTED, TTM_SVD_JACOBI, TTM_SVD_RANDOMIZED, SVD_MODES, TtmTT, TtmTTOut,
+    TtmOptions, TtmStats, load_library, library_path,
 )
 
 __all__ = [
@@ -524,8 +524,15 @@ def ttm_inner_loss(W, A, B, chi_out, tol, contract_precision="f64", **opts):
     """0-d tensor <W, TTM(A, B)> whose backward gives dL/dA.data and
     dL/dB.data (PackedTT data tensors with requires_grad): the environments
     of ttm_inner_grad for dL/dC, then the reverse mode of the truncated
-    product (ttm_multiply_vjp).  W is a constant train."""
+    product (ttm_multiply_vjp).  W is a constant train.  Only the full swap
+    SVD (svd_mode "jacobi") is differentiated; other modes raise TTMError
+    (TTM_EUNSUPPORTED)."""
     global _INNER_LOSS
+    mode = opts.get("svd_mode", "jacobi")
+    if (SVD_MODES[mode] if isinstance(mode, str) else int(mode)) != TTM_SVD_JACOBI:
+        # refused before the forward product: the reverse mode differentiates
+        # the full SVD's truncation only
+        raise TTMError(TTM_EUNSUPPORTED, "ttm_inner_loss (svd_mode %r; only the full SVD is differentiated)" % (mode,))
     if _INNER_LOSS is None:
         _INNER_LOSS = _make_inner_loss_function()
     W, A, B = pack(W), pack(A), pack(B)

@@ -1394,7 +1394,7 @@ const char *ttm_strerror(int code) {
     case TTM_ENONFINITE: return "NaN or Inf in the data";
     case TTM_EHIP: return "HIP runtime error";
     case TTM_EFORCED: return "forced rank list inconsistent with the schedule";
-    case TTM_EUNSUPPORTED: return "unsupported dtype, or an SVD larger than the kernels take";
+    case TTM_EUNSUPPORTED: return "unsupported dtype or option combination, or an SVD larger than the kernels take";
     default: return "unknown error";
   }
 }

@@ -34,3 +34,12 @@ def test_packed_tt_refuses_host_memory():
 def test_workspace_refuses_host_memory():
     with pytest.raises(ValueError, match="GPU memory"):
         T.Workspace(torch.device("cpu")).get(1024)
+
+
+def test_inner_loss_refuses_randomized_svd():
+    """The loss's backward is the reverse mode of the full SVD's truncation,
+    so a randomized swap SVD is refused before the forward product runs."""
+    for mode in ("randomized", 1):
+        with pytest.raises(T.TTMError, match="svd_mode") as e:
+            T.ttm_inner_loss(None, None, None, 8, 1e-14, svd_mode=mode)
+        assert e.value.code == T.TTM_EUNSUPPORTED
