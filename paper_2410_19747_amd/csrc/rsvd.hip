@@ -479,7 +479,7 @@ RsvdResult rsvd_oside(const double *Theta, int m, int n, int cap, int power, dou
     return true;
   };
   auto prod = [&](bool transposed, const double *Xin, double *Xout) {
-    // Xout = Theta Xin (m x l) or Theta^T Xin (n x l); FP32 operands
+    // Xout = Theta Xin (m x l) or Theta^T Xin (n x l), operands in the sketch precision
     GemmArgs g;
     g.prec = sketch_prec;
     if (transposed) {
