@@ -343,8 +343,9 @@ int ttm_inner_grad_ex(const ttm_tt *W, const ttm_tt *A, const ttm_tt *B, int32_t
  * directions by 1/sigma_i^2: it is defined where the kept values are
  * separated from the dropped ones, and its error grows as 1/gap.  A QR
  * adjoint solves with R^T: the unfoldings must have full rank (input bonds
- * within the structural bounds).  Default gauge only (TTM_EUNSUPPORTED for
- * TTM_GAUGE_RIGHT); move_factor is honoured.  dA, dB: device buffers laid out
+ * within the structural bounds).  Default gauge and the full swap SVD only
+ * (TTM_EUNSUPPORTED for TTM_GAUGE_RIGHT or TTM_SVD_RANDOMIZED, from both
+ * calls); move_factor is honoured.  dA, dB: device buffers laid out
  * like A's and B's data.  ws: ttm_vjp_query's bytes (the product's own
  * workspace, the record of its steps, the cotangents and scratch).  opt->profile
  * must be 0.  Blocking like the other entry points. */
